@@ -1,0 +1,181 @@
+/*
+ * nufft_mi355x.h -- C ABI of the low-rank nonuniform FFT for AMD MI355X (gfx950).
+ *
+ * Method: Ruiz-Antolin & Townsend, "A nonuniform fast Fourier transform based
+ * on low rank approximation" (arXiv:1701.04492).  The type-II transform
+ *     f_j = sum_{k=0}^{N-1} c_k exp(-2 pi i x_j k),   0 <= j < M      (Sec. 1, eq. (2))
+ * is evaluated as f ~ sum_{r<K} D_{u_r} I(t,:) F_L D_{v_r} c  (Sec. 2.2, eq. (Fc)):
+ * each sample is rounded to its nearest point s_j/L of a grid of L >= N
+ * points (t_j = s_j mod L), and u_r, v_r are the rank-K Chebyshev/Bessel
+ * factors of exp(-2 pi i (x_j - s_j/L) k) (Sec. 2.1.2, Appendix A) chosen so
+ * that the factorisation error is at most eps.  The online stage is K
+ * diagonally scaled FFTs of size L, a gather by t and a row sum (Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ *  - Array arguments named *_dev are DEVICE pointers (hipMalloc'd or from a
+ *    framework allocator); the caller owns them and keeps them alive until the
+ *    work queued on `stream` has finished.  Arguments named *_host are host
+ *    pointers, read before the call returns.
+ *  - Complex arrays are interleaved (re, im): NUFFT_C64 = two floats,
+ *    NUFFT_C128 = two doubles.  Sample coordinates are always double, on
+ *    every precision path: an FP32 coordinate would carry ~0.2 rad of phase
+ *    error at N = 2^20.
+ *  - Frequencies are 0..N-1 (not centred); forward transforms use the sign
+ *    -2 pi i.  No normalisation is applied anywhere.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Work is stream ordered.  Plans allocate device memory; *_exec calls
+ *    allocate nothing, never synchronise the host and may be captured into a
+ *    HIP graph.  A plan may be used from several streams only sequentially.
+ *  - Errors are returned as nufft_status; the library never aborts.  On an
+ *    error from *_plan, *out is set to NULL and nothing is leaked.
+ *  - Accuracy: with FP32 arithmetic eps must be >= 1e-7, with FP64 >= 1e-15
+ *    (NUFFT_ERR_UNSUPPORTED otherwise).  The approximation error satisfies
+ *    |f~_j - f_j| <= eps ||c||_1 (Sec. 2.4 error bound, max-norm form) plus
+ *    rounding of the working precision.
+ */
+#ifndef NUFFT_MI355X_H
+#define NUFFT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nufft_plan_s *nufft_plan_t;
+
+typedef enum {
+    NUFFT_OK = 0,
+    NUFFT_ERR_INVALID_ARG = 1,   /* bad size, pointer, eps or flag combination   */
+    NUFFT_ERR_UNSUPPORTED = 2,   /* valid request this build cannot serve (size, eps floor) */
+    NUFFT_ERR_ALLOC = 3,         /* device or host allocation failed              */
+    NUFFT_ERR_NONFINITE = 4,     /* a sample coordinate is NaN or infinite        */
+    NUFFT_ERR_HIP = 5            /* a HIP runtime call failed                     */
+} nufft_status;
+
+typedef enum {
+    NUFFT_C64 = 0,               /* complex float data, FP32 arithmetic (fused kernels) */
+    NUFFT_C128 = 1               /* complex double data, FP64 arithmetic               */
+} nufft_dtype;
+
+enum {
+    /* Take gamma = N/(2L) (the largest possible) instead of reading
+     * max|N(x_j - s_j/L)| back from the device: the plan then never
+     * synchronises, at the price of K for gamma = 1/2 (Sec. 2.2). */
+    NUFFT_FLAG_FIX_GAMMA_HALF = 1u,
+    /* Run the plain unfused online stage: scale kernel, stand-alone FFT
+     * passes over a K x L buffer, a stored U table (Sec. 2.3, "Planning the
+     * transform") and a separate gather/row-sum kernel.  Default is fused. */
+    NUFFT_FLAG_PLAIN = 2u
+};
+
+/* ---- 1-D type II / type I / adjoint ----------------------------------- */
+
+/* Planning stage (Sec. 2.3): nearest-grid assignment s = round(L x),
+ * t = s mod L (Sec. 2.2, eq. (t_vec)), gamma = max_j |N(x_j - s_j/L)|, the
+ * rank K(eps, gamma) and the Bessel coefficients a_pr (Sec. 2.1.2), and a
+ * stable sort of the samples by FFT output tile.
+ *   n_modes  N >= 1, number of Fourier coefficients.
+ *   n_pts    M >= 1, number of samples.
+ *   x_dev    M doubles, any finite reals (periodic in 1); read during the call.
+ *   eps      working accuracy, 0 < eps < 1, above the precision floor.
+ * The FFT grid L is the smallest power of two >= N (oversampling with
+ * N <= L < 2N, Sec. 2.3); N up to 2^24.  Synchronises `stream` once to read
+ * gamma back unless NUFFT_FLAG_FIX_GAMMA_HALF is set. */
+nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts,
+                         const double *x_dev, double eps, nufft_dtype dtype,
+                         uint32_t flags, void *stream);
+
+/* Online stage of type II (Sec. 2.3, two-step form):
+ *   f_dev[j] ~ sum_{k<N} c_dev[k] exp(-2 pi i x_j k),  j < M.
+ * c_dev: N complex, f_dev: M complex (dtype of the plan); may not alias. */
+nufft_status nufft2_exec(nufft_plan_t plan, const void *c_dev, void *f_dev, void *stream);
+
+/* Transpose and adjoint of type II (Sec. 3.1):
+ *   sign = -1: f_dev[k] ~ sum_{j<M} c_dev[j] exp(-2 pi i x_j k)   (type I, F2^T c)
+ *   sign = +1: f_dev[k] ~ sum_{j<M} c_dev[j] exp(+2 pi i x_j k)   (adjoint, F2^H c)
+ * c_dev: M complex, f_dev: N complex. */
+nufft_status nufft1_exec(nufft_plan_t plan, const void *c_dev, void *f_dev, int sign,
+                         void *stream);
+
+/* Derivative pass for the gradient in x of a real loss L(f), f = F2 c
+ * (calculus on Sec. 1, eq. (2)):
+ *   gx_dev[j] = Re( conj(g_dev[j]) * sum_k (-2 pi i k) c_dev[k] exp(-2 pi i x_j k) )
+ * with g_j = dL/dRe f_j + i dL/dIm f_j.  One type-II pass on -2 pi i k c,
+ * the factor applied inside the FFT prologue.  c_dev: N complex,
+ * g_dev: M complex, gx_dev: M doubles. */
+nufft_status nufft2_grad_x(nufft_plan_t plan, const void *c_dev, const void *g_dev,
+                           double *gx_dev, void *stream);
+
+/* ---- type III ---------------------------------------------------------- */
+
+/* Type III (Sec. 3.2): f_dev[j] ~ sum_{k<N} c_dev[k] exp(-2 pi i x_j w_k), j < M,
+ * composed as F3 = A o B o F1(t,:) from up to 2K type-I transforms on the
+ * samples w/N.  x_dev: M doubles in [0, 1); w_dev: N doubles in [0, N).
+ * Plans, allocates and synchronises internally (not graph capturable). */
+nufft_status nufft3_exec(int64_t n_pts, const double *x_dev, int64_t n_freq,
+                         const double *w_dev, const void *c_dev, void *f_dev,
+                         double eps, nufft_dtype dtype, void *stream);
+
+/* ---- 2-D type II and its adjoint --------------------------------------- */
+
+/* Planning stage of the 2-D type II (Sec. 4): x pairs with k1 < n1 and
+ * y with k2 < n2; each axis gets rank K(eps/2, gamma_axis).
+ * x_dev, y_dev: M doubles each, any finite reals. */
+nufft_status nufft2d_plan(nufft_plan_t *out, int64_t n1, int64_t n2, int64_t n_pts,
+                          const double *x_dev, const double *y_dev, double eps,
+                          nufft_dtype dtype, uint32_t flags, void *stream);
+
+/* adjoint = 0: f_dev[j] ~ sum_{k1,k2} C_dev[k1*n2+k2] exp(-2 pi i (k1 x_j + k2 y_j))  (Sec. 4)
+ * adjoint = 1: C_dev[k1*n2+k2] ~ sum_j f_dev[j] exp(+2 pi i (k1 x_j + k2 y_j))
+ * C_dev: n1*n2 complex, row-major; f_dev: M complex.  The output is overwritten. */
+nufft_status nufft2d_exec(nufft_plan_t plan, void *C_dev, void *f_dev, int adjoint,
+                          void *stream);
+
+/* ---- batches of independent 1-D type II transforms ---------------------- */
+
+/* Plan B independent type-II transforms of sizes N_b (modes) and M_b
+ * (samples); x_dev_host[b] is a device pointer to M_b doubles.  Each
+ * transform uses the grid L_b = next power of two >= N_b.  Transforms with
+ * L_b <= 4096 run whole in one workgroup; larger ones run as a two-pass
+ * split; all of them go into one persistent launch per exec. */
+nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_modes_host,
+                              const int64_t *n_pts_host, const double *const *x_dev_host,
+                              double eps, nufft_dtype dtype, uint32_t flags, void *stream);
+
+/* c_dev_host[b]: device pointer to N_b complex; f_dev_host[b]: device
+ * pointer to M_b complex.  The pointer arrays are host arrays. */
+nufft_status nufft_batch_exec(nufft_plan_t plan, const void *const *c_dev_host,
+                              void *const *f_dev_host, void *stream);
+
+/* ---- plan queries and lifetime ----------------------------------------- */
+
+/* Any output pointer may be NULL.  For 2-D plans K and gamma describe the
+ * x axis; for batches K is the largest rank and gamma the largest gamma. */
+nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *grid);
+
+/* Copies the plan's sorted sample order to host memory: perm_host[i] is the
+ * sample index at sorted position i (M int32).  1-D plans only. */
+nufft_status nufft_plan_perm(nufft_plan_t plan, int32_t *perm_host);
+
+/* Waits for the plan's work, then frees it.  NULL is accepted. */
+nufft_status nufft_destroy(nufft_plan_t plan);
+
+const char *nufft_status_string(nufft_status status);
+
+/* ---- host-side factor generator (no GPU work) --------------------------- */
+
+/* K(eps, gamma): the smallest K whose Chebyshev truncation tail
+ * sum_{max(p,r)>=K} w_p w_r |a_pr| (w_0 = 1/2) is <= eps (Sec. 2.1.2,
+ * Table 1, Lemma A.1).  gamma in [0, 1/2]; gamma = 0 gives K = 1. */
+nufft_status nufft_choose_rank(double eps, double gamma, int *K);
+
+/* b_host[p*K + r] = a_pr / i^r = 4 J_{(p+r)/2}(-gamma pi/2) J_{(r-p)/2}(-gamma pi/2)
+ * for p = r mod 2, else 0 (Sec. 2.1.2): the real part of the coefficients. */
+nufft_status nufft_bessel_coefficients(double gamma, int K, double *b_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUFFT_MI355X_H */

@@ -1,0 +1,53 @@
+"""torch.autograd.Function around the type-II transform.
+
+Forward: f = F2 c (nufft2_exec).  For a real loss L and g = dL/dRe f + i dL/dIm f
+(torch's gradient convention for complex tensors):
+  * dL/dc = F2^H g                       -- the adjoint kernel (nufft1_exec, sign +1)
+  * dL/dx_j = Re(conj(g_j) (F2 (-2 pi i k c))_j)   -- one more type-II pass
+    with the factor -2 pi i k folded into the scaling (nufft2_grad_x).
+Both follow from differentiating f_j = sum_k c_k exp(-2 pi i x_j k) (Sec. 1, eq. (2)).
+"""
+import torch
+
+from . import binding as B
+
+
+class NufftTypeII(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, c, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(c)
+        return B.nufft2_exec(plan, c.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        (c,) = ctx.saved_tensors
+        g = g.contiguous()
+        plan = ctx.plan
+        gx = gc = None
+        if ctx.needs_input_grad[1]:
+            gc = B.nufft1_exec(plan, g, sign=+1)
+        if ctx.needs_input_grad[0]:
+            gx = B.nufft2_grad_x(plan, c.contiguous(), g)
+        return gx, gc, None
+
+
+class PlanCache:
+    """Re-plans only when the samples change (data pointer or in-place version)."""
+
+    def __init__(self, n_modes, eps, dtype=torch.complex64, flags=0):
+        self.n_modes, self.eps, self.dtype, self.flags = n_modes, eps, dtype, flags
+        self._key = None
+        self._plan = None
+
+    def __call__(self, x):
+        key = (x.data_ptr(), x._version, x.numel())
+        if key != self._key:
+            self._plan = B.nufft2_plan(x.detach(), self.n_modes, self.eps, self.dtype, self.flags)
+            self._key = key
+        return self._plan
+
+
+def nufft2(x, c, plan):
+    """Differentiable f = F2(x) c using a plan built from x."""
+    return NufftTypeII.apply(x, c, plan)

@@ -1,0 +1,233 @@
+"""Thin ctypes binding of ``libnufft_mi355x.so``: one Python function per C
+entry point of ``include/nufft_mi355x.h``, same names, argument marshalling
+only (tensor -> device pointer, torch's current HIP stream -> hipStream_t).
+Every transform runs in the library's HIP kernels; there is no fallback: if
+the library is not built, importing this module raises.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnufft_mi355x.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "nufft_mi355x.h")
+
+NUFFT_C64, NUFFT_C128 = 0, 1
+NUFFT_FLAG_FIX_GAMMA_HALF = 1
+NUFFT_FLAG_PLAIN = 2
+STATUS = {0: "NUFFT_OK", 1: "NUFFT_ERR_INVALID_ARG", 2: "NUFFT_ERR_UNSUPPORTED", 3: "NUFFT_ERR_ALLOC",
+          4: "NUFFT_ERR_NONFINITE", 5: "NUFFT_ERR_HIP"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libnufft_mi355x.so is not built (run paper_1701_04492_amd/build.py "
+                      "or __graft_entry__.build()); there is no CPU fallback")
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_int = ctypes.c_int
+_dbl = ctypes.c_double
+lib = ctypes.CDLL(LIB_PATH)
+_sig = {
+    "nufft2_plan": [ctypes.POINTER(_vp), _i64, _i64, _vp, _dbl, _int, _u32, _vp],
+    "nufft2_exec": [_vp, _vp, _vp, _vp],
+    "nufft1_exec": [_vp, _vp, _vp, _int, _vp],
+    "nufft2_grad_x": [_vp, _vp, _vp, _vp, _vp],
+    "nufft3_exec": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
+    "nufft2d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _dbl, _int, _u32, _vp],
+    "nufft2d_exec": [_vp, _vp, _vp, _int, _vp],
+    "nufft_batch_plan": [ctypes.POINTER(_vp), _int, _vp, _vp, _vp, _dbl, _int, _u32, _vp],
+    "nufft_batch_exec": [_vp, _vp, _vp, _vp],
+    "nufft_plan_info": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl), ctypes.POINTER(_i64)],
+    "nufft_plan_perm": [_vp, _vp],
+    "nufft_destroy": [_vp],
+    "nufft_status_string": [_int],
+    "nufft_choose_rank": [_dbl, _dbl, ctypes.POINTER(_int)],
+    "nufft_bessel_coefficients": [_dbl, _int, _vp],
+}
+for _n, _a in _sig.items():
+    _f = getattr(lib, _n)
+    _f.argtypes = _a
+    _f.restype = _int
+lib.nufft_status_string.restype = ctypes.c_char_p
+
+
+def header_functions():
+    """Names of the functions declared in include/nufft_mi355x.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:nufft_status|const char \*)\s*(\w+)\s*\(", txt, re.M)))
+
+
+class NufftError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = int(status)
+        super().__init__("%s: %s (%s)" % (where, STATUS.get(self.status, "?"),
+                                          lib.nufft_status_string(self.status).decode()))
+
+
+def _check(st, where):
+    if st != 0:
+        raise NufftError(st, where)
+
+
+def _stream(dev):
+    return _vp(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dev_tensor(t, dtype, n, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if n is not None and t.numel() != n:
+        raise ValueError("%s must have %d elements, got %d" % (name, n, t.numel()))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return _vp(t.data_ptr())
+
+
+def _cdtype(dtype):
+    if dtype == torch.complex64:
+        return NUFFT_C64
+    if dtype == torch.complex128:
+        return NUFFT_C128
+    raise ValueError("dtype must be torch.complex64 or torch.complex128")
+
+
+class Plan:
+    """Owner of a nufft_plan_t; destroyed with the object."""
+
+    def __init__(self, handle, kind, dtype, device, **meta):
+        self.handle = handle
+        self.kind = kind
+        self.dtype = dtype
+        self.device = device
+        self.__dict__.update(meta)
+        K = _int()
+        g = _dbl()
+        L = _i64()
+        _check(lib.nufft_plan_info(self.handle, ctypes.byref(K), ctypes.byref(g), ctypes.byref(L)),
+               "nufft_plan_info")
+        self.K, self.gamma, self.grid = K.value, g.value, L.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.nufft_destroy(h)
+            self.handle = None
+
+
+def nufft2_plan(x, n_modes, eps, dtype=torch.complex64, flags=0):
+    """Plan a 1-D type II / type I transform on samples x (float64 CUDA tensor)."""
+    M = x.numel()
+    px = _dev_tensor(x, torch.float64, None, "x")
+    h = _vp()
+    _check(lib.nufft2_plan(ctypes.byref(h), int(n_modes), M, px, float(eps), _cdtype(dtype), int(flags),
+                           _stream(x.device)), "nufft2_plan")
+    return Plan(h, "1d", dtype, x.device, N=int(n_modes), M=M, eps=float(eps), flags=int(flags))
+
+
+def nufft2_exec(plan, c, f=None):
+    if f is None:
+        f = torch.empty(plan.M, dtype=plan.dtype, device=plan.device)
+    _check(lib.nufft2_exec(plan.handle, _dev_tensor(c, plan.dtype, plan.N, "c"),
+                           _dev_tensor(f, plan.dtype, plan.M, "f"), _stream(plan.device)), "nufft2_exec")
+    return f
+
+
+def nufft1_exec(plan, c, sign=-1, f=None):
+    if f is None:
+        f = torch.empty(plan.N, dtype=plan.dtype, device=plan.device)
+    _check(lib.nufft1_exec(plan.handle, _dev_tensor(c, plan.dtype, plan.M, "c"),
+                           _dev_tensor(f, plan.dtype, plan.N, "f"), int(sign), _stream(plan.device)),
+           "nufft1_exec")
+    return f
+
+
+def nufft2_grad_x(plan, c, g, gx=None):
+    if gx is None:
+        gx = torch.empty(plan.M, dtype=torch.float64, device=plan.device)
+    _check(lib.nufft2_grad_x(plan.handle, _dev_tensor(c, plan.dtype, plan.N, "c"),
+                             _dev_tensor(g, plan.dtype, plan.M, "g"),
+                             _dev_tensor(gx, torch.float64, plan.M, "gx"), _stream(plan.device)),
+           "nufft2_grad_x")
+    return gx
+
+
+def nufft3_exec(x, w, c, eps, f=None):
+    M, N = x.numel(), w.numel()
+    if f is None:
+        f = torch.empty(M, dtype=c.dtype, device=c.device)
+    _check(lib.nufft3_exec(M, _dev_tensor(x, torch.float64, M, "x"), N, _dev_tensor(w, torch.float64, N, "w"),
+                           _dev_tensor(c, c.dtype, N, "c"), _dev_tensor(f, c.dtype, M, "f"), float(eps),
+                           _cdtype(c.dtype), _stream(c.device)), "nufft3_exec")
+    return f
+
+
+def nufft2d_plan(x, y, n1, n2, eps, dtype=torch.complex64, flags=0):
+    M = x.numel()
+    h = _vp()
+    _check(lib.nufft2d_plan(ctypes.byref(h), int(n1), int(n2), M, _dev_tensor(x, torch.float64, M, "x"),
+                            _dev_tensor(y, torch.float64, M, "y"), float(eps), _cdtype(dtype), int(flags),
+                            _stream(x.device)), "nufft2d_plan")
+    return Plan(h, "2d", dtype, x.device, n1=int(n1), n2=int(n2), M=M, eps=float(eps), flags=int(flags))
+
+
+def nufft2d_exec(plan, C, f, adjoint=0):
+    _check(lib.nufft2d_exec(plan.handle, _dev_tensor(C, plan.dtype, plan.n1 * plan.n2, "C"),
+                            _dev_tensor(f, plan.dtype, plan.M, "f"), int(adjoint), _stream(plan.device)),
+           "nufft2d_exec")
+
+
+def nufft_batch_plan(n_modes, xs, eps, dtype=torch.complex64, flags=0):
+    B = len(xs)
+    nm = (ctypes.c_int64 * B)(*[int(n) for n in n_modes])
+    npts = (ctypes.c_int64 * B)(*[int(x.numel()) for x in xs])
+    ptrs = (ctypes.c_void_p * B)(*[_dev_tensor(x, torch.float64, None, "x").value for x in xs])
+    h = _vp()
+    _check(lib.nufft_batch_plan(ctypes.byref(h), B, ctypes.cast(nm, _vp), ctypes.cast(npts, _vp),
+                                ctypes.cast(ptrs, _vp), float(eps), _cdtype(dtype), int(flags),
+                                _stream(xs[0].device)), "nufft_batch_plan")
+    return Plan(h, "batch", dtype, xs[0].device, Ns=[int(n) for n in n_modes],
+                Ms=[int(x.numel()) for x in xs], eps=float(eps), flags=int(flags))
+
+
+def nufft_batch_exec(plan, cs, fs):
+    B = len(cs)
+    cp = (ctypes.c_void_p * B)(*[_dev_tensor(c, plan.dtype, n, "c").value for c, n in zip(cs, plan.Ns)])
+    fp = (ctypes.c_void_p * B)(*[_dev_tensor(f, plan.dtype, m, "f").value for f, m in zip(fs, plan.Ms)])
+    _check(lib.nufft_batch_exec(plan.handle, ctypes.cast(cp, _vp), ctypes.cast(fp, _vp),
+                                _stream(plan.device)), "nufft_batch_exec")
+
+
+def nufft_plan_info(plan):
+    return plan.K, plan.gamma, plan.grid
+
+
+def nufft_plan_perm(plan):
+    out = np.empty(plan.M, np.int32)
+    _check(lib.nufft_plan_perm(plan.handle, _vp(out.ctypes.data)), "nufft_plan_perm")
+    return out
+
+
+def nufft_destroy(plan):
+    plan.__del__()
+
+
+def nufft_status_string(status):
+    return lib.nufft_status_string(int(status)).decode()
+
+
+def nufft_choose_rank(eps, gamma):
+    K = _int()
+    _check(lib.nufft_choose_rank(float(eps), float(gamma), ctypes.byref(K)), "nufft_choose_rank")
+    return K.value
+
+
+def nufft_bessel_coefficients(gamma, K):
+    b = np.empty(K * K, np.float64)
+    _check(lib.nufft_bessel_coefficients(float(gamma), int(K), _vp(b.ctypes.data)), "nufft_bessel_coefficients")
+    return b.reshape(K, K)

@@ -1,0 +1,412 @@
+// C ABI of the MI355X low-rank NUFFT: plans, dispatch, error handling.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "factors.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace nufft;
+
+void *nufft_plan_s::alloc(size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    blocks.push_back(p);
+    return p;
+}
+
+nufft_plan_s::~nufft_plan_s()
+{
+    for (void *p : blocks) (void)hipFree(p);
+    for (nufft_plan_s *c : children) delete c;
+}
+
+namespace nufft {
+
+// Grid size and two-pass split: L = smallest power of two >= N (Sec. 2.3,
+// oversampling with N <= L < 2N); L <= 4096 runs in one pass; otherwise
+// L = L1 * L2 with L2 = 2^floor(log2(L)/2) (at most 2048) and L1 = L / L2.
+bool choose_grid(int64_t N, int64_t *L, int *L1, int *L2)
+{
+    int64_t l = 16;
+    while (l < N) l <<= 1;
+    if (l > (int64_t(1) << 23)) return false;
+    *L = l;
+    if (l <= 4096) {
+        *L1 = (int)l;
+        *L2 = 1;
+        return true;
+    }
+    int lg = 0;
+    while ((int64_t(1) << lg) < l) ++lg;
+    int l2 = 1 << (lg / 2);
+    if (l2 > 2048) l2 = 2048;
+    *L2 = l2;
+    *L1 = (int)(l / l2);
+    return *L1 <= 4096;
+}
+
+template <typename R>
+static void fill_factors(Factors<R> &fac, double gamma, int K)
+{
+    std::memset(&fac, 0, sizeof(fac));
+    double mono[NUFFT_KMAX * NUFFT_KMAX];
+    u_monomials(gamma, K, mono);
+    for (int r = 0; r < K; ++r) {
+        const int par = r & 1;
+        int n = 0;
+        for (int m = par; m < K; m += 2) fac.ucoef[r * NUFFT_UCOEF_STRIDE + n++] = (R)mono[r * K + m];
+        fac.nterm[r] = n;
+    }
+    fac.K = K;
+    fac.inv_gamma = gamma > 0 ? (R)(1.0 / gamma) : (R)0;
+}
+
+template <typename R>
+static nufft_status upload_table(Plan *p, const std::vector<double> &d, void **out, hipStream_t s)
+{
+    const size_t n = d.size() / 2;
+    std::vector<R> h(2 * n);
+    for (size_t i = 0; i < 2 * n; ++i) h[i] = (R)d[i];
+    void *dev = p->alloc(h.size() * sizeof(R));
+    if (!dev) return NUFFT_ERR_ALLOC;
+    NUFFT_HIP_CHECK(hipMemcpyAsync(dev, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));   // host staging buffer goes out of scope
+    *out = dev;
+    return NUFFT_OK;
+}
+
+template <typename R>
+nufft_status upload_twiddles(Plan *p, hipStream_t s)
+{
+    std::vector<double> t1(2 * (size_t)p->L1);
+    twiddles(p->L1, p->L1, 1, -1, t1.data());
+    nufft_status st = upload_table<R>(p, t1, &p->tw1, s);
+    if (st) return st;
+    if (p->L2 > 1) {
+        std::vector<double> t2(2 * (size_t)p->L2), lo(2 * 4096), hi(2 * (size_t)(p->L / 4096));
+        twiddles(p->L2, p->L2, 1, -1, t2.data());
+        twiddles(p->L, 4096, 1, -1, lo.data());
+        twiddles(p->L, p->L / 4096, 4096, -1, hi.data());
+        if ((st = upload_table<R>(p, t2, &p->tw2, s))) return st;
+        if ((st = upload_table<R>(p, lo, &p->lo, s))) return st;
+        if ((st = upload_table<R>(p, hi, &p->hi, s))) return st;
+    }
+    return NUFFT_OK;
+}
+
+template nufft_status upload_twiddles<float>(Plan *, hipStream_t);
+template nufft_status upload_twiddles<double>(Plan *, hipStream_t);
+
+// Nearest-grid assignment, gamma, K, factors and the sorted sample order for
+// one 1-D transform (Sec. 2.2, Sec. 2.3 "Planning the transform").
+template <typename R>
+nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
+{
+    const int64_t M = p->M, L = p->L;
+    int log2_L2 = 0;
+    while ((1 << log2_L2) < p->L2) ++log2_L2;
+    p->t = (int32_t *)p->alloc(M * sizeof(int32_t));
+    p->X = p->alloc(M * sizeof(R));
+    p->Xs = p->alloc(M * sizeof(R));
+    p->keys = (uint32_t *)p->alloc(M * sizeof(uint32_t));
+    p->perm = (int32_t *)p->alloc(M * sizeof(int32_t));
+    p->off = (int32_t *)p->alloc((L + 1) * sizeof(int32_t));
+    uint32_t *keys_u = (uint32_t *)p->alloc(M * sizeof(uint32_t));
+    int32_t *iota = (int32_t *)p->alloc(M * sizeof(int32_t));
+    int32_t *hist = (int32_t *)p->alloc((L + 1) * sizeof(int32_t));
+    const int64_t tmp_n = std::max(radix_tmp_elems(M), scan_tmp_elems(L + 1)) + 16;
+    int32_t *tmp = (int32_t *)p->alloc(tmp_n * sizeof(int32_t));
+    unsigned long long *dflags = (unsigned long long *)p->alloc(2 * sizeof(unsigned long long));
+    if (!p->t || !p->X || !p->Xs || !p->keys || !p->perm || !p->off || !keys_u || !iota || !hist || !tmp ||
+        !dflags)
+        return NUFFT_ERR_ALLOC;
+    NUFFT_HIP_CHECK(hipMemsetAsync(hist, 0, (L + 1) * sizeof(int32_t), s));
+    NUFFT_HIP_CHECK(hipMemsetAsync(dflags, 0, 2 * sizeof(unsigned long long), s));
+    NUFFT_HIP_CHECK(launch_assign<R>(x, M, L, (double)p->N / (double)L, p->L1, log2_L2, p->t, (R *)p->X,
+                                     keys_u, hist, dflags, (int *)(dflags + 1), s));
+    NUFFT_HIP_CHECK(exclusive_scan(hist, p->off, L + 1, tmp, s));
+    NUFFT_HIP_CHECK(launch_iota(iota, M, s));
+    int key_bits = 0;
+    while ((int64_t(1) << key_bits) < L) ++key_bits;
+    uint32_t *ks;
+    int32_t *vs;
+    NUFFT_HIP_CHECK(radix_sort_pairs(keys_u, iota, p->keys, p->perm, M, key_bits, tmp, s, &ks, &vs));
+    if (ks != p->keys) {   // odd number of digit passes: result is in the scratch pair
+        NUFFT_HIP_CHECK(hipMemcpyAsync(p->keys, ks, M * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        NUFFT_HIP_CHECK(hipMemcpyAsync(p->perm, vs, M * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    NUFFT_HIP_CHECK(launch_gather_sorted<R>(p->perm, (const R *)p->X, M, (R *)p->Xs, s));
+    unsigned long long hflags[2];
+    NUFFT_HIP_CHECK(hipMemcpyAsync(hflags, dflags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    if ((int)hflags[1] != 0) return NUFFT_ERR_NONFINITE;
+    double gmax;
+    std::memcpy(&gmax, &hflags[0], sizeof(double));
+    p->gamma = (p->flags & NUFFT_FLAG_FIX_GAMMA_HALF) ? (double)p->N / (2.0 * (double)L) : gmax;
+    if (p->gamma > 0.5) p->gamma = 0.5;
+    p->K = choose_rank(p->eps, p->gamma);
+    if (p->K < 0) return NUFFT_ERR_UNSUPPORTED;
+    if (p->dtype == NUFFT_C64) fill_factors(p->facf, p->gamma, p->K);
+    else fill_factors(p->facd, p->gamma, p->K);
+    nufft_status st = upload_twiddles<R>(p, s);
+    if (st) return st;
+    const size_t cs = 2 * sizeof(R);
+    if (p->flags & NUFFT_FLAG_PLAIN) {
+        p->U = p->alloc((size_t)M * p->K * cs);
+        p->W = p->alloc((size_t)p->K * L * cs);
+        if (p->L2 > 1) p->W2 = p->alloc((size_t)p->K * L * cs);
+        if (!p->U || !p->W || (p->L2 > 1 && !p->W2)) return NUFFT_ERR_ALLOC;
+        const Factors<R> &fac = *(const Factors<R> *)p->factors();
+        NUFFT_HIP_CHECK(plain_build_U<R>((const R *)p->X, M, fac, (cx_t<R> *)p->U, s));
+    }
+    if (p->L2 > 1) {
+        p->Y = p->alloc((size_t)p->K * L * cs);
+        if (!p->Y) return NUFFT_ERR_ALLOC;
+    } else {
+        int64_t nparts = (M + 65535) / 65536;
+        if (nparts > 64) nparts = 64;
+        if (nparts > 1) {
+            p->part_cap = nparts * p->N;
+            p->part = p->alloc((size_t)p->part_cap * cs);
+            if (!p->part) return NUFFT_ERR_ALLOC;
+        }
+    }
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    return NUFFT_OK;
+}
+
+template nufft_status build_1d<float>(Plan *, const double *, hipStream_t);
+template nufft_status build_1d<double>(Plan *, const double *, hipStream_t);
+
+template <typename R>
+FusedArgs<R> fused_args(const Plan *p)
+{
+    FusedArgs<R> a;
+    a.N = p->N;
+    a.L = p->L;
+    a.M = p->M;
+    a.L1 = p->L1;
+    a.L2 = p->L2;
+    a.fac = *(const Factors<R> *)p->factors();
+    a.keys = p->keys;
+    a.perm = p->perm;
+    a.Xs = (const R *)p->Xs;
+    a.off = p->off;
+    a.t = p->t;
+    a.X = (const R *)p->X;
+    a.Y = (cx_t<R> *)p->Y;
+    a.tw1 = (const cx_t<R> *)p->tw1;
+    a.tw2 = (const cx_t<R> *)p->tw2;
+    a.hi = (const cx_t<R> *)p->hi;
+    a.lo = (const cx_t<R> *)p->lo;
+    a.part = (cx_t<R> *)p->part;
+    a.part_cap = p->part_cap;
+    return a;
+}
+
+template FusedArgs<float> fused_args<float>(const Plan *);
+template FusedArgs<double> fused_args<double>(const Plan *);
+
+template <typename R>
+static hipError_t exec_type2(const Plan *p, const void *c, void *f, int mode, const void *g, double *gx,
+                             hipStream_t s)
+{
+    using C = cx_t<R>;
+    if (p->flags & NUFFT_FLAG_PLAIN) {
+        PlainArgs<R> a;
+        a.c = (const C *)c;
+        a.N = p->N;
+        a.L = p->L;
+        a.M = p->M;
+        a.L1 = p->L1;
+        a.L2 = p->L2;
+        a.K = p->K;
+        a.mode = mode;
+        a.W = (C *)p->W;
+        a.W2 = (C *)p->W2;
+        a.tw1 = (const C *)p->tw1;
+        a.tw2 = (const C *)p->tw2;
+        a.hi = (const C *)p->hi;
+        a.lo = (const C *)p->lo;
+        a.U = (const C *)p->U;
+        a.t = p->t;
+        a.f = (C *)f;
+        a.g = (const C *)g;
+        a.gx = gx;
+        return plain_exec<R>(a, s);
+    }
+    return fused_type2<R>(fused_args<R>(p), (const C *)c, (C *)f, mode, (const C *)g, gx, s);
+}
+
+}  // namespace nufft
+
+// ============================================================================
+// exported entry points
+// ============================================================================
+
+static nufft_status from_hip(hipError_t e) { return e == hipSuccess ? NUFFT_OK : NUFFT_ERR_HIP; }
+
+static bool eps_ok(double eps, nufft_dtype dt, nufft_status *st)
+{
+    if (!(eps > 0.0 && eps < 1.0)) { *st = NUFFT_ERR_INVALID_ARG; return false; }
+    const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
+    if (eps < floor_eps) { *st = NUFFT_ERR_UNSUPPORTED; return false; }
+    return true;
+}
+
+extern "C" {
+
+nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, const double *x_dev, double eps,
+                         nufft_dtype dtype, uint32_t flags, void *stream)
+{
+    if (!out) return NUFFT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n_modes < 1 || n_pts < 1 || !x_dev) return NUFFT_ERR_INVALID_ARG;
+    if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_PLAIN)) return NUFFT_ERR_INVALID_ARG;
+    if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
+    nufft_status st;
+    if (!eps_ok(eps, dtype, &st)) return st;
+    Plan *p = new (std::nothrow) Plan();
+    if (!p) return NUFFT_ERR_ALLOC;
+    p->kind = PLAN_1D;
+    p->dtype = dtype;
+    p->flags = flags;
+    p->N = n_modes;
+    p->M = n_pts;
+    p->eps = eps;
+    if (!choose_grid(n_modes, &p->L, &p->L1, &p->L2)) {
+        delete p;
+        return NUFFT_ERR_UNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    st = dtype == NUFFT_C64 ? build_1d<float>(p, x_dev, s) : build_1d<double>(p, x_dev, s);
+    if (st != NUFFT_OK) {
+        (void)hipStreamSynchronize(s);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return NUFFT_OK;
+}
+
+nufft_status nufft2_exec(nufft_plan_t plan, const void *c, void *f, void *stream)
+{
+    if (!plan || plan->kind != PLAN_1D || !c || !f) return NUFFT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    return from_hip(plan->dtype == NUFFT_C64 ? exec_type2<float>(plan, c, f, 0, nullptr, nullptr, s)
+                                             : exec_type2<double>(plan, c, f, 0, nullptr, nullptr, s));
+}
+
+nufft_status nufft2_grad_x(nufft_plan_t plan, const void *c, const void *g, double *gx, void *stream)
+{
+    if (!plan || plan->kind != PLAN_1D || !c || !g || !gx) return NUFFT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    return from_hip(plan->dtype == NUFFT_C64 ? exec_type2<float>(plan, c, nullptr, 1, g, gx, s)
+                                             : exec_type2<double>(plan, c, nullptr, 1, g, gx, s));
+}
+
+nufft_status nufft1_exec(nufft_plan_t plan, const void *c, void *f, int sign, void *stream)
+{
+    if (!plan || plan->kind != PLAN_1D || !c || !f || (sign != 1 && sign != -1)) return NUFFT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->dtype == NUFFT_C64)
+        return from_hip(fused_type1<float>(fused_args<float>(plan), (const float2 *)c, (float2 *)f, sign, s));
+    return from_hip(fused_type1<double>(fused_args<double>(plan), (const double2 *)c, (double2 *)f, sign, s));
+}
+
+nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *grid)
+{
+    if (!plan) return NUFFT_ERR_INVALID_ARG;
+    if (K) *K = plan->K;
+    if (gamma) *gamma = plan->gamma;
+    if (grid) *grid = plan->L;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_plan_perm(nufft_plan_t plan, int32_t *perm_host)
+{
+    if (!plan || plan->kind != PLAN_1D || !perm_host) return NUFFT_ERR_INVALID_ARG;
+    if (hipMemcpy(perm_host, plan->perm, plan->M * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return NUFFT_ERR_HIP;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_destroy(nufft_plan_t plan)
+{
+    if (!plan) return NUFFT_OK;
+    (void)hipDeviceSynchronize();
+    delete plan;
+    return NUFFT_OK;
+}
+
+const char *nufft_status_string(nufft_status status)
+{
+    switch (status) {
+    case NUFFT_OK: return "ok";
+    case NUFFT_ERR_INVALID_ARG: return "invalid argument";
+    case NUFFT_ERR_UNSUPPORTED: return "unsupported request";
+    case NUFFT_ERR_ALLOC: return "allocation failed";
+    case NUFFT_ERR_NONFINITE: return "non-finite sample coordinate";
+    case NUFFT_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+nufft_status nufft_choose_rank(double eps, double gamma, int *K)
+{
+    if (!K || !(eps > 0.0 && eps < 1.0) || !(gamma >= 0.0 && gamma <= 0.5)) return NUFFT_ERR_INVALID_ARG;
+    const int k = choose_rank(eps, gamma);
+    if (k < 0) return NUFFT_ERR_UNSUPPORTED;
+    *K = k;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_bessel_coefficients(double gamma, int K, double *b_host)
+{
+    if (!b_host || K < 1 || K > 64 || !(gamma >= 0.0 && gamma <= 0.5)) return NUFFT_ERR_INVALID_ARG;
+    bessel_b(gamma, K, b_host);
+    return NUFFT_OK;
+}
+
+}  // extern "C"
+
+// ---- entry points still to be implemented --------------------------------
+extern "C" {
+
+nufft_status nufft3_exec(int64_t, const double *, int64_t, const double *, const void *, void *, double,
+                         nufft_dtype, void *)
+{
+    return NUFFT_ERR_UNSUPPORTED;
+}
+
+nufft_status nufft2d_plan(nufft_plan_t *out, int64_t, int64_t, int64_t, const double *, const double *, double,
+                          nufft_dtype, uint32_t, void *)
+{
+    if (out) *out = nullptr;
+    return NUFFT_ERR_UNSUPPORTED;
+}
+
+nufft_status nufft2d_exec(nufft_plan_t, void *, void *, int, void *) { return NUFFT_ERR_UNSUPPORTED; }
+
+nufft_status nufft_batch_plan(nufft_plan_t *out, int, const int64_t *, const int64_t *, const double *const *,
+                              double, nufft_dtype, uint32_t, void *)
+{
+    if (out) *out = nullptr;
+    return NUFFT_ERR_UNSUPPORTED;
+}
+
+nufft_status nufft_batch_exec(nufft_plan_t, const void *const *, void *const *, void *)
+{
+    return NUFFT_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+// Workgroup-level FFT building blocks for gfx950.
+//
+// A length-L transform (L a power of two, 16 <= L <= 4096) is held in LDS and
+// computed by L/16 threads with 16 complex values per thread per stage
+// (Stockham auto-sort: radix-16 stages, then one radix-2/4/8 stage if L is
+// not a power of 16).  Several transforms share a workgroup; every thread of
+// the workgroup runs the same stage sequence, so __syncthreads() separates
+// the read and write phases of each stage.
+//
+// LDS layout: element i of a transform lives at lds_pad(i) = i + i/16 (one
+// spare slot per 16 breaks the power-of-two strides of the radix-16 write
+// phase), and consecutive transforms are fft_pitch(L) elements apart (odd,
+// so that the same element of neighbouring transforms falls in different
+// banks).
+//
+// Direction DIR = -1 computes X_n = sum_k x_k exp(-2 pi i n k / L) (the DFT of
+// Sec. 1); DIR = +1 the unnormalised inverse.  Twiddles come from a table
+// tw[m] = exp(DIR 2 pi i m / L), m < L, computed in FP64 on the host.
+#pragma once
+
+#include "common.h"
+
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int fft_pitch(int L) { return L + L / 16 + 1; }
+
+namespace fftk {
+
+template <typename C, int DIR>
+__device__ __forceinline__ C mul_w4(C a)   // a * exp(DIR 2 pi i / 4) = a * (DIR i)
+{
+    return DIR < 0 ? cmake<C>(a.y, -a.x) : cmake<C>(-a.y, a.x);
+}
+
+template <typename C, int DIR>
+__device__ __forceinline__ void dft2(C &a, C &b)
+{
+    C t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <typename C, int DIR>
+__device__ __forceinline__ void dft4(C &a0, C &a1, C &a2, C &a3)
+{
+    C t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    C t2 = cadd(a1, a3), t3 = mul_w4<C, DIR>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+// exp(DIR 2 pi i m / 16) for the radix-8/16 internal twiddles.
+template <typename C, int DIR>
+__device__ __forceinline__ C w16(int m)
+{
+    using R = decltype(C{}.x);
+    const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173, h = (R)0.70710678118654752440;
+    R c, s;
+    switch (m) {
+    case 0: c = 1; s = 0; break;
+    case 1: c = c1; s = s1; break;
+    case 2: c = h; s = h; break;
+    case 3: c = s1; s = c1; break;
+    case 4: c = 0; s = 1; break;
+    case 6: c = -h; s = h; break;
+    default: c = -c1; s = -s1; break;    // m = 9
+    }
+    return cmake<C>(c, DIR * s);
+}
+
+template <typename C, int DIR>
+__device__ __forceinline__ void dft8(C *v)
+{
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<C, DIR>(e0, e1, e2, e3);
+    dft4<C, DIR>(o0, o1, o2, o3);
+    o1 = cmul(o1, w16<C, DIR>(2));
+    o2 = mul_w4<C, DIR>(o2);
+    o3 = cmul(o3, w16<C, DIR>(6));
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+// 16-point DFT as 4 x 4: inner DFT4 over stride-4 groups, twiddle W16^(l k1), outer DFT4.
+template <typename C, int DIR>
+__device__ __forceinline__ void dft16(C *v)
+{
+    C a[4][4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        C a0 = v[l], a1 = v[4 + l], a2 = v[8 + l], a3 = v[12 + l];
+        dft4<C, DIR>(a0, a1, a2, a3);
+        a[l][0] = a0; a[l][1] = a1; a[l][2] = a2; a[l][3] = a3;
+    }
+#pragma unroll
+    for (int l = 1; l < 4; ++l)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) {
+            const int m = l * k1;
+            if (m == 4) a[l][k1] = mul_w4<C, DIR>(a[l][k1]);
+            else a[l][k1] = cmul(a[l][k1], w16<C, DIR>(m));
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C b0 = a[0][k1], b1 = a[1][k1], b2 = a[2][k1], b3 = a[3][k1];
+        dft4<C, DIR>(b0, b1, b2, b3);
+        v[k1] = b0; v[k1 + 4] = b1; v[k1 + 8] = b2; v[k1 + 12] = b3;
+    }
+}
+
+template <int R, typename C, int DIR>
+__device__ __forceinline__ void dft(C *v)
+{
+    if constexpr (R == 2) dft2<C, DIR>(v[0], v[1]);
+    else if constexpr (R == 4) dft4<C, DIR>(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<C, DIR>(v);
+    else dft16<C, DIR>(v);
+}
+
+// One Stockham stage on a transform already in registers: v holds, for each
+// of the 16/R butterflies b = lt + i*(L/16) this thread owns, the R inputs
+// x[b + q*L/R].  Applies the stage twiddles, the radix-R DFT, and writes the
+// outputs to LDS in auto-sorted order.
+template <typename C, int L, int DIR, int NS, int R>
+__device__ __forceinline__ void stage_compute_store(C *buf, const C *tw, int lt, C *v)
+{
+    constexpr int BPT = 16 / R;
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = lt + i * (L / 16);
+        if constexpr (NS > 1) {
+            const int k = b % NS;
+#pragma unroll
+            for (int q = 1; q < R; ++q)
+                v[i * R + q] = cmul(v[i * R + q], tw[q * k * (L / (NS * R))]);
+        }
+        dft<R, C, DIR>(v + i * R);
+    }
+    __syncthreads();   // every thread has read its inputs of this stage
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = lt + i * (L / 16);
+        const int base = (b / NS) * NS * R + (b % NS);
+#pragma unroll
+        for (int q = 0; q < R; ++q) buf[lds_pad(base + q * NS)] = v[i * R + q];
+    }
+    __syncthreads();
+}
+
+template <typename C, int L, int DIR, int NS>
+__device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt)
+{
+    if constexpr (NS < L) {
+        constexpr int R = (L / NS >= 16) ? 16 : (L / NS);
+        constexpr int BPT = 16 / R;
+        C v[16];
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            const int b = lt + i * (L / 16);
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[i * R + q] = buf[lds_pad(b + q * (L / R))];
+        }
+        stage_compute_store<C, L, DIR, NS, R>(buf, tw, lt, v);
+        stages_from<C, L, DIR, NS * R>(buf, tw, lt);
+    }
+}
+
+}  // namespace fftk
+
+// Full transform whose input is already in LDS (natural order, padded).
+// Result: natural order in the same buffer.  Called by all threads of the
+// workgroup; lt in [0, L/16) is this thread's lane within the transform.
+template <typename C, int L, int DIR>
+__device__ __forceinline__ void block_fft_lds(C *buf, const C *tw, int lt)
+{
+    static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "unsupported FFT length");
+    fftk::stages_from<C, L, DIR, 1>(buf, tw, lt);
+}
+
+// Full transform whose input is in registers: v[q] = x[lt + q*L/16], q < 16
+// (exactly the operands of the first radix-16 stage, so that stage skips the
+// LDS round trip).  The caller must have finished every earlier read of buf
+// (a __syncthreads() since the last use).  Result: natural order in buf.
+template <typename C, int L, int DIR>
+__device__ __forceinline__ void block_fft_regs(C *buf, const C *tw, int lt, C *v)
+{
+    static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "unsupported FFT length");
+    // first stage: NS = 1, R = 16, one butterfly per thread, no twiddles
+    fftk::dft<16, C, DIR>(v);
+    const int base = lt * 16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) buf[lds_pad(base + q)] = v[q];
+    __syncthreads();
+    fftk::stages_from<C, L, DIR, 16>(buf, tw, lt);
+}

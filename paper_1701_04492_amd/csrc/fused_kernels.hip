@@ -1,0 +1,634 @@
+// Fused online stage of the low-rank NUFFT (Sec. 2.2-2.3 and Sec. 3.1).
+//
+// Type II, f_j = sum_r u_r(j) X_r[t_j] with X_r = F_L (v_r o c):
+//  * L <= 4096: one kernel.  Each workgroup rebuilds all K spectra in LDS
+//    (scale, FFT) and serves a slice of the samples straight from LDS.
+//  * L = L1 * L2: two kernels around one K-wide exchange through HBM.
+//    Pass A (per group of G columns k1): c is held in registers; for each r
+//    it is scaled by v_r, transformed along k2 and multiplied by the
+//    inter-pass twiddle, giving Y_r[n2][k1].
+//    Pass B (per output tile n2): for each r the row Y_r[n2][:] is
+//    transformed along k1 into X_r[n2 + L2 n1] in LDS; the samples whose
+//    t_j falls in the tile (sorted there by the plan) accumulate
+//    u_r(j) X_r[t_j] in registers and are written once.
+// The factors are evaluated on the fly: v_r(k) = T_r(2k/N - 1) by its
+// three-term recurrence and u_r(X) = i^r exp(-i pi X) P_r(X/gamma) with P_r
+// from its monomial form (Sec. 2.1.2), so no N x K table is read.
+//
+// Type I / adjoint run the same two passes in reverse (Sec. 3.1): the
+// samples of a tile are summed per grid point (the sorted order makes each
+// point's samples one contiguous segment: a deterministic sum, no atomics),
+// transformed along n1, and pass A' transforms along n2, scales by v_r and
+// sums over r in registers.
+#include "fft.h"
+#include "kernels.h"
+
+namespace nufft {
+
+template <typename C, int L, int DIR>
+__device__ __forceinline__ void load_tw_s(C *tw_s, const C *__restrict__ tw_g)
+{
+    for (int m = threadIdx.x; m < L; m += blockDim.x) {
+        C w = tw_g[m];
+        tw_s[m] = DIR < 0 ? w : cconj(w);
+    }
+}
+
+template <typename C, int DIR>
+__device__ __forceinline__ C tw_big(const C *__restrict__ hi, const C *__restrict__ lo, int64_t m)
+{
+    C w = cmul(hi[m >> 12], lo[m & 4095]);
+    return DIR < 0 ? w : cconj(w);
+}
+
+// T_r(z) (v_0 = 1/2 is the halved T_0) by the three-term recurrence.
+template <typename R>
+__device__ __forceinline__ R cheb_v(int r, R z)
+{
+    if (r == 0) return (R)0.5;
+    R a = 1, b = z;
+    for (int q = 1; q < r; ++q) {
+        const R c = 2 * z * b - a;
+        a = b;
+        b = c;
+    }
+    return b;
+}
+
+// c_k, or -2 pi i k c_k for the derivative pass.
+template <typename R>
+__device__ __forceinline__ cx_t<R> load_coef(const cx_t<R> *__restrict__ c, int64_t k, int64_t N, int mode)
+{
+    using C = cx_t<R>;
+    if (k >= N) return cmake<C>(0, 0);
+    C ck = c[k];
+    if (mode == 1) {
+        const R w = (R)(-2.0 * M_PI * (double)k);
+        ck = cmake<C>(-w * ck.y, w * ck.x);
+    }
+    return ck;
+}
+
+template <typename R>
+__device__ __forceinline__ R zcoord(int64_t k, int64_t N)
+{
+    return (R)(2.0 * (double)k / (double)N - 1.0);
+}
+
+// ============================================================================
+// L <= 4096: whole transform per workgroup
+// ============================================================================
+
+#define SMALL_NT 256
+#define SMALL_SLOTS 8
+
+template <typename R, int L>
+__global__ void __launch_bounds__(SMALL_NT)
+k_small_fwd(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, const int32_t *__restrict__ t,
+            const R *__restrict__ X, Factors<R> fac, const cx_t<R> *__restrict__ tw_g,
+            cx_t<R> *__restrict__ f, int mode, const cx_t<R> *__restrict__ gup, double *__restrict__ gx)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L / 16;
+    constexpr int RC = SMALL_NT / TPF;          // transforms computed side by side
+    constexpr int P = fft_pitch(L);
+    __shared__ C buf[RC * P];
+    __shared__ C tw[L];
+    load_tw_s<C, L, -1>(tw, tw_g);
+
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * (SMALL_NT * SMALL_SLOTS);
+    int pos[SMALL_SLOTS];
+    R zz[SMALL_SLOTS];
+    C acc[SMALL_SLOTS];
+#pragma unroll
+    for (int s = 0; s < SMALL_SLOTS; ++s) {
+        const int64_t j = j0 + s * SMALL_NT + tid;
+        pos[s] = 0;
+        zz[s] = 0;
+        acc[s] = cmake<C>(0, 0);
+        if (j < M) {
+            pos[s] = t[j];
+            zz[s] = X[j] * fac.inv_gamma;
+        }
+    }
+    const int g = tid / TPF, lt = tid % TPF;
+    for (int r0 = 0; r0 < fac.K; r0 += RC) {
+        const int r = r0 + g;
+        C v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t k = lt + q * TPF;
+            C w = cmake<C>(0, 0);
+            if (r < fac.K && k < N) w = cscale(load_coef<R>(c, k, N, mode), cheb_v<R>(r, zcoord<R>(k, N)));
+            v[q] = w;
+        }
+        __syncthreads();   // previous gather finished with buf
+        block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
+        const int nr = min(RC, fac.K - r0);
+#pragma unroll
+        for (int s = 0; s < SMALL_SLOTS; ++s) {
+            for (int gg = 0; gg < nr; ++gg) {
+                const int rr = r0 + gg;
+                const C xv = buf[gg * P + lds_pad(pos[s])];
+                acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fac, rr, zz[s])), rr));
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < SMALL_SLOTS; ++s) {
+        const int64_t j = j0 + s * SMALL_NT + tid;
+        if (j < M) {
+            R sn, cs;
+            sincospi_r(X[j], &sn, &cs);
+            const C out = cmul(cmake<C>(cs, -sn), acc[s]);
+            if (mode == 0) f[j] = out;
+            else {
+                const C gj = gup[j];
+                gx[j] = (double)(gj.x * out.x + gj.y * out.y);
+            }
+        }
+    }
+}
+
+// Type I (DIR = -1) / adjoint (DIR = +1) for L <= 4096.  Workgroup b spreads
+// the sorted samples [b*span, (b+1)*span) and writes its N outputs to
+// out + b*N (partial sums, added in order by k_sum_parts when there are
+// several workgroups).
+template <typename R, int L, int DIR>
+__global__ void __launch_bounds__(SMALL_NT)
+k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
+            const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
+            Factors<R> fac, const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ out)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L / 16;
+    constexpr int RC = SMALL_NT / TPF;
+    constexpr int P = fft_pitch(L);
+    constexpr int OPT = (L + SMALL_NT - 1) / SMALL_NT;   // outputs per thread
+    __shared__ C buf[RC * P];
+    __shared__ C tw[L];
+    load_tw_s<C, L, DIR>(tw, tw_g);
+
+    const int tid = threadIdx.x;
+    const int64_t lo = (int64_t)blockIdx.x * span, hi = min(M, lo + span);
+    const int g = tid / TPF, lt = tid % TPF;
+    C oacc[OPT];
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) oacc[m] = cmake<C>(0, 0);
+
+    for (int r0 = 0; r0 < fac.K; r0 += RC) {
+        const int r = r0 + g;
+        C v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int n = lt + q * TPF;
+            C a = cmake<C>(0, 0);
+            if (r < fac.K) {
+                const int64_t b0 = max((int64_t)off[n], lo), b1 = min((int64_t)off[n + 1], hi);
+                for (int64_t i = b0; i < b1; ++i) {
+                    const R Xi = Xs[i];
+                    R sn, cs;
+                    sincospi_r(Xi, &sn, &cs);
+                    const C e = cmake<C>(cs, DIR * sn);          // exp(DIR i pi X)
+                    const C val = cmul(e, c[perm[i]]);
+                    a = cadd(a, cscale(val, upoly(fac, r, Xi * fac.inv_gamma)));
+                }
+                a = crot(a, -DIR * r);                            // i^r (type I) or i^-r (adjoint)
+            }
+            v[q] = a;
+        }
+        __syncthreads();
+        block_fft_regs<C, L, DIR>(buf + g * P, tw, lt, v);
+        const int nr = min(RC, fac.K - r0);
+#pragma unroll
+        for (int m = 0; m < OPT; ++m) {
+            const int k = tid + m * SMALL_NT;
+            if (k < N && k < L) {
+                const R z = zcoord<R>(k, N);
+                for (int gg = 0; gg < nr; ++gg)
+                    oacc[m] = cadd(oacc[m], cscale(buf[gg * P + lds_pad(k)], cheb_v<R>(r0 + gg, z)));
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) {
+        const int k = tid + m * SMALL_NT;
+        if (k < N && k < L) out[(int64_t)blockIdx.x * N + k] = oacc[m];
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_sum_parts(const cx_t<R> *__restrict__ part, int nparts, int64_t N, cx_t<R> *__restrict__ f)
+{
+    using C = cx_t<R>;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    C a = part[k];
+    for (int b = 1; b < nparts; ++b) a = cadd(a, part[(int64_t)b * N + k]);
+    f[k] = a;
+}
+
+// ============================================================================
+// L = L1 * L2: pass A (columns) and pass B (rows + samples)
+// ============================================================================
+
+// Pass A of type II.  Workgroup: G adjacent columns k1 (k = k1 + L1 k2);
+// each column is one length-L2 transform done by L2/16 threads.  The thread's
+// 16 coefficients sit in registers for all K ranks, in the operand order of
+// the first radix-16 stage (k2 = lt + q L2/16).
+template <typename R, int L2, int G>
+__global__ void __launch_bounds__(G * L2 / 16)
+k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int mode,
+        const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
+        cx_t<R> *__restrict__ Y)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L2 / 16;
+    constexpr int NT = G * TPF;
+    constexpr int P = fft_pitch(L2);
+    __shared__ C buf[G * P];
+    __shared__ C tw[L2];
+    load_tw_s<C, L2, -1>(tw, tw_g);
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t k1_0 = (int64_t)blockIdx.x * G;
+    const int64_t L = L1 * L2;
+    C cv[16];
+    R zk[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t k = (k1_0 + g) + L1 * (int64_t)(lt + q * TPF);
+        cv[q] = load_coef<R>(c, k, N, mode);
+        zk[q] = zcoord<R>(k, N);
+    }
+    for (int r = 0; r < K; ++r) {
+        C v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], cheb_v<R>(r, zk[q]));
+        __syncthreads();   // previous epilogue finished reading buf
+        block_fft_regs<C, L2, -1>(buf + g * P, tw, lt, v);
+        C *Yr = Y + (int64_t)r * L + k1_0;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            const int gg = i % G, n2 = i / G;
+            const C w = tw_big<C, -1>(hi, lo, (k1_0 + gg) * (int64_t)n2);
+            Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], w);
+        }
+    }
+}
+
+#define PB_SLOTS 8
+
+// Pass B of type II.  Workgroup: one output tile n2; RC ranks are transformed
+// side by side (one length-L1 transform per L1/16 threads), then every
+// sample of the tile gathers its RC spectrum values from LDS.
+template <typename R, int L1, int RC>
+__global__ void __launch_bounds__(RC * L1 / 16)
+k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
+        const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
+        Factors<R> fac, const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ f, int mode,
+        const cx_t<R> *__restrict__ gup, double *__restrict__ gx)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L1 / 16;
+    constexpr int NT = RC * TPF;
+    constexpr int P = fft_pitch(L1);
+    constexpr int CAP = NT * PB_SLOTS;
+    __shared__ C buf[RC * P];
+    __shared__ C tw[L1];
+    load_tw_s<C, L1, -1>(tw, tw_g);
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t n2 = blockIdx.x;
+    const int64_t L = (int64_t)L1 * L2;
+    const int64_t tile_lo = off[n2 * L1], tile_hi = off[(n2 + 1) * L1];
+    const C *Yrow = Y + n2 * L1;
+
+    for (int64_t c0 = tile_lo; c0 < tile_hi || (c0 == tile_lo && tile_hi == tile_lo && false); c0 += CAP) {
+        int pos[PB_SLOTS];
+        R zz[PB_SLOTS];
+        C acc[PB_SLOTS];
+#pragma unroll
+        for (int s = 0; s < PB_SLOTS; ++s) {
+            const int64_t i = c0 + s * NT + tid;
+            pos[s] = 0;
+            zz[s] = 0;
+            acc[s] = cmake<C>(0, 0);
+            if (i < tile_hi) {
+                pos[s] = (int)(keys[i] & (uint32_t)(L1 - 1));
+                zz[s] = Xs[i] * fac.inv_gamma;
+            }
+        }
+        for (int r0 = 0; r0 < fac.K; r0 += RC) {
+            const int r = r0 + g;
+            C v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                v[q] = (r < fac.K) ? Yrow[(int64_t)r * L + lt + q * TPF] : cmake<C>(0, 0);
+            __syncthreads();
+            block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
+            const int nr = min(RC, fac.K - r0);
+#pragma unroll
+            for (int s = 0; s < PB_SLOTS; ++s) {
+                for (int gg = 0; gg < nr; ++gg) {
+                    const int rr = r0 + gg;
+                    const C xv = buf[gg * P + lds_pad(pos[s])];
+                    acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fac, rr, zz[s])), rr));
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < PB_SLOTS; ++s) {
+            const int64_t i = c0 + s * NT + tid;
+            if (i < tile_hi) {
+                R sn, cs;
+                sincospi_r(Xs[i], &sn, &cs);
+                const C out = cmul(cmake<C>(cs, -sn), acc[s]);
+                const int64_t j = perm[i];
+                if (mode == 0) f[j] = out;
+                else {
+                    const C gj = gup[j];
+                    gx[j] = (double)(gj.x * out.x + gj.y * out.y);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Pass B' of type I / adjoint.  Workgroup: tile n2.  Thread (rank r, lane lt)
+// sums, for its 16 grid points n1 = lt + q L1/16, the contributions
+// u_r(j) c_j (type I) or conj(u_r(j)) c_j (adjoint) of the samples at key
+// n2*L1 + n1, transforms along n1 and multiplies by exp(DIR 2 pi i n2 k1 / L):
+// Z_r[n2][k1].
+template <typename R, int L1, int RC, int DIR>
+__global__ void __launch_bounds__(RC * L1 / 16)
+k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict__ perm,
+            const R *__restrict__ Xs, const int32_t *__restrict__ off, Factors<R> fac,
+            const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
+            cx_t<R> *__restrict__ Z)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L1 / 16;
+    constexpr int P = fft_pitch(L1);
+    __shared__ C buf[RC * P];
+    __shared__ C tw[L1];
+    load_tw_s<C, L1, DIR>(tw, tw_g);
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t n2 = blockIdx.x;
+    const int64_t L = (int64_t)L1 * L2;
+    for (int r0 = 0; r0 < fac.K; r0 += RC) {
+        const int r = r0 + g;
+        C v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t key = n2 * L1 + lt + q * TPF;
+            C a = cmake<C>(0, 0);
+            if (r < fac.K) {
+                const int b0 = off[key], b1 = off[key + 1];
+                for (int i = b0; i < b1; ++i) {
+                    const R Xi = Xs[i];
+                    R sn, cs;
+                    sincospi_r(Xi, &sn, &cs);
+                    const C val = cmul(cmake<C>(cs, DIR * sn), c[perm[i]]);
+                    a = cadd(a, cscale(val, upoly(fac, r, Xi * fac.inv_gamma)));
+                }
+                a = crot(a, -DIR * r);
+            }
+            v[q] = a;
+        }
+        __syncthreads();
+        block_fft_regs<C, L1, DIR>(buf + g * P, tw, lt, v);
+        if (r < fac.K) {
+            C *Zr = Z + (int64_t)r * L + n2 * L1;
+#pragma unroll 4
+            for (int q = 0; q < 16; ++q) {
+                const int k1 = lt + q * TPF;
+                Zr[k1] = cmul(buf[g * P + lds_pad(k1)], tw_big<C, DIR>(hi, lo, n2 * (int64_t)k1));
+            }
+        }
+    }
+}
+
+// Pass A' of type I / adjoint.  Workgroup: G adjacent columns k1.  For each r
+// the columns Z_r[:][k1] are transformed along n2 (-> k2) and accumulated
+// with weight v_r(k1 + L1 k2) in registers; the sum over r is written once.
+template <typename R, int L2, int G, int DIR>
+__global__ void __launch_bounds__(G * L2 / 16)
+k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const cx_t<R> *__restrict__ tw_g,
+            cx_t<R> *__restrict__ out)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L2 / 16;
+    constexpr int NT = G * TPF;
+    constexpr int P = fft_pitch(L2);
+    __shared__ C buf[G * P];
+    __shared__ C tw[L2];
+    load_tw_s<C, L2, DIR>(tw, tw_g);
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t k1_0 = (int64_t)blockIdx.x * G;
+    const int64_t L = L1 * L2;
+    C acc[16];
+    R zk[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * NT;
+        const int64_t k = k1_0 + (i % G) + L1 * (int64_t)(i / G);
+        acc[e] = cmake<C>(0, 0);
+        zk[e] = zcoord<R>(k, N);
+    }
+    for (int r = 0; r < K; ++r) {
+        const C *Zr = Z + (int64_t)r * L + k1_0;
+        __syncthreads();   // previous readers of buf are done
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            const int gg = i % G, n2 = i / G;
+            buf[gg * P + lds_pad(n2)] = Zr[(int64_t)n2 * L1 + gg];
+        }
+        __syncthreads();
+        block_fft_lds<C, L2, DIR>(buf + g * P, tw, lt);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            const int gg = i % G, k2 = i / G;
+            acc[e] = cadd(acc[e], cscale(buf[gg * P + lds_pad(k2)], cheb_v<R>(r, zk[e])));
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * NT;
+        const int64_t k = k1_0 + (i % G) + L1 * (int64_t)(i / G);
+        if (k < N) out[k] = acc[e];
+    }
+}
+
+// ============================================================================
+// dispatch
+// ============================================================================
+
+static inline int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
+
+template <typename R, int L>
+static void run_small_fwd(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int mode,
+                          const cx_t<R> *g, double *gx, hipStream_t s)
+{
+    const int64_t per = SMALL_NT * SMALL_SLOTS;
+    const unsigned nb = (unsigned)((a.M + per - 1) / per);
+    if (nb == 0) return;
+    hipLaunchKernelGGL((k_small_fwd<R, L>), dim3(nb), dim3(SMALL_NT), 0, s, c, a.N, a.M, a.t, a.X, a.fac,
+                       a.tw1, f, mode, g, gx);
+}
+
+template <typename R, int L, int DIR>
+static hipError_t run_small_adj(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, hipStream_t s)
+{
+    const int64_t span_min = 65536;
+    int64_t nparts = (a.M + span_min - 1) / span_min;
+    if (nparts < 1) nparts = 1;
+    if (nparts > 1 && nparts * a.N > a.part_cap) nparts = a.part_cap / a.N;
+    if (nparts < 1) nparts = 1;
+    const int64_t span = (a.M + nparts - 1) / nparts;
+    if (nparts == 1) {
+        hipLaunchKernelGGL((k_small_adj<R, L, DIR>), dim3(1), dim3(SMALL_NT), 0, s, c, a.N, a.M,
+                           (int64_t)(a.M > 0 ? a.M : 1), a.perm, a.Xs, a.off, a.fac, a.tw1, f);
+    } else {
+        hipLaunchKernelGGL((k_small_adj<R, L, DIR>), dim3((unsigned)nparts), dim3(SMALL_NT), 0, s, c, a.N,
+                           a.M, span, a.perm, a.Xs, a.off, a.fac, a.tw1, a.part);
+        hipLaunchKernelGGL(k_sum_parts<R>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s,
+                           (const cx_t<R> *)a.part, (int)nparts, a.N, f);
+    }
+    return hipGetLastError();
+}
+
+#define SMALL_SWITCH(MACRO) \
+    switch (a.L) {          \
+        MACRO(16)           \
+        MACRO(32)           \
+        MACRO(64)           \
+        MACRO(128)          \
+        MACRO(256)          \
+        MACRO(512)          \
+        MACRO(1024)         \
+        MACRO(2048)         \
+        MACRO(4096)         \
+    default: return hipErrorInvalidValue; \
+    }
+
+// Column groups per pass-A workgroup: 8 adjacent columns (64-byte runs in
+// FP32) while the LDS budget allows.
+template <typename R> struct Cfg;
+template <> struct Cfg<float> {
+    static constexpr int G1024 = 8, G2048 = 4;
+};
+template <> struct Cfg<double> {
+    static constexpr int G1024 = 4, G2048 = 2;
+};
+
+template <typename R>
+hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int mode, const cx_t<R> *g,
+                       double *gx, hipStream_t s)
+{
+    if (a.L2 == 1) {
+#define SF(LL) case LL: run_small_fwd<R, LL>(a, c, f, mode, g, gx, s); break;
+        SMALL_SWITCH(SF)
+#undef SF
+        return hipGetLastError();
+    }
+    // pass A
+    switch (a.L2) {
+#define PA(LL, GG)                                                                                       \
+    case LL:                                                                                             \
+        hipLaunchKernelGGL((k_passA<R, LL, GG>), dim3((unsigned)(a.L1 / GG)), dim3(GG * LL / 16), 0, s, c, \
+                           a.N, (int64_t)a.L1, a.fac.K, mode, a.tw2, a.hi, a.lo, a.Y);                   \
+        break;
+        PA(64, 8)
+        PA(128, 8)
+        PA(256, 8)
+        PA(512, 8)
+        PA(1024, Cfg<R>::G1024)
+        PA(2048, Cfg<R>::G2048)
+#undef PA
+    default: return hipErrorInvalidValue;
+    }
+    // pass B
+    switch (a.L1) {
+#define PB(LL, RR)                                                                                       \
+    case LL:                                                                                             \
+        hipLaunchKernelGGL((k_passB<R, LL, RR>), dim3((unsigned)a.L2), dim3(RR * LL / 16), 0, s,          \
+                           (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,   \
+                           a.tw1, f, mode, g, gx);                                                        \
+        break;
+        PB(128, 16)
+        PB(256, 16)
+        PB(512, 8)
+        PB(1024, 4)
+        PB(2048, 2)
+        PB(4096, 1)
+#undef PB
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int DIR>
+static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, hipStream_t s)
+{
+    if (a.L2 == 1) {
+#define SA(LL) case LL: return run_small_adj<R, LL, DIR>(a, c, f, s);
+        SMALL_SWITCH(SA)
+#undef SA
+    }
+    switch (a.L1) {
+#define PBA(LL, RR)                                                                                      \
+    case LL:                                                                                             \
+        hipLaunchKernelGGL((k_passB_adj<R, LL, RR, DIR>), dim3((unsigned)a.L2), dim3(RR * LL / 16), 0, s, \
+                           c, (int64_t)a.L2, a.perm, a.Xs, a.off, a.fac, a.tw1, a.hi, a.lo, a.Y);          \
+        break;
+        PBA(128, 16)
+        PBA(256, 16)
+        PBA(512, 8)
+        PBA(1024, 4)
+        PBA(2048, 2)
+        PBA(4096, 1)
+#undef PBA
+    default: return hipErrorInvalidValue;
+    }
+    switch (a.L2) {
+#define PAA(LL, GG)                                                                                      \
+    case LL:                                                                                             \
+        hipLaunchKernelGGL((k_passA_adj<R, LL, GG, DIR>), dim3((unsigned)(a.L1 / GG)), dim3(GG * LL / 16), \
+                           0, s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, a.tw2, f);           \
+        break;
+        PAA(64, 8)
+        PAA(128, 8)
+        PAA(256, 8)
+        PAA(512, 8)
+        PAA(1024, Cfg<R>::G1024)
+        PAA(2048, Cfg<R>::G2048)
+#undef PAA
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t fused_type1(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int sign, hipStream_t s)
+{
+    return sign < 0 ? fused_type1_dir<R, -1>(a, c, f, s) : fused_type1_dir<R, 1>(a, c, f, s);
+}
+
+template hipError_t fused_type2<float>(const FusedArgs<float> &, const float2 *, float2 *, int, const float2 *,
+                                       double *, hipStream_t);
+template hipError_t fused_type2<double>(const FusedArgs<double> &, const double2 *, double2 *, int,
+                                        const double2 *, double *, hipStream_t);
+template hipError_t fused_type1<float>(const FusedArgs<float> &, const float2 *, float2 *, int, hipStream_t);
+template hipError_t fused_type1<double>(const FusedArgs<double> &, const double2 *, double2 *, int,
+                                        hipStream_t);
+
+}  // namespace nufft

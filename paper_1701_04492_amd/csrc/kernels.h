@@ -1,0 +1,86 @@
+// Internal declarations shared by the kernel translation units and the C ABI.
+#pragma once
+
+#include "common.h"
+
+namespace nufft {
+
+__device__ __forceinline__ void sincospi_r(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sincospi(x, s, c); }
+
+// P_r(z) = sum'_p b_pr T_p(z), evaluated from its monomial form: only powers
+// of the parity of r occur, so P_r(z) = z^(r&1) * Q_r(z^2) with Q_r by Horner.
+template <typename R>
+__device__ __forceinline__ R upoly(const Factors<R> &fac, int r, R z)
+{
+    const R w = z * z;
+    const R *cf = fac.ucoef + r * NUFFT_UCOEF_STRIDE;
+    const int n = fac.nterm[r];
+    R acc = cf[n - 1];
+    for (int m = n - 2; m >= 0; --m) acc = acc * w + cf[m];
+    return (r & 1) ? acc * z : acc;
+}
+
+// ---- plan kernels ----------------------------------------------------------
+template <typename R>
+hipError_t launch_assign(const double *x, int64_t M, int64_t L, double n_over_L, int L1, int log2_L2,
+                         int32_t *t, R *X, uint32_t *key, int32_t *hist, unsigned long long *gbits,
+                         int *bad, hipStream_t s);
+template <typename R>
+hipError_t launch_gather_sorted(const int32_t *perm, const R *X, int64_t n, R *Xs, hipStream_t s);
+hipError_t launch_iota(int32_t *v, int64_t n, hipStream_t s);
+hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s);
+int64_t scan_tmp_elems(int64_t n);
+int64_t radix_tmp_elems(int64_t n);
+hipError_t radix_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_alt, int32_t *vals_alt,
+                            int64_t n, int key_bits, int32_t *tmp, hipStream_t s,
+                            uint32_t **keys_sorted, int32_t **vals_sorted);
+
+// ---- plain (unfused) online stage -------------------------------------------
+template <typename R>
+struct PlainArgs {
+    const cx_t<R> *c;      // N coefficients
+    int64_t N, L, M;
+    int L1, L2;            // L = L1 * L2; L2 == 1 means one-pass FFTs of length L
+    int K, mode;           // mode 0: f = F2 c; mode 1: gx = Re(conj(g) F2(-2 pi i k c))
+    cx_t<R> *W, *W2;       // K x L work buffers
+    const cx_t<R> *tw1, *tw2, *hi, *lo;   // twiddle tables (forward sign)
+    const cx_t<R> *U;      // M x K stored factors
+    const int32_t *t;      // M grid indices
+    cx_t<R> *f;            // M outputs (mode 0)
+    const cx_t<R> *g;      // M upstream gradients (mode 1)
+    double *gx;            // M outputs (mode 1)
+};
+
+template <typename R>
+hipError_t plain_build_U(const R *X, int64_t M, const Factors<R> &fac, cx_t<R> *U, hipStream_t s);
+template <typename R>
+hipError_t plain_exec(const PlainArgs<R> &a, hipStream_t s);
+
+// ---- fused online stage -------------------------------------------------------
+template <typename R>
+struct FusedArgs {
+    int64_t N, L, M;
+    int L1, L2;              // L = L1 * L2 (L2 == 1: the whole transform in one workgroup)
+    Factors<R> fac;
+    const uint32_t *keys;    // M sorted keys: (t mod L2) * L1 + t / L2
+    const int32_t *perm;     // M: sample index at each sorted position
+    const R *Xs;             // M sorted perturbations X = N (x - s/L)
+    const int32_t *off;      // L + 1: first sorted position of each key
+    const int32_t *t;        // M grid indices, sample order
+    const R *X;              // M perturbations, sample order
+    cx_t<R> *Y;              // K x L intermediate of the two-pass split
+    const cx_t<R> *tw1, *tw2, *hi, *lo;
+    cx_t<R> *part;           // scratch for partial sums of the one-workgroup adjoint
+    int64_t part_cap;        // complex elements available in part
+};
+
+// f = F2 c (mode 0), or gx = Re(conj(g) F2(-2 pi i k c)) (mode 1)
+template <typename R>
+hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int mode,
+                       const cx_t<R> *g, double *gx, hipStream_t s);
+// sign -1: f = F2^T c (type I); sign +1: f = F2^H c (adjoint)
+template <typename R>
+hipError_t fused_type1(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int sign, hipStream_t s);
+
+}  // namespace nufft

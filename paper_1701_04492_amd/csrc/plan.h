@@ -1,0 +1,48 @@
+// Plan object behind the opaque nufft_plan_t handle.
+#pragma once
+
+#include <vector>
+
+#include "kernels.h"
+
+enum PlanKind { PLAN_1D = 1, PLAN_2D = 2, PLAN_BATCH = 3 };
+
+struct nufft_plan_s {
+    int kind = 0;
+    nufft_dtype dtype = NUFFT_C64;
+    uint32_t flags = 0;
+    int64_t N = 0, M = 0, L = 0;    // modes, samples, FFT grid
+    int L1 = 0, L2 = 1;             // L = L1 * L2 (L2 == 1: one-pass)
+    double eps = 0, gamma = 0;
+    int K = 0;
+    Factors<float> facf;
+    Factors<double> facd;
+
+    // device buffers (owned)
+    int32_t *t = nullptr;           // M grid indices, sample order
+    void *X = nullptr;              // M perturbations N(x - s/L), sample order
+    void *Xs = nullptr;             // M perturbations, sorted order
+    uint32_t *keys = nullptr;       // M sorted keys (t mod L2) * L1 + t / L2
+    int32_t *perm = nullptr;        // M sample index per sorted position
+    int32_t *off = nullptr;         // L + 1 CSR offsets per key
+    void *U = nullptr, *W = nullptr, *W2 = nullptr;   // plain path
+    void *Y = nullptr;              // K x L two-pass intermediate
+    void *tw1 = nullptr, *tw2 = nullptr, *hi = nullptr, *lo = nullptr;
+    void *part = nullptr;           // partial sums of the one-workgroup adjoint
+    int64_t part_cap = 0;
+
+    std::vector<void *> blocks;
+    std::vector<nufft_plan_s *> children;   // sub-plans (2-D axes, batch members)
+
+    void *alloc(size_t bytes);
+    const void *factors() const { return dtype == NUFFT_C64 ? (const void *)&facf : (const void *)&facd; }
+    ~nufft_plan_s();
+};
+
+namespace nufft {
+using Plan = nufft_plan_s;
+bool choose_grid(int64_t N, int64_t *L, int *L1, int *L2);
+template <typename R> nufft_status build_1d(Plan *p, const double *x, hipStream_t s);
+template <typename R> FusedArgs<R> fused_args(const Plan *p);
+template <typename R> nufft_status upload_twiddles(Plan *p, hipStream_t s);
+}  // namespace nufft

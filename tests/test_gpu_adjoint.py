@@ -1,0 +1,165 @@
+"""GPU parity of the type-I / adjoint kernels (Sec. 3.1) and of the gradient
+passes behind torch.autograd, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nudft as D
+from paper_1701_04492_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1701_04492_amd")
+DEV = torch.device("cuda:0")
+C64, C128 = torch.complex64, torch.complex128
+EPS = {C64: 1e-6, C128: 1e-12}
+
+
+def _t(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def check_type1(x, g, N, dtype, sign, kq=None, label=""):
+    eps = EPS[dtype]
+    _say("type1", label, "N=%d M=%d sign=%d" % (N, x.shape[0], sign), dtype)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, eps, dtype)
+    gt = _t(g, dtype)
+    out = P.nufft1_exec(plan, gt, sign=sign)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    gg = gt.cpu().numpy().astype(np.complex128)
+    if kq is None:
+        ref, got = D.nudft1(x, gg, N, sign=sign), out
+    else:
+        ref, got = D.nudft1(x, gg, N, k=kq, sign=sign), out[kq]
+    err = np.abs(got - ref).max() / np.abs(gg).sum()
+    _say("   K=%d err/||g||_1 = %.3e" % (plan.K, err))
+    assert np.all(np.isfinite(out))
+    assert err <= 4 * eps
+    return plan, out, err
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+@pytest.mark.parametrize("sign", [-1, 1])
+@pytest.mark.parametrize("N,M", [(1, 3), (16, 40), (1000, 3001), (4096, 4096), (3000, 200000)])
+def test_one_pass(dtype, sign, N, M):
+    rng = W.rng_for(30)
+    x = rng.random(M) * 2.0 - 0.5
+    g = W.complex_normal(rng, M)
+    _, _, err = check_type1(x, g, N, dtype, sign, label="one-pass")
+    if dtype == C64 and N >= 64:
+        # regression gate; a handful of terms does not average the factorisation error down
+        assert err < 2e-7
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+@pytest.mark.parametrize("sign", [-1, 1])
+@pytest.mark.parametrize("N,dist", [(8192, "iid"), (16384, "jitter"), (20000, "iid")])
+def test_two_pass(dtype, sign, N, dist):
+    x, g = W.type2_case(31, N, N, dist)
+    _, _, err = check_type1(x, g, N, dtype, sign, label="two-pass " + dist)
+    if dtype == C64:
+        assert err < 2e-7
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_adjoint_dot_product(dtype):
+    """<F2 c, g> = <c, F2^H g> up to the approximation error of both sides."""
+    N = 1 << 14
+    rng = W.rng_for(32)
+    x = rng.random(N)
+    c, g = W.complex_normal(rng, N), W.complex_normal(rng, N)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS[dtype], dtype)
+    f = P.nufft2_exec(plan, _t(c, dtype)).cpu().numpy()
+    a = P.nufft1_exec(plan, _t(g, dtype), sign=+1).cpu().numpy()
+    lhs, rhs = np.vdot(g, f), np.vdot(a, c)
+    assert abs(lhs - rhs) <= 8 * EPS[dtype] * np.abs(c).sum() * np.abs(g).sum()
+
+
+def test_adjoint_deterministic():
+    N = 1 << 16
+    x, g = W.type2_case(33, N)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, 1e-6, C64)
+    gt = _t(g, C64)
+    a1 = P.nufft1_exec(plan, gt, sign=+1).cpu()
+    a2 = P.nufft1_exec(plan, gt, sign=+1).cpu()
+    assert torch.equal(a1, a2)
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_n2p20_sampled(dtype):
+    N = 1 << 20
+    x, g = W.type2_case(2, N)
+    kq = np.sort(np.random.default_rng(5).choice(N, 192, replace=False))
+    kq = np.concatenate([[0, 1, N - 1], kq])
+    check_type1(x, g, N, dtype, +1, kq=kq, label="2^20 adjoint")
+    check_type1(x, g, N, dtype, -1, kq=kq, label="2^20 type I")
+
+
+# ---- gradients --------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_grad_x_pass(dtype):
+    N, M = 4096, 3000
+    rng = W.rng_for(34)
+    x = rng.random(M)
+    c, g = W.complex_normal(rng, N), W.complex_normal(rng, M)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS[dtype], dtype)
+    ct, gt = _t(c, dtype), _t(g, dtype)
+    gx = P.nufft2_grad_x(plan, ct, gt).cpu().numpy()
+    cc, gg = ct.cpu().numpy().astype(np.complex128), gt.cpu().numpy().astype(np.complex128)
+    ref = D.grad_x(x, cc, gg)
+    # |error| <= eps |g_j| 2 pi sum_k k |c_k|  (error bound applied to -2 pi i k c)
+    bound = 4 * EPS[dtype] * np.abs(gg) * 2 * np.pi * (np.arange(N) * np.abs(cc)).sum()
+    _say("grad_x", dtype, "max err/bound %.3e" % (np.abs(gx - ref) / bound).max())
+    assert np.all(np.abs(gx - ref) <= bound)
+
+
+def test_autograd_fp64_against_oracle_and_fd():
+    """Loss ||f - y||^2 at N = 4096 in FP64: both gradients against the oracle's,
+    and the oracle's against central differences of the oracle."""
+    N = 4096
+    rng = W.rng_for(3)
+    x = rng.random(N)
+    c, y = W.complex_normal(rng, N), W.complex_normal(rng, N)
+    xt = _t(x, torch.float64).requires_grad_(True)
+    ct = _t(c, C128).requires_grad_(True)
+    yt = _t(y, C128)
+    plan = P.nufft2_plan(xt.detach(), N, 1e-12, C128)
+    f = P.nufft2(xt, ct, plan)
+    loss = ((f - yt).abs() ** 2).sum()
+    loss.backward()
+    gref = 2.0 * (D.nudft2(x, c) - y)
+    gc_ref = D.nudft1(x, gref, N, sign=+1)
+    gx_ref = D.grad_x(x, c, gref)
+    gc = ct.grad.cpu().numpy()
+    gx = xt.grad.cpu().numpy()
+    assert np.abs(gc - gc_ref).max() <= 4e-12 * np.abs(gref).sum() + 1e-9
+    scale = np.abs(gref) * 2 * np.pi * (np.arange(N) * np.abs(c)).sum()
+    assert np.all(np.abs(gx - gx_ref) <= 4e-12 * scale + 1e-8)
+    # the oracle's gradient against central differences of the oracle itself
+    h = 1e-6 / N
+    for j in np.random.default_rng(3).choice(N, 6, replace=False):
+        xp, xm = x.copy(), x.copy()
+        xp[j] += h
+        xm[j] -= h
+        fd = (np.sum(np.abs(D.nudft2(xp, c) - y) ** 2) - np.sum(np.abs(D.nudft2(xm, c) - y) ** 2)) / (xp[j] - xm[j])
+        assert abs(fd - gx_ref[j]) <= 1e-6 * (abs(gx_ref[j]) + np.abs(gref[j]) * N)
+
+
+def test_gradcheck_tiny():
+    """torch.autograd.gradcheck in FP64 on a tiny transform (eps 1e-14)."""
+    N, M = 24, 20
+    rng = W.rng_for(35)
+    x = _t(rng.random(M), torch.float64).requires_grad_(True)
+    c = _t(W.complex_normal(rng, N), C128).requires_grad_(True)
+    plan = P.nufft2_plan(x.detach(), N, 1e-14, C128)
+    assert torch.autograd.gradcheck(lambda cc: P.nufft2(x.detach(), cc, plan), (c,), eps=1e-6, atol=1e-7)
+    # the plan encodes x, so the x-check re-plans at every evaluation
+    assert torch.autograd.gradcheck(
+        lambda xx: P.nufft2(xx, c.detach(), P.nufft2_plan(xx.detach(), N, 1e-14, C128)), (x,),
+        eps=1e-9, atol=1e-5, rtol=1e-4)
