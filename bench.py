@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the low-rank NUFFT hot path on one MI355X; prints one JSON line.
+
+Step (the timed unit): one forward + backward pass of the 1-D type-II
+transform through torch.autograd -- f = F2(x) c, loss = ||f - y||^2, then
+dL/dc (adjoint kernels) and dL/dx (derivative pass) -- at N = M = 2^22,
+complex64, eps = 1e-6, samples iid uniform on [0, 1) (synthetic, seeded).
+value = nonuniform points per second through that step (M / step time).
+
+Alongside: per-kernel durations from HIP events recorded by the library on
+the launch stream (the roofline of the dominant kernel against 8 TB/s, with
+algorithmic bytes = compulsory I/O + one K-wide exchange), the forward
+transform alone at N = 2^20 on the fused FP32 path and on the plain FP64
+path at the same accuracy (and at eps = 1e-12), and the FP64 direct-sum
+oracle timed on the host cores over a bounded sample of rows.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _fail_multi(n):
+    print("bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus %d)" % n,
+          file=sys.stderr)
+    sys.exit(2)
+
+
+def kernel_bytes(name, K, N, M, L, cs):
+    """Algorithmic bytes moved by one launch of a fused kernel: compulsory I/O plus the
+    K-wide intermediate written by the first pass and read by the second."""
+    inter = K * L * cs
+    plan_pts = M * (4 + 4 + 4)           # sorted key, perturbation X (f32), sample index
+    table = {
+        "fwd_passA": N * cs + inter,
+        "fwd_passB": inter + plan_pts + M * cs,
+        "gradx_passA": N * cs + inter,
+        "gradx_passB": inter + plan_pts + M * cs + M * 8,       # reads g, writes gx (f64)
+        "adj_passB": M * cs + M * (4 + 4) + (L + 1) * 4 + inter,  # g, X, perm, offsets -> Z
+        "adj_passA": inter + N * cs,
+        "type1_passB": M * cs + M * (4 + 4) + (L + 1) * 4 + inter,
+        "type1_passA": inter + N * cs,
+    }
+    return table.get(name)
+
+
+def time_loop(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1701_04492_amd", "csrc", "fused_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha256_16") != h:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(x, c, N, seconds):
+    """The FP64 direct-sum oracle on a bounded row sample of the same workload."""
+    import numpy as np
+    from oracle import nudft as D
+    cores = D.max_threads()
+    rows = 8
+    t0 = time.perf_counter()
+    D.nudft2(x[:rows], c)
+    dt = time.perf_counter() - t0
+    rows = int(min(4096, max(8, rows * seconds / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    D.nudft2(x[:rows], c)
+    dt = time.perf_counter() - t0
+    # the step needs three N-term sums per point: f_j, (F2^H g)_k and the x-derivative
+    return {
+        "value": rows / dt / 3.0,
+        "unit": "nonuniform pts/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "%d rows of the N=M=2^22 workload, each a direct FP64 compensated sum of 2^22 "
+                  "terms (%.1f s); the fwd+bwd step costs 3 such sums per point" % (rows, dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        _fail_multi(max(args.gpus, int(os.environ.get("WORLD_SIZE", "1"))))
+
+    import numpy as np
+    import torch
+
+    import paper_1701_04492_amd as P
+    from paper_1701_04492_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    N = M = 1 << 22
+    eps = 1e-6
+    rng = W.rng_for(3)
+    c_np = W.complex_normal(rng, N)
+    x_np = W.iid_samples(rng, M)
+    y_np = W.complex_normal(rng, M)
+    x = torch.from_numpy(x_np).to(dev)
+    c = torch.from_numpy(c_np).to(torch.complex64).to(dev)
+    y = torch.from_numpy(y_np).to(torch.complex64).to(dev)
+    t0 = time.perf_counter()
+    plan = P.nufft2_plan(x, N, eps, torch.complex64)
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - t0)
+    xg = x.clone().requires_grad_(True)
+    cg = c.clone().requires_grad_(True)
+
+    def step():
+        xg.grad = None
+        cg.grad = None
+        f = P.nufft2(xg, cg, plan)
+        loss = torch.view_as_real(f - y).pow(2).sum()
+        loss.backward()
+
+    ms = time_loop(step, args.steps, args.warmup, torch)
+    assert xg.grad is not None and cg.grad is not None
+    value = M / (ms * 1e-3)
+
+    # per-kernel durations: same step, events around every library kernel
+    P.nufft_plan_profile(plan, 1, reserve=8 * (args.steps + 1))
+    step()
+    torch.cuda.synchronize()
+    P.nufft_plan_profile(plan, 1)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = P.nufft_plan_profile_read(plan)
+    P.nufft_plan_profile(plan, 0)
+    kernels = {}
+    for name, (calls, tot) in prof.items():
+        avg = tot / calls
+        by = kernel_bytes(name, plan.K, N, M, plan.grid, 8)
+        kernels[name] = {"calls": calls, "avg_us": round(avg * 1e3, 2),
+                         "alg_bytes": by, "GBs": None if by is None else round(by / (avg * 1e-3) / 1e9, 1)}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["calls"])
+    dk = kernels[dom]
+    lib_us = sum(v["avg_us"] * v["calls"] for v in kernels.values()) / args.steps
+    lib_bytes = sum(v["alg_bytes"] * v["calls"] for v in kernels.values() if v["alg_bytes"]) / args.steps
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dk["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic_record(dom),
+                "alg_bytes_per_launch": dk["alg_bytes"], "avg_us": dk["avg_us"],
+                "all_library_kernels": {"us_per_step": round(lib_us, 2),
+                                        "GBs": round(lib_bytes / (lib_us * 1e-6) / 1e9, 1),
+                                        "frac": round(lib_bytes / (lib_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+                "kernels": kernels}
+
+    out = {
+        "metric": "NUFFT-II nonuniform pts/s at eps=1e-6 FP32 vs plain FP64; fwd+bwd %HBM roofline",
+        "value": value,
+        "unit": "nonuniform pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (fp32 arithmetic, fp64 samples and factors)",
+        "data": "synthetic (seeded numpy PCG64: c, y complex N(0,1), x iid U[0,1))",
+        "config": {"workload": "1-D NUFFT-II forward+backward via autograd (type II, adjoint for dL/dc, "
+                               "derivative pass for dL/dx), N=M=2^22, complex64, eps=1e-6, iid x, "
+                               "loss ||f-y||^2",
+                   "N": N, "M": M, "eps": eps, "K": plan.K, "gamma": plan.gamma, "grid": plan.grid,
+                   "plan_ms": round(plan_ms, 1)},
+        "roofline": roofline,
+    }
+
+    if not args.no_secondary:
+        # forward transform alone at N = 2^20: fused FP32 vs plain FP64 at the same eps, and FP64 at 1e-12
+        N2 = 1 << 20
+        r2 = W.rng_for(2)
+        c2 = W.complex_normal(r2, N2)
+        x2 = torch.from_numpy(W.iid_samples(r2, N2)).to(dev)
+        sec = {}
+        for label, dt, e, fl in (("fused_fp32_eps1e-6", torch.complex64, 1e-6, 0),
+                                 ("plain_fp64_eps1e-6", torch.complex128, 1e-6, P.NUFFT_FLAG_PLAIN),
+                                 ("fused_fp64_eps1e-12", torch.complex128, 1e-12, 0),
+                                 ("plain_fp64_eps1e-12", torch.complex128, 1e-12, P.NUFFT_FLAG_PLAIN)):
+            pl = P.nufft2_plan(x2, N2, e, dt, fl)
+            ct = torch.from_numpy(c2).to(dt).to(dev)
+            ft = torch.empty(N2, dtype=dt, device=dev)
+            t = time_loop(lambda: P.nufft2_exec(pl, ct, ft), 20, 3, torch)
+            sec[label] = {"K": pl.K, "us": round(t * 1e3, 2), "pts_per_s": N2 / (t * 1e-3)}
+            del pl
+        sec["speedup_fused_fp32_vs_plain_fp64_same_eps"] = round(
+            sec["plain_fp64_eps1e-6"]["us"] / sec["fused_fp32_eps1e-6"]["us"], 2)
+        out["forward_2p20"] = sec
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x_np, c_np, N, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -59,9 +59,9 @@ typedef enum {
 } nufft_dtype;
 
 enum {
-    /* Take gamma = N/(2L) (the largest possible) instead of reading
-     * max|N(x_j - s_j/L)| back from the device: the plan then never
-     * synchronises, at the price of K for gamma = 1/2 (Sec. 2.2). */
+    /* Take gamma = N/(2L) (the largest possible) instead of the measured
+     * max|N(x_j - s_j/L)|: K then depends only on N, L and eps (Sec. 2.2),
+     * e.g. for plans rebuilt as samples move during optimisation. */
     NUFFT_FLAG_FIX_GAMMA_HALF = 1u,
     /* Run the plain unfused online stage: scale kernel, stand-alone FFT
      * passes over a K x L buffer, a stored U table (Sec. 2.3, "Planning the
@@ -79,9 +79,10 @@ enum {
  *   n_pts    M >= 1, number of samples.
  *   x_dev    M doubles, any finite reals (periodic in 1); read during the call.
  *   eps      working accuracy, 0 < eps < 1, above the precision floor.
- * The FFT grid L is the smallest power of two >= N (oversampling with
- * N <= L < 2N, Sec. 2.3); N up to 2^24.  Synchronises `stream` once to read
- * gamma back unless NUFFT_FLAG_FIX_GAMMA_HALF is set. */
+ * The FFT grid L is the smallest power of two >= 16 and >= N (oversampling
+ * with N <= L < 2N, Sec. 2.3); N up to 2^23 (NUFFT_ERR_UNSUPPORTED beyond),
+ * M up to 2^30.  Synchronises `stream` once, to read gamma and the
+ * non-finite flag back (NUFFT_ERR_NONFINITE). */
 nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts,
                          const double *x_dev, double eps, nufft_dtype dtype,
                          uint32_t flags, void *stream);
@@ -162,6 +163,23 @@ nufft_status nufft_plan_perm(nufft_plan_t plan, int32_t *perm_host);
 nufft_status nufft_destroy(nufft_plan_t plan);
 
 const char *nufft_status_string(nufft_status status);
+
+/* ---- per-kernel timing (profiling aid) ---------------------------------- */
+
+/* enable != 0: from now on every exec call on this plan records a pair of
+ * HIP events on its stream around each kernel it launches (kernels of one
+ * exec are stream ordered, so a pair brackets exactly one kernel).  Any
+ * call resets the record; `reserve` pre-creates that many event pairs so
+ * that timed loops do not create events.  Profiled exec calls must not be
+ * captured into a graph. */
+nufft_status nufft_plan_profile(nufft_plan_t plan, int enable, int reserve);
+
+/* index-th distinct kernel name (in order of first launch) recorded since the
+ * last reset: its name (copied, NUL-terminated, into name[name_len]), the
+ * number of launches and their summed durations in ms.  Waits for the
+ * recorded events.  NUFFT_ERR_INVALID_ARG past the last name. */
+nufft_status nufft_plan_profile_read(nufft_plan_t plan, int index, char *name, int name_len, int *calls,
+                                     double *total_ms);
 
 /* ---- host-side factor generator (no GPU work) --------------------------- */
 

@@ -45,6 +45,8 @@ _sig = {
     "nufft_plan_perm": [_vp, _vp],
     "nufft_destroy": [_vp],
     "nufft_status_string": [_int],
+    "nufft_plan_profile": [_vp, _int, _int],
+    "nufft_plan_profile_read": [_vp, _int, ctypes.c_char_p, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl)],
     "nufft_choose_rank": [_dbl, _dbl, ctypes.POINTER(_int)],
     "nufft_bessel_coefficients": [_dbl, _int, _vp],
 }
@@ -215,6 +217,27 @@ def nufft_plan_perm(plan):
 
 def nufft_destroy(plan):
     plan.__del__()
+
+
+def nufft_plan_profile(plan, enable=1, reserve=0):
+    _check(lib.nufft_plan_profile(plan.handle, int(enable), int(reserve)), "nufft_plan_profile")
+
+
+def nufft_plan_profile_read(plan):
+    """{kernel name: (launches, total ms)} recorded since the last nufft_plan_profile call."""
+    out = {}
+    i = 0
+    buf = ctypes.create_string_buffer(64)
+    while True:
+        calls = _int()
+        ms = _dbl()
+        st = lib.nufft_plan_profile_read(plan.handle, i, buf, 64, ctypes.byref(calls), ctypes.byref(ms))
+        if st == 1:
+            break
+        _check(st, "nufft_plan_profile_read")
+        out[buf.value.decode()] = (calls.value, ms.value)
+        i += 1
+    return out
 
 
 def nufft_status_string(status):

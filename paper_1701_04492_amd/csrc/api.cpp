@@ -28,6 +28,34 @@ nufft_plan_s::~nufft_plan_s()
     for (nufft_plan_s *c : children) delete c;
 }
 
+Profiler::~Profiler()
+{
+    for (Rec &r : pool) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+}
+
+void prof_begin(Profiler *p, const char *name, hipStream_t s)
+{
+    if (!p || !p->on) return;
+    if (p->used == p->pool.size()) {
+        Profiler::Rec r;
+        if (hipEventCreate(&r.a) != hipSuccess) return;
+        if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return; }
+        p->pool.push_back(r);
+    }
+    p->pool[p->used].name = name;
+    (void)hipEventRecord(p->pool[p->used].a, s);
+}
+
+void prof_end(Profiler *p, hipStream_t s)
+{
+    if (!p || !p->on || p->used == p->pool.size()) return;
+    (void)hipEventRecord(p->pool[p->used].b, s);
+    ++p->used;
+}
+
 namespace nufft {
 
 // Grid size and two-pass split: L = smallest power of two >= N (Sec. 2.3,
@@ -209,6 +237,7 @@ FusedArgs<R> fused_args(const Plan *p)
     a.lo = (const cx_t<R> *)p->lo;
     a.part = (cx_t<R> *)p->part;
     a.part_cap = p->part_cap;
+    a.prof = const_cast<Profiler *>(&p->prof);
     return a;
 }
 
@@ -241,6 +270,7 @@ static hipError_t exec_type2(const Plan *p, const void *c, void *f, int mode, co
         a.f = (C *)f;
         a.g = (const C *)g;
         a.gx = gx;
+        a.prof = const_cast<Profiler *>(&p->prof);
         return plain_exec<R>(a, s);
     }
     return fused_type2<R>(fused_args<R>(p), (const C *)c, (C *)f, mode, (const C *)g, gx, s);
@@ -345,6 +375,52 @@ nufft_status nufft_destroy(nufft_plan_t plan)
     if (!plan) return NUFFT_OK;
     (void)hipDeviceSynchronize();
     delete plan;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_plan_profile(nufft_plan_t plan, int enable, int reserve)
+{
+    if (!plan || reserve < 0) return NUFFT_ERR_INVALID_ARG;
+    plan->prof.on = enable != 0;
+    plan->prof.used = 0;
+    while ((int)plan->prof.pool.size() < reserve) {
+        Profiler::Rec r;
+        if (hipEventCreate(&r.a) != hipSuccess) return NUFFT_ERR_HIP;
+        if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return NUFFT_ERR_HIP; }
+        r.name = "";
+        plan->prof.pool.push_back(r);
+    }
+    return NUFFT_OK;
+}
+
+nufft_status nufft_plan_profile_read(nufft_plan_t plan, int index, char *name, int name_len, int *calls,
+                                     double *total_ms)
+{
+    if (!plan || index < 0 || !name || name_len < 1 || !calls || !total_ms) return NUFFT_ERR_INVALID_ARG;
+    Profiler &pr = plan->prof;
+    // distinct names in order of first appearance
+    std::vector<const char *> names;
+    for (size_t i = 0; i < pr.used; ++i) {
+        bool seen = false;
+        for (const char *n : names) seen = seen || std::strcmp(n, pr.pool[i].name) == 0;
+        if (!seen) names.push_back(pr.pool[i].name);
+    }
+    if (index >= (int)names.size()) return NUFFT_ERR_INVALID_ARG;
+    const char *want = names[index];
+    int cnt = 0;
+    double tot = 0.0;
+    for (size_t i = 0; i < pr.used; ++i) {
+        if (std::strcmp(pr.pool[i].name, want) != 0) continue;
+        if (hipEventSynchronize(pr.pool[i].b) != hipSuccess) return NUFFT_ERR_HIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pr.pool[i].a, pr.pool[i].b) != hipSuccess) return NUFFT_ERR_HIP;
+        tot += ms;
+        ++cnt;
+    }
+    std::strncpy(name, want, (size_t)name_len - 1);
+    name[name_len - 1] = 0;
+    *calls = cnt;
+    *total_ms = tot;
     return NUFFT_OK;
 }
 

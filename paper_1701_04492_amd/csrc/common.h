@@ -55,6 +55,12 @@ struct Factors {
     R inv_gamma;             // 1/gamma, or 0 when gamma == 0
 };
 
+// Optional per-kernel timing: when enabled on a plan, a pair of HIP events is
+// recorded on the launch stream around every kernel of an exec call.
+struct Profiler;
+void prof_begin(Profiler *p, const char *name, hipStream_t s);
+void prof_end(Profiler *p, hipStream_t s);
+
 #define NUFFT_HIP_CHECK(expr)                                   \
     do {                                                        \
         hipError_t _e = (expr);                                 \

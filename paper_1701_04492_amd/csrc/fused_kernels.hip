@@ -481,8 +481,10 @@ static void run_small_fwd(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, i
     const int64_t per = SMALL_NT * SMALL_SLOTS;
     const unsigned nb = (unsigned)((a.M + per - 1) / per);
     if (nb == 0) return;
+    prof_begin(a.prof, mode ? "gradx_small" : "fwd_small", s);
     hipLaunchKernelGGL((k_small_fwd<R, L>), dim3(nb), dim3(SMALL_NT), 0, s, c, a.N, a.M, a.t, a.X, a.fac,
                        a.tw1, f, mode, g, gx);
+    prof_end(a.prof, s);
 }
 
 template <typename R, int L, int DIR>
@@ -494,14 +496,21 @@ static hipError_t run_small_adj(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R>
     if (nparts > 1 && nparts * a.N > a.part_cap) nparts = a.part_cap / a.N;
     if (nparts < 1) nparts = 1;
     const int64_t span = (a.M + nparts - 1) / nparts;
+    const char *nm = DIR > 0 ? "adj_small" : "type1_small";
     if (nparts == 1) {
+        prof_begin(a.prof, nm, s);
         hipLaunchKernelGGL((k_small_adj<R, L, DIR>), dim3(1), dim3(SMALL_NT), 0, s, c, a.N, a.M,
                            (int64_t)(a.M > 0 ? a.M : 1), a.perm, a.Xs, a.off, a.fac, a.tw1, f);
+        prof_end(a.prof, s);
     } else {
+        prof_begin(a.prof, nm, s);
         hipLaunchKernelGGL((k_small_adj<R, L, DIR>), dim3((unsigned)nparts), dim3(SMALL_NT), 0, s, c, a.N,
                            a.M, span, a.perm, a.Xs, a.off, a.fac, a.tw1, a.part);
+        prof_end(a.prof, s);
+        prof_begin(a.prof, "sum_parts", s);
         hipLaunchKernelGGL(k_sum_parts<R>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s,
                            (const cx_t<R> *)a.part, (int)nparts, a.N, f);
+        prof_end(a.prof, s);
     }
     return hipGetLastError();
 }
@@ -541,6 +550,7 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
         return hipGetLastError();
     }
     // pass A
+    prof_begin(a.prof, mode ? "gradx_passA" : "fwd_passA", s);
     switch (a.L2) {
 #define PA(LL, GG)                                                                                       \
     case LL:                                                                                             \
@@ -556,7 +566,9 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
 #undef PA
     default: return hipErrorInvalidValue;
     }
+    prof_end(a.prof, s);
     // pass B
+    prof_begin(a.prof, mode ? "gradx_passB" : "fwd_passB", s);
     switch (a.L1) {
 #define PB(LL, RR)                                                                                       \
     case LL:                                                                                             \
@@ -573,6 +585,7 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
 #undef PB
     default: return hipErrorInvalidValue;
     }
+    prof_end(a.prof, s);
     return hipGetLastError();
 }
 
@@ -584,6 +597,7 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         SMALL_SWITCH(SA)
 #undef SA
     }
+    prof_begin(a.prof, DIR > 0 ? "adj_passB" : "type1_passB", s);
     switch (a.L1) {
 #define PBA(LL, RR)                                                                                      \
     case LL:                                                                                             \
@@ -599,6 +613,8 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
 #undef PBA
     default: return hipErrorInvalidValue;
     }
+    prof_end(a.prof, s);
+    prof_begin(a.prof, DIR > 0 ? "adj_passA" : "type1_passA", s);
     switch (a.L2) {
 #define PAA(LL, GG)                                                                                      \
     case LL:                                                                                             \
@@ -614,6 +630,7 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
 #undef PAA
     default: return hipErrorInvalidValue;
     }
+    prof_end(a.prof, s);
     return hipGetLastError();
 }
 

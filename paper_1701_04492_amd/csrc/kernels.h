@@ -50,6 +50,7 @@ struct PlainArgs {
     cx_t<R> *f;            // M outputs (mode 0)
     const cx_t<R> *g;      // M upstream gradients (mode 1)
     double *gx;            // M outputs (mode 1)
+    Profiler *prof;
 };
 
 template <typename R>
@@ -73,6 +74,7 @@ struct FusedArgs {
     const cx_t<R> *tw1, *tw2, *hi, *lo;
     cx_t<R> *part;           // scratch for partial sums of the one-workgroup adjoint
     int64_t part_cap;        // complex elements available in part
+    Profiler *prof;
 };
 
 // f = F2 c (mode 0), or gx = Re(conj(g) F2(-2 pi i k c)) (mode 1)

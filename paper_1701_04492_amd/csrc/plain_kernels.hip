@@ -244,22 +244,33 @@ hipError_t plain_exec(const PlainArgs<R> &a, hipStream_t s)
 {
     using C = cx_t<R>;
     const int64_t L = a.L;
+    prof_begin(a.prof, "plain_scale", s);
     hipLaunchKernelGGL(k_scale<R>, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, a.c, a.N, L, a.K,
                        a.mode, a.W);
+    prof_end(a.prof, s);
     bool ok;
     const C *spec;
     if (a.L2 == 1) {   // one-pass FFT of each row, in place
+        prof_begin(a.prof, "plain_fft", s);
         ok = dispatch_rows<R, -1, 0>((int)L, a.W, a.W, 1, a.K, a.tw1, s);
+        prof_end(a.prof, s);
         spec = a.W;
     } else {
+        prof_begin(a.prof, "plain_fft_cols", s);
         ok = dispatch_cols<R, -1>(a.L2, a.W, a.L1, a.K, a.tw2, a.hi, a.lo, s);
+        prof_end(a.prof, s);
+        prof_begin(a.prof, "plain_fft_rows", s);
         ok = ok && dispatch_rows<R, -1, 1>(a.L1, a.W, a.W2, a.L2, a.K, a.tw1, s);
+        prof_end(a.prof, s);
         spec = a.W2;
     }
     if (!ok) return hipErrorInvalidValue;
-    if (a.M > 0)
+    if (a.M > 0) {
+        prof_begin(a.prof, "plain_gather", s);
         hipLaunchKernelGGL(k_gather<R>, dim3((unsigned)((a.M + 255) / 256)), dim3(256), 0, s, a.U, spec,
                            a.t, a.M, a.K, L, a.f, a.mode, a.g, a.gx);
+        prof_end(a.prof, s);
+    }
     return hipGetLastError();
 }
 

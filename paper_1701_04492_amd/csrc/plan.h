@@ -7,6 +7,17 @@
 
 enum PlanKind { PLAN_1D = 1, PLAN_2D = 2, PLAN_BATCH = 3 };
 
+struct Profiler {
+    struct Rec {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    bool on = false;
+    std::vector<Rec> pool;   // event pairs, reused across enable/reset
+    size_t used = 0;
+    ~Profiler();
+};
+
 struct nufft_plan_s {
     int kind = 0;
     nufft_dtype dtype = NUFFT_C64;
@@ -30,6 +41,8 @@ struct nufft_plan_s {
     void *tw1 = nullptr, *tw2 = nullptr, *hi = nullptr, *lo = nullptr;
     void *part = nullptr;           // partial sums of the one-workgroup adjoint
     int64_t part_cap = 0;
+
+    Profiler prof;
 
     std::vector<void *> blocks;
     std::vector<nufft_plan_s *> children;   // sub-plans (2-D axes, batch members)

@@ -183,3 +183,21 @@ def test_n2p22_fp32_sampled():
     x, c = W.type2_case(3, N)
     rows = _rows_subset(x, N, N, 128, 9)
     check_type2(x, c, N, C64, rows=rows, label="2^22")
+
+
+def test_kernel_profiling_hook():
+    N = 1 << 16
+    x, c = W.type2_case(26, N)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, 1e-6, C64)
+    ct = _t(c, C64)
+    P.nufft_plan_profile(plan, 1, reserve=8)
+    for _ in range(3):
+        P.nufft2_exec(plan, ct)
+    P.nufft1_exec(plan, ct, sign=+1)
+    prof = P.nufft_plan_profile_read(plan)
+    assert set(prof) == {"fwd_passA", "fwd_passB", "adj_passB", "adj_passA"}
+    assert prof["fwd_passA"][0] == 3 and prof["adj_passA"][0] == 1
+    assert all(ms > 0 for _, ms in prof.values())
+    P.nufft_plan_profile(plan, 0)
+    P.nufft2_exec(plan, ct)
+    assert P.nufft_plan_profile_read(plan) == {}
