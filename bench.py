@@ -215,6 +215,18 @@ def main():
             ft = torch.empty(N2, dtype=dt, device=dev)
             t = time_loop(lambda: P.nufft2_exec(pl, ct, ft), 20, 3, torch)
             sec[label] = {"K": pl.K, "us": round(t * 1e3, 2), "pts_per_s": N2 / (t * 1e-3)}
+            if label == "fused_fp32_eps1e-6":
+                # per-kernel durations of the forward and of the adjoint at this size
+                P.nufft_plan_profile(pl, 1, reserve=64)
+                for _ in range(10):
+                    P.nufft2_exec(pl, ct, ft)
+                    P.nufft1_exec(pl, ft, +1, ct)
+                torch.cuda.synchronize()
+                sec["kernels_fused_fp32"] = {
+                    k: {"avg_us": round(ms / n * 1e3, 2),
+                        "GBs": round(kernel_bytes(k, pl.K, N2, N2, pl.grid, 8) / (ms / n * 1e-3) / 1e9, 1)}
+                    for k, (n, ms) in P.nufft_plan_profile_read(pl).items()}
+                P.nufft_plan_profile(pl, 0)
             del pl
         sec["speedup_fused_fp32_vs_plain_fp64_same_eps"] = round(
             sec["plain_fp64_eps1e-6"]["us"] / sec["fused_fp32_eps1e-6"]["us"], 2)

@@ -17,6 +17,8 @@ FLAGS = [
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep LDS use to the arrays the kernels declare (private arrays stay in registers)
+    "-mllvm", "-disable-promote-alloca-to-lds",
     "-Wno-unused-command-line-argument",
 ]
 

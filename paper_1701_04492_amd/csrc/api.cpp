@@ -114,10 +114,12 @@ static nufft_status upload_table(Plan *p, const std::vector<double> &d, void **o
 template <typename R>
 nufft_status upload_twiddles(Plan *p, hipStream_t s)
 {
-    std::vector<double> t1(2 * (size_t)p->L1);
+    std::vector<double> t1(2 * (size_t)p->L1), t1i(2 * (size_t)p->L1);
     twiddles(p->L1, p->L1, 1, -1, t1.data());
+    twiddles(p->L1, p->L1, 1, 1, t1i.data());
     nufft_status st = upload_table<R>(p, t1, &p->tw1, s);
     if (st) return st;
+    if ((st = upload_table<R>(p, t1i, &p->tw1i, s))) return st;
     if (p->L2 > 1) {
         std::vector<double> t2(2 * (size_t)p->L2), lo(2 * 4096), hi(2 * (size_t)(p->L / 4096));
         twiddles(p->L2, p->L2, 1, -1, t2.data());
@@ -232,6 +234,7 @@ FusedArgs<R> fused_args(const Plan *p)
     a.X = (const R *)p->X;
     a.Y = (cx_t<R> *)p->Y;
     a.tw1 = (const cx_t<R> *)p->tw1;
+    a.tw1i = (const cx_t<R> *)p->tw1i;
     a.tw2 = (const cx_t<R> *)p->tw2;
     a.hi = (const cx_t<R> *)p->hi;
     a.lo = (const cx_t<R> *)p->lo;

@@ -168,7 +168,11 @@ k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
     constexpr int OPT = (L + SMALL_NT - 1) / SMALL_NT;   // outputs per thread
     __shared__ C buf[RC * P];
     __shared__ C tw[L];
+    __shared__ R ucoef_s[NUFFT_KMAX * NUFFT_UCOEF_STRIDE];
+    __shared__ int nterm_s[NUFFT_KMAX];
     load_tw_s<C, L, DIR>(tw, tw_g);
+    stage_factors(fac, ucoef_s, nterm_s);
+    __syncthreads();
 
     const int tid = threadIdx.x;
     const int64_t lo = (int64_t)blockIdx.x * span, hi = min(M, lo + span);
@@ -192,7 +196,7 @@ k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
                     sincospi_r(Xi, &sn, &cs);
                     const C e = cmake<C>(cs, DIR * sn);          // exp(DIR i pi X)
                     const C val = cmul(e, c[perm[i]]);
-                    a = cadd(a, cscale(val, upoly(fac, r, Xi * fac.inv_gamma)));
+                    a = cadd(a, cscale(val, upoly_lds(ucoef_s, nterm_s, r, Xi * fac.inv_gamma)));
                 }
                 a = crot(a, -DIR * r);                            // i^r (type I) or i^-r (adjoint)
             }
@@ -234,13 +238,31 @@ k_sum_parts(const cx_t<R> *__restrict__ part, int nparts, int64_t N, cx_t<R> *__
 // L = L1 * L2: pass A (columns) and pass B (rows + samples)
 // ============================================================================
 
-// Pass A of type II.  Workgroup: G adjacent columns k1 (k = k1 + L1 k2);
-// each column is one length-L2 transform done by L2/16 threads.  The thread's
-// 16 coefficients sit in registers for all K ranks, in the operand order of
-// the first radix-16 stage (k2 = lt + q L2/16).
+// Workgroups are dispatched to the eight XCDs round robin (block b runs on
+// XCD b mod 8).  Renumbering the tasks so that consecutive tasks share an
+// XCD lets neighbouring tasks hit the same L2 (the column block of c read by
+// every rank chunk of pass A; the halves of a cache line written by
+// neighbouring tiles).  The grid is 8 * ceil(T / 8); surplus blocks return.
+__device__ __forceinline__ int xcd_task(int T)
+{
+    const int per = (T + 7) >> 3;
+    const int b = blockIdx.x;
+    const int task = (b & 7) * per + (b >> 3);
+    return task < T ? task : -1;
+}
+
+static inline unsigned xcd_grid(int T) { return (unsigned)(8 * ((T + 7) / 8)); }
+
+// Pass A of type II.  Task = (G adjacent columns k1, a chunk of RCA ranks);
+// k = k1 + L1 k2.  Each column is one length-L2 transform done by L2/16
+// threads.  The G x L2 block of c is read with coalesced G-wide rows and
+// transposed through LDS into the operand order of the first radix-16 stage
+// (k2 = lt + q L2/16); for each rank of the chunk it is scaled by v_r,
+// transformed, multiplied by exp(-2 pi i k1 n2 / L) and stored as
+// Y_r[n2][k1] (G-element runs).
 template <typename R, int L2, int G>
 __global__ void __launch_bounds__(G * L2 / 16)
-k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int mode,
+k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, int mode,
         const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
         cx_t<R> *__restrict__ Y)
 {
@@ -250,24 +272,35 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int mode,
     constexpr int P = fft_pitch(L2);
     __shared__ C buf[G * P];
     __shared__ C tw[L2];
+    const int nrc = (K + RCA - 1) / RCA;
+    const int task = xcd_task((int)(L1 / G) * nrc);
+    if (task < 0) return;
+    const int cg = task / nrc, rc = task % nrc;
+    const int r_lo = rc * RCA, r_hi = min(K, r_lo + RCA);
     load_tw_s<C, L2, -1>(tw, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
-    const int64_t k1_0 = (int64_t)blockIdx.x * G;
+    const int64_t k1_0 = (int64_t)cg * G;
     const int64_t L = L1 * L2;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * NT;
+        const int gg = i % G, k2 = i / G;
+        buf[gg * P + lds_pad(k2)] = load_coef<R>(c, k1_0 + gg + L1 * (int64_t)k2, N, mode);
+    }
+    __syncthreads();
     C cv[16];
     R zk[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const int64_t k = (k1_0 + g) + L1 * (int64_t)(lt + q * TPF);
-        cv[q] = load_coef<R>(c, k, N, mode);
-        zk[q] = zcoord<R>(k, N);
+        cv[q] = buf[g * P + lds_pad(lt + q * TPF)];
+        zk[q] = zcoord<R>((k1_0 + g) + L1 * (int64_t)(lt + q * TPF), N);
     }
-    for (int r = 0; r < K; ++r) {
+    for (int r = r_lo; r < r_hi; ++r) {
         C v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], cheb_v<R>(r, zk[q]));
-        __syncthreads();   // previous epilogue finished reading buf
+        __syncthreads();   // earlier readers of buf are done
         block_fft_regs<C, L2, -1>(buf + g * P, tw, lt, v);
         C *Yr = Y + (int64_t)r * L + k1_0;
 #pragma unroll 4
@@ -280,12 +313,12 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int mode,
     }
 }
 
-#define PB_SLOTS 8
-
-// Pass B of type II.  Workgroup: one output tile n2; RC ranks are transformed
-// side by side (one length-L1 transform per L1/16 threads), then every
-// sample of the tile gathers its RC spectrum values from LDS.
-template <typename R, int L1, int RC>
+// Pass B of type II.  Task = one output tile n2.  RC ranks are transformed
+// side by side (L1/16 threads each); the next chunk's rows are loaded into
+// registers while the current chunk is transformed and gathered.  Every
+// sample of the tile (up to NT*S per round) gathers its RC spectrum values
+// from LDS and accumulates u_r(j) X_r[t_j] in registers.
+template <typename R, int L1, int RC, int S>
 __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
         const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
@@ -296,23 +329,25 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     constexpr int TPF = L1 / 16;
     constexpr int NT = RC * TPF;
     constexpr int P = fft_pitch(L1);
-    constexpr int CAP = NT * PB_SLOTS;
+    constexpr int CAP = NT * S;
     __shared__ C buf[RC * P];
     __shared__ C tw[L1];
+    const int task = xcd_task((int)L2);
+    if (task < 0) return;
     load_tw_s<C, L1, -1>(tw, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
-    const int64_t n2 = blockIdx.x;
+    const int64_t n2 = task;
     const int64_t L = (int64_t)L1 * L2;
     const int64_t tile_lo = off[n2 * L1], tile_hi = off[(n2 + 1) * L1];
-    const C *Yrow = Y + n2 * L1;
+    const C *Yrow = Y + n2 * L1 + lt;
 
-    for (int64_t c0 = tile_lo; c0 < tile_hi || (c0 == tile_lo && tile_hi == tile_lo && false); c0 += CAP) {
-        int pos[PB_SLOTS];
-        R zz[PB_SLOTS];
-        C acc[PB_SLOTS];
+    for (int64_t c0 = tile_lo; c0 < tile_hi; c0 += CAP) {
+        int pos[S];
+        R zz[S];
+        C acc[S];
 #pragma unroll
-        for (int s = 0; s < PB_SLOTS; ++s) {
+        for (int s = 0; s < S; ++s) {
             const int64_t i = c0 + s * NT + tid;
             pos[s] = 0;
             zz[s] = 0;
@@ -322,17 +357,23 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
                 zz[s] = Xs[i] * fac.inv_gamma;
             }
         }
+        C vn[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) vn[q] = (g < fac.K) ? Yrow[(int64_t)g * L + q * TPF] : cmake<C>(0, 0);
         for (int r0 = 0; r0 < fac.K; r0 += RC) {
-            const int r = r0 + g;
             C v[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                v[q] = (r < fac.K) ? Yrow[(int64_t)r * L + lt + q * TPF] : cmake<C>(0, 0);
+            for (int q = 0; q < 16; ++q) v[q] = vn[q];
+            const int rn = r0 + RC + g;
+            if (r0 + RC < fac.K) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) vn[q] = (rn < fac.K) ? Yrow[(int64_t)rn * L + q * TPF] : cmake<C>(0, 0);
+            }
             __syncthreads();
             block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
             const int nr = min(RC, fac.K - r0);
 #pragma unroll
-            for (int s = 0; s < PB_SLOTS; ++s) {
+            for (int s = 0; s < S; ++s) {
                 for (int gg = 0; gg < nr; ++gg) {
                     const int rr = r0 + gg;
                     const C xv = buf[gg * P + lds_pad(pos[s])];
@@ -341,7 +382,7 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             }
         }
 #pragma unroll
-        for (int s = 0; s < PB_SLOTS; ++s) {
+        for (int s = 0; s < S; ++s) {
             const int64_t i = c0 + s * NT + tid;
             if (i < tile_hi) {
                 R sn, cs;
@@ -359,63 +400,126 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     }
 }
 
-// Pass B' of type I / adjoint.  Workgroup: tile n2.  Thread (rank r, lane lt)
-// sums, for its 16 grid points n1 = lt + q L1/16, the contributions
-// u_r(j) c_j (type I) or conj(u_r(j)) c_j (adjoint) of the samples at key
-// n2*L1 + n1, transforms along n1 and multiplies by exp(DIR 2 pi i n2 k1 / L):
-// Z_r[n2][k1].
-template <typename R, int L1, int RC, int DIR>
+// Pass B' of type I / adjoint.  Task = tile n2.  The tile's samples are
+// staged once in LDS as exp(DIR i pi X_j) c_j, z_j = X_j / gamma and their
+// grid point n1 (up to SCAP of them; any further ones are read from global
+// memory).  For each chunk of RC ranks, thread t owns the contiguous grid
+// points [t*GPT, (t+1)*GPT), GPT = L1/NT: their samples are one contiguous
+// run of the sorted order, which the thread walks once, summing
+// P_r(z_j) exp(DIR i pi X_j) c_j for every rank of the chunk in fixed order
+// and storing each grid value (times i^r for type I, i^-r for the adjoint)
+// when the grid point changes.  The RC grids are then transformed along n1
+// and multiplied by exp(DIR 2 pi i n2 k1 / L): Z_r[n2][k1].
+// TWG: read the FFT twiddles (already of sign DIR) from global memory instead
+// of an LDS copy, for the sizes where LDS would otherwise cap occupancy.
+template <typename R, int L1, int RC, int SCAP, int dir, bool TWG>
 __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict__ perm,
-            const R *__restrict__ Xs, const int32_t *__restrict__ off, Factors<R> fac,
-            const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
-            cx_t<R> *__restrict__ Z)
+            const R *__restrict__ Xs, const uint32_t *__restrict__ keys, const int32_t *__restrict__ off,
+            Factors<R> fac, const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi,
+            const cx_t<R> *__restrict__ lo, cx_t<R> *__restrict__ Z)
 {
     using C = cx_t<R>;
     constexpr int TPF = L1 / 16;
+    constexpr int NT = RC * TPF;
+    constexpr int GPT = L1 / NT;          // grid points per thread in the spread phase
     constexpr int P = fft_pitch(L1);
     __shared__ C buf[RC * P];
-    __shared__ C tw[L1];
-    load_tw_s<C, L1, DIR>(tw, tw_g);
+    __shared__ C tw_s[TWG ? 1 : L1];
+    const C *tw = TWG ? tw_g : tw_s;
+    __shared__ C sval[SCAP];
+    __shared__ R sz[SCAP];
+    __shared__ unsigned short spos[SCAP];
+    __shared__ int soff[L1 + 1];
+    const int task = xcd_task((int)L2);
+    if (task < 0) return;
     const int tid = threadIdx.x;
+    if (!TWG)
+        for (int m = tid; m < L1; m += NT) tw_s[m] = tw_g[m];
     const int g = tid / TPF, lt = tid % TPF;
-    const int64_t n2 = blockIdx.x;
+    const int64_t n2 = task;
     const int64_t L = (int64_t)L1 * L2;
+    const int tile_lo = off[n2 * L1];
+    for (int m = tid; m <= L1; m += NT) soff[m] = off[n2 * L1 + m] - tile_lo;
+    const int cnt = off[(n2 + 1) * L1] - tile_lo;
+    const int nst = min(cnt, SCAP);
+    for (int i = tid; i < nst; i += NT) {
+        const R Xi = Xs[tile_lo + i];
+        R sn, cs;
+        sincospi_r(Xi, &sn, &cs);
+        sval[i] = cmul(cmake<C>(cs, dir * sn), c[perm[tile_lo + i]]);
+        sz[i] = Xi * fac.inv_gamma;
+        spos[i] = (unsigned short)(keys[tile_lo + i] & (uint32_t)(L1 - 1));
+    }
+    __syncthreads();
+    const int n_lo = tid * GPT;
     for (int r0 = 0; r0 < fac.K; r0 += RC) {
-        const int r = r0 + g;
-        C v[16];
+        const int nr = min(RC, fac.K - r0);
+        // spread: zero this thread's grid points, then one walk over their samples
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int64_t key = n2 * L1 + lt + q * TPF;
-            C a = cmake<C>(0, 0);
-            if (r < fac.K) {
-                const int b0 = off[key], b1 = off[key + 1];
-                for (int i = b0; i < b1; ++i) {
-                    const R Xi = Xs[i];
-                    R sn, cs;
-                    sincospi_r(Xi, &sn, &cs);
-                    const C val = cmul(cmake<C>(cs, DIR * sn), c[perm[i]]);
-                    a = cadd(a, cscale(val, upoly(fac, r, Xi * fac.inv_gamma)));
-                }
-                a = crot(a, -DIR * r);
+        for (int gg = 0; gg < RC; ++gg)
+#pragma unroll
+            for (int q = 0; q < GPT; ++q) buf[gg * P + lds_pad(n_lo + q)] = cmake<C>(0, 0);
+        const int i0 = soff[n_lo], i1 = soff[n_lo + GPT];
+        C a[RC];
+#pragma unroll
+        for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+        int ncur = -1;
+        for (int i = i0; i < i1; ++i) {
+            C val;
+            R z;
+            int n1;
+            if (i < SCAP) {
+                val = sval[i];
+                z = sz[i];
+                n1 = spos[i];
+            } else {
+                const R Xi = Xs[tile_lo + i];
+                R sn, cs;
+                sincospi_r(Xi, &sn, &cs);
+                val = cmul(cmake<C>(cs, dir * sn), c[perm[tile_lo + i]]);
+                z = Xi * fac.inv_gamma;
+                n1 = (int)(keys[tile_lo + i] & (uint32_t)(L1 - 1));
             }
-            v[q] = a;
+            if (n1 != ncur) {
+                if (ncur >= 0) {
+#pragma unroll
+                    for (int gg = 0; gg < RC; ++gg)
+                        if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -dir * (r0 + gg));
+                }
+#pragma unroll
+                for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+                ncur = n1;
+            }
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg)
+                if (gg < nr) a[gg] = cadd(a[gg], cscale(val, upoly(fac, r0 + gg, z)));
+        }
+        if (ncur >= 0) {
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg)
+                if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -dir * (r0 + gg));
         }
         __syncthreads();
-        block_fft_regs<C, L1, DIR>(buf + g * P, tw, lt, v);
+        block_fft_lds<C, L1, dir>(buf + g * P, tw, lt);
+        const int r = r0 + g;
         if (r < fac.K) {
             C *Zr = Z + (int64_t)r * L + n2 * L1;
 #pragma unroll 4
             for (int q = 0; q < 16; ++q) {
                 const int k1 = lt + q * TPF;
-                Zr[k1] = cmul(buf[g * P + lds_pad(k1)], tw_big<C, DIR>(hi, lo, n2 * (int64_t)k1));
+                C w = tw_big<C, -1>(hi, lo, n2 * (int64_t)k1);
+                if (dir > 0) w = cconj(w);
+                Zr[k1] = cmul(buf[g * P + lds_pad(k1)], w);
             }
         }
+        __syncthreads();   // the next chunk overwrites buf
     }
 }
 
-// Pass A' of type I / adjoint.  Workgroup: G adjacent columns k1.  For each r
-// the columns Z_r[:][k1] are transformed along n2 (-> k2) and accumulated
+// Pass A' of type I / adjoint.  Task = G adjacent columns k1.  For each r the
+// columns Z_r[:][k1] (the next rank's block is loaded into registers while
+// this one is transformed) are transformed along n2 -> k2 and accumulated
 // with weight v_r(k1 + L1 k2) in registers; the sum over r is written once.
 template <typename R, int L2, int G, int DIR>
 __global__ void __launch_bounds__(G * L2 / 16)
@@ -428,36 +532,43 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
     constexpr int P = fft_pitch(L2);
     __shared__ C buf[G * P];
     __shared__ C tw[L2];
+    const int task = xcd_task((int)(L1 / G));
+    if (task < 0) return;
     load_tw_s<C, L2, DIR>(tw, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
-    const int64_t k1_0 = (int64_t)blockIdx.x * G;
+    const int64_t k1_0 = (int64_t)task * G;
     const int64_t L = L1 * L2;
     C acc[16];
-    R zk[16];
+    C zn[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int i = tid + e * NT;
-        const int64_t k = k1_0 + (i % G) + L1 * (int64_t)(i / G);
         acc[e] = cmake<C>(0, 0);
-        zk[e] = zcoord<R>(k, N);
+        zn[e] = Z[k1_0 + (i % G) + (int64_t)(i / G) * L1];
     }
     for (int r = 0; r < K; ++r) {
-        const C *Zr = Z + (int64_t)r * L + k1_0;
         __syncthreads();   // previous readers of buf are done
-#pragma unroll 4
+#pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;
-            const int gg = i % G, n2 = i / G;
-            buf[gg * P + lds_pad(n2)] = Zr[(int64_t)n2 * L1 + gg];
+            buf[(i % G) * P + lds_pad(i / G)] = zn[e];
+        }
+        if (r + 1 < K) {
+            const C *Zr = Z + (int64_t)(r + 1) * L + k1_0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int i = tid + e * NT;
+                zn[e] = Zr[(int64_t)(i / G) * L1 + (i % G)];
+            }
         }
         __syncthreads();
         block_fft_lds<C, L2, DIR>(buf + g * P, tw, lt);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;
-            const int gg = i % G, k2 = i / G;
-            acc[e] = cadd(acc[e], cscale(buf[gg * P + lds_pad(k2)], cheb_v<R>(r, zk[e])));
+            const R z = zcoord<R>(k1_0 + (i % G) + L1 * (int64_t)(i / G), N);
+            acc[e] = cadd(acc[e], cscale(buf[(i % G) * P + lds_pad(i / G)], cheb_v<R>(r, z)));
         }
     }
 #pragma unroll
@@ -539,6 +650,18 @@ template <> struct Cfg<double> {
     static constexpr int G1024 = 4, G2048 = 2;
 };
 
+// Ranks per pass-A task.  Every task pays a fixed set-up (twiddle table and
+// the column block of c), so ranks are split only until there are about one
+// task per CU.
+static inline int pass_a_ranks(int K, int ncg)
+{
+    const int want = 256;
+    int nrc = (want + ncg - 1) / ncg;           // rank chunks per column group
+    if (nrc < 1) nrc = 1;
+    if (nrc > K) nrc = K;
+    return (K + nrc - 1) / nrc;
+}
+
 template <typename R>
 hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int mode, const cx_t<R> *g,
                        double *gx, hipStream_t s)
@@ -552,11 +675,15 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     // pass A
     prof_begin(a.prof, mode ? "gradx_passA" : "fwd_passA", s);
     switch (a.L2) {
-#define PA(LL, GG)                                                                                       \
-    case LL:                                                                                             \
-        hipLaunchKernelGGL((k_passA<R, LL, GG>), dim3((unsigned)(a.L1 / GG)), dim3(GG * LL / 16), 0, s, c, \
-                           a.N, (int64_t)a.L1, a.fac.K, mode, a.tw2, a.hi, a.lo, a.Y);                   \
-        break;
+#define PA(LL, GG)                                                                                         \
+    case LL: {                                                                                             \
+        constexpr int G = GG;                                                                              \
+        const int ncg = a.L1 / G, rca = pass_a_ranks(a.fac.K, ncg);                                        \
+        const int T = ncg * ((a.fac.K + rca - 1) / rca);                                                   \
+        hipLaunchKernelGGL((k_passA<R, LL, G>), dim3(xcd_grid(T)), dim3(G * LL / 16), 0, s, c, a.N,          \
+                           (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);                     \
+        break;                                                                                             \
+    }
         PA(64, 8)
         PA(128, 8)
         PA(256, 8)
@@ -567,21 +694,25 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     default: return hipErrorInvalidValue;
     }
     prof_end(a.prof, s);
-    // pass B
+    // pass B: RC ranks side by side, S sample slots per thread (about 1.25 x the
+    // mean tile population L1 when M = N)
     prof_begin(a.prof, mode ? "gradx_passB" : "fwd_passB", s);
     switch (a.L1) {
-#define PB(LL, RR)                                                                                       \
-    case LL:                                                                                             \
-        hipLaunchKernelGGL((k_passB<R, LL, RR>), dim3((unsigned)a.L2), dim3(RR * LL / 16), 0, s,          \
-                           (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,   \
-                           a.tw1, f, mode, g, gx);                                                        \
-        break;
-        PB(128, 16)
-        PB(256, 16)
-        PB(512, 8)
-        PB(1024, 4)
-        PB(2048, 2)
-        PB(4096, 1)
+#define PB(LL, RF, SF, RD, SD)                                                                             \
+    case LL: {                                                                                             \
+        constexpr bool F = sizeof(R) == 4;                                                                 \
+        constexpr int RR = F ? RF : RD, SS = F ? SF : SD;                                                  \
+        hipLaunchKernelGGL((k_passB<R, LL, RR, SS>), dim3(xcd_grid(a.L2)), dim3(RR * LL / 16), 0, s,        \
+                           (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,     \
+                           a.tw1, f, mode, g, gx);                                                          \
+        break;                                                                                             \
+    }
+        PB(128, 16, 1, 8, 2)
+        PB(256, 16, 2, 8, 3)
+        PB(512, 8, 3, 4, 5)
+        PB(1024, 4, 5, 4, 5)
+        PB(2048, 4, 5, 2, 5)
+        PB(4096, 2, 10, 1, 5)
 #undef PB
     default: return hipErrorInvalidValue;
     }
@@ -599,28 +730,34 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
     }
     prof_begin(a.prof, DIR > 0 ? "adj_passB" : "type1_passB", s);
     switch (a.L1) {
-#define PBA(LL, RR)                                                                                      \
-    case LL:                                                                                             \
-        hipLaunchKernelGGL((k_passB_adj<R, LL, RR, DIR>), dim3((unsigned)a.L2), dim3(RR * LL / 16), 0, s, \
-                           c, (int64_t)a.L2, a.perm, a.Xs, a.off, a.fac, a.tw1, a.hi, a.lo, a.Y);          \
-        break;
-        PBA(128, 16)
-        PBA(256, 16)
-        PBA(512, 8)
-        PBA(1024, 4)
-        PBA(2048, 2)
-        PBA(4096, 1)
+#define PBA(LL, RF, SCF, RD, SCD, TG)                                                                      \
+    case LL: {                                                                                             \
+        constexpr bool F = sizeof(R) == 4;                                                                 \
+        constexpr int RR = F ? RF : RD, SC = F ? SCF : SCD;                                                \
+        hipLaunchKernelGGL((k_passB_adj<R, LL, RR, SC, DIR, TG>), dim3(xcd_grid(a.L2)), dim3(RR * LL / 16), \
+                           0, s, c, (int64_t)a.L2, a.perm, a.Xs, a.keys, a.off, a.fac,                      \
+                           DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, a.Y);                                     \
+        break;                                                                                             \
+    }
+        PBA(128, 16, 256, 8, 256, false)
+        PBA(256, 16, 384, 8, 384, false)
+        PBA(512, 8, 768, 4, 768, false)
+        PBA(1024, 4, 1280, 4, 1280, false)
+        PBA(2048, 2, 2304, 2, 1280, true)
+        PBA(4096, 1, 2304, 1, 256, true)
 #undef PBA
     default: return hipErrorInvalidValue;
     }
     prof_end(a.prof, s);
     prof_begin(a.prof, DIR > 0 ? "adj_passA" : "type1_passA", s);
     switch (a.L2) {
-#define PAA(LL, GG)                                                                                      \
-    case LL:                                                                                             \
-        hipLaunchKernelGGL((k_passA_adj<R, LL, GG, DIR>), dim3((unsigned)(a.L1 / GG)), dim3(GG * LL / 16), \
-                           0, s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, a.tw2, f);           \
-        break;
+#define PAA(LL, GG)                                                                                        \
+    case LL: {                                                                                             \
+        constexpr int G = GG;                                                                              \
+        hipLaunchKernelGGL((k_passA_adj<R, LL, G, DIR>), dim3(xcd_grid(a.L1 / G)), dim3(G * LL / 16), 0,    \
+                           s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, a.tw2, f);                \
+        break;                                                                                             \
+    }
         PAA(64, 8)
         PAA(128, 8)
         PAA(256, 8)

@@ -21,6 +21,27 @@ __device__ __forceinline__ R upoly(const Factors<R> &fac, int r, R z)
     return (r & 1) ? acc * z : acc;
 }
 
+// Same polynomial from a coefficient table staged in LDS: for kernels where the
+// rank differs between the lanes of a wave (a per-lane index into the
+// kernel-argument table would turn every coefficient into a vector load).
+template <typename R>
+__device__ __forceinline__ R upoly_lds(const R *ucoef_s, const int *nterm_s, int r, R z)
+{
+    const R w = z * z;
+    const R *cf = ucoef_s + r * NUFFT_UCOEF_STRIDE;
+    const int n = nterm_s[r];
+    R acc = cf[n - 1];
+    for (int m = n - 2; m >= 0; --m) acc = acc * w + cf[m];
+    return (r & 1) ? acc * z : acc;
+}
+
+template <typename R>
+__device__ __forceinline__ void stage_factors(const Factors<R> &fac, R *ucoef_s, int *nterm_s)
+{
+    for (int i = threadIdx.x; i < NUFFT_KMAX * NUFFT_UCOEF_STRIDE; i += blockDim.x) ucoef_s[i] = fac.ucoef[i];
+    for (int i = threadIdx.x; i < NUFFT_KMAX; i += blockDim.x) nterm_s[i] = fac.nterm[i];
+}
+
 // ---- plan kernels ----------------------------------------------------------
 template <typename R>
 hipError_t launch_assign(const double *x, int64_t M, int64_t L, double n_over_L, int L1, int log2_L2,
@@ -72,6 +93,7 @@ struct FusedArgs {
     const R *X;              // M perturbations, sample order
     cx_t<R> *Y;              // K x L intermediate of the two-pass split
     const cx_t<R> *tw1, *tw2, *hi, *lo;
+    const cx_t<R> *tw1i;     // inverse-sign twiddles of length L1
     cx_t<R> *part;           // scratch for partial sums of the one-workgroup adjoint
     int64_t part_cap;        // complex elements available in part
     Profiler *prof;

@@ -39,6 +39,7 @@ struct nufft_plan_s {
     void *U = nullptr, *W = nullptr, *W2 = nullptr;   // plain path
     void *Y = nullptr;              // K x L two-pass intermediate
     void *tw1 = nullptr, *tw2 = nullptr, *hi = nullptr, *lo = nullptr;
+    void *tw1i = nullptr;            // inverse-sign table of length L1
     void *part = nullptr;           // partial sums of the one-workgroup adjoint
     int64_t part_cap = 0;
 
