@@ -7,6 +7,7 @@
 #include "factors.h"
 #include "kernels.h"
 #include "plan.h"
+#include "kernels_2d.h"
 
 using namespace nufft;
 
@@ -122,7 +123,10 @@ nufft_status upload_twiddles(Plan *p, hipStream_t s)
     if ((st = upload_table<R>(p, t1i, &p->tw1i, s))) return st;
     if (p->L2 > 1) {
         std::vector<double> t2(2 * (size_t)p->L2), lo(2 * 4096), hi(2 * (size_t)(p->L / 4096));
+        std::vector<double> t2i(2 * (size_t)p->L2);
         twiddles(p->L2, p->L2, 1, -1, t2.data());
+        twiddles(p->L2, p->L2, 1, 1, t2i.data());
+        if ((st = upload_table<R>(p, t2i, &p->tw2i, s))) return st;
         twiddles(p->L, 4096, 1, -1, lo.data());
         twiddles(p->L, p->L / 4096, 4096, -1, hi.data());
         if ((st = upload_table<R>(p, t2, &p->tw2, s))) return st;
@@ -235,6 +239,7 @@ FusedArgs<R> fused_args(const Plan *p)
     a.Y = (cx_t<R> *)p->Y;
     a.tw1 = (const cx_t<R> *)p->tw1;
     a.tw1i = (const cx_t<R> *)p->tw1i;
+    a.tw2i = (const cx_t<R> *)p->tw2i;
     a.tw2 = (const cx_t<R> *)p->tw2;
     a.hi = (const cx_t<R> *)p->hi;
     a.lo = (const cx_t<R> *)p->lo;
@@ -279,6 +284,236 @@ static hipError_t exec_type2(const Plan *p, const void *c, void *f, int mode, co
     return fused_type2<R>(fused_args<R>(p), (const C *)c, (C *)f, mode, (const C *)g, gx, s);
 }
 
+
+// ---- type III (Sec. 3.2) ---------------------------------------------------
+
+hipError_t t3_assign(const double *x, int64_t M, int64_t N, int32_t *t, double *d, int32_t *wrap,
+                     unsigned long long *gbits, int *flags, hipStream_t s);
+hipError_t t3_freq(const double *w, int64_t N, double *xs, int *flags, hipStream_t s);
+template <typename R>
+hipError_t t3_scale(const cx_t<R> *c, const double *w, int64_t N, int r, int with_wrap, cx_t<R> *c1, cx_t<R> *c2,
+                    hipStream_t s);
+template <typename R>
+hipError_t t3_accum(const double *d, const int32_t *t, const int32_t *wrap, int64_t M, const Factors<double> &fac,
+                    int r, const cx_t<R> *y, const cx_t<R> *y2, cx_t<R> *f, hipStream_t s);
+
+template <typename R>
+static nufft_status type3(int64_t M, const double *x, int64_t N, const double *w, const void *c, void *f,
+                          double eps, nufft_dtype dt, hipStream_t s)
+{
+    using C = cx_t<R>;
+    Plan tmp;   // owns the temporaries
+    struct SyncGuard {   // destroyed before tmp: no temporary is freed under a running kernel
+        hipStream_t s;
+        ~SyncGuard() { (void)hipStreamSynchronize(s); }
+    } guard{s};
+    int32_t *t = (int32_t *)tmp.alloc(M * sizeof(int32_t));
+    int32_t *wrap = (int32_t *)tmp.alloc(M * sizeof(int32_t));
+    double *d = (double *)tmp.alloc(M * sizeof(double));
+    double *xs = (double *)tmp.alloc(N * sizeof(double));
+    unsigned long long *flags = (unsigned long long *)tmp.alloc(2 * sizeof(unsigned long long));
+    C *c1 = (C *)tmp.alloc(N * sizeof(C));
+    C *c2 = (C *)tmp.alloc(N * sizeof(C));
+    C *y = (C *)tmp.alloc(N * sizeof(C));
+    C *y2 = (C *)tmp.alloc(N * sizeof(C));
+    if (!t || !wrap || !d || !xs || !flags || !c1 || !c2 || !y || !y2) return NUFFT_ERR_ALLOC;
+    NUFFT_HIP_CHECK(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), s));
+    NUFFT_HIP_CHECK(t3_assign(x, M, N, t, d, wrap, flags, (int *)(flags + 1), s));
+    NUFFT_HIP_CHECK(t3_freq(w, N, xs, (int *)(flags + 1), s));
+    unsigned long long h[2];
+    NUFFT_HIP_CHECK(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    const int bad = (int)h[1];
+    if (bad & 5) return NUFFT_ERR_INVALID_ARG;   // x outside [0,1) / w outside [0,N) or not finite
+    const int any_wrap = (bad & 2) ? 1 : 0;
+    double gamma;
+    std::memcpy(&gamma, &h[0], sizeof(double));
+    if (gamma > 0.5) gamma = 0.5;
+    // half of eps for the factorisation of A, half for the inner type-I transforms,
+    // whose errors are weighted by sum_r |u_r| <= sum_r sum'_p |b_pr|
+    const int K = choose_rank(eps / 2.0, gamma);
+    if (K < 0) return NUFFT_ERR_UNSUPPORTED;
+    Factors<double> fac;
+    {
+        std::memset(&fac, 0, sizeof(fac));
+        double mono[NUFFT_KMAX * NUFFT_KMAX];
+        u_monomials(gamma, K, mono);
+        for (int r = 0; r < K; ++r) {
+            int n = 0;
+            for (int m = (r & 1); m < K; m += 2) fac.ucoef[r * NUFFT_UCOEF_STRIDE + n++] = mono[r * K + m];
+            fac.nterm[r] = n;
+        }
+        fac.K = K;
+        fac.inv_gamma = gamma > 0 ? 1.0 / gamma : 0.0;
+    }
+    double b[NUFFT_KMAX * NUFFT_KMAX], su = 0.0;
+    bessel_b(gamma, K, b);
+    for (int p = 0; p < K; ++p)
+        for (int r = 0; r < K; ++r) su += (p == 0 ? 0.5 : 1.0) * std::fabs(b[p * K + r]);
+    const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
+    double eps_i = eps / (2.0 * (su > 1.0 ? su : 1.0));
+    if (eps_i < floor_eps) eps_i = floor_eps;
+    // inner type-I plan on the samples w/N with N modes
+    Plan *inner = new (std::nothrow) Plan();
+    if (!inner) return NUFFT_ERR_ALLOC;
+    tmp.children.push_back(inner);
+    inner->kind = PLAN_1D;
+    inner->dtype = dt;
+    inner->N = N;
+    inner->M = N;
+    inner->eps = eps_i;
+    if (!choose_grid(N, &inner->L, &inner->L1, &inner->L2)) return NUFFT_ERR_UNSUPPORTED;
+    nufft_status st = build_1d<R>(inner, xs, s);
+    if (st) return st;
+    const FusedArgs<R> ia = fused_args<R>(inner);
+    for (int r = 0; r < K; ++r) {
+        NUFFT_HIP_CHECK(t3_scale<R>((const C *)c, w, N, r, any_wrap, c1, c2, s));
+        NUFFT_HIP_CHECK(fused_type1<R>(ia, c1, y, -1, s));
+        if (any_wrap) NUFFT_HIP_CHECK(fused_type1<R>(ia, c2, y2, -1, s));
+        NUFFT_HIP_CHECK(t3_accum<R>(d, t, wrap, M, fac, r, y, any_wrap ? y2 : nullptr, (C *)f, s));
+    }
+    return NUFFT_OK;
+}
+
+// ---- 2-D type II (Sec. 4) -------------------------------------------------------
+
+template <typename R>
+static void fill_factors_2d(Factors<R> &fac, double gamma, int K) { fill_factors(fac, gamma, K); }
+
+template <typename R>
+nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
+{
+    const int64_t M = p->M;
+    const int64_t G2 = (int64_t)p->Gx * p->Gy;
+    R *Xx = (R *)p->alloc(M * sizeof(R));
+    R *Xy = (R *)p->alloc(M * sizeof(R));
+    p->Xxs = p->alloc(M * sizeof(R));
+    p->Xys = p->alloc(M * sizeof(R));
+    uint32_t *keys_u = (uint32_t *)p->alloc(M * sizeof(uint32_t));
+    int32_t *iota = (int32_t *)p->alloc(M * sizeof(int32_t));
+    p->keys = (uint32_t *)p->alloc(M * sizeof(uint32_t));
+    p->perm = (int32_t *)p->alloc(M * sizeof(int32_t));
+    int32_t *hist = (int32_t *)p->alloc((G2 + 1) * sizeof(int32_t));
+    p->off = (int32_t *)p->alloc((G2 + 1) * sizeof(int32_t));
+    const int64_t tmp_n = std::max(radix_tmp_elems(M), scan_tmp_elems(G2 + 1)) + 16;
+    int32_t *tmp = (int32_t *)p->alloc(tmp_n * sizeof(int32_t));
+    unsigned long long *dflags = (unsigned long long *)p->alloc(3 * sizeof(unsigned long long));
+    if (!Xx || !Xy || !p->Xxs || !p->Xys || !keys_u || !iota || !p->keys || !p->perm || !hist || !p->off || !tmp ||
+        !dflags)
+        return NUFFT_ERR_ALLOC;
+    NUFFT_HIP_CHECK(hipMemsetAsync(hist, 0, (G2 + 1) * sizeof(int32_t), s));
+    NUFFT_HIP_CHECK(hipMemsetAsync(dflags, 0, 3 * sizeof(unsigned long long), s));
+    NUFFT_HIP_CHECK(launch_assign2d<R>(x, y, M, p->Gx, p->Gy, (double)p->N1 / p->Gx, (double)p->N2 / p->Gy, Xx, Xy,
+                                       keys_u, hist, dflags, (int *)(dflags + 2), s));
+    NUFFT_HIP_CHECK(exclusive_scan(hist, p->off, G2 + 1, tmp, s));
+    NUFFT_HIP_CHECK(launch_iota(iota, M, s));
+    int key_bits = 0;
+    while ((int64_t(1) << key_bits) < G2) ++key_bits;
+    uint32_t *ks;
+    int32_t *vs;
+    NUFFT_HIP_CHECK(radix_sort_pairs(keys_u, iota, p->keys, p->perm, M, key_bits, tmp, s, &ks, &vs));
+    if (ks != p->keys) {
+        NUFFT_HIP_CHECK(hipMemcpyAsync(p->keys, ks, M * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        NUFFT_HIP_CHECK(hipMemcpyAsync(p->perm, vs, M * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    NUFFT_HIP_CHECK(launch_gather_sorted<R>(p->perm, Xx, M, (R *)p->Xxs, s));
+    NUFFT_HIP_CHECK(launch_gather_sorted<R>(p->perm, Xy, M, (R *)p->Xys, s));
+    unsigned long long h[3];
+    std::vector<int32_t> toff((size_t)p->Gy + 1);
+    NUFFT_HIP_CHECK(hipMemcpyAsync(h, dflags, sizeof(h), hipMemcpyDeviceToHost, s));
+    for (int n2 = 0; n2 <= p->Gy; ++n2)
+        NUFFT_HIP_CHECK(hipMemcpyAsync(&toff[n2], p->off + (int64_t)n2 * p->Gx, sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    if ((int)h[2] != 0) return NUFFT_ERR_NONFINITE;
+    double gx, gy;
+    std::memcpy(&gx, &h[0], sizeof(double));
+    std::memcpy(&gy, &h[1], sizeof(double));
+    if (p->flags & NUFFT_FLAG_FIX_GAMMA_HALF) {
+        gx = (double)p->N1 / (2.0 * p->Gx);
+        gy = (double)p->N2 / (2.0 * p->Gy);
+    }
+    p->gammax = gx > 0.5 ? 0.5 : gx;
+    p->gammay = gy > 0.5 ? 0.5 : gy;
+    // |A^x A^y - A^x_K A^y_K| <= eps_x + eps_y + eps_x eps_y: half of eps per axis
+    p->Kx = choose_rank(p->eps / 2.0, p->gammax);
+    p->Ky = choose_rank(p->eps / 2.0, p->gammay);
+    if (p->Kx < 0 || p->Ky < 0) return NUFFT_ERR_UNSUPPORTED;
+    p->K = p->Kx;
+    p->gamma = p->gammax;
+    if (p->dtype == NUFFT_C64) {
+        fill_factors(p->ffx, p->gammax, p->Kx);
+        fill_factors(p->ffy, p->gammay, p->Ky);
+    } else {
+        fill_factors(p->fdx, p->gammax, p->Kx);
+        fill_factors(p->fdy, p->gammay, p->Ky);
+    }
+    std::vector<double> t(2 * (size_t)std::max(p->Gx, p->Gy));
+    nufft_status st;
+    twiddles(p->Gx, p->Gx, 1, -1, t.data());
+    if ((st = upload_table<R>(p, std::vector<double>(t.begin(), t.begin() + 2 * p->Gx), &p->twx, s))) return st;
+    twiddles(p->Gx, p->Gx, 1, 1, t.data());
+    if ((st = upload_table<R>(p, std::vector<double>(t.begin(), t.begin() + 2 * p->Gx), &p->twxi, s))) return st;
+    twiddles(p->Gy, p->Gy, 1, -1, t.data());
+    if ((st = upload_table<R>(p, std::vector<double>(t.begin(), t.begin() + 2 * p->Gy), &p->twy, s))) return st;
+    twiddles(p->Gy, p->Gy, 1, 1, t.data());
+    if ((st = upload_table<R>(p, std::vector<double>(t.begin(), t.begin() + 2 * p->Gy), &p->twyi, s))) return st;
+    // forward pass-B tasks: each column n2 split into sample ranges of at most cap
+    const int cap = pass_b2d_cap(p->Gx, p->dtype == NUFFT_C64);
+    if (cap <= 0) return NUFFT_ERR_UNSUPPORTED;
+    std::vector<int4> tk;
+    for (int n2 = 0; n2 < p->Gy; ++n2)
+        for (int a = toff[n2]; a < toff[n2 + 1]; a += cap) {
+            int4 v;
+            v.x = n2;
+            v.y = a;
+            v.z = std::min(a + cap, toff[n2 + 1]);
+            v.w = 0;
+            tk.push_back(v);
+        }
+    p->ntasks = (int)tk.size();
+    p->tasks = (int4 *)p->alloc(std::max<size_t>(1, tk.size()) * sizeof(int4));
+    if (!p->tasks) return NUFFT_ERR_ALLOC;
+    if (!tk.empty()) {
+        NUFFT_HIP_CHECK(hipMemcpyAsync(p->tasks, tk.data(), tk.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+        NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    }
+    p->Y = p->alloc((size_t)p->Ky * G2 * 2 * sizeof(R));
+    if (!p->Y) return NUFFT_ERR_ALLOC;
+    return NUFFT_OK;
+}
+
+template <typename R>
+static Args2D<R> args_2d(const Plan *p)
+{
+    Args2D<R> a;
+    a.N1 = p->N1;
+    a.N2 = p->N2;
+    a.M = p->M;
+    a.Gx = p->Gx;
+    a.Gy = p->Gy;
+    if constexpr (sizeof(R) == 4) {
+        a.fx = p->ffx;
+        a.fy = p->ffy;
+    } else {
+        a.fx = p->fdx;
+        a.fy = p->fdy;
+    }
+    a.keys = p->keys;
+    a.perm = p->perm;
+    a.Xxs = (const R *)p->Xxs;
+    a.Xys = (const R *)p->Xys;
+    a.off = p->off;
+    a.tasks = p->tasks;
+    a.ntasks = p->ntasks;
+    a.H = (cx_t<R> *)p->Y;
+    a.twx = (const cx_t<R> *)p->twx;
+    a.twxi = (const cx_t<R> *)p->twxi;
+    a.twy = (const cx_t<R> *)p->twy;
+    a.twyi = (const cx_t<R> *)p->twyi;
+    a.prof = const_cast<Profiler *>(&p->prof);
+    return a;
+}
 }  // namespace nufft
 
 // ============================================================================
@@ -354,6 +589,77 @@ nufft_status nufft1_exec(nufft_plan_t plan, const void *c, void *f, int sign, vo
     if (plan->dtype == NUFFT_C64)
         return from_hip(fused_type1<float>(fused_args<float>(plan), (const float2 *)c, (float2 *)f, sign, s));
     return from_hip(fused_type1<double>(fused_args<double>(plan), (const double2 *)c, (double2 *)f, sign, s));
+}
+
+nufft_status nufft3_exec(int64_t n_pts, const double *x, int64_t n_freq, const double *w, const void *c, void *f,
+                         double eps, nufft_dtype dtype, void *stream)
+{
+    if (n_pts < 1 || n_freq < 1 || !x || !w || !c || !f) return NUFFT_ERR_INVALID_ARG;
+    if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
+    if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
+    nufft_status st;
+    if (!eps_ok(eps, dtype, &st)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = dtype == NUFFT_C64 ? type3<float>(n_pts, x, n_freq, w, c, f, eps, dtype, s)
+                            : type3<double>(n_pts, x, n_freq, w, c, f, eps, dtype, s);
+    if (st != NUFFT_OK) (void)hipStreamSynchronize(s);
+    return st;
+}
+
+nufft_status nufft2d_plan(nufft_plan_t *out, int64_t n1, int64_t n2, int64_t n_pts, const double *x_dev,
+                          const double *y_dev, double eps, nufft_dtype dtype, uint32_t flags, void *stream)
+{
+    if (!out) return NUFFT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n1 < 1 || n2 < 1 || n_pts < 1 || !x_dev || !y_dev) return NUFFT_ERR_INVALID_ARG;
+    if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)NUFFT_FLAG_FIX_GAMMA_HALF) return NUFFT_ERR_INVALID_ARG;
+    if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
+    nufft_status st;
+    if (!eps_ok(eps, dtype, &st)) return st;
+    int gx = 16, gy = 16;
+    while (gx < n1) gx <<= 1;
+    while (gy < n2) gy <<= 1;
+    if (gx > 2048 || gy > 2048) return NUFFT_ERR_UNSUPPORTED;
+    Plan *p = new (std::nothrow) Plan();
+    if (!p) return NUFFT_ERR_ALLOC;
+    p->kind = PLAN_2D;
+    p->dtype = dtype;
+    p->flags = flags;
+    p->N1 = n1;
+    p->N2 = n2;
+    p->N = n1 * n2;
+    p->M = n_pts;
+    p->eps = eps;
+    p->Gx = gx;
+    p->Gy = gy;
+    p->L = (int64_t)gx * gy;
+    hipStream_t s = (hipStream_t)stream;
+    st = dtype == NUFFT_C64 ? build_2d<float>(p, x_dev, y_dev, s) : build_2d<double>(p, x_dev, y_dev, s);
+    if (st != NUFFT_OK) {
+        (void)hipStreamSynchronize(s);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return NUFFT_OK;
+}
+
+nufft_status nufft2d_exec(nufft_plan_t plan, void *C, void *f, int adjoint, void *stream)
+{
+    if (!plan || plan->kind != PLAN_2D || !C || !f || (adjoint != 0 && adjoint != 1)) return NUFFT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (plan->dtype == NUFFT_C64) {
+        const Args2D<float> a = args_2d<float>(plan);
+        e = adjoint ? fused_2d_adj<float>(a, (const float2 *)f, (float2 *)C, s)
+                    : fused_2d<float>(a, (const float2 *)C, (float2 *)f, s);
+    } else {
+        const Args2D<double> a = args_2d<double>(plan);
+        e = adjoint ? fused_2d_adj<double>(a, (const double2 *)f, (double2 *)C, s)
+                    : fused_2d<double>(a, (const double2 *)C, (double2 *)f, s);
+    }
+    return from_hip(e);
 }
 
 nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *grid)
@@ -461,20 +767,9 @@ nufft_status nufft_bessel_coefficients(double gamma, int K, double *b_host)
 // ---- entry points still to be implemented --------------------------------
 extern "C" {
 
-nufft_status nufft3_exec(int64_t, const double *, int64_t, const double *, const void *, void *, double,
-                         nufft_dtype, void *)
-{
-    return NUFFT_ERR_UNSUPPORTED;
-}
 
-nufft_status nufft2d_plan(nufft_plan_t *out, int64_t, int64_t, int64_t, const double *, const double *, double,
-                          nufft_dtype, uint32_t, void *)
-{
-    if (out) *out = nullptr;
-    return NUFFT_ERR_UNSUPPORTED;
-}
 
-nufft_status nufft2d_exec(nufft_plan_t, void *, void *, int, void *) { return NUFFT_ERR_UNSUPPORTED; }
+
 
 nufft_status nufft_batch_plan(nufft_plan_t *out, int, const int64_t *, const int64_t *, const double *const *,
                               double, nufft_dtype, uint32_t, void *)

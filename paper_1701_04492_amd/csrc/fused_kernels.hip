@@ -20,60 +20,9 @@
 // point's samples one contiguous segment: a deterministic sum, no atomics),
 // transformed along n1, and pass A' transforms along n2, scales by v_r and
 // sums over r in registers.
-#include "fft.h"
-#include "kernels.h"
+#include "fused_common.h"
 
 namespace nufft {
-
-template <typename C, int L, int DIR>
-__device__ __forceinline__ void load_tw_s(C *tw_s, const C *__restrict__ tw_g)
-{
-    for (int m = threadIdx.x; m < L; m += blockDim.x) {
-        C w = tw_g[m];
-        tw_s[m] = DIR < 0 ? w : cconj(w);
-    }
-}
-
-template <typename C, int DIR>
-__device__ __forceinline__ C tw_big(const C *__restrict__ hi, const C *__restrict__ lo, int64_t m)
-{
-    C w = cmul(hi[m >> 12], lo[m & 4095]);
-    return DIR < 0 ? w : cconj(w);
-}
-
-// T_r(z) (v_0 = 1/2 is the halved T_0) by the three-term recurrence.
-template <typename R>
-__device__ __forceinline__ R cheb_v(int r, R z)
-{
-    if (r == 0) return (R)0.5;
-    R a = 1, b = z;
-    for (int q = 1; q < r; ++q) {
-        const R c = 2 * z * b - a;
-        a = b;
-        b = c;
-    }
-    return b;
-}
-
-// c_k, or -2 pi i k c_k for the derivative pass.
-template <typename R>
-__device__ __forceinline__ cx_t<R> load_coef(const cx_t<R> *__restrict__ c, int64_t k, int64_t N, int mode)
-{
-    using C = cx_t<R>;
-    if (k >= N) return cmake<C>(0, 0);
-    C ck = c[k];
-    if (mode == 1) {
-        const R w = (R)(-2.0 * M_PI * (double)k);
-        ck = cmake<C>(-w * ck.y, w * ck.x);
-    }
-    return ck;
-}
-
-template <typename R>
-__device__ __forceinline__ R zcoord(int64_t k, int64_t N)
-{
-    return (R)(2.0 * (double)k / (double)N - 1.0);
-}
 
 // ============================================================================
 // L <= 4096: whole transform per workgroup
@@ -238,21 +187,6 @@ k_sum_parts(const cx_t<R> *__restrict__ part, int nparts, int64_t N, cx_t<R> *__
 // L = L1 * L2: pass A (columns) and pass B (rows + samples)
 // ============================================================================
 
-// Workgroups are dispatched to the eight XCDs round robin (block b runs on
-// XCD b mod 8).  Renumbering the tasks so that consecutive tasks share an
-// XCD lets neighbouring tasks hit the same L2 (the column block of c read by
-// every rank chunk of pass A; the halves of a cache line written by
-// neighbouring tiles).  The grid is 8 * ceil(T / 8); surplus blocks return.
-__device__ __forceinline__ int xcd_task(int T)
-{
-    const int per = (T + 7) >> 3;
-    const int b = blockIdx.x;
-    const int task = (b & 7) * per + (b >> 3);
-    return task < T ? task : -1;
-}
-
-static inline unsigned xcd_grid(int T) { return (unsigned)(8 * ((T + 7) / 8)); }
-
 // Pass A of type II.  Task = (G adjacent columns k1, a chunk of RCA ranks);
 // k = k1 + L1 k2.  Each column is one length-L2 transform done by L2/16
 // threads.  The G x L2 block of c is read with coalesced G-wide rows and
@@ -260,7 +194,7 @@ static inline unsigned xcd_grid(int T) { return (unsigned)(8 * ((T + 7) / 8)); }
 // (k2 = lt + q L2/16); for each rank of the chunk it is scaled by v_r,
 // transformed, multiplied by exp(-2 pi i k1 n2 / L) and stored as
 // Y_r[n2][k1] (G-element runs).
-template <typename R, int L2, int G>
+template <typename R, int L2, int G, bool TWG>
 __global__ void __launch_bounds__(G * L2 / 16)
 k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, int mode,
         const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
@@ -271,13 +205,14 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     constexpr int NT = G * TPF;
     constexpr int P = fft_pitch(L2);
     __shared__ C buf[G * P];
-    __shared__ C tw[L2];
+    __shared__ C tw_s[TWG ? 1 : L2];
+    const C *tw = TWG ? tw_g : tw_s;
     const int nrc = (K + RCA - 1) / RCA;
     const int task = xcd_task((int)(L1 / G) * nrc);
     if (task < 0) return;
     const int cg = task / nrc, rc = task % nrc;
     const int r_lo = rc * RCA, r_hi = min(K, r_lo + RCA);
-    load_tw_s<C, L2, -1>(tw, tw_g);
+    if (!TWG) load_tw_s<C, L2, -1>(tw_s, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)cg * G;
@@ -318,7 +253,7 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
 // registers while the current chunk is transformed and gathered.  Every
 // sample of the tile (up to NT*S per round) gathers its RC spectrum values
 // from LDS and accumulates u_r(j) X_r[t_j] in registers.
-template <typename R, int L1, int RC, int S>
+template <typename R, int L1, int RC, int S, bool TWG>
 __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
         const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
@@ -331,10 +266,11 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     constexpr int P = fft_pitch(L1);
     constexpr int CAP = NT * S;
     __shared__ C buf[RC * P];
-    __shared__ C tw[L1];
+    __shared__ C tw_s[TWG ? 1 : L1];
+    const C *tw = TWG ? tw_g : tw_s;
     const int task = xcd_task((int)L2);
     if (task < 0) return;
-    load_tw_s<C, L1, -1>(tw, tw_g);
+    if (!TWG) load_tw_s<C, L1, -1>(tw_s, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t n2 = task;
@@ -521,7 +457,7 @@ k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict
 // columns Z_r[:][k1] (the next rank's block is loaded into registers while
 // this one is transformed) are transformed along n2 -> k2 and accumulated
 // with weight v_r(k1 + L1 k2) in registers; the sum over r is written once.
-template <typename R, int L2, int G, int DIR>
+template <typename R, int L2, int G, int DIR, bool TWG>
 __global__ void __launch_bounds__(G * L2 / 16)
 k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const cx_t<R> *__restrict__ tw_g,
             cx_t<R> *__restrict__ out)
@@ -531,10 +467,12 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
     constexpr int NT = G * TPF;
     constexpr int P = fft_pitch(L2);
     __shared__ C buf[G * P];
-    __shared__ C tw[L2];
+    __shared__ C tw_s[TWG ? 1 : L2];
+    const C *tw = TWG ? tw_g : tw_s;   // tw_g already has sign DIR
     const int task = xcd_task((int)(L1 / G));
     if (task < 0) return;
-    load_tw_s<C, L2, DIR>(tw, tw_g);
+    if (!TWG)
+        for (int m = threadIdx.x; m < L2; m += NT) tw_s[m] = tw_g[m];
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)task * G;
@@ -680,7 +618,8 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
         constexpr int G = GG;                                                                              \
         const int ncg = a.L1 / G, rca = pass_a_ranks(a.fac.K, ncg);                                        \
         const int T = ncg * ((a.fac.K + rca - 1) / rca);                                                   \
-        hipLaunchKernelGGL((k_passA<R, LL, G>), dim3(xcd_grid(T)), dim3(G * LL / 16), 0, s, c, a.N,          \
+        hipLaunchKernelGGL((k_passA<R, LL, G, false>), dim3(xcd_grid(T)), dim3(G * LL / 16), 0, s, c, \
+                           a.N,                                                                            \
                            (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);                     \
         break;                                                                                             \
     }
@@ -702,7 +641,8 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     case LL: {                                                                                             \
         constexpr bool F = sizeof(R) == 4;                                                                 \
         constexpr int RR = F ? RF : RD, SS = F ? SF : SD;                                                  \
-        hipLaunchKernelGGL((k_passB<R, LL, RR, SS>), dim3(xcd_grid(a.L2)), dim3(RR * LL / 16), 0, s,        \
+        hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false>), dim3(xcd_grid(a.L2)), dim3(RR * LL / 16),  \
+                           0, s,                                                                           \
                            (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,     \
                            a.tw1, f, mode, g, gx);                                                          \
         break;                                                                                             \
@@ -754,8 +694,9 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
 #define PAA(LL, GG)                                                                                        \
     case LL: {                                                                                             \
         constexpr int G = GG;                                                                              \
-        hipLaunchKernelGGL((k_passA_adj<R, LL, G, DIR>), dim3(xcd_grid(a.L1 / G)), dim3(G * LL / 16), 0,    \
-                           s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, a.tw2, f);                \
+        hipLaunchKernelGGL((k_passA_adj<R, LL, G, DIR, false>), dim3(xcd_grid(a.L1 / G)),            \
+                           dim3(G * LL / 16), 0, s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K,      \
+                           DIR < 0 ? a.tw2 : a.tw2i, f);                                                   \
         break;                                                                                             \
     }
         PAA(64, 8)

@@ -93,7 +93,7 @@ struct FusedArgs {
     const R *X;              // M perturbations, sample order
     cx_t<R> *Y;              // K x L intermediate of the two-pass split
     const cx_t<R> *tw1, *tw2, *hi, *lo;
-    const cx_t<R> *tw1i;     // inverse-sign twiddles of length L1
+    const cx_t<R> *tw1i, *tw2i;   // inverse-sign twiddles of lengths L1, L2
     cx_t<R> *part;           // scratch for partial sums of the one-workgroup adjoint
     int64_t part_cap;        // complex elements available in part
     Profiler *prof;

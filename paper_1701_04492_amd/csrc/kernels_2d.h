@@ -1,0 +1,34 @@
+// 2-D type II (Sec. 4): arguments and launchers.
+#pragma once
+
+#include "kernels.h"
+
+namespace nufft {
+
+template <typename R>
+struct Args2D {
+    int64_t N1, N2, M;        // coefficient rows (x, k1), columns (y, k2), samples
+    int Gx, Gy;               // FFT grids of the two axes (powers of two >= 16)
+    Factors<R> fx, fy;        // rank factors of the two axes
+    const uint32_t *keys;     // M sorted keys ty * Gx + tx
+    const int32_t *perm;      // M sample index per sorted position
+    const R *Xxs, *Xys;       // M sorted perturbations of the two axes
+    const int32_t *off;       // Gx * Gy + 1 first sorted position per key
+    const int4 *tasks;        // forward pass-B tasks (column n2, first, end)
+    int ntasks;
+    cx_t<R> *H;               // Ky x Gy x Gx intermediate [r2][n2][k1]
+    const cx_t<R> *twx, *twxi, *twy, *twyi;   // FFT tables, both signs
+    Profiler *prof;
+};
+
+template <typename R>
+hipError_t fused_2d(const Args2D<R> &a, const cx_t<R> *Cin, cx_t<R> *f, hipStream_t s);
+template <typename R>
+hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, hipStream_t s);
+int pass_b2d_cap(int GX, bool fp32);
+template <typename R>
+hipError_t launch_assign2d(const double *x, const double *y, int64_t M, int64_t GX, int64_t GY, double sx,
+                           double sy, R *Xx, R *Xy, uint32_t *key, int32_t *hist, unsigned long long *gbits,
+                           int *bad, hipStream_t s);
+
+}  // namespace nufft

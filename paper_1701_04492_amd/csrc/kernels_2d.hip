@@ -1,0 +1,516 @@
+// 2-D type II and its adjoint (Sec. 4).
+//
+//   f_j = sum_{k1<N1, k2<N2} C[k1][k2] exp(-2 pi i (k1 x_j + k2 y_j))
+//       ~ sum_{r1<Kx, r2<Ky} u^x_r1(j) u^y_r2(j) G_{r1 r2}[tx_j][ty_j],
+//   G_{r1 r2} = F_{Gx} (v^x_r1 o C o v^y_r2) F_{Gy}^T  (eq. (NUFFTII_2D)),
+// x pairing with k1 on a grid of Gx points and y with k2 on Gy points.  The
+// transform along k2 does not depend on r1 and is done once per r2 (the
+// saving noted at the end of Sec. 4):
+//   pass A (per group of G rows k1, chunk of ranks r2):
+//     H_r2[n2][k1] = sum_k2 C[k1][k2] v^y_r2(k2) exp(-2 pi i k2 n2 / Gy)
+//   pass B (per column n2 and sample range): for every r2, r1:
+//     X = F_{Gx}(v^x_r1 o H_r2[n2][:]) and f_j += u^x_r1 u^y_r2 X[tx_j] for
+//     the samples with ty_j = n2 (sorted there by the plan).
+// The adjoint runs the two passes in reverse with the conjugate factors.
+#include "fused_common.h"
+#include "kernels_2d.h"
+
+namespace nufft {
+
+// ---- pass A: rows of C, FFT along k2, transposed store ---------------------
+template <typename R, int GY, int G>
+__global__ void __launch_bounds__(G * GY / 16)
+k_2d_passA(const cx_t<R> *__restrict__ Cin, int64_t N1, int64_t N2, int64_t GX, Factors<R> fy, int RCA,
+           const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ H)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = GY / 16;
+    constexpr int NT = G * TPF;
+    constexpr int P = fft_pitch(GY);
+    __shared__ C buf[G * P];
+    __shared__ C tw[GY];
+    const int K = fy.K;
+    const int nrc = (K + RCA - 1) / RCA;
+    const int ncg = (int)((N1 + G - 1) / G);
+    const int task = xcd_task(ncg * nrc);
+    if (task < 0) return;
+    const int cg = task / nrc, rc = task % nrc;
+    const int r_lo = rc * RCA, r_hi = min(K, r_lo + RCA);
+    load_tw_s<C, GY, -1>(tw, tw_g);
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t k1_0 = (int64_t)cg * G;
+    const int64_t k1 = k1_0 + g;
+    C cv[16];
+    R zk[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t k2 = lt + q * TPF;
+        cv[q] = (k1 < N1 && k2 < N2) ? Cin[k1 * N2 + k2] : cmake<C>(0, 0);
+        zk[q] = zcoord<R>(k2, N2);
+    }
+    for (int r = r_lo; r < r_hi; ++r) {
+        C v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], cheb_v<R>(r, zk[q]));
+        __syncthreads();
+        block_fft_regs<C, GY, -1>(buf + g * P, tw, lt, v);
+        C *Hr = H + (int64_t)r * GY * GX + k1_0;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            const int gg = i % G, n2 = i / G;
+            if (k1_0 + gg < N1) Hr[(int64_t)n2 * GX + gg] = buf[gg * P + lds_pad(n2)];
+        }
+    }
+}
+
+// ---- pass B: one column n2, a range of its samples ---------------------------
+template <typename R, int GX, int RC, int S>
+__global__ void __launch_bounds__(RC * GX / 16)
+k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__restrict__ tasks, int ntasks,
+           const uint32_t *__restrict__ keys, const int32_t *__restrict__ perm, const R *__restrict__ Xxs,
+           const R *__restrict__ Xys, Factors<R> fx, Factors<R> fy, const cx_t<R> *__restrict__ tw_g,
+           cx_t<R> *__restrict__ f)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = GX / 16;
+    constexpr int NT = RC * TPF;
+    constexpr int P = fft_pitch(GX);
+    __shared__ C buf[RC * P];
+    __shared__ C tw[GX];
+    const int task = xcd_task(ntasks);
+    if (task < 0) return;
+    const int4 tk = tasks[task];
+    const int64_t n2 = tk.x, i_lo = tk.y, i_hi = tk.z;
+    load_tw_s<C, GX, -1>(tw, tw_g);
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    int pos[S];
+    R zx[S], zy[S], py[S];
+    C acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int64_t i = i_lo + s * NT + tid;
+        pos[s] = 0;
+        zx[s] = zy[s] = 0;
+        acc[s] = cmake<C>(0, 0);
+        if (i < i_hi) {
+            pos[s] = (int)(keys[i] & (uint32_t)(GX - 1));
+            zx[s] = Xxs[i] * fx.inv_gamma;
+            zy[s] = Xys[i] * fy.inv_gamma;
+        }
+    }
+    R zk[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) zk[q] = zcoord<R>(lt + q * TPF, N1);
+    for (int r2 = 0; r2 < fy.K; ++r2) {
+        C cv[16];
+        const C *Hrow = H + ((int64_t)r2 * GY + n2) * GX;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k1 = lt + q * TPF;
+            cv[q] = k1 < N1 ? Hrow[k1] : cmake<C>(0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) py[s] = upoly(fy, r2, zy[s]);
+        for (int r0 = 0; r0 < fx.K; r0 += RC) {
+            const int r1 = r0 + g;
+            C v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = r1 < fx.K ? cscale(cv[q], cheb_v<R>(r1, zk[q])) : cmake<C>(0, 0);
+            __syncthreads();
+            block_fft_regs<C, GX, -1>(buf + g * P, tw, lt, v);
+            const int nr = min(RC, fx.K - r0);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                for (int gg = 0; gg < nr; ++gg) {
+                    const int rr = r0 + gg;
+                    const C xv = buf[gg * P + lds_pad(pos[s])];
+                    acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fx, rr, zx[s]) * py[s]), rr + r2));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int64_t i = i_lo + s * NT + tid;
+        if (i < i_hi) {
+            R sn, cs;
+            sincospi_r(Xxs[i] + Xys[i], &sn, &cs);
+            f[perm[i]] = cmul(cmake<C>(cs, -sn), acc[s]);
+        }
+    }
+}
+
+// ---- adjoint pass B': one column n2 -> Z_r2[n2][k1] -----------------------------
+// The column's samples are staged in LDS (exp(+i pi (Xx + Xy)) g_j, zx, zy, tx);
+// for each r2 and chunk of RC ranks r1 the samples are summed per grid point
+// (each thread walks the contiguous run of samples of its own grid points),
+// transformed along n1 (inverse sign), weighted by v^x_r1(k1) and summed over r1
+// in registers; the row Z_r2[n2][:] is written once per r2.
+template <typename R, int GX, int RC, int SCAP, bool TWG>
+__global__ void __launch_bounds__(RC * GX / 16)
+k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const int32_t *__restrict__ perm,
+               const uint32_t *__restrict__ keys, const R *__restrict__ Xxs, const R *__restrict__ Xys,
+               const int32_t *__restrict__ off, Factors<R> fx, Factors<R> fy, const cx_t<R> *__restrict__ twi_g,
+               cx_t<R> *__restrict__ Z)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = GX / 16;
+    constexpr int NT = RC * TPF;
+    constexpr int GPT = GX / NT;
+    constexpr int ZA = GX / NT;           // output positions per thread
+    constexpr int P = fft_pitch(GX);
+    __shared__ C buf[RC * P];
+    __shared__ C tw_s[TWG ? 1 : GX];
+    __shared__ C sval[SCAP];
+    __shared__ R szx[SCAP], spy[SCAP];
+    __shared__ unsigned short spos[SCAP];
+    __shared__ int soff[GX + 1];
+    const C *tw = TWG ? twi_g : tw_s;
+    const int task = xcd_task((int)GY);
+    if (task < 0) return;
+    const int tid = threadIdx.x;
+    if (!TWG)
+        for (int m = tid; m < GX; m += NT) tw_s[m] = twi_g[m];
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t n2 = task;
+    const int tile_lo = off[n2 * GX];
+    for (int m = tid; m <= GX; m += NT) soff[m] = off[n2 * GX + m] - tile_lo;
+    const int cnt = off[(n2 + 1) * GX] - tile_lo;
+    const int nst = min(cnt, SCAP);
+    for (int i = tid; i < nst; i += NT) {
+        const R ax = Xxs[tile_lo + i], ay = Xys[tile_lo + i];
+        R sn, cs;
+        sincospi_r(ax + ay, &sn, &cs);
+        sval[i] = cmul(cmake<C>(cs, sn), gin[perm[tile_lo + i]]);
+        szx[i] = ax * fx.inv_gamma;
+        spos[i] = (unsigned short)(keys[tile_lo + i] & (uint32_t)(GX - 1));
+    }
+    const int n_lo = tid * GPT;
+    for (int r2 = 0; r2 < fy.K; ++r2) {
+        for (int i = tid; i < nst; i += NT) spy[i] = upoly(fy, r2, Xys[tile_lo + i] * fy.inv_gamma);
+        __syncthreads();
+        C za[ZA];
+#pragma unroll
+        for (int m = 0; m < ZA; ++m) za[m] = cmake<C>(0, 0);
+        for (int r0 = 0; r0 < fx.K; r0 += RC) {
+            const int nr = min(RC, fx.K - r0);
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg)
+#pragma unroll
+                for (int q = 0; q < GPT; ++q) buf[gg * P + lds_pad(n_lo + q)] = cmake<C>(0, 0);
+            const int i0 = soff[n_lo], i1 = soff[n_lo + GPT];
+            C a[RC];
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+            int ncur = -1;
+            for (int i = i0; i < i1; ++i) {
+                C val;
+                R zxv, pyv;
+                int n1;
+                if (i < SCAP) {
+                    val = sval[i];
+                    zxv = szx[i];
+                    pyv = spy[i];
+                    n1 = spos[i];
+                } else {
+                    const R ax = Xxs[tile_lo + i], ay = Xys[tile_lo + i];
+                    R sn, cs;
+                    sincospi_r(ax + ay, &sn, &cs);
+                    val = cmul(cmake<C>(cs, sn), gin[perm[tile_lo + i]]);
+                    zxv = ax * fx.inv_gamma;
+                    pyv = upoly(fy, r2, ay * fy.inv_gamma);
+                    n1 = (int)(keys[tile_lo + i] & (uint32_t)(GX - 1));
+                }
+                if (n1 != ncur) {
+                    if (ncur >= 0) {
+#pragma unroll
+                        for (int gg = 0; gg < RC; ++gg)
+                            if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -(r0 + gg + r2));
+                    }
+#pragma unroll
+                    for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+                    ncur = n1;
+                }
+#pragma unroll
+                for (int gg = 0; gg < RC; ++gg)
+                    if (gg < nr) a[gg] = cadd(a[gg], cscale(val, upoly(fx, r0 + gg, zxv) * pyv));
+            }
+            if (ncur >= 0) {
+#pragma unroll
+                for (int gg = 0; gg < RC; ++gg)
+                    if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -(r0 + gg + r2));
+            }
+            __syncthreads();
+            block_fft_lds<C, GX, 1>(buf + g * P, tw, lt);
+#pragma unroll
+            for (int m = 0; m < ZA; ++m) {
+                const int k1 = tid + m * NT;
+                const R z = zcoord<R>(k1, N1);
+                for (int gg = 0; gg < nr; ++gg)
+                    za[m] = cadd(za[m], cscale(buf[gg * P + lds_pad(k1)], cheb_v<R>(r0 + gg, z)));
+            }
+            __syncthreads();
+        }
+        C *Zrow = Z + ((int64_t)r2 * GY + n2) * GX;
+#pragma unroll
+        for (int m = 0; m < ZA; ++m) Zrow[tid + m * NT] = za[m];
+    }
+}
+
+// ---- adjoint pass A': G rows k1, FFT along n2 -> k2, weighted sum over r2 --------
+template <typename R, int GY, int G>
+__global__ void __launch_bounds__(G * GY / 16)
+k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX, int Ky,
+               const cx_t<R> *__restrict__ twi_g, cx_t<R> *__restrict__ Cout)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = GY / 16;
+    constexpr int NT = G * TPF;
+    constexpr int P = fft_pitch(GY);
+    __shared__ C buf[G * P];
+    __shared__ C tw[GY];
+    const int ncg = (int)((N1 + G - 1) / G);
+    const int task = xcd_task(ncg);
+    if (task < 0) return;
+    const int tid = threadIdx.x;
+    for (int m = tid; m < GY; m += NT) tw[m] = twi_g[m];
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t k1_0 = (int64_t)task * G;
+    C acc[16], zn[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * NT;
+        acc[e] = cmake<C>(0, 0);
+        zn[e] = (k1_0 + (i % G) < N1) ? Z[(int64_t)(i / G) * GX + k1_0 + (i % G)] : cmake<C>(0, 0);
+    }
+    for (int r = 0; r < Ky; ++r) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            buf[(i % G) * P + lds_pad(i / G)] = zn[e];
+        }
+        if (r + 1 < Ky) {
+            const C *Zr = Z + (int64_t)(r + 1) * GY * GX + k1_0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int i = tid + e * NT;
+                zn[e] = (k1_0 + (i % G) < N1) ? Zr[(int64_t)(i / G) * GX + (i % G)] : cmake<C>(0, 0);
+            }
+        }
+        __syncthreads();
+        block_fft_lds<C, GY, 1>(buf + g * P, tw, lt);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            const R z = zcoord<R>(i / G, N2);
+            acc[e] = cadd(acc[e], cscale(buf[(i % G) * P + lds_pad(i / G)], cheb_v<R>(r, z)));
+        }
+    }
+    // transpose through LDS so that rows of C are written contiguously
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * NT;
+        buf[(i % G) * P + lds_pad(i / G)] = acc[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * NT;
+        const int gg = i / GY, k2 = i % GY;
+        if (k1_0 + gg < N1 && k2 < N2) Cout[(k1_0 + gg) * N2 + k2] = buf[gg * P + lds_pad(k2)];
+    }
+}
+
+// ---- dispatch -----------------------------------------------------------------
+
+template <typename R>
+hipError_t fused_2d(const Args2D<R> &a, const cx_t<R> *Cin, cx_t<R> *f, hipStream_t s)
+{
+    constexpr bool F = sizeof(R) == 4;
+    prof_begin(a.prof, "fwd2d_passA", s);
+    switch (a.Gy) {
+#define A2(GG, GF, GD)                                                                                      \
+    case GG: {                                                                                              \
+        constexpr int G = F ? GF : GD;                                                                      \
+        const int ncg = (int)((a.N1 + G - 1) / G);                                                          \
+        int nrc = (256 + ncg - 1) / ncg;                                                                    \
+        nrc = nrc < 1 ? 1 : (nrc > a.fy.K ? a.fy.K : nrc);                                                  \
+        const int rca = (a.fy.K + nrc - 1) / nrc;                                                           \
+        const int T = ncg * ((a.fy.K + rca - 1) / rca);                                                     \
+        hipLaunchKernelGGL((k_2d_passA<R, GG, G>), dim3(xcd_grid(T)), dim3(G * GG / 16), 0, s, Cin, a.N1, a.N2, \
+                           (int64_t)a.Gx, a.fy, rca, a.twy, a.H);                                           \
+        break;                                                                                              \
+    }
+        A2(16, 8, 8)
+        A2(32, 8, 8)
+        A2(64, 8, 8)
+        A2(128, 8, 8)
+        A2(256, 8, 8)
+        A2(512, 8, 4)
+        A2(1024, 8, 4)
+        A2(2048, 4, 2)
+#undef A2
+    default: return hipErrorInvalidValue;
+    }
+    prof_end(a.prof, s);
+    prof_begin(a.prof, "fwd2d_passB", s);
+    switch (a.Gx) {
+#define B2(GG, RF, SF, RD, SD)                                                                              \
+    case GG: {                                                                                              \
+        constexpr int RR = F ? RF : RD, SS = F ? SF : SD;                                                   \
+        hipLaunchKernelGGL((k_2d_passB<R, GG, RR, SS>), dim3(xcd_grid(a.ntasks)), dim3(RR * GG / 16), 0, s,   \
+                           (const cx_t<R> *)a.H, a.N1, (int64_t)a.Gy, a.tasks, a.ntasks, a.keys, a.perm,     \
+                           a.Xxs, a.Xys, a.fx, a.fy, a.twx, f);                                             \
+        break;                                                                                              \
+    }
+        B2(16, 16, 4, 16, 4)
+        B2(32, 16, 4, 16, 4)
+        B2(64, 16, 4, 16, 4)
+        B2(128, 16, 4, 8, 4)
+        B2(256, 16, 4, 8, 4)
+        B2(512, 8, 8, 4, 4)
+        B2(1024, 4, 8, 4, 4)
+        B2(2048, 2, 8, 2, 4)
+#undef B2
+    default: return hipErrorInvalidValue;
+    }
+    prof_end(a.prof, s);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, hipStream_t s)
+{
+    constexpr bool F = sizeof(R) == 4;
+    prof_begin(a.prof, "adj2d_passB", s);
+    switch (a.Gx) {
+#define BA2(GG, RF, SCF, RD, SCD, TG)                                                                        \
+    case GG: {                                                                                              \
+        constexpr int RR = F ? RF : RD, SC = F ? SCF : SCD;                                                 \
+        hipLaunchKernelGGL((k_2d_passB_adj<R, GG, RR, SC, TG>), dim3(xcd_grid(a.Gy)), dim3(RR * GG / 16), 0, \
+                           s, gin, a.N1, (int64_t)a.Gy, a.perm, a.keys, a.Xxs, a.Xys, a.off, a.fx, a.fy,     \
+                           a.twxi, a.H);                                                                    \
+        break;                                                                                              \
+    }
+        BA2(16, 16, 256, 16, 256, false)
+        BA2(32, 16, 256, 16, 256, false)
+        BA2(64, 16, 256, 16, 256, false)
+        BA2(128, 16, 512, 8, 512, false)
+        BA2(256, 16, 512, 8, 512, false)
+        BA2(512, 8, 1024, 4, 768, false)
+        BA2(1024, 4, 2048, 4, 1024, false)
+        BA2(2048, 2, 2304, 2, 1280, true)
+#undef BA2
+    default: return hipErrorInvalidValue;
+    }
+    prof_end(a.prof, s);
+    prof_begin(a.prof, "adj2d_passA", s);
+    switch (a.Gy) {
+#define AA2(GG, GF, GD)                                                                                     \
+    case GG: {                                                                                              \
+        constexpr int G = F ? GF : GD;                                                                      \
+        const int ncg = (int)((a.N1 + G - 1) / G);                                                          \
+        hipLaunchKernelGGL((k_2d_passA_adj<R, GG, G>), dim3(xcd_grid(ncg)), dim3(G * GG / 16), 0, s,         \
+                           (const cx_t<R> *)a.H, a.N1, a.N2, (int64_t)a.Gx, a.fy.K, a.twyi, Cout);          \
+        break;                                                                                              \
+    }
+        AA2(16, 8, 8)
+        AA2(32, 8, 8)
+        AA2(64, 8, 8)
+        AA2(128, 8, 8)
+        AA2(256, 8, 8)
+        AA2(512, 8, 4)
+        AA2(1024, 8, 4)
+        AA2(2048, 4, 2)
+#undef AA2
+    default: return hipErrorInvalidValue;
+    }
+    prof_end(a.prof, s);
+    return hipGetLastError();
+}
+
+// Samples per forward pass-B task (threads x slots of the instantiation above).
+int pass_b2d_cap(int GX, bool fp32)
+{
+    switch (GX) {
+    case 16: case 32: case 64: return (16 * GX / 16) * 4;
+    case 128: case 256: return fp32 ? (16 * GX / 16) * 4 : (8 * GX / 16) * 4;
+    case 512: return fp32 ? (8 * 512 / 16) * 8 : (4 * 512 / 16) * 4;
+    case 1024: return fp32 ? (4 * 1024 / 16) * 8 : (4 * 1024 / 16) * 4;
+    case 2048: return fp32 ? (2 * 2048 / 16) * 8 : (2 * 2048 / 16) * 4;
+    default: return 0;
+    }
+}
+
+// ---- plan kernel: both axes at once ----------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_assign2d(const double *__restrict__ x, const double *__restrict__ y, int64_t M, int64_t GX, int64_t GY,
+           double sx, double sy, R *__restrict__ Xx, R *__restrict__ Xy, uint32_t *__restrict__ key,
+           int32_t *__restrict__ hist, unsigned long long *gbits, int *bad)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double ax = 0.0, ay = 0.0;
+    if (j < M) {
+        const double xj = x[j], yj = y[j];
+        int tx = 0, ty = 0;
+        double dx = 0.0, dy = 0.0;
+        if (!isfinite(xj) || !isfinite(yj)) {
+            atomicOr(bad, 1);
+        } else {
+            const double gx = (double)GX, gy = (double)GY;
+            const double s1 = rint(gx * xj), s2 = rint(gy * yj);
+            dx = fma(gx, xj, -s1) * sx;
+            dy = fma(gy, yj, -s2) * sy;
+            double t1 = fmod(s1, gx), t2 = fmod(s2, gy);
+            if (t1 < 0.0) t1 += gx;
+            if (t2 < 0.0) t2 += gy;
+            tx = (int)t1;
+            ty = (int)t2;
+            ax = fabs(dx);
+            ay = fabs(dy);
+        }
+        const uint32_t k = (uint32_t)ty * (uint32_t)GX + (uint32_t)tx;
+        Xx[j] = (R)dx;
+        Xy[j] = (R)dy;
+        key[j] = k;
+        atomicAdd(&hist[k], 1);
+    }
+    // wave maxima, then one atomic per wave and axis
+    for (int o = 32; o > 0; o >>= 1) {
+        ax = fmax(ax, __shfl_xor(ax, o, 64));
+        ay = fmax(ay, __shfl_xor(ay, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(gbits, (unsigned long long)__double_as_longlong(ax));
+        atomicMax(gbits + 1, (unsigned long long)__double_as_longlong(ay));
+    }
+}
+
+template <typename R>
+hipError_t launch_assign2d(const double *x, const double *y, int64_t M, int64_t GX, int64_t GY, double sx,
+                           double sy, R *Xx, R *Xy, uint32_t *key, int32_t *hist, unsigned long long *gbits,
+                           int *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_assign2d<R>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, x, y, M, GX, GY, sx, sy,
+                       Xx, Xy, key, hist, gbits, bad);
+    return hipGetLastError();
+}
+
+template hipError_t fused_2d<float>(const Args2D<float> &, const float2 *, float2 *, hipStream_t);
+template hipError_t fused_2d<double>(const Args2D<double> &, const double2 *, double2 *, hipStream_t);
+template hipError_t fused_2d_adj<float>(const Args2D<float> &, const float2 *, float2 *, hipStream_t);
+template hipError_t fused_2d_adj<double>(const Args2D<double> &, const double2 *, double2 *, hipStream_t);
+template hipError_t launch_assign2d<float>(const double *, const double *, int64_t, int64_t, int64_t, double,
+                                           double, float *, float *, uint32_t *, int32_t *, unsigned long long *,
+                                           int *, hipStream_t);
+template hipError_t launch_assign2d<double>(const double *, const double *, int64_t, int64_t, int64_t, double,
+                                            double, double *, double *, uint32_t *, int32_t *,
+                                            unsigned long long *, int *, hipStream_t);
+
+}  // namespace nufft

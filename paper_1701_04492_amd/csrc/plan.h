@@ -39,9 +39,20 @@ struct nufft_plan_s {
     void *U = nullptr, *W = nullptr, *W2 = nullptr;   // plain path
     void *Y = nullptr;              // K x L two-pass intermediate
     void *tw1 = nullptr, *tw2 = nullptr, *hi = nullptr, *lo = nullptr;
-    void *tw1i = nullptr;            // inverse-sign table of length L1
+    void *tw1i = nullptr, *tw2i = nullptr;   // inverse-sign tables
     void *part = nullptr;           // partial sums of the one-workgroup adjoint
     int64_t part_cap = 0;
+
+    // 2-D plans (Sec. 4): x pairs with k1 < N1 on Gx points, y with k2 < N2 on Gy points
+    int64_t N1 = 0, N2 = 0;
+    int Gx = 0, Gy = 0, Kx = 0, Ky = 0;
+    double gammax = 0, gammay = 0;
+    Factors<float> ffx, ffy;
+    Factors<double> fdx, fdy;
+    void *Xxs = nullptr, *Xys = nullptr;
+    int4 *tasks = nullptr;
+    int ntasks = 0;
+    void *twx = nullptr, *twxi = nullptr, *twy = nullptr, *twyi = nullptr;
 
     Profiler prof;
 
