@@ -66,7 +66,10 @@ enum {
     /* Run the plain unfused online stage: scale kernel, stand-alone FFT
      * passes over a K x L buffer, a stored U table (Sec. 2.3, "Planning the
      * transform") and a separate gather/row-sum kernel.  Default is fused. */
-    NUFFT_FLAG_PLAIN = 2u
+    NUFFT_FLAG_PLAIN = 2u,
+    /* Batches only: time the persistent launch at a few grid sizes while
+     * planning and keep the fastest (reported as `grid` by nufft_plan_info). */
+    NUFFT_FLAG_AUTOTUNE = 4u
 };
 
 /* ---- 1-D type II / type I / adjoint ----------------------------------- */
@@ -135,24 +138,31 @@ nufft_status nufft2d_exec(nufft_plan_t plan, void *C_dev, void *f_dev, int adjoi
 
 /* ---- batches of independent 1-D type II transforms ---------------------- */
 
-/* Plan B independent type-II transforms of sizes N_b (modes) and M_b
- * (samples); x_dev_host[b] is a device pointer to M_b doubles.  Each
- * transform uses the grid L_b = next power of two >= N_b.  Transforms with
- * L_b <= 4096 run whole in one workgroup; larger ones run as a two-pass
- * split; all of them go into one persistent launch per exec. */
+/* Plan B independent type-II transforms of sizes N_b (modes, 1 <= N_b <= 2^20)
+ * and M_b (samples); x_dev_host[b] is a device pointer to M_b doubles (a
+ * host array of device pointers).  Each transform uses the grid
+ * L_b = next power of two >= N_b (oversampling, Sec. 2.3) and its own rank
+ * K_b(eps, gamma_b).  Transforms with L_b <= 4096 run whole in one
+ * workgroup; larger ones run as a two-pass split; all of them go into one
+ * persistent launch per exec, tasks in decreasing order of size.
+ * Flags: NUFFT_FLAG_FIX_GAMMA_HALF, NUFFT_FLAG_AUTOTUNE. */
 nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_modes_host,
                               const int64_t *n_pts_host, const double *const *x_dev_host,
                               double eps, nufft_dtype dtype, uint32_t flags, void *stream);
 
 /* c_dev_host[b]: device pointer to N_b complex; f_dev_host[b]: device
- * pointer to M_b complex.  The pointer arrays are host arrays. */
+ * pointer to M_b complex.  The pointer arrays are host arrays; when they
+ * differ from the previous call they are copied to the device first (a
+ * synchronous upload), so for HIP graph capture run one exec with the same
+ * pointers before capturing: the captured work is then the single kernel. */
 nufft_status nufft_batch_exec(nufft_plan_t plan, const void *const *c_dev_host,
                               void *const *f_dev_host, void *stream);
 
 /* ---- plan queries and lifetime ----------------------------------------- */
 
 /* Any output pointer may be NULL.  For 2-D plans K and gamma describe the
- * x axis; for batches K is the largest rank and gamma the largest gamma. */
+ * x axis and grid is Gx * Gy; for batches K is the largest rank, gamma the
+ * largest gamma and grid the number of workgroups of the persistent launch. */
 nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *grid);
 
 /* Copies the plan's sorted sample order to host memory: perm_host[i] is the

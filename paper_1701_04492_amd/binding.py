@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "nufft_mi355x.h")
 NUFFT_C64, NUFFT_C128 = 0, 1
 NUFFT_FLAG_FIX_GAMMA_HALF = 1
 NUFFT_FLAG_PLAIN = 2
+NUFFT_FLAG_AUTOTUNE = 4
 STATUS = {0: "NUFFT_OK", 1: "NUFFT_ERR_INVALID_ARG", 2: "NUFFT_ERR_UNSUPPORTED", 3: "NUFFT_ERR_ALLOC",
           4: "NUFFT_ERR_NONFINITE", 5: "NUFFT_ERR_HIP"}
 

@@ -2,12 +2,14 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "factors.h"
 #include "kernels.h"
 #include "plan.h"
 #include "kernels_2d.h"
+#include "batch.h"
 
 using namespace nufft;
 
@@ -514,6 +516,165 @@ static Args2D<R> args_2d(const Plan *p)
     a.prof = const_cast<Profiler *>(&p->prof);
     return a;
 }
+
+// ---- batches in one persistent launch ------------------------------------------
+
+template <typename R>
+static nufft_status batch_upload_ptrs(Plan *p, const void *const *cs, void *const *fs, hipStream_t s)
+{
+    const size_t B = p->children.size();
+    bool same = p->hcs.size() == B;
+    for (size_t b = 0; same && b < B; ++b) same = p->hcs[b] == cs[b] && p->hfs[b] == fs[b];
+    if (same) return NUFFT_OK;
+    p->hcs.assign(cs, cs + B);
+    p->hfs.assign(fs, fs + B);
+    NUFFT_HIP_CHECK(hipMemcpyAsync(p->bcs, p->hcs.data(), B * sizeof(void *), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(p->bfs, p->hfs.data(), B * sizeof(void *), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    return NUFFT_OK;
+}
+
+template <typename R>
+static hipError_t batch_run(const Plan *p, int grid, hipStream_t s)
+{
+    return batch_launch<R>((const BatchDesc<R> *)p->bdesc, (const int4 *)p->btasks, p->bntasks, (BatchCtl *)p->bctl,
+                           (const cx_t<R> *const *)p->bcs, (cx_t<R> *const *)p->bfs, grid, p->blds, s);
+}
+
+template <typename R>
+static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t *Ms, const double *const *xs,
+                                hipStream_t s)
+{
+    std::vector<BatchDesc<R>> desc(B);
+    std::vector<Factors<R>> facs(B);
+    size_t lds = 0;
+    int kmax = 0;
+    double gmax = 0;
+    for (int b = 0; b < B; ++b) {
+        Plan *c = new (std::nothrow) Plan();
+        if (!c) return NUFFT_ERR_ALLOC;
+        p->children.push_back(c);
+        c->kind = PLAN_1D;
+        c->dtype = p->dtype;
+        c->flags = p->flags & NUFFT_FLAG_FIX_GAMMA_HALF;
+        c->N = Ns[b];
+        c->M = Ms[b];
+        c->eps = p->eps;
+        if (!choose_grid(c->N, &c->L, &c->L1, &c->L2) || c->L > (int64_t(1) << 20)) return NUFFT_ERR_UNSUPPORTED;
+        nufft_status st = build_1d<R>(c, xs[b], s);
+        if (st) return st;
+        facs[b] = *(const Factors<R> *)c->factors();
+        BatchDesc<R> &d = desc[b];
+        d.N = c->N;
+        d.M = c->M;
+        d.L = c->L;
+        d.L1 = c->L1;
+        d.L2 = c->L2;
+        d.n_pass_a = c->L2 > 1 ? c->L1 / batch_pass_a_cols(c->L2) : 0;
+        d.t = c->t;
+        d.X = (const R *)c->X;
+        d.keys = c->keys;
+        d.perm = c->perm;
+        d.Xs = (const R *)c->Xs;
+        d.off = c->off;
+        d.Y = (cx_t<R> *)c->Y;
+        d.tw1 = (const cx_t<R> *)c->tw1;
+        d.tw2 = (const cx_t<R> *)c->tw2;
+        d.hi = (const cx_t<R> *)c->hi;
+        d.lo = (const cx_t<R> *)c->lo;
+        lds = std::max(lds, batch_lds_bytes((int)c->L, c->L1, c->L2, p->dtype == NUFFT_C64));
+        kmax = std::max(kmax, c->K);
+        gmax = std::max(gmax, c->gamma);
+    }
+    p->K = kmax;
+    p->gamma = gmax;
+    p->blds = lds;
+    // task table: phase 1 (whole small transforms, pass-A column groups), then pass-B tiles;
+    // members in decreasing order of grid size so that the long tasks start first
+    std::vector<int> order(B);
+    for (int b = 0; b < B; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return desc[a].L > desc[b].L; });
+    std::vector<int4> tk;
+    const int chunk = batch_small_chunk();
+    for (int b : order) {
+        if (desc[b].L2 == 1) {
+            for (int64_t j = 0; j < desc[b].M; j += chunk) tk.push_back(make_int4(BATCH_SMALL, b, (int)(j / chunk), 0));
+        } else {
+            for (int cg = 0; cg < desc[b].n_pass_a; ++cg) tk.push_back(make_int4(BATCH_PASS_A, b, cg, 0));
+        }
+    }
+    for (int b : order)
+        if (desc[b].L2 > 1)
+            for (int n2 = 0; n2 < desc[b].L2; ++n2) tk.push_back(make_int4(BATCH_PASS_B, b, n2, 0));
+    p->bntasks = (int)tk.size();
+    Factors<R> *dfac = (Factors<R> *)p->alloc(B * sizeof(Factors<R>));
+    p->bdesc = p->alloc(B * sizeof(BatchDesc<R>));
+    p->btasks = p->alloc(tk.size() * sizeof(int4));
+    const size_t ctl_bytes = sizeof(BatchCtl) + (size_t)B * sizeof(int);
+    p->bctl = p->alloc(ctl_bytes);
+    p->bcs = (void **)p->alloc(B * sizeof(void *));
+    p->bfs = (void **)p->alloc(B * sizeof(void *));
+    if (!dfac || !p->bdesc || !p->btasks || !p->bctl || !p->bcs || !p->bfs) return NUFFT_ERR_ALLOC;
+    for (int b = 0; b < B; ++b) desc[b].fac = dfac + b;
+    std::vector<char> ctl(ctl_bytes, 0);
+    ((BatchCtl *)ctl.data())->ntransforms = B;
+    NUFFT_HIP_CHECK(hipMemcpyAsync(dfac, facs.data(), B * sizeof(Factors<R>), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(p->bdesc, desc.data(), B * sizeof(BatchDesc<R>), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(p->btasks, tk.data(), tk.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(p->bctl, ctl.data(), ctl_bytes, hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    NUFFT_HIP_CHECK(batch_set_lds_limit<R>(lds));
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    p->bgrid = 2 * cus;
+    if (p->flags & NUFFT_FLAG_AUTOTUNE) {
+        // time the launch at 1..4 workgroups per CU on scratch inputs, keep the fastest
+        int64_t nc = 0, nf = 0;
+        for (int b = 0; b < B; ++b) {
+            nc += desc[b].N;
+            nf += desc[b].M;
+        }
+        Plan scratch;
+        cx_t<R> *cbuf = (cx_t<R> *)scratch.alloc(nc * sizeof(cx_t<R>));
+        cx_t<R> *fbuf = (cx_t<R> *)scratch.alloc(nf * sizeof(cx_t<R>));
+        if (!cbuf || !fbuf) return NUFFT_ERR_ALLOC;
+        NUFFT_HIP_CHECK(hipMemsetAsync(cbuf, 0, nc * sizeof(cx_t<R>), s));
+        std::vector<const void *> cp(B);
+        std::vector<void *> fp(B);
+        for (int b = 0, oc = 0, of = 0; b < B; ++b) {
+            cp[b] = cbuf + oc;
+            fp[b] = fbuf + of;
+            oc += (int)desc[b].N;
+            of += (int)desc[b].M;
+        }
+        nufft_status st = batch_upload_ptrs<R>(p, cp.data(), fp.data(), s);
+        if (st) return st;
+        hipEvent_t e0, e1;
+        NUFFT_HIP_CHECK(hipEventCreate(&e0));
+        NUFFT_HIP_CHECK(hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int wpc = 1; wpc <= 4; ++wpc) {
+            const int grid = wpc * cus;
+            NUFFT_HIP_CHECK(batch_run<R>(p, grid, s));   // warm-up
+            NUFFT_HIP_CHECK(hipEventRecord(e0, s));
+            for (int rep = 0; rep < 3; ++rep) NUFFT_HIP_CHECK(batch_run<R>(p, grid, s));
+            NUFFT_HIP_CHECK(hipEventRecord(e1, s));
+            NUFFT_HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0;
+            NUFFT_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                p->bgrid = grid;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        p->hcs.clear();   // scratch pointers: force the next exec to upload its own
+        p->hfs.clear();
+    }
+    return NUFFT_OK;
+}
 }  // namespace nufft
 
 // ============================================================================
@@ -662,6 +823,53 @@ nufft_status nufft2d_exec(nufft_plan_t plan, void *C, void *f, int adjoint, void
     return from_hip(e);
 }
 
+nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_modes, const int64_t *n_pts,
+                              const double *const *x_dev, double eps, nufft_dtype dtype, uint32_t flags,
+                              void *stream)
+{
+    if (!out) return NUFFT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (batch < 1 || !n_modes || !n_pts || !x_dev) return NUFFT_ERR_INVALID_ARG;
+    if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_AUTOTUNE)) return NUFFT_ERR_INVALID_ARG;
+    for (int b = 0; b < batch; ++b) {
+        if (n_modes[b] < 1 || n_pts[b] < 1 || !x_dev[b]) return NUFFT_ERR_INVALID_ARG;
+        if (n_modes[b] > (int64_t(1) << 20) || n_pts[b] > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
+    }
+    nufft_status st;
+    if (!eps_ok(eps, dtype, &st)) return st;
+    Plan *p = new (std::nothrow) Plan();
+    if (!p) return NUFFT_ERR_ALLOC;
+    p->kind = PLAN_BATCH;
+    p->dtype = dtype;
+    p->flags = flags;
+    p->eps = eps;
+    hipStream_t s = (hipStream_t)stream;
+    st = dtype == NUFFT_C64 ? build_batch<float>(p, batch, n_modes, n_pts, x_dev, s)
+                            : build_batch<double>(p, batch, n_modes, n_pts, x_dev, s);
+    if (st != NUFFT_OK) {
+        (void)hipStreamSynchronize(s);
+        delete p;
+        return st;
+    }
+    p->L = p->bgrid;
+    *out = p;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_batch_exec(nufft_plan_t plan, const void *const *c, void *const *f, void *stream)
+{
+    if (!plan || plan->kind != PLAN_BATCH || !c || !f) return NUFFT_ERR_INVALID_ARG;
+    for (size_t b = 0; b < plan->children.size(); ++b)
+        if (!c[b] || !f[b]) return NUFFT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    nufft_status st = plan->dtype == NUFFT_C64 ? batch_upload_ptrs<float>(plan, c, f, s)
+                                               : batch_upload_ptrs<double>(plan, c, f, s);
+    if (st) return st;
+    return from_hip(plan->dtype == NUFFT_C64 ? batch_run<float>(plan, plan->bgrid, s)
+                                             : batch_run<double>(plan, plan->bgrid, s));
+}
+
 nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *grid)
 {
     if (!plan) return NUFFT_ERR_INVALID_ARG;
@@ -771,16 +979,6 @@ extern "C" {
 
 
 
-nufft_status nufft_batch_plan(nufft_plan_t *out, int, const int64_t *, const int64_t *, const double *const *,
-                              double, nufft_dtype, uint32_t, void *)
-{
-    if (out) *out = nullptr;
-    return NUFFT_ERR_UNSUPPORTED;
-}
 
-nufft_status nufft_batch_exec(nufft_plan_t, const void *const *, void *const *, void *)
-{
-    return NUFFT_ERR_UNSUPPORTED;
-}
 
 }  // extern "C"

@@ -1,0 +1,310 @@
+// Batches of independent type-II transforms of uneven sizes in one persistent
+// launch (oversampled grids L_b >= N_b as in Sec. 2.3).
+//
+// A task table, built by the plan, lists for every transform b either
+//   SMALL tasks (L_b <= 4096: scale, all K FFTs in LDS and a slice of the
+//   samples, as the one-workgroup kernel does), or
+//   PASS_A tasks (a group of columns of the two-pass split) followed, after
+//   every phase-1 task of the batch, by PASS_B tasks (one output tile each).
+// Workgroups claim tasks in table order from an atomic counter.  A PASS_B
+// task waits until every PASS_A task of its transform has finished (counter
+// per transform, device-scope release/acquire).  Because all phase-1 tasks
+// precede all PASS_B tasks in the table and a phase-1 task never waits, every
+// wait ends: each unfinished PASS_A task the waiter depends on is already
+// held by a running workgroup.  The last workgroup to leave resets the
+// counters, so the launch can be replayed (HIP graph) without any memset.
+#include "batch.h"
+#include "fused_common.h"
+
+namespace nufft {
+
+#define BNT 256              // threads per workgroup of the persistent kernel
+#define BSLOTS 8             // sample slots per thread in SMALL tasks
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---- SMALL: whole transform in LDS, samples [chunk * BNT * BSLOTS, ...) -----------------
+template <typename R, int L>
+__device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx_t<R> *__restrict__ f, int chunk,
+                        char *lds)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L / 16;
+    constexpr int RC = BNT / TPF;
+    constexpr int P = fft_pitch(L);
+    C *buf = (C *)lds;
+    C *tw = buf + RC * P;
+    for (int m = threadIdx.x; m < L; m += BNT) tw[m] = d.tw1[m];
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)chunk * (BNT * BSLOTS);
+    const Factors<R> &fac = *d.fac;
+    const int K = fac.K;
+    int pos[BSLOTS];
+    R zz[BSLOTS];
+    C acc[BSLOTS];
+#pragma unroll
+    for (int s = 0; s < BSLOTS; ++s) {
+        const int64_t j = j0 + s * BNT + tid;
+        pos[s] = 0;
+        zz[s] = 0;
+        acc[s] = cmake<C>(0, 0);
+        if (j < d.M) {
+            pos[s] = d.t[j];
+            zz[s] = d.X[j] * fac.inv_gamma;
+        }
+    }
+    const int g = tid / TPF, lt = tid % TPF;
+    for (int r0 = 0; r0 < K; r0 += RC) {
+        const int r = r0 + g;
+        C v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t k = lt + q * TPF;
+            C w = cmake<C>(0, 0);
+            if (r < K && k < d.N) w = cscale(c[k], cheb_v<R>(r, zcoord<R>(k, d.N)));
+            v[q] = w;
+        }
+        __syncthreads();
+        block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
+        const int nr = min(RC, K - r0);
+#pragma unroll
+        for (int s = 0; s < BSLOTS; ++s)
+            for (int gg = 0; gg < nr; ++gg) {
+                const int rr = r0 + gg;
+                acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])], upoly(fac, rr, zz[s])), rr));
+            }
+    }
+#pragma unroll
+    for (int s = 0; s < BSLOTS; ++s) {
+        const int64_t j = j0 + s * BNT + tid;
+        if (j < d.M) {
+            R sn, cs;
+            sincospi_r(d.X[j], &sn, &cs);
+            f[j] = cmul(cmake<C>(cs, -sn), acc[s]);
+        }
+    }
+}
+
+// ---- PASS_A: G = 4096 / L2 adjacent columns, all K ranks -------------------------------
+template <typename R, int L2>
+__device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, int cg, char *lds)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L2 / 16;
+    constexpr int G = BNT / TPF;
+    constexpr int P = fft_pitch(L2);
+    C *buf = (C *)lds;
+    C *tw = buf + G * P;
+    for (int m = threadIdx.x; m < L2; m += BNT) tw[m] = d.tw2[m];
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t L1 = d.L1;
+    const int64_t k1_0 = (int64_t)cg * G;
+    const int64_t L = d.L;
+    const int K = d.fac->K;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * BNT;
+        const int gg = i % G, k2 = i / G;
+        const int64_t k = k1_0 + gg + L1 * (int64_t)k2;
+        buf[gg * P + lds_pad(k2)] = k < d.N ? c[k] : cmake<C>(0, 0);
+    }
+    __syncthreads();
+    C cv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cv[q] = buf[g * P + lds_pad(lt + q * TPF)];
+    for (int r = 0; r < K; ++r) {
+        C v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = cscale(cv[q], cheb_v<R>(r, zcoord<R>((k1_0 + g) + L1 * (int64_t)(lt + q * TPF), d.N)));
+        __syncthreads();
+        block_fft_regs<C, L2, -1>(buf + g * P, tw, lt, v);
+        C *Yr = d.Y + (int64_t)r * L + k1_0;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * BNT;
+            const int gg = i % G, n2 = i / G;
+            const C w = tw_big<C, -1>(d.hi, d.lo, (k1_0 + gg) * (int64_t)n2);
+            Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], w);
+        }
+    }
+    __syncthreads();   // LDS is reused by the next task
+}
+
+// ---- PASS_B: one tile n2, RC = 4096 / L1 ranks side by side ------------------------------
+template <typename R, int L1, int S>
+__device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2, char *lds)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L1 / 16;
+    constexpr int RC = BNT / TPF;
+    constexpr int P = fft_pitch(L1);
+    constexpr int CAP = BNT * S;
+    C *buf = (C *)lds;
+    C *tw = buf + RC * P;
+    for (int m = threadIdx.x; m < L1; m += BNT) tw[m] = d.tw1[m];
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t L = d.L;
+    const Factors<R> &fac = *d.fac;
+    const int K = fac.K;
+    const int64_t tile_lo = d.off[(int64_t)n2 * L1], tile_hi = d.off[(int64_t)(n2 + 1) * L1];
+    const C *Yrow = d.Y + (int64_t)n2 * L1 + lt;
+    for (int64_t c0 = tile_lo; c0 < tile_hi; c0 += CAP) {
+        int pos[S];
+        R zz[S];
+        C acc[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t i = c0 + s * BNT + tid;
+            pos[s] = 0;
+            zz[s] = 0;
+            acc[s] = cmake<C>(0, 0);
+            if (i < tile_hi) {
+                pos[s] = (int)(d.keys[i] & (uint32_t)(L1 - 1));
+                zz[s] = d.Xs[i] * fac.inv_gamma;
+            }
+        }
+        for (int r0 = 0; r0 < K; r0 += RC) {
+            const int r = r0 + g;
+            C v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = r < K ? Yrow[(int64_t)r * L + q * TPF] : cmake<C>(0, 0);
+            __syncthreads();
+            block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
+            const int nr = min(RC, K - r0);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                for (int gg = 0; gg < nr; ++gg) {
+                    const int rr = r0 + gg;
+                    acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])], upoly(fac, rr, zz[s])), rr));
+                }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t i = c0 + s * BNT + tid;
+            if (i < tile_hi) {
+                R sn, cs;
+                sincospi_r(d.Xs[i], &sn, &cs);
+                f[d.perm[i]] = cmul(cmake<C>(cs, -sn), acc[s]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BNT)
+k_batch(const BatchDesc<R> *__restrict__ descs, const int4 *__restrict__ tasks, int ntasks, BatchCtl *ctl,
+        const cx_t<R> *const *__restrict__ cs, cx_t<R> *const *__restrict__ fs, int64_t spin_limit)
+{
+    extern __shared__ __align__(16) char lds[];
+    __shared__ int s_task;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_task = atomicAdd(&ctl->next, 1);
+        __syncthreads();
+        const int t = uniform(s_task);
+        __syncthreads();   // s_task is rewritten only after everyone has read it
+        if (t >= ntasks) break;
+        const int4 tk = tasks[t];
+        const int type = uniform(tk.x), b = uniform(tk.y), par = uniform(tk.z);
+        const BatchDesc<R> &d = descs[b];
+        if (type == BATCH_PASS_B) {
+            if (tid == 0) {
+                int64_t it = 0;
+                while (__hip_atomic_load(&ctl->done_a[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < d.n_pass_a) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++it > spin_limit) {   // cannot happen by construction; never hang
+                        atomicOr(&ctl->error, 1);
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+            __threadfence();   // acquire: see the pass-A results of other workgroups
+        }
+        switch (type) {
+        case BATCH_SMALL:
+            switch (d.L) {
+#define BS(LL) case LL: b_small<R, LL>(d, cs[b], fs[b], par, lds); break;
+                BS(16) BS(32) BS(64) BS(128) BS(256) BS(512) BS(1024) BS(2048) BS(4096)
+#undef BS
+            default: break;
+            }
+            break;
+        case BATCH_PASS_A:
+            switch (d.L2) {
+#define BA(LL) case LL: b_passA<R, LL>(d, cs[b], par, lds); break;
+                BA(64) BA(128) BA(256) BA(512) BA(1024)
+#undef BA
+            default: break;
+            }
+            __threadfence();   // release the pass-A results
+            __syncthreads();
+            if (tid == 0) atomicAdd(&ctl->done_a[b], 1);
+            break;
+        default:
+            switch (d.L1) {
+#define BB(LL, SS) case LL: b_passB<R, LL, SS>(d, fs[b], par, lds); break;
+                BB(128, 1) BB(256, 2) BB(512, 3) BB(1024, 5)
+#undef BB
+            default: break;
+            }
+            break;
+        }
+        __syncthreads();
+    }
+    // the last workgroup out resets the queue for the next launch
+    if (tid == 0) {
+        __threadfence();
+        const int e = atomicAdd(&ctl->exited, 1);
+        if (e == (int)gridDim.x - 1) {
+            for (int i = 0; i < ctl->ntransforms; ++i) atomicExch(&ctl->done_a[i], 0);
+            atomicExch(&ctl->next, 0);
+            __threadfence();
+            atomicExch(&ctl->exited, 0);
+        }
+    }
+}
+
+size_t batch_lds_bytes(int L, int L1, int L2, bool fp32)
+{
+    const size_t es = fp32 ? 8 : 16;
+    if (L2 == 1) {
+        const int tpf = L / 16, rc = BNT / tpf;
+        return es * ((size_t)rc * fft_pitch(L) + L);
+    }
+    const size_t a = es * ((size_t)(BNT / (L2 / 16)) * fft_pitch(L2) + L2);
+    const size_t b = es * ((size_t)(BNT / (L1 / 16)) * fft_pitch(L1) + L1);
+    return a > b ? a : b;
+}
+
+int batch_threads() { return BNT; }
+int batch_small_chunk() { return BNT * BSLOTS; }
+int batch_pass_a_cols(int L2) { return BNT / (L2 / 16); }
+
+template <typename R>
+hipError_t batch_launch(const BatchDesc<R> *descs, const int4 *tasks, int ntasks, BatchCtl *ctl,
+                        const cx_t<R> *const *cs, cx_t<R> *const *fs, int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch<R>, dim3(grid), dim3(BNT), lds, s, descs, tasks, ntasks, ctl, cs, fs,
+                       (int64_t)1 << 28);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t batch_set_lds_limit(size_t lds)
+{
+    return hipFuncSetAttribute((const void *)k_batch<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template hipError_t batch_launch<float>(const BatchDesc<float> *, const int4 *, int, BatchCtl *,
+                                        const float2 *const *, float2 *const *, int, size_t, hipStream_t);
+template hipError_t batch_launch<double>(const BatchDesc<double> *, const int4 *, int, BatchCtl *,
+                                         const double2 *const *, double2 *const *, int, size_t, hipStream_t);
+template hipError_t batch_set_lds_limit<float>(size_t);
+template hipError_t batch_set_lds_limit<double>(size_t);
+
+}  // namespace nufft

@@ -54,6 +54,14 @@ struct nufft_plan_s {
     int ntasks = 0;
     void *twx = nullptr, *twxi = nullptr, *twy = nullptr, *twyi = nullptr;
 
+    // batch plans: member plans are the children
+    void *bdesc = nullptr, *bfac = nullptr, *btasks = nullptr, *bctl = nullptr;
+    void **bcs = nullptr, **bfs = nullptr;          // device arrays of member pointers
+    std::vector<const void *> hcs;                   // last uploaded pointers
+    std::vector<void *> hfs;
+    int bntasks = 0, bgrid = 0;
+    size_t blds = 0;
+
     Profiler prof;
 
     std::vector<void *> blocks;
