@@ -104,6 +104,70 @@ def cpu_baseline(x, c, N, seconds):
     }
 
 
+def bench_batch(P, W, torch, dev):
+    """512 type-II transforms, N_b = round(2^U(8,16)), eps 1e-6 FP32: one persistent launch
+    (eager and replayed from a HIP graph) against 512 separate launches."""
+    Ns, xs_np, cs_np = W.batch_case(4)
+    Ns = [int(n) for n in Ns]
+    xs = [torch.from_numpy(x).to(dev) for x in xs_np]
+    cs = [torch.from_numpy(c).to(torch.complex64).to(dev) for c in cs_np]
+    fs = [torch.empty(n, dtype=torch.complex64, device=dev) for n in Ns]
+    pts = sum(Ns)
+    t0 = time.perf_counter()
+    plan = P.nufft_batch_plan(Ns, xs, 1e-6, torch.complex64, P.NUFFT_FLAG_AUTOTUNE)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    t_batch = time_loop(lambda: P.nufft_batch_exec(plan, cs, fs), 20, 3, torch)
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            P.nufft_batch_exec(plan, cs, fs)
+    t_graph = time_loop(lambda: g.replay(), 20, 3, torch)
+    singles = [P.nufft2_plan(x, n, 1e-6, torch.complex64) for x, n in zip(xs, Ns)]
+
+    def run_singles():
+        for pl, c, f in zip(singles, cs, fs):
+            P.nufft2_exec(pl, c, f)
+    t_sep = time_loop(run_singles, 5, 1, torch)
+    del singles
+    plains = [P.nufft2_plan(x, n, 1e-6, torch.complex64, P.NUFFT_FLAG_PLAIN) for x, n in zip(xs, Ns)]
+
+    def run_plains():
+        for pl, c, f in zip(plains, cs, fs):
+            P.nufft2_exec(pl, c, f)
+    t_plain = time_loop(run_plains, 5, 1, torch)
+    del plains
+    return {"members": len(Ns), "points": pts, "K_max": plan.K, "persistent_grid": plan.grid,
+            "plan_s": round(plan_s, 2),
+            "persistent_us": round(t_batch * 1e3, 1), "persistent_pts_per_s": pts / (t_batch * 1e-3),
+            "graph_replay_us": round(t_graph * 1e3, 1),
+            "separate_fused_launches_us": round(t_sep * 1e3, 1),
+            "separate_plain_launches_us": round(t_plain * 1e3, 1),
+            "speedup_vs_separate_plain": round(t_plain / t_graph, 2)}
+
+
+def bench_2d(P, W, torch, dev):
+    """2-D type II and adjoint, 1024 x 1024 coefficients, 2^20 polar samples, eps 1e-6 FP32."""
+    x, y, C = W.polar_case(5)
+    xt, yt = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    Ct = torch.from_numpy(C.ravel()).to(torch.complex64).to(dev)
+    f = torch.empty(x.shape[0], dtype=torch.complex64, device=dev)
+    Co = torch.empty_like(Ct)
+    plan = P.nufft2d_plan(xt, yt, 1024, 1024, 1e-6, torch.complex64)
+    t_f = time_loop(lambda: P.nufft2d_exec(plan, Ct, f, 0), 10, 2, torch)
+    t_a = time_loop(lambda: P.nufft2d_exec(plan, Co, f, 1), 10, 2, torch)
+    P.nufft_plan_profile(plan, 1, reserve=64)
+    for _ in range(5):
+        P.nufft2d_exec(plan, Ct, f, 0)
+        P.nufft2d_exec(plan, Co, f, 1)
+    torch.cuda.synchronize()
+    kern = {k: round(ms / n * 1e3, 1) for k, (n, ms) in P.nufft_plan_profile_read(plan).items()}
+    P.nufft_plan_profile(plan, 0)
+    return {"Kx": plan.K, "forward_us": round(t_f * 1e3, 1), "adjoint_us": round(t_a * 1e3, 1),
+            "forward_pts_per_s": x.shape[0] / (t_f * 1e-3), "kernels_avg_us": kern}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +295,10 @@ def main():
         sec["speedup_fused_fp32_vs_plain_fp64_same_eps"] = round(
             sec["plain_fp64_eps1e-6"]["us"] / sec["fused_fp32_eps1e-6"]["us"], 2)
         out["forward_2p20"] = sec
+
+    if not args.no_secondary:
+        out["batch_512"] = bench_batch(P, W, torch, dev)
+        out["polar_2d"] = bench_2d(P, W, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, c_np, N, args.cpu_seconds)

@@ -68,11 +68,13 @@ __device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx
         block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
         const int nr = min(RC, K - r0);
 #pragma unroll
-        for (int s = 0; s < BSLOTS; ++s)
+        for (int s = 0; s < BSLOTS; ++s) {
+            if (j0 + s * BNT >= d.M) break;
             for (int gg = 0; gg < nr; ++gg) {
                 const int rr = r0 + gg;
                 acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])], upoly(fac, rr, zz[s])), rr));
             }
+        }
     }
 #pragma unroll
     for (int s = 0; s < BSLOTS; ++s) {
@@ -92,7 +94,7 @@ __device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, in
     using C = cx_t<R>;
     constexpr int TPF = L2 / 16;
     constexpr int G = BNT / TPF;
-    constexpr int P = fft_pitch(L2);
+    constexpr int P = fft_pitch_g(L2, G);
     C *buf = (C *)lds;
     C *tw = buf + G * P;
     for (int m = threadIdx.x; m < L2; m += BNT) tw[m] = d.tw2[m];
@@ -175,11 +177,13 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2, 
             block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
             const int nr = min(RC, K - r0);
 #pragma unroll
-            for (int s = 0; s < S; ++s)
+            for (int s = 0; s < S; ++s) {
+                if (c0 + s * BNT >= tile_hi) break;
                 for (int gg = 0; gg < nr; ++gg) {
                     const int rr = r0 + gg;
                     acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])], upoly(fac, rr, zz[s])), rr));
                 }
+            }
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -276,7 +280,7 @@ size_t batch_lds_bytes(int L, int L1, int L2, bool fp32)
         const int tpf = L / 16, rc = BNT / tpf;
         return es * ((size_t)rc * fft_pitch(L) + L);
     }
-    const size_t a = es * ((size_t)(BNT / (L2 / 16)) * fft_pitch(L2) + L2);
+    const size_t a = es * ((size_t)(BNT / (L2 / 16)) * fft_pitch_g(L2, BNT / (L2 / 16)) + L2);
     const size_t b = es * ((size_t)(BNT / (L1 / 16)) * fft_pitch(L1) + L1);
     return a > b ? a : b;
 }

@@ -23,7 +23,34 @@
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int fft_pitch(int L) { return L + L / 16 + 1; }
 
+// Pitch for G transforms that are also accessed across transforms (lane order:
+// transform index fastest, then element).  With P = 32/G (mod 32) float2
+// slots, the G transforms x 32/G consecutive elements touched by 32 lanes
+// fall into 32 distinct bank pairs.
+__host__ __device__ constexpr int fft_pitch_g(int L, int G)
+{
+    const int target = G >= 32 ? 1 : 32 / G;
+    int p = L + L / 16;
+    while (p % 32 != target % 32) ++p;
+    return p;
+}
+
 namespace fftk {
+
+// Ordering between the read and write phases of a stage.  WS (wave sync): the
+// transform's threads all belong to one wavefront and no other wave touches
+// its buffer, so LDS ordering inside the wave suffices (no workgroup barrier).
+template <bool WS>
+__device__ __forceinline__ void stage_sync()
+{
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
 
 template <typename C, int DIR>
 __device__ __forceinline__ C mul_w4(C a)   // a * exp(DIR 2 pi i / 4) = a * (DIR i)
@@ -125,7 +152,7 @@ __device__ __forceinline__ void dft(C *v)
 // of the 16/R butterflies b = lt + i*(L/16) this thread owns, the R inputs
 // x[b + q*L/R].  Applies the stage twiddles, the radix-R DFT, and writes the
 // outputs to LDS in auto-sorted order.
-template <typename C, int L, int DIR, int NS, int R>
+template <typename C, int L, int DIR, int NS, int R, bool WS>
 __device__ __forceinline__ void stage_compute_store(C *buf, const C *tw, int lt, C *v)
 {
     constexpr int BPT = 16 / R;
@@ -140,7 +167,7 @@ __device__ __forceinline__ void stage_compute_store(C *buf, const C *tw, int lt,
         }
         dft<R, C, DIR>(v + i * R);
     }
-    __syncthreads();   // every thread has read its inputs of this stage
+    stage_sync<WS>();   // every thread has read its inputs of this stage
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
         const int b = lt + i * (L / 16);
@@ -148,10 +175,10 @@ __device__ __forceinline__ void stage_compute_store(C *buf, const C *tw, int lt,
 #pragma unroll
         for (int q = 0; q < R; ++q) buf[lds_pad(base + q * NS)] = v[i * R + q];
     }
-    __syncthreads();
+    stage_sync<WS>();
 }
 
-template <typename C, int L, int DIR, int NS>
+template <typename C, int L, int DIR, int NS, bool WS>
 __device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt)
 {
     if constexpr (NS < L) {
@@ -164,8 +191,8 @@ __device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt)
 #pragma unroll
             for (int q = 0; q < R; ++q) v[i * R + q] = buf[lds_pad(b + q * (L / R))];
         }
-        stage_compute_store<C, L, DIR, NS, R>(buf, tw, lt, v);
-        stages_from<C, L, DIR, NS * R>(buf, tw, lt);
+        stage_compute_store<C, L, DIR, NS, R, WS>(buf, tw, lt, v);
+        stages_from<C, L, DIR, NS * R, WS>(buf, tw, lt);
     }
 }
 
@@ -174,26 +201,28 @@ __device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt)
 // Full transform whose input is already in LDS (natural order, padded).
 // Result: natural order in the same buffer.  Called by all threads of the
 // workgroup; lt in [0, L/16) is this thread's lane within the transform.
-template <typename C, int L, int DIR>
+template <typename C, int L, int DIR, bool WS = false>
 __device__ __forceinline__ void block_fft_lds(C *buf, const C *tw, int lt)
 {
     static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "unsupported FFT length");
-    fftk::stages_from<C, L, DIR, 1>(buf, tw, lt);
+    static_assert(!WS || L <= 1024, "a wave-synchronous transform must fit one wavefront");
+    fftk::stages_from<C, L, DIR, 1, WS>(buf, tw, lt);
 }
 
 // Full transform whose input is in registers: v[q] = x[lt + q*L/16], q < 16
 // (exactly the operands of the first radix-16 stage, so that stage skips the
 // LDS round trip).  The caller must have finished every earlier read of buf
 // (a __syncthreads() since the last use).  Result: natural order in buf.
-template <typename C, int L, int DIR>
+template <typename C, int L, int DIR, bool WS = false>
 __device__ __forceinline__ void block_fft_regs(C *buf, const C *tw, int lt, C *v)
 {
     static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "unsupported FFT length");
+    static_assert(!WS || L <= 1024, "a wave-synchronous transform must fit one wavefront");
     // first stage: NS = 1, R = 16, one butterfly per thread, no twiddles
     fftk::dft<16, C, DIR>(v);
     const int base = lt * 16;
 #pragma unroll
     for (int q = 0; q < 16; ++q) buf[lds_pad(base + q)] = v[q];
-    __syncthreads();
-    fftk::stages_from<C, L, DIR, 16>(buf, tw, lt);
+    fftk::stage_sync<WS>();
+    fftk::stages_from<C, L, DIR, 16, WS>(buf, tw, lt);
 }

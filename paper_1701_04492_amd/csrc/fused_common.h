@@ -71,4 +71,89 @@ __device__ __forceinline__ int xcd_task(int T)
 
 static inline unsigned xcd_grid(int T) { return (unsigned)(8 * ((T + 7) / 8)); }
 
+
+// Deterministic segmented sum of per-sample contributions into RC grids in LDS.
+// The cnt samples of a tile are sorted by grid point; thread t takes the
+// balanced slice [t*cnt/NT, (t+1)*cnt/NT), sums contrib(i, gg) over runs of
+// equal grid point and stores every run that starts and ends inside its slice
+// straight into grid gg.  A run that crosses a slice boundary leaves one
+// partial per thread in head/tail slots; the thread in whose slice the run
+// starts adds the partials of the following threads in thread order.  The
+// result does not depend on timing, and one heavily populated grid point is
+// spread over many threads instead of being walked by one.
+// Grids must be zero on entry where no sample falls; the caller synchronises
+// before reading them.  Scratch: hv, tv (RC*NT values), hi, ti (NT ints).
+template <typename C, int RC, int NT, typename PosF, typename ContribF>
+__device__ __forceinline__ void seg_spread(int cnt, int nr, PosF pos, ContribF contrib, C *grid, int pitch,
+                                           C *hv, C *tv, int *hix, int *tix)
+{
+    const int tid = threadIdx.x;
+    const int i0 = (int)(((int64_t)tid * cnt) / NT), i1 = (int)(((int64_t)(tid + 1) * cnt) / NT);
+    C a[RC];
+#pragma unroll
+    for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+    int ncur = -1, nfirst = -1;
+    for (int i = i0; i < i1; ++i) {
+        const int n = pos(i);
+        if (n != ncur) {
+            if (ncur >= 0) {
+                if (ncur == nfirst) {
+#pragma unroll
+                    for (int gg = 0; gg < RC; ++gg) hv[gg * NT + tid] = a[gg];
+                } else {
+#pragma unroll
+                    for (int gg = 0; gg < RC; ++gg)
+                        if (gg < nr) grid[gg * pitch + lds_pad(ncur)] = a[gg];
+                }
+            } else {
+                nfirst = n;
+            }
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+            ncur = n;
+        }
+#pragma unroll
+        for (int gg = 0; gg < RC; ++gg)
+            if (gg < nr) a[gg] = cadd(a[gg], contrib(i, gg));
+    }
+    // the last run of the slice (possibly also its first)
+    if (ncur >= 0) {
+        if (ncur == nfirst) {
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg) hv[gg * NT + tid] = a[gg];
+        }
+#pragma unroll
+        for (int gg = 0; gg < RC; ++gg) tv[gg * NT + tid] = a[gg];
+    }
+    hix[tid] = nfirst;   // -1 for an empty slice
+    tix[tid] = ncur;
+    __syncthreads();
+    // runs crossing into later slices: owned by the slice where they start
+    if (nfirst >= 0) {
+        const bool head_starts_here = (i0 == 0) || pos(i0 - 1) != nfirst;
+        // the first run: complete here unless it is also the last run (then handled below)
+        if (head_starts_here && nfirst != ncur) {
+            // the first run ended inside this slice: it is complete
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg)
+                if (gg < nr) grid[gg * pitch + lds_pad(nfirst)] = hv[gg * NT + tid];
+        }
+        const bool last_starts_here = (nfirst != ncur) || head_starts_here;
+        if (last_starts_here) {
+            C sum[RC];
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg) sum[gg] = tv[gg * NT + tid];
+            for (int u = tid + 1; u < NT; ++u) {
+                if (hix[u] < 0) continue;               // empty slice
+                if (hix[u] != ncur) break;
+#pragma unroll
+                for (int gg = 0; gg < RC; ++gg) sum[gg] = cadd(sum[gg], hv[gg * NT + u]);
+                if (tix[u] != ncur) break;               // the run ends inside slice u
+            }
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg)
+                if (gg < nr) grid[gg * pitch + lds_pad(ncur)] = sum[gg];
+        }
+    }
+}
 }  // namespace nufft

@@ -77,6 +77,7 @@ k_small_fwd(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, const int32_t *
         const int nr = min(RC, fac.K - r0);
 #pragma unroll
         for (int s = 0; s < SMALL_SLOTS; ++s) {
+            if (j0 + s * SMALL_NT >= M) break;   // no lane has a sample in this slot or later
             for (int gg = 0; gg < nr; ++gg) {
                 const int rr = r0 + gg;
                 const C xv = buf[gg * P + lds_pad(pos[s])];
@@ -203,7 +204,7 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     using C = cx_t<R>;
     constexpr int TPF = L2 / 16;
     constexpr int NT = G * TPF;
-    constexpr int P = fft_pitch(L2);
+    constexpr int P = fft_pitch_g(L2, G);
     __shared__ C buf[G * P];
     __shared__ C tw_s[TWG ? 1 : L2];
     const C *tw = TWG ? tw_g : tw_s;
@@ -310,6 +311,7 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             const int nr = min(RC, fac.K - r0);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
+                if (c0 + s * NT >= tile_hi) break;   // no lane has a sample in this slot or later
                 for (int gg = 0; gg < nr; ++gg) {
                     const int rr = r0 + gg;
                     const C xv = buf[gg * P + lds_pad(pos[s])];
@@ -465,7 +467,7 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
     using C = cx_t<R>;
     constexpr int TPF = L2 / 16;
     constexpr int NT = G * TPF;
-    constexpr int P = fft_pitch(L2);
+    constexpr int P = fft_pitch_g(L2, G);
     __shared__ C buf[G * P];
     __shared__ C tw_s[TWG ? 1 : L2];
     const C *tw = TWG ? tw_g : tw_s;   // tw_g already has sign DIR

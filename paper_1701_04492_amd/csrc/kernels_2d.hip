@@ -26,7 +26,7 @@ k_2d_passA(const cx_t<R> *__restrict__ Cin, int64_t N1, int64_t N2, int64_t GX, 
     using C = cx_t<R>;
     constexpr int TPF = GY / 16;
     constexpr int NT = G * TPF;
-    constexpr int P = fft_pitch(GY);
+    constexpr int P = fft_pitch_g(GY, G);
     __shared__ C buf[G * P];
     __shared__ C tw[GY];
     const int K = fy.K;
@@ -113,7 +113,8 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
             cv[q] = k1 < N1 ? Hrow[k1] : cmake<C>(0, 0);
         }
 #pragma unroll
-        for (int s = 0; s < S; ++s) py[s] = upoly(fy, r2, zy[s]);
+        for (int s = 0; s < S; ++s)
+            if (i_lo + s * NT < i_hi) py[s] = upoly(fy, r2, zy[s]);
         for (int r0 = 0; r0 < fx.K; r0 += RC) {
             const int r1 = r0 + g;
             C v[16];
@@ -124,6 +125,7 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
             const int nr = min(RC, fx.K - r0);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
+                if (i_lo + s * NT >= i_hi) break;   // no lane has a sample in this slot or later
                 for (int gg = 0; gg < nr; ++gg) {
                     const int rr = r0 + gg;
                     const C xv = buf[gg * P + lds_pad(pos[s])];
@@ -159,7 +161,6 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     using C = cx_t<R>;
     constexpr int TPF = GX / 16;
     constexpr int NT = RC * TPF;
-    constexpr int GPT = GX / NT;
     constexpr int ZA = GX / NT;           // output positions per thread
     constexpr int P = fft_pitch(GX);
     __shared__ C buf[RC * P];
@@ -167,7 +168,8 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     __shared__ C sval[SCAP];
     __shared__ R szx[SCAP], spy[SCAP];
     __shared__ unsigned short spos[SCAP];
-    __shared__ int soff[GX + 1];
+    __shared__ C hv[RC * NT], tv[RC * NT];
+    __shared__ int hix[NT], tix[NT];
     const C *tw = TWG ? twi_g : tw_s;
     const int task = xcd_task((int)GY);
     if (task < 0) return;
@@ -177,7 +179,6 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t n2 = task;
     const int tile_lo = off[n2 * GX];
-    for (int m = tid; m <= GX; m += NT) soff[m] = off[n2 * GX + m] - tile_lo;
     const int cnt = off[(n2 + 1) * GX] - tile_lo;
     const int nst = min(cnt, SCAP);
     for (int i = tid; i < nst; i += NT) {
@@ -188,7 +189,6 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
         szx[i] = ax * fx.inv_gamma;
         spos[i] = (unsigned short)(keys[tile_lo + i] & (uint32_t)(GX - 1));
     }
-    const int n_lo = tid * GPT;
     for (int r2 = 0; r2 < fy.K; ++r2) {
         for (int i = tid; i < nst; i += NT) spy[i] = upoly(fy, r2, Xys[tile_lo + i] * fy.inv_gamma);
         __syncthreads();
@@ -197,52 +197,22 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
         for (int m = 0; m < ZA; ++m) za[m] = cmake<C>(0, 0);
         for (int r0 = 0; r0 < fx.K; r0 += RC) {
             const int nr = min(RC, fx.K - r0);
-#pragma unroll
-            for (int gg = 0; gg < RC; ++gg)
-#pragma unroll
-                for (int q = 0; q < GPT; ++q) buf[gg * P + lds_pad(n_lo + q)] = cmake<C>(0, 0);
-            const int i0 = soff[n_lo], i1 = soff[n_lo + GPT];
-            C a[RC];
-#pragma unroll
-            for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
-            int ncur = -1;
-            for (int i = i0; i < i1; ++i) {
-                C val;
-                R zxv, pyv;
-                int n1;
-                if (i < SCAP) {
-                    val = sval[i];
-                    zxv = szx[i];
-                    pyv = spy[i];
-                    n1 = spos[i];
-                } else {
-                    const R ax = Xxs[tile_lo + i], ay = Xys[tile_lo + i];
-                    R sn, cs;
-                    sincospi_r(ax + ay, &sn, &cs);
-                    val = cmul(cmake<C>(cs, sn), gin[perm[tile_lo + i]]);
-                    zxv = ax * fx.inv_gamma;
-                    pyv = upoly(fy, r2, ay * fy.inv_gamma);
-                    n1 = (int)(keys[tile_lo + i] & (uint32_t)(GX - 1));
-                }
-                if (n1 != ncur) {
-                    if (ncur >= 0) {
-#pragma unroll
-                        for (int gg = 0; gg < RC; ++gg)
-                            if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -(r0 + gg + r2));
-                    }
-#pragma unroll
-                    for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
-                    ncur = n1;
-                }
-#pragma unroll
-                for (int gg = 0; gg < RC; ++gg)
-                    if (gg < nr) a[gg] = cadd(a[gg], cscale(val, upoly(fx, r0 + gg, zxv) * pyv));
-            }
-            if (ncur >= 0) {
-#pragma unroll
-                for (int gg = 0; gg < RC; ++gg)
-                    if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -(r0 + gg + r2));
-            }
+            for (int m = tid; m < RC * P; m += NT) buf[m] = cmake<C>(0, 0);
+            __syncthreads();
+            auto pos = [&](int i) -> int {
+                return i < SCAP ? (int)spos[i] : (int)(keys[tile_lo + i] & (uint32_t)(GX - 1));
+            };
+            auto contrib = [&](int i, int gg) -> C {
+                const int r1 = r0 + gg;
+                if (i < SCAP) return crot(cscale(sval[i], upoly(fx, r1, szx[i]) * spy[i]), -(r1 + r2));
+                const R ax = Xxs[tile_lo + i], ay = Xys[tile_lo + i];
+                R sn, cs;
+                sincospi_r(ax + ay, &sn, &cs);
+                const C val = cmul(cmake<C>(cs, sn), gin[perm[tile_lo + i]]);
+                return crot(cscale(val, upoly(fx, r1, ax * fx.inv_gamma) * upoly(fy, r2, ay * fy.inv_gamma)),
+                            -(r1 + r2));
+            };
+            seg_spread<C, RC, NT>(cnt, nr, pos, contrib, buf, P, hv, tv, hix, tix);
             __syncthreads();
             block_fft_lds<C, GX, 1>(buf + g * P, tw, lt);
 #pragma unroll
@@ -269,7 +239,7 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
     using C = cx_t<R>;
     constexpr int TPF = GY / 16;
     constexpr int NT = G * TPF;
-    constexpr int P = fft_pitch(GY);
+    constexpr int P = fft_pitch_g(GY, G);
     __shared__ C buf[G * P];
     __shared__ C tw[GY];
     const int ncg = (int)((N1 + G - 1) / G);

@@ -106,7 +106,7 @@ k_fft_cols(cx_t<R> *__restrict__ data, int64_t L1, const cx_t<R> *__restrict__ t
 {
     using C = cx_t<R>;
     constexpr int NT = G * L2 / 16;
-    constexpr int P = fft_pitch(L2);
+    constexpr int P = fft_pitch_g(L2, G);
     __shared__ C buf[G * P];
     __shared__ C tw[L2];
     const int64_t b = blockIdx.y;
