@@ -34,45 +34,41 @@ __device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx
     constexpr int P = fft_pitch(L);
     C *buf = (C *)lds;
     C *tw = buf + RC * P;
-    for (int m = threadIdx.x; m < L; m += BNT) tw[m] = d.tw1[m];
+    load_tw_s<C, L, -1, BNT>(tw, d.tw1);
     const int tid = threadIdx.x;
     const int64_t j0 = (int64_t)chunk * (BNT * BSLOTS);
     const Factors<R> &fac = *d.fac;
     const int K = fac.K;
     int pos[BSLOTS];
-    R zz[BSLOTS];
+    R xs[BSLOTS];
     C acc[BSLOTS];
 #pragma unroll
     for (int s = 0; s < BSLOTS; ++s) {
-        const int64_t j = j0 + s * BNT + tid;
-        pos[s] = 0;
-        zz[s] = 0;
+        const int64_t j = min(j0 + s * BNT + tid, d.M - 1);   // clamped: loads issued together
+        pos[s] = d.t[j];
+        xs[s] = d.X[j];
         acc[s] = cmake<C>(0, 0);
-        if (j < d.M) {
-            pos[s] = d.t[j];
-            zz[s] = d.X[j] * fac.inv_gamma;
-        }
     }
     const int g = tid / TPF, lt = tid % TPF;
+    const ZMap zm = zmap(d.N);
     for (int r0 = 0; r0 < K; r0 += RC) {
         const int r = r0 + g;
         C v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int64_t k = lt + q * TPF;
-            C w = cmake<C>(0, 0);
-            if (r < K && k < d.N) w = cscale(c[k], cheb_v<R>(r, zcoord<R>(k, d.N)));
-            v[q] = w;
-        }
+        for (int q = 0; q < 16; ++q) v[q] = load_coef<R>(c, lt + q * TPF, d.N, 0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = r < K ? cscale(v[q], cheb_v<R>(r, zcoord<R>(lt + q * TPF, zm))) : cmake<C>(0, 0);
         __syncthreads();
         block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
         const int nr = min(RC, K - r0);
 #pragma unroll
         for (int s = 0; s < BSLOTS; ++s) {
             if (j0 + s * BNT >= d.M) break;
+            const R z = xs[s] * fac.inv_gamma;
             for (int gg = 0; gg < nr; ++gg) {
                 const int rr = r0 + gg;
-                acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])], upoly(fac, rr, zz[s])), rr));
+                acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])], upoly(fac, rr, z)), rr));
             }
         }
     }
@@ -81,7 +77,7 @@ __device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx
         const int64_t j = j0 + s * BNT + tid;
         if (j < d.M) {
             R sn, cs;
-            sincospi_r(d.X[j], &sn, &cs);
+            sincospi_r(xs[s], &sn, &cs);
             f[j] = cmul(cmake<C>(cs, -sn), acc[s]);
         }
     }
@@ -97,29 +93,36 @@ __device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, in
     constexpr int P = fft_pitch_g(L2, G);
     C *buf = (C *)lds;
     C *tw = buf + G * P;
-    for (int m = threadIdx.x; m < L2; m += BNT) tw[m] = d.tw2[m];
+    load_tw_s<C, L2, -1, BNT>(tw, d.tw2);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t L1 = d.L1;
     const int64_t k1_0 = (int64_t)cg * G;
     const int64_t L = d.L;
     const int K = d.fac->K;
+    {
+        C cl[16];   // all loads in flight before the first LDS store
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int i = tid + e * BNT;
-        const int gg = i % G, k2 = i / G;
-        const int64_t k = k1_0 + gg + L1 * (int64_t)k2;
-        buf[gg * P + lds_pad(k2)] = k < d.N ? c[k] : cmake<C>(0, 0);
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * BNT;
+            cl[e] = load_coef<R>(c, k1_0 + i % G + L1 * (int64_t)(i / G), d.N, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * BNT;
+            buf[(i % G) * P + lds_pad(i / G)] = cl[e];
+        }
     }
     __syncthreads();
     C cv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) cv[q] = buf[g * P + lds_pad(lt + q * TPF)];
+    const ZMap zm = zmap(d.N);
     for (int r = 0; r < K; ++r) {
         C v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q)
-            v[q] = cscale(cv[q], cheb_v<R>(r, zcoord<R>((k1_0 + g) + L1 * (int64_t)(lt + q * TPF), d.N)));
+            v[q] = cscale(cv[q], cheb_v<R>(r, zcoord<R>((k1_0 + g) + L1 * (int64_t)(lt + q * TPF), zm)));
         __syncthreads();
         block_fft_regs<C, L2, -1>(buf + g * P, tw, lt, v);
         C *Yr = d.Y + (int64_t)r * L + k1_0;
@@ -145,7 +148,7 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2, 
     constexpr int CAP = BNT * S;
     C *buf = (C *)lds;
     C *tw = buf + RC * P;
-    for (int m = threadIdx.x; m < L1; m += BNT) tw[m] = d.tw1[m];
+    load_tw_s<C, L1, -1, BNT>(tw, d.tw1);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t L = d.L;
@@ -154,44 +157,51 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2, 
     const int64_t tile_lo = d.off[(int64_t)n2 * L1], tile_hi = d.off[(int64_t)(n2 + 1) * L1];
     const C *Yrow = d.Y + (int64_t)n2 * L1 + lt;
     for (int64_t c0 = tile_lo; c0 < tile_hi; c0 += CAP) {
-        int pos[S];
-        R zz[S];
-        C acc[S];
+        uint32_t kv[S];
+        R xs[S];
+        int32_t jv[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int64_t i = c0 + s * BNT + tid;
-            pos[s] = 0;
-            zz[s] = 0;
-            acc[s] = cmake<C>(0, 0);
-            if (i < tile_hi) {
-                pos[s] = (int)(d.keys[i] & (uint32_t)(L1 - 1));
-                zz[s] = d.Xs[i] * fac.inv_gamma;
-            }
+            const int64_t i = min(c0 + s * BNT + tid, tile_hi - 1);   // clamped: loads issued together
+            kv[s] = d.keys[i];
+            xs[s] = d.Xs[i];
+            jv[s] = d.perm[i];
         }
+        C vn[16];   // rows of the next rank chunk, loaded while this one is used
+#pragma unroll
+        for (int q = 0; q < 16; ++q) vn[q] = g < K ? Yrow[(int64_t)g * L + q * TPF] : cmake<C>(0, 0);
+        C acc[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] = cmake<C>(0, 0);
         for (int r0 = 0; r0 < K; r0 += RC) {
-            const int r = r0 + g;
             C v[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = r < K ? Yrow[(int64_t)r * L + q * TPF] : cmake<C>(0, 0);
+            for (int q = 0; q < 16; ++q) v[q] = vn[q];
+            const int rn = r0 + RC + g;
+            if (r0 + RC < K) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) vn[q] = rn < K ? Yrow[(int64_t)rn * L + q * TPF] : cmake<C>(0, 0);
+            }
             __syncthreads();
             block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
             const int nr = min(RC, K - r0);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 if (c0 + s * BNT >= tile_hi) break;
+                const int pos = (int)(kv[s] & (uint32_t)(L1 - 1));
+                const R z = xs[s] * fac.inv_gamma;
                 for (int gg = 0; gg < nr; ++gg) {
                     const int rr = r0 + gg;
-                    acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])], upoly(fac, rr, zz[s])), rr));
+                    acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos)], upoly(fac, rr, z)), rr));
                 }
             }
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int64_t i = c0 + s * BNT + tid;
-            if (i < tile_hi) {
+            if (c0 + s * BNT + tid < tile_hi) {
                 R sn, cs;
-                sincospi_r(d.Xs[i], &sn, &cs);
-                f[d.perm[i]] = cmul(cmake<C>(cs, -sn), acc[s]);
+                sincospi_r(xs[s], &sn, &cs);
+                f[jv[s]] = cmul(cmake<C>(cs, -sn), acc[s]);
             }
         }
         __syncthreads();

@@ -6,12 +6,21 @@
 
 namespace nufft {
 
-template <typename C, int L, int DIR>
+// Copies the length-L FFT twiddle table (conjugated for DIR = +1) into LDS
+// with the workgroup's NT threads.  Every load is issued before the first
+// store (clamped addresses, no branch around a load), so the copy costs one
+// memory latency instead of one per iteration.
+template <typename C, int L, int DIR, int NT>
 __device__ __forceinline__ void load_tw_s(C *tw_s, const C *__restrict__ tw_g)
 {
-    for (int m = threadIdx.x; m < L; m += blockDim.x) {
-        C w = tw_g[m];
-        tw_s[m] = DIR < 0 ? w : cconj(w);
+    constexpr int E = (L + NT - 1) / NT;
+    C w[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) w[e] = tw_g[min((int)threadIdx.x + e * NT, L - 1)];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = threadIdx.x + e * NT;
+        if (m < L) tw_s[m] = DIR < 0 ? w[e] : cconj(w[e]);
     }
 }
 
@@ -36,24 +45,33 @@ __device__ __forceinline__ R cheb_v(int r, R z)
     return b;
 }
 
-// c_k, or -2 pi i k c_k for the derivative pass.
+// c_k, or -2 pi i k c_k for the derivative pass; zero for k >= N.  The load
+// itself is unconditional (from a clamped index), so that a run of such
+// loads is issued back to back and waited for once.
 template <typename R>
 __device__ __forceinline__ cx_t<R> load_coef(const cx_t<R> *__restrict__ c, int64_t k, int64_t N, int mode)
 {
     using C = cx_t<R>;
-    if (k >= N) return cmake<C>(0, 0);
-    C ck = c[k];
+    const bool in = k < N;
+    C ck = c[in ? k : N - 1];
     if (mode == 1) {
         const R w = (R)(-2.0 * M_PI * (double)k);
         ck = cmake<C>(-w * ck.y, w * ck.x);
     }
-    return ck;
+    return in ? ck : cmake<C>(0, 0);
 }
 
+// Chebyshev coordinate 2k/N - 1 of mode k: zmap(N) holds 2/N (one FP64
+// division per thread), zcoord is one FP64 fma rounded once to R.  Mode
+// indices are below 2^31 (N <= 2^23).
+struct ZMap {
+    double s;
+};
+__device__ __forceinline__ ZMap zmap(int64_t N) { return ZMap{2.0 / (double)N}; }
 template <typename R>
-__device__ __forceinline__ R zcoord(int64_t k, int64_t N)
+__device__ __forceinline__ R zcoord(int64_t k, ZMap z)
 {
-    return (R)(2.0 * (double)k / (double)N - 1.0);
+    return (R)__builtin_fma((double)(int32_t)k, z.s, -1.0);
 }
 
 // Workgroups are dispatched to the eight XCDs round robin (block b runs on

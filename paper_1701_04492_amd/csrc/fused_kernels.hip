@@ -43,60 +43,59 @@ k_small_fwd(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, const int32_t *
     constexpr int P = fft_pitch(L);
     __shared__ C buf[RC * P];
     __shared__ C tw[L];
-    load_tw_s<C, L, -1>(tw, tw_g);
+    load_tw_s<C, L, -1, SMALL_NT>(tw, tw_g);
 
     const int tid = threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.x * (SMALL_NT * SMALL_SLOTS);
+    // sample data: all loads issued together (clamped indices), one wait
     int pos[SMALL_SLOTS];
-    R zz[SMALL_SLOTS];
+    R xs[SMALL_SLOTS];
     C acc[SMALL_SLOTS];
 #pragma unroll
     for (int s = 0; s < SMALL_SLOTS; ++s) {
-        const int64_t j = j0 + s * SMALL_NT + tid;
-        pos[s] = 0;
-        zz[s] = 0;
+        const int64_t j = min(j0 + s * SMALL_NT + tid, M - 1);
+        pos[s] = t[j];
+        xs[s] = X[j];
         acc[s] = cmake<C>(0, 0);
-        if (j < M) {
-            pos[s] = t[j];
-            zz[s] = X[j] * fac.inv_gamma;
-        }
     }
     const int g = tid / TPF, lt = tid % TPF;
+    const ZMap zm = zmap(N);
     for (int r0 = 0; r0 < fac.K; r0 += RC) {
         const int r = r0 + g;
         C v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int64_t k = lt + q * TPF;
-            C w = cmake<C>(0, 0);
-            if (r < fac.K && k < N) w = cscale(load_coef<R>(c, k, N, mode), cheb_v<R>(r, zcoord<R>(k, N)));
-            v[q] = w;
-        }
+        for (int q = 0; q < 16; ++q) v[q] = load_coef<R>(c, lt + q * TPF, N, mode);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = r < fac.K ? cscale(v[q], cheb_v<R>(r, zcoord<R>(lt + q * TPF, zm)))
+                                                      : cmake<C>(0, 0);
         __syncthreads();   // previous gather finished with buf
         block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
         const int nr = min(RC, fac.K - r0);
 #pragma unroll
         for (int s = 0; s < SMALL_SLOTS; ++s) {
             if (j0 + s * SMALL_NT >= M) break;   // no lane has a sample in this slot or later
+            const R z = xs[s] * fac.inv_gamma;
             for (int gg = 0; gg < nr; ++gg) {
                 const int rr = r0 + gg;
                 const C xv = buf[gg * P + lds_pad(pos[s])];
-                acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fac, rr, zz[s])), rr));
+                acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fac, rr, z)), rr));
             }
         }
+    }
+    C gj[SMALL_SLOTS];
+    if (mode != 0) {
+#pragma unroll
+        for (int s = 0; s < SMALL_SLOTS; ++s) gj[s] = gup[min(j0 + s * SMALL_NT + tid, M - 1)];
     }
 #pragma unroll
     for (int s = 0; s < SMALL_SLOTS; ++s) {
         const int64_t j = j0 + s * SMALL_NT + tid;
         if (j < M) {
             R sn, cs;
-            sincospi_r(X[j], &sn, &cs);
+            sincospi_r(xs[s], &sn, &cs);
             const C out = cmul(cmake<C>(cs, -sn), acc[s]);
             if (mode == 0) f[j] = out;
-            else {
-                const C gj = gup[j];
-                gx[j] = (double)(gj.x * out.x + gj.y * out.y);
-            }
+            else gx[j] = (double)(gj[s].x * out.x + gj[s].y * out.y);
         }
     }
 }
@@ -120,7 +119,7 @@ k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
     __shared__ C tw[L];
     __shared__ R ucoef_s[NUFFT_KMAX * NUFFT_UCOEF_STRIDE];
     __shared__ int nterm_s[NUFFT_KMAX];
-    load_tw_s<C, L, DIR>(tw, tw_g);
+    load_tw_s<C, L, DIR, SMALL_NT>(tw, tw_g);
     stage_factors(fac, ucoef_s, nterm_s);
     __syncthreads();
 
@@ -130,6 +129,7 @@ k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
     C oacc[OPT];
 #pragma unroll
     for (int m = 0; m < OPT; ++m) oacc[m] = cmake<C>(0, 0);
+    const ZMap zm = zmap(N);
 
     for (int r0 = 0; r0 < fac.K; r0 += RC) {
         const int r = r0 + g;
@@ -159,7 +159,7 @@ k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
         for (int m = 0; m < OPT; ++m) {
             const int k = tid + m * SMALL_NT;
             if (k < N && k < L) {
-                const R z = zcoord<R>(k, N);
+                const R z = zcoord<R>(k, zm);
                 for (int gg = 0; gg < nr; ++gg)
                     oacc[m] = cadd(oacc[m], cscale(buf[gg * P + lds_pad(k)], cheb_v<R>(r0 + gg, z)));
             }
@@ -213,24 +213,32 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     if (task < 0) return;
     const int cg = task / nrc, rc = task % nrc;
     const int r_lo = rc * RCA, r_hi = min(K, r_lo + RCA);
-    if (!TWG) load_tw_s<C, L2, -1>(tw_s, tw_g);
+    if (!TWG) load_tw_s<C, L2, -1, NT>(tw_s, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)cg * G;
     const int64_t L = L1 * L2;
+    {
+        C cl[16];   // all 16 loads in flight before the first LDS store
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int i = tid + e * NT;
-        const int gg = i % G, k2 = i / G;
-        buf[gg * P + lds_pad(k2)] = load_coef<R>(c, k1_0 + gg + L1 * (int64_t)k2, N, mode);
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            cl[e] = load_coef<R>(c, k1_0 + i % G + L1 * (int64_t)(i / G), N, mode);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            buf[(i % G) * P + lds_pad(i / G)] = cl[e];
+        }
     }
     __syncthreads();
     C cv[16];
     R zk[16];
+    const ZMap zm = zmap(N);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         cv[q] = buf[g * P + lds_pad(lt + q * TPF)];
-        zk[q] = zcoord<R>((k1_0 + g) + L1 * (int64_t)(lt + q * TPF), N);
+        zk[q] = zcoord<R>((k1_0 + g) + L1 * (int64_t)(lt + q * TPF), zm);
     }
     for (int r = r_lo; r < r_hi; ++r) {
         C v[16];
@@ -271,7 +279,7 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     const C *tw = TWG ? tw_g : tw_s;
     const int task = xcd_task((int)L2);
     if (task < 0) return;
-    if (!TWG) load_tw_s<C, L1, -1>(tw_s, tw_g);
+    if (!TWG) load_tw_s<C, L1, -1, NT>(tw_s, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t n2 = task;
@@ -280,23 +288,24 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     const C *Yrow = Y + n2 * L1 + lt;
 
     for (int64_t c0 = tile_lo; c0 < tile_hi; c0 += CAP) {
-        int pos[S];
-        R zz[S];
-        C acc[S];
+        // the round's sample data: every load issued before any is used
+        // (indices clamped into the tile), then one wait
+        uint32_t kv[S];
+        R xs[S];
+        int32_t jv[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int64_t i = c0 + s * NT + tid;
-            pos[s] = 0;
-            zz[s] = 0;
-            acc[s] = cmake<C>(0, 0);
-            if (i < tile_hi) {
-                pos[s] = (int)(keys[i] & (uint32_t)(L1 - 1));
-                zz[s] = Xs[i] * fac.inv_gamma;
-            }
+            const int64_t i = min(c0 + s * NT + tid, tile_hi - 1);
+            kv[s] = keys[i];
+            xs[s] = Xs[i];
+            jv[s] = perm[i];
         }
         C vn[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) vn[q] = (g < fac.K) ? Yrow[(int64_t)g * L + q * TPF] : cmake<C>(0, 0);
+        C acc[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] = cmake<C>(0, 0);
         for (int r0 = 0; r0 < fac.K; r0 += RC) {
             C v[16];
 #pragma unroll
@@ -312,26 +321,28 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 if (c0 + s * NT >= tile_hi) break;   // no lane has a sample in this slot or later
+                const int pos = (int)(kv[s] & (uint32_t)(L1 - 1));
+                const R z = xs[s] * fac.inv_gamma;
                 for (int gg = 0; gg < nr; ++gg) {
                     const int rr = r0 + gg;
-                    const C xv = buf[gg * P + lds_pad(pos[s])];
-                    acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fac, rr, zz[s])), rr));
+                    const C xv = buf[gg * P + lds_pad(pos)];
+                    acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fac, rr, z)), rr));
                 }
             }
         }
+        C gj[S];
+        if (mode != 0) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) gj[s] = gup[jv[s]];
+        }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int64_t i = c0 + s * NT + tid;
-            if (i < tile_hi) {
+            if (c0 + s * NT + tid < tile_hi) {
                 R sn, cs;
-                sincospi_r(Xs[i], &sn, &cs);
+                sincospi_r(xs[s], &sn, &cs);
                 const C out = cmul(cmake<C>(cs, -sn), acc[s]);
-                const int64_t j = perm[i];
-                if (mode == 0) f[j] = out;
-                else {
-                    const C gj = gup[j];
-                    gx[j] = (double)(gj.x * out.x + gj.y * out.y);
-                }
+                if (mode == 0) f[jv[s]] = out;
+                else gx[jv[s]] = (double)(gj[s].x * out.x + gj[s].y * out.y);
             }
         }
         __syncthreads();
@@ -372,22 +383,50 @@ k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict
     const int task = xcd_task((int)L2);
     if (task < 0) return;
     const int tid = threadIdx.x;
-    if (!TWG)
-        for (int m = tid; m < L1; m += NT) tw_s[m] = tw_g[m];
+    if (!TWG) load_tw_s<C, L1, -1, NT>(tw_s, tw_g);   // tw_g already has the sign DIR
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t n2 = task;
     const int64_t L = (int64_t)L1 * L2;
     const int tile_lo = off[n2 * L1];
-    for (int m = tid; m <= L1; m += NT) soff[m] = off[n2 * L1 + m] - tile_lo;
+    {
+        constexpr int E = (L1 + 1 + NT - 1) / NT;
+        int o[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) o[e] = off[n2 * L1 + min(tid + e * NT, L1)];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (tid + e * NT <= L1) soff[tid + e * NT] = o[e] - tile_lo;
+    }
     const int cnt = off[(n2 + 1) * L1] - tile_lo;
     const int nst = min(cnt, SCAP);
-    for (int i = tid; i < nst; i += NT) {
-        const R Xi = Xs[tile_lo + i];
-        R sn, cs;
-        sincospi_r(Xi, &sn, &cs);
-        sval[i] = cmul(cmake<C>(cs, dir * sn), c[perm[tile_lo + i]]);
-        sz[i] = Xi * fac.inv_gamma;
-        spos[i] = (unsigned short)(keys[tile_lo + i] & (uint32_t)(L1 - 1));
+    if (nst > 0) {
+        // stage the tile's samples: all index/value loads of a thread in flight
+        // together (clamped indices), then the dependent loads of c, one wait each
+        constexpr int SU = (SCAP + NT - 1) / NT;
+        R xv[SU];
+        int32_t jv[SU];
+        uint32_t kv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = tile_lo + min(tid + u * NT, nst - 1);
+            xv[u] = Xs[i];
+            jv[u] = perm[i];
+            kv[u] = keys[i];
+        }
+        C cj[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) cj[u] = c[jv[u]];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = tid + u * NT;
+            if (i < nst) {
+                R sn, cs;
+                sincospi_r(xv[u], &sn, &cs);
+                sval[i] = cmul(cmake<C>(cs, dir * sn), cj[u]);
+                sz[i] = xv[u] * fac.inv_gamma;
+                spos[i] = (unsigned short)(kv[u] & (uint32_t)(L1 - 1));
+            }
+        }
     }
     __syncthreads();
     const int n_lo = tid * GPT;
@@ -473,12 +512,12 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
     const C *tw = TWG ? tw_g : tw_s;   // tw_g already has sign DIR
     const int task = xcd_task((int)(L1 / G));
     if (task < 0) return;
-    if (!TWG)
-        for (int m = threadIdx.x; m < L2; m += NT) tw_s[m] = tw_g[m];
+    if (!TWG) load_tw_s<C, L2, -1, NT>(tw_s, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)task * G;
     const int64_t L = L1 * L2;
+    const ZMap zm = zmap(N);
     C acc[16];
     C zn[16];
 #pragma unroll
@@ -507,7 +546,7 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;
-            const R z = zcoord<R>(k1_0 + (i % G) + L1 * (int64_t)(i / G), N);
+            const R z = zcoord<R>(k1_0 + (i % G) + L1 * (int64_t)(i / G), zm);
             acc[e] = cadd(acc[e], cscale(buf[(i % G) * P + lds_pad(i / G)], cheb_v<R>(r, z)));
         }
     }

@@ -36,18 +36,21 @@ k_2d_passA(const cx_t<R> *__restrict__ Cin, int64_t N1, int64_t N2, int64_t GX, 
     if (task < 0) return;
     const int cg = task / nrc, rc = task % nrc;
     const int r_lo = rc * RCA, r_hi = min(K, r_lo + RCA);
-    load_tw_s<C, GY, -1>(tw, tw_g);
+    load_tw_s<C, GY, -1, NT>(tw, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)cg * G;
     const int64_t k1 = k1_0 + g;
+    const ZMap zm = zmap(N2);
     C cv[16];
     R zk[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 16; ++q) {   // clamped address, no branch: the 16 loads issue together
         const int64_t k2 = lt + q * TPF;
-        cv[q] = (k1 < N1 && k2 < N2) ? Cin[k1 * N2 + k2] : cmake<C>(0, 0);
-        zk[q] = zcoord<R>(k2, N2);
+        const bool in = k1 < N1 && k2 < N2;
+        const C v = Cin[min(k1, N1 - 1) * N2 + min(k2, N2 - 1)];
+        cv[q] = in ? v : cmake<C>(0, 0);
+        zk[q] = zcoord<R>(k2, zm);
     }
     for (int r = r_lo; r < r_hi; ++r) {
         C v[16];
@@ -79,68 +82,85 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
     constexpr int P = fft_pitch(GX);
     __shared__ C buf[RC * P];
     __shared__ C tw[GX];
+    __shared__ C hrow[GX];
     const int task = xcd_task(ntasks);
     if (task < 0) return;
     const int4 tk = tasks[task];
     const int64_t n2 = tk.x, i_lo = tk.y, i_hi = tk.z;
-    load_tw_s<C, GX, -1>(tw, tw_g);
+    load_tw_s<C, GX, -1, NT>(tw, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
-    int pos[S];
-    R zx[S], zy[S], py[S];
-    C acc[S];
+    // sample data of the task: loads issued together (clamped indices), one wait
+    uint32_t kv[S];
+    R xx[S], xy[S], py[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const int64_t i = i_lo + s * NT + tid;
-        pos[s] = 0;
-        zx[s] = zy[s] = 0;
-        acc[s] = cmake<C>(0, 0);
-        if (i < i_hi) {
-            pos[s] = (int)(keys[i] & (uint32_t)(GX - 1));
-            zx[s] = Xxs[i] * fx.inv_gamma;
-            zy[s] = Xys[i] * fy.inv_gamma;
-        }
+        const int64_t i = min(i_lo + s * NT + tid, i_hi - 1);
+        kv[s] = keys[i];
+        xx[s] = Xxs[i];
+        xy[s] = Xys[i];
     }
-    R zk[16];
+    C acc[S];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) zk[q] = zcoord<R>(lt + q * TPF, N1);
-    for (int r2 = 0; r2 < fy.K; ++r2) {
-        C cv[16];
+    for (int s = 0; s < S; ++s) acc[s] = cmake<C>(0, 0);
+    const ZMap zm = zmap(N1);
+    // The RC transforms of a round all start from the same row H_r2[n2][:]: it
+    // is staged once per r2 in LDS (GX/NT elements per thread), and the next
+    // row is loaded into registers while the current one is in use.  Rows
+    // k1 >= N1 of H are never written: they read as zero.
+    constexpr int HE = GX / NT;
+    C hn[HE];
+    auto load_row = [&](int r2) {
         const C *Hrow = H + ((int64_t)r2 * GY + n2) * GX;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int k1 = lt + q * TPF;
-            cv[q] = k1 < N1 ? Hrow[k1] : cmake<C>(0, 0);
+        for (int e = 0; e < HE; ++e) {
+            const int k1 = tid + e * NT;
+            const C v = Hrow[min(k1, (int)N1 - 1)];
+            hn[e] = k1 < N1 ? v : cmake<C>(0, 0);
         }
+    };
+    load_row(0);
+    for (int r2 = 0; r2 < fy.K; ++r2) {
+        __syncthreads();   // every reader of the previous row is done
+#pragma unroll
+        for (int e = 0; e < HE; ++e) hrow[tid + e * NT] = hn[e];
+        if (r2 + 1 < fy.K) load_row(r2 + 1);
 #pragma unroll
         for (int s = 0; s < S; ++s)
-            if (i_lo + s * NT < i_hi) py[s] = upoly(fy, r2, zy[s]);
+            if (i_lo + s * NT < i_hi) py[s] = upoly(fy, r2, xy[s] * fy.inv_gamma);
         for (int r0 = 0; r0 < fx.K; r0 += RC) {
             const int r1 = r0 + g;
+            __syncthreads();   // the row is staged; the previous gather is finished with buf
             C v[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = r1 < fx.K ? cscale(cv[q], cheb_v<R>(r1, zk[q])) : cmake<C>(0, 0);
-            __syncthreads();
+            for (int q = 0; q < 16; ++q)
+                v[q] = r1 < fx.K ? cscale(hrow[lt + q * TPF], cheb_v<R>(r1, zcoord<R>(lt + q * TPF, zm)))
+                                 : cmake<C>(0, 0);
             block_fft_regs<C, GX, -1>(buf + g * P, tw, lt, v);
             const int nr = min(RC, fx.K - r0);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 if (i_lo + s * NT >= i_hi) break;   // no lane has a sample in this slot or later
+                const int pos = (int)(kv[s] & (uint32_t)(GX - 1));
+                const R zx = xx[s] * fx.inv_gamma;
                 for (int gg = 0; gg < nr; ++gg) {
                     const int rr = r0 + gg;
-                    const C xv = buf[gg * P + lds_pad(pos[s])];
-                    acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fx, rr, zx[s]) * py[s]), rr + r2));
+                    const C xv = buf[gg * P + lds_pad(pos)];
+                    acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fx, rr, zx) * py[s]), rr + r2));
                 }
             }
         }
     }
+    int32_t jv[S];   // output positions, loaded together at the end
+#pragma unroll
+    for (int s = 0; s < S; ++s) jv[s] = perm[min(i_lo + s * NT + tid, i_hi - 1)];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int64_t i = i_lo + s * NT + tid;
         if (i < i_hi) {
             R sn, cs;
-            sincospi_r(Xxs[i] + Xys[i], &sn, &cs);
-            f[perm[i]] = cmul(cmake<C>(cs, -sn), acc[s]);
+            sincospi_r(xx[s] + xy[s], &sn, &cs);
+            f[jv[s]] = cmul(cmake<C>(cs, -sn), acc[s]);
         }
     }
 }
@@ -166,7 +186,7 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     __shared__ C buf[RC * P];
     __shared__ C tw_s[TWG ? 1 : GX];
     __shared__ C sval[SCAP];
-    __shared__ R szx[SCAP], spy[SCAP];
+    __shared__ R szx[SCAP], szy[SCAP], spy[SCAP];
     __shared__ unsigned short spos[SCAP];
     __shared__ C hv[RC * NT], tv[RC * NT];
     __shared__ int hix[NT], tix[NT];
@@ -174,23 +194,47 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     const int task = xcd_task((int)GY);
     if (task < 0) return;
     const int tid = threadIdx.x;
-    if (!TWG)
-        for (int m = tid; m < GX; m += NT) tw_s[m] = twi_g[m];
+    if (!TWG) load_tw_s<C, GX, -1, NT>(tw_s, twi_g);   // twi_g already has the + sign
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t n2 = task;
     const int tile_lo = off[n2 * GX];
     const int cnt = off[(n2 + 1) * GX] - tile_lo;
     const int nst = min(cnt, SCAP);
-    for (int i = tid; i < nst; i += NT) {
-        const R ax = Xxs[tile_lo + i], ay = Xys[tile_lo + i];
-        R sn, cs;
-        sincospi_r(ax + ay, &sn, &cs);
-        sval[i] = cmul(cmake<C>(cs, sn), gin[perm[tile_lo + i]]);
-        szx[i] = ax * fx.inv_gamma;
-        spos[i] = (unsigned short)(keys[tile_lo + i] & (uint32_t)(GX - 1));
+    if (nst > 0) {
+        // stage the column's samples: index/value loads of a thread issued
+        // together (clamped indices), then the dependent loads of g
+        constexpr int SU = (SCAP + NT - 1) / NT;
+        R ax[SU], ay[SU];
+        int32_t jv[SU];
+        uint32_t kv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = tile_lo + min(tid + u * NT, nst - 1);
+            ax[u] = Xxs[i];
+            ay[u] = Xys[i];
+            jv[u] = perm[i];
+            kv[u] = keys[i];
+        }
+        C gv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) gv[u] = gin[jv[u]];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = tid + u * NT;
+            if (i < nst) {
+                R sn, cs;
+                sincospi_r(ax[u] + ay[u], &sn, &cs);
+                sval[i] = cmul(cmake<C>(cs, sn), gv[u]);
+                szx[i] = ax[u] * fx.inv_gamma;
+                szy[i] = ay[u] * fy.inv_gamma;
+                spos[i] = (unsigned short)(kv[u] & (uint32_t)(GX - 1));
+            }
+        }
     }
+    const ZMap zm = zmap(N1);
     for (int r2 = 0; r2 < fy.K; ++r2) {
-        for (int i = tid; i < nst; i += NT) spy[i] = upoly(fy, r2, Xys[tile_lo + i] * fy.inv_gamma);
+        __syncthreads();   // staging done / previous readers of spy done
+        for (int i = tid; i < nst; i += NT) spy[i] = upoly(fy, r2, szy[i]);
         __syncthreads();
         C za[ZA];
 #pragma unroll
@@ -218,7 +262,7 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
 #pragma unroll
             for (int m = 0; m < ZA; ++m) {
                 const int k1 = tid + m * NT;
-                const R z = zcoord<R>(k1, N1);
+                const R z = zcoord<R>(k1, zm);
                 for (int gg = 0; gg < nr; ++gg)
                     za[m] = cadd(za[m], cscale(buf[gg * P + lds_pad(k1)], cheb_v<R>(r0 + gg, z)));
             }
@@ -246,15 +290,17 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
     const int task = xcd_task(ncg);
     if (task < 0) return;
     const int tid = threadIdx.x;
-    for (int m = tid; m < GY; m += NT) tw[m] = twi_g[m];
+    load_tw_s<C, GY, -1, NT>(tw, twi_g);   // twi_g already has the + sign
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)task * G;
+    const ZMap zm = zmap(N2);
     C acc[16], zn[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int i = tid + e * NT;
         acc[e] = cmake<C>(0, 0);
-        zn[e] = (k1_0 + (i % G) < N1) ? Z[(int64_t)(i / G) * GX + k1_0 + (i % G)] : cmake<C>(0, 0);
+        const C v = Z[(int64_t)(i / G) * GX + min(k1_0 + (i % G), N1 - 1)];   // clamped: no branch
+        zn[e] = (k1_0 + (i % G) < N1) ? v : cmake<C>(0, 0);
     }
     for (int r = 0; r < Ky; ++r) {
         __syncthreads();
@@ -268,7 +314,8 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int i = tid + e * NT;
-                zn[e] = (k1_0 + (i % G) < N1) ? Zr[(int64_t)(i / G) * GX + (i % G)] : cmake<C>(0, 0);
+                const C v = Zr[(int64_t)(i / G) * GX + min((int64_t)(i % G), N1 - 1 - k1_0)];
+                zn[e] = (k1_0 + (i % G) < N1) ? v : cmake<C>(0, 0);
             }
         }
         __syncthreads();
@@ -276,7 +323,7 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;
-            const R z = zcoord<R>(i / G, N2);
+            const R z = zcoord<R>(i / G, zm);
             acc[e] = cadd(acc[e], cscale(buf[(i % G) * P + lds_pad(i / G)], cheb_v<R>(r, z)));
         }
     }
@@ -373,7 +420,7 @@ hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, h
         BA2(128, 16, 512, 8, 512, false)
         BA2(256, 16, 512, 8, 512, false)
         BA2(512, 8, 1024, 4, 768, false)
-        BA2(1024, 4, 2048, 4, 1024, false)
+        BA2(1024, 4, 2048, 4, 768, false)
         BA2(2048, 2, 2304, 2, 1280, true)
 #undef BA2
     default: return hipErrorInvalidValue;
