@@ -62,13 +62,14 @@ __device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx
         __syncthreads();
         block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
         const int nr = min(RC, K - r0);
+        for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
+            const int rr = r0 + gg;
+            const RankPoly<R> up = rank_poly(fac, rr);
 #pragma unroll
-        for (int s = 0; s < BSLOTS; ++s) {
-            if (j0 + s * BNT >= d.M) break;
-            const R z = xs[s] * fac.inv_gamma;
-            for (int gg = 0; gg < nr; ++gg) {
-                const int rr = r0 + gg;
-                acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])], upoly(fac, rr, z)), rr));
+            for (int s = 0; s < BSLOTS; ++s) {
+                if (j0 + s * BNT < d.M)
+                    acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos[s])],
+                                                      rank_eval(up, xs[s] * fac.inv_gamma)), rr));
             }
         }
     }
@@ -185,14 +186,16 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2, 
             __syncthreads();
             block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
             const int nr = min(RC, K - r0);
+            for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
+                const int rr = r0 + gg;
+                const RankPoly<R> up = rank_poly(fac, rr);
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                if (c0 + s * BNT >= tile_hi) break;
-                const int pos = (int)(kv[s] & (uint32_t)(L1 - 1));
-                const R z = xs[s] * fac.inv_gamma;
-                for (int gg = 0; gg < nr; ++gg) {
-                    const int rr = r0 + gg;
-                    acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos)], upoly(fac, rr, z)), rr));
+                for (int s = 0; s < S; ++s) {
+                    if (c0 + s * BNT < tile_hi) {
+                        const int pos = (int)(kv[s] & (uint32_t)(L1 - 1));
+                        acc[s] = cadd(acc[s], crot(cscale(buf[gg * P + lds_pad(pos)],
+                                                          rank_eval(up, xs[s] * fac.inv_gamma)), rr));
+                    }
                 }
             }
         }

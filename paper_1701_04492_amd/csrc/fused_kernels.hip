@@ -71,14 +71,16 @@ k_small_fwd(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, const int32_t *
         __syncthreads();   // previous gather finished with buf
         block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
         const int nr = min(RC, fac.K - r0);
+        // rank outer (coefficients loaded once), samples inner
+        for (int gg = 0; gg < nr; ++gg) {
+            const int rr = r0 + gg;
+            const RankPoly<R> up = rank_poly(fac, rr);
 #pragma unroll
-        for (int s = 0; s < SMALL_SLOTS; ++s) {
-            if (j0 + s * SMALL_NT >= M) break;   // no lane has a sample in this slot or later
-            const R z = xs[s] * fac.inv_gamma;
-            for (int gg = 0; gg < nr; ++gg) {
-                const int rr = r0 + gg;
-                const C xv = buf[gg * P + lds_pad(pos[s])];
-                acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fac, rr, z)), rr));
+            for (int s = 0; s < SMALL_SLOTS; ++s) {
+                if (j0 + s * SMALL_NT < M) {   // else no lane has a sample in this slot
+                    const C xv = buf[gg * P + lds_pad(pos[s])];
+                    acc[s] = cadd(acc[s], crot(cscale(xv, rank_eval(up, xs[s] * fac.inv_gamma)), rr));
+                }
             }
         }
     }
@@ -292,13 +294,11 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
         // (indices clamped into the tile), then one wait
         uint32_t kv[S];
         R xs[S];
-        int32_t jv[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int64_t i = min(c0 + s * NT + tid, tile_hi - 1);
             kv[s] = keys[i];
             xs[s] = Xs[i];
-            jv[s] = perm[i];
         }
         C vn[16];
 #pragma unroll
@@ -318,18 +318,25 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             __syncthreads();
             block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
             const int nr = min(RC, fac.K - r0);
+            // rank outer (its coefficients loaded once), samples inner
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                if (c0 + s * NT >= tile_hi) break;   // no lane has a sample in this slot or later
-                const int pos = (int)(kv[s] & (uint32_t)(L1 - 1));
-                const R z = xs[s] * fac.inv_gamma;
-                for (int gg = 0; gg < nr; ++gg) {
+            for (int gg = 0; gg < RC; ++gg) {
+                if (gg < nr) {
                     const int rr = r0 + gg;
-                    const C xv = buf[gg * P + lds_pad(pos)];
-                    acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fac, rr, z)), rr));
+                    const RankPoly<R> up = rank_poly(fac, rr);
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        if (c0 + s * NT < tile_hi) {   // else no lane has a sample in this slot
+                            const C xv = buf[gg * P + lds_pad((int)(kv[s] & (uint32_t)(L1 - 1)))];
+                            acc[s] = cadd(acc[s], crot(cscale(xv, rank_eval(up, xs[s] * fac.inv_gamma)), rr));
+                        }
+                    }
                 }
             }
         }
+        int32_t jv[S];   // output positions: loaded together once the sums are done
+#pragma unroll
+        for (int s = 0; s < S; ++s) jv[s] = perm[min(c0 + s * NT + tid, tile_hi - 1)];
         C gj[S];
         if (mode != 0) {
 #pragma unroll
@@ -441,6 +448,9 @@ k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict
         C a[RC];
 #pragma unroll
         for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+        RankPoly<R> up[RC];
+#pragma unroll
+        for (int gg = 0; gg < RC; ++gg) up[gg] = rank_poly(fac, min(r0 + gg, fac.K - 1));
         int ncur = -1;
         for (int i = i0; i < i1; ++i) {
             C val;
@@ -470,7 +480,7 @@ k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict
             }
 #pragma unroll
             for (int gg = 0; gg < RC; ++gg)
-                if (gg < nr) a[gg] = cadd(a[gg], cscale(val, upoly(fac, r0 + gg, z)));
+                if (gg < nr) a[gg] = cadd(a[gg], cscale(val, rank_eval(up[gg], z)));
         }
         if (ncur >= 0) {
 #pragma unroll
@@ -619,14 +629,43 @@ static hipError_t run_small_adj(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R>
     default: return hipErrorInvalidValue; \
     }
 
-// Column groups per pass-A workgroup: 8 adjacent columns (64-byte runs in
+// Launch shapes of the two-pass kernels at the large tile sizes (FP32).  The
+// defaults can be overridden at compile time to compare shapes.
+#ifndef NUFFT_F32_GA1024
+#define NUFFT_F32_GA1024 8      // pass A: adjacent columns per workgroup at L2 = 1024
+#endif
+#ifndef NUFFT_F32_GA2048
+#define NUFFT_F32_GA2048 4
+#endif
+#ifndef NUFFT_F32_GAA1024
+#define NUFFT_F32_GAA1024 4     // pass A'
+#endif
+#ifndef NUFFT_F32_GAA2048
+#define NUFFT_F32_GAA2048 2
+#endif
+#ifndef NUFFT_F32_PB2048_RC
+#define NUFFT_F32_PB2048_RC 4   // pass B at L1 = 2048: ranks side by side, sample slots
+#endif
+#ifndef NUFFT_F32_PB2048_S
+#define NUFFT_F32_PB2048_S 5
+#endif
+#ifndef NUFFT_F32_PB1024_RC
+#define NUFFT_F32_PB1024_RC 4
+#endif
+#ifndef NUFFT_F32_PB1024_S
+#define NUFFT_F32_PB1024_S 5
+#endif
+
+// Column groups per pass-A workgroup: G adjacent columns (G x 8-byte runs in
 // FP32) while the LDS budget allows.
 template <typename R> struct Cfg;
 template <> struct Cfg<float> {
-    static constexpr int G1024 = 8, G2048 = 4;
+    static constexpr int G1024 = NUFFT_F32_GA1024, G2048 = NUFFT_F32_GA2048;
+    static constexpr int GA1024 = NUFFT_F32_GAA1024, GA2048 = NUFFT_F32_GAA2048;
 };
 template <> struct Cfg<double> {
     static constexpr int G1024 = 4, G2048 = 2;
+    static constexpr int GA1024 = 4, GA2048 = 2;
 };
 
 // Ranks per pass-A task.  Every task pays a fixed set-up (twiddle table and
@@ -691,8 +730,8 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
         PB(128, 16, 1, 8, 2)
         PB(256, 16, 2, 8, 3)
         PB(512, 8, 3, 4, 5)
-        PB(1024, 4, 5, 4, 5)
-        PB(2048, 4, 5, 2, 5)
+        PB(1024, NUFFT_F32_PB1024_RC, NUFFT_F32_PB1024_S, 4, 5)
+        PB(2048, NUFFT_F32_PB2048_RC, NUFFT_F32_PB2048_S, 2, 5)
         PB(4096, 2, 10, 1, 5)
 #undef PB
     default: return hipErrorInvalidValue;
@@ -744,8 +783,8 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         PAA(128, 8)
         PAA(256, 8)
         PAA(512, 8)
-        PAA(1024, Cfg<R>::G1024)
-        PAA(2048, Cfg<R>::G2048)
+        PAA(1024, Cfg<R>::GA1024)
+        PAA(2048, Cfg<R>::GA2048)
 #undef PAA
     default: return hipErrorInvalidValue;
     }

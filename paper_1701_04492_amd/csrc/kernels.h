@@ -21,6 +21,36 @@ __device__ __forceinline__ R upoly(const Factors<R> &fac, int r, R z)
     return (r & 1) ? acc * z : acc;
 }
 
+// The same polynomial for one rank r that is uniform across the workgroup,
+// with its coefficients loaded once into registers and reused for every
+// sample (a per-term load inside the evaluation would wait for each term).
+// Since K <= NUFFT_KMAX, no rank has more than NUFFT_KMAX / 2 terms and the
+// table is zero past nterm[r]: a fixed-length Horner chain over the first
+// NUFFT_KMAX / 2 coefficients gives the same value with no branch or select.
+template <typename R>
+struct RankPoly {
+    R c[NUFFT_KMAX / 2];
+    int odd;
+};
+template <typename R>
+__device__ __forceinline__ RankPoly<R> rank_poly(const Factors<R> &fac, int r)
+{
+    RankPoly<R> p;
+#pragma unroll
+    for (int m = 0; m < NUFFT_KMAX / 2; ++m) p.c[m] = fac.ucoef[r * NUFFT_UCOEF_STRIDE + m];
+    p.odd = r & 1;
+    return p;
+}
+template <typename R>
+__device__ __forceinline__ R rank_eval(const RankPoly<R> &p, R z)
+{
+    const R w = z * z;
+    R acc = p.c[NUFFT_KMAX / 2 - 1];
+#pragma unroll
+    for (int m = NUFFT_KMAX / 2 - 2; m >= 0; --m) acc = acc * w + p.c[m];
+    return p.odd ? acc * z : acc;
+}
+
 // Same polynomial from a coefficient table staged in LDS: for kernels where the
 // rank differs between the lanes of a wave (a per-lane index into the
 // kernel-argument table would turn every coefficient into a vector load).

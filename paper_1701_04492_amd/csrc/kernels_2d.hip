@@ -125,9 +125,12 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
 #pragma unroll
         for (int e = 0; e < HE; ++e) hrow[tid + e * NT] = hn[e];
         if (r2 + 1 < fy.K) load_row(r2 + 1);
+        {
+            const RankPoly<R> uy = rank_poly(fy, r2);
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            if (i_lo + s * NT < i_hi) py[s] = upoly(fy, r2, xy[s] * fy.inv_gamma);
+            for (int s = 0; s < S; ++s)
+                if (i_lo + s * NT < i_hi) py[s] = rank_eval(uy, xy[s] * fy.inv_gamma);
+        }
         for (int r0 = 0; r0 < fx.K; r0 += RC) {
             const int r1 = r0 + g;
             __syncthreads();   // the row is staged; the previous gather is finished with buf
@@ -138,15 +141,16 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
                                  : cmake<C>(0, 0);
             block_fft_regs<C, GX, -1>(buf + g * P, tw, lt, v);
             const int nr = min(RC, fx.K - r0);
+            for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
+                const int rr = r0 + gg;
+                const RankPoly<R> ux = rank_poly(fx, rr);
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                if (i_lo + s * NT >= i_hi) break;   // no lane has a sample in this slot or later
-                const int pos = (int)(kv[s] & (uint32_t)(GX - 1));
-                const R zx = xx[s] * fx.inv_gamma;
-                for (int gg = 0; gg < nr; ++gg) {
-                    const int rr = r0 + gg;
-                    const C xv = buf[gg * P + lds_pad(pos)];
-                    acc[s] = cadd(acc[s], crot(cscale(xv, upoly(fx, rr, zx) * py[s]), rr + r2));
+                for (int s = 0; s < S; ++s) {
+                    if (i_lo + s * NT < i_hi) {
+                        const int pos = (int)(kv[s] & (uint32_t)(GX - 1));
+                        const C xv = buf[gg * P + lds_pad(pos)];
+                        acc[s] = cadd(acc[s], crot(cscale(xv, rank_eval(ux, xx[s] * fx.inv_gamma) * py[s]), rr + r2));
+                    }
                 }
             }
         }
@@ -234,7 +238,10 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     const ZMap zm = zmap(N1);
     for (int r2 = 0; r2 < fy.K; ++r2) {
         __syncthreads();   // staging done / previous readers of spy done
-        for (int i = tid; i < nst; i += NT) spy[i] = upoly(fy, r2, szy[i]);
+        {
+            const RankPoly<R> uy = rank_poly(fy, r2);
+            for (int i = tid; i < nst; i += NT) spy[i] = rank_eval(uy, szy[i]);
+        }
         __syncthreads();
         C za[ZA];
 #pragma unroll
@@ -246,9 +253,12 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
             auto pos = [&](int i) -> int {
                 return i < SCAP ? (int)spos[i] : (int)(keys[tile_lo + i] & (uint32_t)(GX - 1));
             };
+            RankPoly<R> ux[RC];
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg) ux[gg] = rank_poly(fx, min(r0 + gg, fx.K - 1));
             auto contrib = [&](int i, int gg) -> C {
                 const int r1 = r0 + gg;
-                if (i < SCAP) return crot(cscale(sval[i], upoly(fx, r1, szx[i]) * spy[i]), -(r1 + r2));
+                if (i < SCAP) return crot(cscale(sval[i], rank_eval(ux[gg], szx[i]) * spy[i]), -(r1 + r2));
                 const R ax = Xxs[tile_lo + i], ay = Xys[tile_lo + i];
                 R sn, cs;
                 sincospi_r(ax + ay, &sn, &cs);
