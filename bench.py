@@ -42,8 +42,12 @@ def kernel_bytes(name, K, N, M, L, cs):
         "fwd_passA": N * cs + inter,
         "fwd_passB": inter + plan_pts + M * cs,
         "gradx_passA": N * cs + inter,
-        "gradx_passB": inter + plan_pts + M * cs + M * 8,       # reads g, writes gx (f64)
-        "adj_passB": M * cs + M * (4 + 4) + (L + 1) * 4 + inter,  # g, X, perm, offsets -> Z
+        "gradx_passB": inter + plan_pts + M * cs + M * 8,       # reads sorted g, writes gx (f64)
+        "adj_sort": M * cs + M * 4 + M * cs,                    # g, sorted position -> g sorted
+        "gradx_sort": M * cs + M * 4 + M * cs,
+        "bwd_sort": M * cs + M * 4 + M * cs,
+        "type1_sort": M * cs + M * 4 + M * cs,
+        "adj_passB": M * cs + M * (4 + 4) + (L + 1) * 4 + inter,  # sorted g, X, key, offsets -> Z
         "adj_passA": inter + N * cs,
         "type1_passB": M * cs + M * (4 + 4) + (L + 1) * 4 + inter,
         "type1_passA": inter + N * cs,
@@ -65,19 +69,99 @@ def time_loop(fn, steps, warmup, torch):
     return a.elapsed_time(b) / steps
 
 
+def kernel_source_hash():
+    """Hash of every HIP/C++ source the kernels are built from."""
+    d = os.path.join(ROOT, "paper_1701_04492_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_record(kernel):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken
-    on the current kernel source; else None."""
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1701_04492_amd", "csrc", "fused_kernels.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("source_sha256_16") != h:
+    if rec.get("source_sha256_16") != kernel_source_hash():
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+# Counter runs (rocprofv3 --pmc): the six kernels of one fwd+bwd step at N = M = 2^22
+# in the order the autograd step launches them, then a plain copy of known size whose
+# counters calibrate FETCH_SIZE / WRITE_SIZE.
+COUNTER_ORDER = ["fwd_passA", "fwd_passB", "adj_passB", "adj_passA", "gradx_passA", "gradx_passB"]
+CALIB_BYTES = 256 << 20
+
+
+def counter_run(steps):
+    import torch
+    import paper_1701_04492_amd as P
+    from paper_1701_04492_amd import workloads as W
+    dev = torch.device("cuda:0")
+    N = 1 << 22
+    rng = W.rng_for(3)
+    c = torch.from_numpy(W.complex_normal(rng, N)).to(torch.complex64).to(dev)
+    x = torch.from_numpy(W.iid_samples(rng, N)).to(dev)
+    g = torch.from_numpy(W.complex_normal(rng, N)).to(torch.complex64).to(dev)
+    plan = P.nufft2_plan(x, N, 1e-6, torch.complex64)
+    f = torch.empty_like(c)
+    gc = torch.empty_like(c)
+    gx = torch.empty(N, dtype=torch.float64, device=dev)
+    for _ in range(steps):
+        P.nufft2_exec(plan, c, f)              # fwd_passA, fwd_passB
+        P.nufft1_exec(plan, g, +1, gc)         # adj_passB, adj_passA
+        P.nufft2_grad_x(plan, c, g, gx)        # gradx_passA, gradx_passB
+    src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)               # calibration: reads and writes CALIB_BYTES
+    torch.cuda.synchronize()
+    print("counter run done: %d steps, K=%d" % (steps, plan.K), flush=True)
+
+
+def traffic_summary(fetch_dir, write_dir, out_path, command):
+    """rocprofv3 counter CSVs -> HBM bytes per launch of each step kernel."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(fn)):
+                if r["Counter_Name"] == counter:
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        rows.sort()
+        lib = [(n, v) for _, n, v in rows if "nufft::k_pass" in n]
+        cal = [v for _, n, v in rows if "MulFunctor" in n]
+        if not cal or not lib or len(lib) % len(COUNTER_ORDER):
+            raise SystemExit("unexpected dispatches in %s (%d library, %d calibration)" % (d, len(lib), len(cal)))
+        per = {k: [] for k in COUNTER_ORDER}
+        names = {}
+        for i, (n, v) in enumerate(lib):
+            k = COUNTER_ORDER[i % len(COUNTER_ORDER)]
+            per[k].append(v)
+            names[k] = n.split("(")[0]
+        scale = CALIB_BYTES / (cal[-1] * 1024.0)   # true bytes per counted byte
+        return {k: sum(v) / len(v) for k, v in per.items()}, scale, names
+
+    fetch, fs, names = read(fetch_dir, "FETCH_SIZE")
+    write, ws, _ = read(write_dir, "WRITE_SIZE")
+    rec = {"source_sha256_16": kernel_source_hash(), "command": command,
+           "calibration": {"copy_bytes_each_way": CALIB_BYTES, "fetch_scale": round(fs, 4),
+                           "write_scale": round(ws, 4)},
+           "kernels": {}}
+    for k in COUNTER_ORDER:
+        b = fetch[k] * 1024.0 * fs + write[k] * 1024.0 * ws
+        rec["kernels"][k] = {"kernel": names[k], "fetch_kib": round(fetch[k], 1), "write_kib": round(write[k], 1),
+                             "bytes_per_launch": int(b)}
+    json.dump(rec, open(out_path, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(x, c, N, seconds):
@@ -176,7 +260,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--counter-run", action="store_true",
+                    help="launch the step kernels in a fixed order plus a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 counter output folders")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary[0], args.traffic_summary[1],
+                        os.path.join(ROOT, "profiles", "traffic.json"),
+                        ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -- "
+                         "python3 bench.py --counter-run --steps 3",
+                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -- "
+                         "python3 bench.py --counter-run --steps 3",
+                         "python3 bench.py --traffic-summary <FETCH_DIR> <WRITE_DIR>"])
+        return
+    if args.counter_run:
+        counter_run(args.steps)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         _fail_multi(max(args.gpus, int(os.environ.get("WORLD_SIZE", "1"))))
 

@@ -111,6 +111,16 @@ nufft_status nufft1_exec(nufft_plan_t plan, const void *c_dev, void *f_dev, int 
 nufft_status nufft2_grad_x(nufft_plan_t plan, const void *c_dev, const void *g_dev,
                            double *gx_dev, void *stream);
 
+/* Both gradients of a real loss L(f), f = F2 c, in one call (the backward of
+ * type II):
+ *   gc_dev = F2^H g                      (as nufft1_exec with sign = +1)
+ *   gx_dev[j] = Re(conj(g_j) (F2 (-2 pi i k c))_j)   (as nufft2_grad_x)
+ * g_dev (M complex) is put in the plan's sorted sample order once and read
+ * by both passes.  Either output may be NULL to skip it (not both).
+ * c_dev: N complex, gc_dev: N complex, gx_dev: M doubles. */
+nufft_status nufft2_backward(nufft_plan_t plan, const void *c_dev, const void *g_dev,
+                             void *gc_dev, double *gx_dev, void *stream);
+
 /* ---- type III ---------------------------------------------------------- */
 
 /* Type III (Sec. 3.2): f_dev[j] ~ sum_{k<N} c_dev[k] exp(-2 pi i x_j w_k), j < M,

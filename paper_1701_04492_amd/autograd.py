@@ -22,13 +22,11 @@ class NufftTypeII(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (c,) = ctx.saved_tensors
-        g = g.contiguous()
-        plan = ctx.plan
-        gx = gc = None
-        if ctx.needs_input_grad[1]:
-            gc = B.nufft1_exec(plan, g, sign=+1)
-        if ctx.needs_input_grad[0]:
-            gx = B.nufft2_grad_x(plan, c.contiguous(), g)
+        need_x, need_c = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_x or need_c):
+            return None, None, None
+        # one call: g is put in the plan's sample order once for both passes
+        gc, gx = B.nufft2_backward(ctx.plan, c.contiguous(), g.contiguous(), need_c=need_c, need_x=need_x)
         return gx, gc, None
 
 

@@ -37,6 +37,7 @@ _sig = {
     "nufft2_exec": [_vp, _vp, _vp, _vp],
     "nufft1_exec": [_vp, _vp, _vp, _int, _vp],
     "nufft2_grad_x": [_vp, _vp, _vp, _vp, _vp],
+    "nufft2_backward": [_vp, _vp, _vp, _vp, _vp, _vp],
     "nufft3_exec": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
     "nufft2d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _dbl, _int, _u32, _vp],
     "nufft2d_exec": [_vp, _vp, _vp, _int, _vp],
@@ -158,6 +159,23 @@ def nufft2_grad_x(plan, c, g, gx=None):
                              _dev_tensor(gx, torch.float64, plan.M, "gx"), _stream(plan.device)),
            "nufft2_grad_x")
     return gx
+
+
+def nufft2_backward(plan, c, g, gc=None, gx=None, need_c=True, need_x=True):
+    """Both gradients of a real loss through f = F2 c: (F2^H g, Re(conj(g) F2(-2 pi i k c)));
+    a gradient that is not needed is returned as None."""
+    if not (need_c or need_x):
+        raise ValueError("nufft2_backward: nothing requested")
+    if need_c and gc is None:
+        gc = torch.empty(plan.N, dtype=plan.dtype, device=plan.device)
+    if need_x and gx is None:
+        gx = torch.empty(plan.M, dtype=torch.float64, device=plan.device)
+    _check(lib.nufft2_backward(plan.handle, _dev_tensor(c, plan.dtype, plan.N, "c") if need_x else None,
+                               _dev_tensor(g, plan.dtype, plan.M, "g"),
+                               _dev_tensor(gc, plan.dtype, plan.N, "gc") if need_c else None,
+                               _dev_tensor(gx, torch.float64, plan.M, "gx") if need_x else None,
+                               _stream(plan.device)), "nufft2_backward")
+    return (gc if need_c else None), (gx if need_x else None)
 
 
 def nufft3_exec(x, w, c, eps, f=None):

@@ -205,7 +205,10 @@ nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
     }
     if (p->L2 > 1) {
         p->Y = p->alloc((size_t)p->K * L * cs);
-        if (!p->Y) return NUFFT_ERR_ALLOC;
+        p->sinv = (int32_t *)p->alloc((size_t)M * sizeof(int32_t));
+        p->gsort = p->alloc((size_t)M * cs);
+        if (!p->Y || !p->sinv || !p->gsort) return NUFFT_ERR_ALLOC;
+        NUFFT_HIP_CHECK(launch_invert_perm(p->perm, M, p->sinv, s));
     } else {
         int64_t nparts = (M + 65535) / 65536;
         if (nparts > 64) nparts = 64;
@@ -236,6 +239,9 @@ FusedArgs<R> fused_args(const Plan *p)
     a.perm = p->perm;
     a.Xs = (const R *)p->Xs;
     a.off = p->off;
+    a.sinv = p->sinv;
+    a.gsort = (cx_t<R> *)p->gsort;
+    a.presorted = 0;
     a.t = p->t;
     a.X = (const R *)p->X;
     a.Y = (cx_t<R> *)p->Y;
@@ -284,6 +290,24 @@ static hipError_t exec_type2(const Plan *p, const void *c, void *f, int mode, co
         return plain_exec<R>(a, s);
     }
     return fused_type2<R>(fused_args<R>(p), (const C *)c, (C *)f, mode, (const C *)g, gx, s);
+}
+
+template <typename R>
+static nufft_status exec_backward(const Plan *p, const void *c, const void *g, void *gc, double *gx, hipStream_t s)
+{
+    using C = cx_t<R>;
+    FusedArgs<R> a = fused_args<R>(p);
+    const bool share = !(p->flags & NUFFT_FLAG_PLAIN) && p->L2 > 1 && gc && gx;
+    if (share) {
+        NUFFT_HIP_CHECK(fused_sort_input<R>(a, (const C *)g, "bwd_sort", s));
+        a.presorted = 1;
+    }
+    if (gc) NUFFT_HIP_CHECK(fused_type1<R>(a, (const C *)g, (C *)gc, +1, s));
+    if (gx) {
+        if (share) NUFFT_HIP_CHECK(fused_type2<R>(a, (const C *)c, nullptr, 1, (const C *)g, gx, s));
+        else NUFFT_HIP_CHECK(exec_type2<R>(p, c, nullptr, 1, g, gx, s));
+    }
+    return NUFFT_OK;
 }
 
 
@@ -741,6 +765,14 @@ nufft_status nufft2_grad_x(nufft_plan_t plan, const void *c, const void *g, doub
     hipStream_t s = (hipStream_t)stream;
     return from_hip(plan->dtype == NUFFT_C64 ? exec_type2<float>(plan, c, nullptr, 1, g, gx, s)
                                              : exec_type2<double>(plan, c, nullptr, 1, g, gx, s));
+}
+
+nufft_status nufft2_backward(nufft_plan_t plan, const void *c, const void *g, void *gc, double *gx, void *stream)
+{
+    if (!plan || plan->kind != PLAN_1D || !g || (!gc && !gx) || (gx && !c)) return NUFFT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    return plan->dtype == NUFFT_C64 ? exec_backward<float>(plan, c, g, gc, gx, s)
+                                    : exec_backward<double>(plan, c, g, gc, gx, s);
 }
 
 nufft_status nufft1_exec(nufft_plan_t plan, const void *c, void *f, int sign, void *stream)

@@ -186,6 +186,28 @@ k_sum_parts(const cx_t<R> *__restrict__ part, int nparts, int64_t N, cx_t<R> *__
     f[k] = a;
 }
 
+// out[sinv[j]] = in[j]: a sample-ordered vector put in the plan's sorted order.
+// Reads are coalesced and the writes scattered; a gather in sorted order would
+// instead fetch a whole cache line per 8- or 16-byte element.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_scatter_sorted(const cx_t<R> *__restrict__ in, const int32_t *__restrict__ sinv, int64_t M,
+                 cx_t<R> *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < M) out[sinv[j]] = in[j];
+}
+
+template <typename R>
+hipError_t fused_sort_input(const FusedArgs<R> &a, const cx_t<R> *in, const char *name, hipStream_t s)
+{
+    prof_begin(a.prof, name, s);
+    hipLaunchKernelGGL(k_scatter_sorted<R>, dim3((unsigned)((a.M + 255) / 256)), dim3(256), 0, s, in, a.sinv, a.M,
+                       a.gsort);
+    prof_end(a.prof, s);
+    return hipGetLastError();
+}
+
 // ============================================================================
 // L = L1 * L2: pass A (columns) and pass B (rows + samples)
 // ============================================================================
@@ -242,6 +264,13 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
         cv[q] = buf[g * P + lds_pad(lt + q * TPF)];
         zk[q] = zcoord<R>((k1_0 + g) + L1 * (int64_t)(lt + q * TPF), zm);
     }
+    // inter-pass twiddles of this thread's 16 output positions: the same for every rank
+    C wt[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * NT;
+        wt[e] = tw_big<C, -1>(hi, lo, (k1_0 + i % G) * (int64_t)(i / G));
+    }
     for (int r = r_lo; r < r_hi; ++r) {
         C v[16];
 #pragma unroll
@@ -249,12 +278,11 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
         __syncthreads();   // earlier readers of buf are done
         block_fft_regs<C, L2, -1>(buf + g * P, tw, lt, v);
         C *Yr = Y + (int64_t)r * L + k1_0;
-#pragma unroll 4
+#pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;
             const int gg = i % G, n2 = i / G;
-            const C w = tw_big<C, -1>(hi, lo, (k1_0 + gg) * (int64_t)n2);
-            Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], w);
+            Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], wt[e]);
         }
     }
 }
@@ -335,12 +363,12 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             }
         }
         int32_t jv[S];   // output positions: loaded together once the sums are done
+        C gj[S];         // derivative pass: g in sorted order (contiguous)
 #pragma unroll
-        for (int s = 0; s < S; ++s) jv[s] = perm[min(c0 + s * NT + tid, tile_hi - 1)];
-        C gj[S];
-        if (mode != 0) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) gj[s] = gup[jv[s]];
+        for (int s = 0; s < S; ++s) {
+            const int64_t i = min(c0 + s * NT + tid, tile_hi - 1);
+            jv[s] = perm[i];
+            if (mode != 0) gj[s] = gup[i];
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -370,8 +398,8 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
 // of an LDS copy, for the sizes where LDS would otherwise cap occupancy.
 template <typename R, int L1, int RC, int SCAP, int dir, bool TWG>
 __global__ void __launch_bounds__(RC * L1 / 16)
-k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict__ perm,
-            const R *__restrict__ Xs, const uint32_t *__restrict__ keys, const int32_t *__restrict__ off,
+k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__ Xs,
+            const uint32_t *__restrict__ keys, const int32_t *__restrict__ off,
             Factors<R> fac, const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi,
             const cx_t<R> *__restrict__ lo, cx_t<R> *__restrict__ Z)
 {
@@ -411,18 +439,15 @@ k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict
         // together (clamped indices), then the dependent loads of c, one wait each
         constexpr int SU = (SCAP + NT - 1) / NT;
         R xv[SU];
-        int32_t jv[SU];
         uint32_t kv[SU];
+        C cj[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int i = tile_lo + min(tid + u * NT, nst - 1);
             xv[u] = Xs[i];
-            jv[u] = perm[i];
             kv[u] = keys[i];
+            cj[u] = csort[i];
         }
-        C cj[SU];
-#pragma unroll
-        for (int u = 0; u < SU; ++u) cj[u] = c[jv[u]];
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int i = tid + u * NT;
@@ -434,6 +459,13 @@ k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict
                 spos[i] = (unsigned short)(kv[u] & (uint32_t)(L1 - 1));
             }
         }
+    }
+    // inter-pass twiddles of this thread's 16 grid points k1 (the same for every rank)
+    C wt[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const C w = tw_big<C, -1>(hi, lo, n2 * (int64_t)(lt + q * TPF));
+        wt[q] = dir > 0 ? cconj(w) : w;
     }
     __syncthreads();
     const int n_lo = tid * GPT;
@@ -464,7 +496,7 @@ k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict
                 const R Xi = Xs[tile_lo + i];
                 R sn, cs;
                 sincospi_r(Xi, &sn, &cs);
-                val = cmul(cmake<C>(cs, dir * sn), c[perm[tile_lo + i]]);
+                val = cmul(cmake<C>(cs, dir * sn), csort[tile_lo + i]);
                 z = Xi * fac.inv_gamma;
                 n1 = (int)(keys[tile_lo + i] & (uint32_t)(L1 - 1));
             }
@@ -492,12 +524,10 @@ k_passB_adj(const cx_t<R> *__restrict__ c, int64_t L2, const int32_t *__restrict
         const int r = r0 + g;
         if (r < fac.K) {
             C *Zr = Z + (int64_t)r * L + n2 * L1;
-#pragma unroll 4
+#pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int k1 = lt + q * TPF;
-                C w = tw_big<C, -1>(hi, lo, n2 * (int64_t)k1);
-                if (dir > 0) w = cconj(w);
-                Zr[k1] = cmul(buf[g * P + lds_pad(k1)], w);
+                Zr[k1] = cmul(buf[g * P + lds_pad(k1)], wt[q]);
             }
         }
         __syncthreads();   // the next chunk overwrites buf
@@ -690,6 +720,13 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
 #undef SF
         return hipGetLastError();
     }
+    if (mode != 0) {   // the derivative pass reads g in sorted order
+        if (!a.presorted) {
+            const hipError_t e = fused_sort_input<R>(a, g, "gradx_sort", s);
+            if (e != hipSuccess) return e;
+        }
+        g = a.gsort;
+    }
     // pass A
     prof_begin(a.prof, mode ? "gradx_passA" : "fwd_passA", s);
     switch (a.L2) {
@@ -748,6 +785,10 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         SMALL_SWITCH(SA)
 #undef SA
     }
+    if (!a.presorted) {
+        const hipError_t e = fused_sort_input<R>(a, c, DIR > 0 ? "adj_sort" : "type1_sort", s);
+        if (e != hipSuccess) return e;
+    }
     prof_begin(a.prof, DIR > 0 ? "adj_passB" : "type1_passB", s);
     switch (a.L1) {
 #define PBA(LL, RF, SCF, RD, SCD, TG)                                                                      \
@@ -755,7 +796,7 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         constexpr bool F = sizeof(R) == 4;                                                                 \
         constexpr int RR = F ? RF : RD, SC = F ? SCF : SCD;                                                \
         hipLaunchKernelGGL((k_passB_adj<R, LL, RR, SC, DIR, TG>), dim3(xcd_grid(a.L2)), dim3(RR * LL / 16), \
-                           0, s, c, (int64_t)a.L2, a.perm, a.Xs, a.keys, a.off, a.fac,                      \
+                           0, s, a.gsort, (int64_t)a.L2, a.Xs, a.keys, a.off, a.fac,                        \
                            DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, a.Y);                                     \
         break;                                                                                             \
     }
@@ -802,6 +843,9 @@ template hipError_t fused_type2<float>(const FusedArgs<float> &, const float2 *,
                                        double *, hipStream_t);
 template hipError_t fused_type2<double>(const FusedArgs<double> &, const double2 *, double2 *, int,
                                         const double2 *, double *, hipStream_t);
+template hipError_t fused_sort_input<float>(const FusedArgs<float> &, const float2 *, const char *, hipStream_t);
+template hipError_t fused_sort_input<double>(const FusedArgs<double> &, const double2 *, const char *,
+                                             hipStream_t);
 template hipError_t fused_type1<float>(const FusedArgs<float> &, const float2 *, float2 *, int, hipStream_t);
 template hipError_t fused_type1<double>(const FusedArgs<double> &, const double2 *, double2 *, int,
                                         hipStream_t);

@@ -80,6 +80,7 @@ hipError_t launch_assign(const double *x, int64_t M, int64_t L, double n_over_L,
 template <typename R>
 hipError_t launch_gather_sorted(const int32_t *perm, const R *X, int64_t n, R *Xs, hipStream_t s);
 hipError_t launch_iota(int32_t *v, int64_t n, hipStream_t s);
+hipError_t launch_invert_perm(const int32_t *perm, int64_t n, int32_t *sinv, hipStream_t s);
 hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
 int64_t radix_tmp_elems(int64_t n);
@@ -119,6 +120,9 @@ struct FusedArgs {
     const int32_t *perm;     // M: sample index at each sorted position
     const R *Xs;             // M sorted perturbations X = N (x - s/L)
     const int32_t *off;      // L + 1: first sorted position of each key
+    const int32_t *sinv;     // M: sorted position of each sample (two-pass plans)
+    cx_t<R> *gsort;          // M: a sample-ordered input put in sorted order (two-pass plans)
+    int presorted;           // 1: gsort already holds the sorted input of this call
     const int32_t *t;        // M grid indices, sample order
     const R *X;              // M perturbations, sample order
     cx_t<R> *Y;              // K x L intermediate of the two-pass split
@@ -136,5 +140,8 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
 // sign -1: f = F2^T c (type I); sign +1: f = F2^H c (adjoint)
 template <typename R>
 hipError_t fused_type1(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int sign, hipStream_t s);
+// a sample-ordered M-vector into a.gsort (two-pass plans); `name` labels it for the profiler
+template <typename R>
+hipError_t fused_sort_input(const FusedArgs<R> &a, const cx_t<R> *in, const char *name, hipStream_t s);
 
 }  // namespace nufft

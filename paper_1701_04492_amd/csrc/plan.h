@@ -36,6 +36,8 @@ struct nufft_plan_s {
     uint32_t *keys = nullptr;       // M sorted keys (t mod L2) * L1 + t / L2
     int32_t *perm = nullptr;        // M sample index per sorted position
     int32_t *off = nullptr;         // L + 1 CSR offsets per key
+    int32_t *sinv = nullptr;        // M sorted position per sample (two-pass)
+    void *gsort = nullptr;          // M complex: sample-ordered input in sorted order (two-pass)
     void *U = nullptr, *W = nullptr, *W2 = nullptr;   // plain path
     void *Y = nullptr;              // K x L two-pass intermediate
     void *tw1 = nullptr, *tw2 = nullptr, *hi = nullptr, *lo = nullptr;

@@ -230,6 +230,13 @@ __global__ void k_iota(int32_t *v, int64_t n)
     if (i < n) v[i] = (int32_t)i;
 }
 
+// sinv[perm[i]] = i: the sorted position of every sample.
+__global__ void k_invert_perm(const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ sinv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) sinv[perm[i]] = (int32_t)i;
+}
+
 int64_t radix_tmp_elems(int64_t n)
 {
     const int64_t nb = (n + RS_BLOCK - 1) / RS_BLOCK;
@@ -292,6 +299,13 @@ hipError_t launch_iota(int32_t *v, int64_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_perm(const int32_t *perm, int64_t n, int32_t *sinv, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_invert_perm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, perm, n, sinv);
     return hipGetLastError();
 }
 

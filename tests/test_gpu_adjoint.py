@@ -119,6 +119,26 @@ def test_grad_x_pass(dtype):
     assert np.all(np.abs(gx - ref) <= bound)
 
 
+@pytest.mark.parametrize("N,M", [(3000, 2500), (20000, 17000), (1 << 16, 1 << 16)])
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_backward_matches_separate_calls(N, M, dtype):
+    """nufft2_backward (g sorted once, shared) gives exactly the results of the two separate calls."""
+    rng = W.rng_for(35)
+    x = rng.random(M)
+    c, g = W.complex_normal(rng, N), W.complex_normal(rng, M)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS[dtype], dtype)
+    ct, gt = _t(c, dtype), _t(g, dtype)
+    gc_ref = P.nufft1_exec(plan, gt, sign=+1)
+    gx_ref = P.nufft2_grad_x(plan, ct, gt)
+    gc, gx = P.nufft2_backward(plan, ct, gt)
+    assert torch.equal(gc, gc_ref) and torch.equal(gx, gx_ref)
+    gc_only, none_x = P.nufft2_backward(plan, ct, gt, need_x=False)
+    none_c, gx_only = P.nufft2_backward(plan, ct, gt, need_c=False)
+    assert none_x is None and none_c is None
+    assert torch.equal(gc_only, gc_ref) and torch.equal(gx_only, gx_ref)
+    _say("backward", N, M, dtype, "identical to separate calls")
+
+
 def test_autograd_fp64_against_oracle_and_fd():
     """Loss ||f - y||^2 at N = 4096 in FP64: both gradients against the oracle's,
     and the oracle's against central differences of the oracle."""

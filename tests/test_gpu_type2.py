@@ -195,7 +195,7 @@ def test_kernel_profiling_hook():
         P.nufft2_exec(plan, ct)
     P.nufft1_exec(plan, ct, sign=+1)
     prof = P.nufft_plan_profile_read(plan)
-    assert set(prof) == {"fwd_passA", "fwd_passB", "adj_passB", "adj_passA"}
+    assert set(prof) == {"fwd_passA", "fwd_passB", "adj_sort", "adj_passB", "adj_passA"}
     assert prof["fwd_passA"][0] == 3 and prof["adj_passA"][0] == 1
     assert all(ms > 0 for _, ms in prof.values())
     P.nufft_plan_profile(plan, 0)
