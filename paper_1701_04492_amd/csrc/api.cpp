@@ -118,16 +118,16 @@ template <typename R>
 nufft_status upload_twiddles(Plan *p, hipStream_t s)
 {
     std::vector<double> t1(2 * (size_t)p->L1), t1i(2 * (size_t)p->L1);
-    twiddles(p->L1, p->L1, 1, -1, t1.data());
-    twiddles(p->L1, p->L1, 1, 1, t1i.data());
+    fft_twiddles(p->L1, -1, t1.data());
+    fft_twiddles(p->L1, 1, t1i.data());
     nufft_status st = upload_table<R>(p, t1, &p->tw1, s);
     if (st) return st;
     if ((st = upload_table<R>(p, t1i, &p->tw1i, s))) return st;
     if (p->L2 > 1) {
         std::vector<double> t2(2 * (size_t)p->L2), lo(2 * 4096), hi(2 * (size_t)(p->L / 4096));
         std::vector<double> t2i(2 * (size_t)p->L2);
-        twiddles(p->L2, p->L2, 1, -1, t2.data());
-        twiddles(p->L2, p->L2, 1, 1, t2i.data());
+        fft_twiddles(p->L2, -1, t2.data());
+        fft_twiddles(p->L2, 1, t2i.data());
         if ((st = upload_table<R>(p, t2i, &p->tw2i, s))) return st;
         twiddles(p->L, 4096, 1, -1, lo.data());
         twiddles(p->L, p->L / 4096, 4096, -1, hi.data());
@@ -476,13 +476,13 @@ nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
     }
     std::vector<double> t(2 * (size_t)std::max(p->Gx, p->Gy));
     nufft_status st;
-    twiddles(p->Gx, p->Gx, 1, -1, t.data());
+    fft_twiddles(p->Gx, -1, t.data());
     if ((st = upload_table<R>(p, std::vector<double>(t.begin(), t.begin() + 2 * p->Gx), &p->twx, s))) return st;
-    twiddles(p->Gx, p->Gx, 1, 1, t.data());
+    fft_twiddles(p->Gx, 1, t.data());
     if ((st = upload_table<R>(p, std::vector<double>(t.begin(), t.begin() + 2 * p->Gx), &p->twxi, s))) return st;
-    twiddles(p->Gy, p->Gy, 1, -1, t.data());
+    fft_twiddles(p->Gy, -1, t.data());
     if ((st = upload_table<R>(p, std::vector<double>(t.begin(), t.begin() + 2 * p->Gy), &p->twy, s))) return st;
-    twiddles(p->Gy, p->Gy, 1, 1, t.data());
+    fft_twiddles(p->Gy, 1, t.data());
     if ((st = upload_table<R>(p, std::vector<double>(t.begin(), t.begin() + 2 * p->Gy), &p->twyi, s))) return st;
     // forward pass-B tasks: each column n2 split into sample ranges of at most cap
     const int cap = pass_b2d_cap(p->Gx, p->dtype == NUFFT_C64);

@@ -107,6 +107,29 @@ void cis_2pi_frac(int64_t m, int64_t L, double *c, double *s)
     }
 }
 
+void fft_twiddles(int64_t L, int dir, double *out)
+{
+    // Stage-major layout read by the LDS FFT: the stage that combines NS-point
+    // transforms with radix R keeps exp(dir 2 pi i q k / (NS R)), 0 <= k < NS,
+    // 1 <= q < R, at NS - 1 + k (R - 1) + q - 1 (the stages tile [0, L - 1)).
+    // Consecutive k are R - 1 elements apart: an odd stride, so the lanes of a
+    // wave read different LDS banks.
+    out[2 * (L - 1)] = 1.0;   // entry L - 1 is unused
+    out[2 * (L - 1) + 1] = 0.0;
+    for (int64_t NS = 1; NS < L;) {
+        const int64_t R = (L / NS >= 16) ? 16 : L / NS;
+        for (int64_t k = 0; k < NS; ++k)
+            for (int64_t q = 1; q < R; ++q) {
+                double c, s;
+                cis_2pi_frac(q * k, NS * R, &c, &s);
+                const int64_t m = NS - 1 + k * (R - 1) + q - 1;
+                out[2 * m] = c;
+                out[2 * m + 1] = dir * s;
+            }
+        NS *= R;
+    }
+}
+
 void twiddles(int64_t L, int64_t count, int64_t step, int dir, double *out)
 {
     for (int64_t m = 0; m < count; ++m) {

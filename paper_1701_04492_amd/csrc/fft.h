@@ -14,8 +14,11 @@
 // banks).
 //
 // Direction DIR = -1 computes X_n = sum_k x_k exp(-2 pi i n k / L) (the DFT of
-// Sec. 1); DIR = +1 the unnormalised inverse.  Twiddles come from a table
-// tw[m] = exp(DIR 2 pi i m / L), m < L, computed in FP64 on the host.
+// Sec. 1); DIR = +1 the unnormalised inverse.  Twiddles come from an L-entry
+// table computed in FP64 on the host, stage-major: the stage that combines
+// NS-point transforms with radix R reads exp(DIR 2 pi i q k / (NS R)) at
+// NS - 1 + k (R - 1) + q - 1 (an odd stride between consecutive k, so the
+// lanes of a wave hit different LDS banks).
 #pragma once
 
 #include "common.h"
@@ -163,7 +166,7 @@ __device__ __forceinline__ void stage_compute_store(C *buf, const C *tw, int lt,
             const int k = b % NS;
 #pragma unroll
             for (int q = 1; q < R; ++q)
-                v[i * R + q] = cmul(v[i * R + q], tw[q * k * (L / (NS * R))]);
+                v[i * R + q] = cmul(v[i * R + q], tw[(NS - 1) + k * (R - 1) + (q - 1)]);
         }
         dft<R, C, DIR>(v + i * R);
     }
