@@ -7,6 +7,7 @@ the library is not built, importing this module raises.
 import ctypes
 import os
 import re
+import sys
 
 import numpy as np
 import torch
@@ -119,7 +120,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        # at interpreter exit the process releases device memory itself
+        if h and lib is not None and not sys.is_finalizing():
             lib.nufft_destroy(h)
             self.handle = None
 

@@ -504,6 +504,39 @@ nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
         NUFFT_HIP_CHECK(hipMemcpyAsync(p->tasks, tk.data(), tk.size() * sizeof(int4), hipMemcpyHostToDevice, s));
         NUFFT_HIP_CHECK(hipStreamSynchronize(s));
     }
+    // adjoint pass-B' tasks: a column whose samples exceed the LDS staging of one
+    // workgroup is split into slices that write partial rows (summed in order)
+    const int acap = pass_b2d_adj_cap(p->Gx, p->dtype == NUFFT_C64);
+    if (acap <= 0) return NUFFT_ERR_UNSUPPORTED;
+    std::vector<int4> at, rt;
+    int nslots = 0;
+    for (int n2 = 0; n2 < p->Gy; ++n2) {
+        const int a0 = toff[n2], a1 = toff[n2 + 1];
+        if (a1 - a0 <= acap) {
+            at.push_back(make_int4(n2, a0, a1, -1));   // also empty columns: their rows are zero
+            continue;
+        }
+        const int parts = (a1 - a0 + acap - 1) / acap;
+        rt.push_back(make_int4(n2, nslots, parts, 0));
+        for (int q = 0; q < parts; ++q) {
+            const int b0 = a0 + (int)((int64_t)(a1 - a0) * q / parts);
+            const int b1 = a0 + (int)((int64_t)(a1 - a0) * (q + 1) / parts);
+            at.push_back(make_int4(n2, b0, b1, nslots++));
+        }
+    }
+    p->natasks = (int)at.size();
+    p->nrtasks = (int)rt.size();
+    p->atasks = (int4 *)p->alloc(at.size() * sizeof(int4));
+    p->rtasks = (int4 *)p->alloc(std::max<size_t>(1, rt.size()) * sizeof(int4));
+    if (!p->atasks || !p->rtasks) return NUFFT_ERR_ALLOC;
+    if (nslots > 0) {
+        p->Zp = p->alloc((size_t)nslots * p->Ky * p->Gx * 2 * sizeof(R));
+        if (!p->Zp) return NUFFT_ERR_ALLOC;
+    }
+    NUFFT_HIP_CHECK(hipMemcpyAsync(p->atasks, at.data(), at.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    if (!rt.empty())
+        NUFFT_HIP_CHECK(hipMemcpyAsync(p->rtasks, rt.data(), rt.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));   // the host task tables go out of scope
     p->Y = p->alloc((size_t)p->Ky * G2 * 2 * sizeof(R));
     if (!p->Y) return NUFFT_ERR_ALLOC;
     return NUFFT_OK;
@@ -532,6 +565,11 @@ static Args2D<R> args_2d(const Plan *p)
     a.off = p->off;
     a.tasks = p->tasks;
     a.ntasks = p->ntasks;
+    a.atasks = p->atasks;
+    a.natasks = p->natasks;
+    a.rtasks = p->rtasks;
+    a.nrtasks = p->nrtasks;
+    a.Zp = (cx_t<R> *)p->Zp;
     a.H = (cx_t<R> *)p->Y;
     a.twx = (const cx_t<R> *)p->twx;
     a.twxi = (const cx_t<R> *)p->twxi;
@@ -627,9 +665,14 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
             for (int cg = 0; cg < desc[b].n_pass_a; ++cg) tk.push_back(make_int4(BATCH_PASS_A, b, cg, 0));
         }
     }
+    // PASS_B tasks: runs of consecutive tiles holding about batch_pass_b_points() grid
+    // points, so that the per-task set-up (claim, descriptor, twiddle table) is amortised
     for (int b : order)
-        if (desc[b].L2 > 1)
-            for (int n2 = 0; n2 < desc[b].L2; ++n2) tk.push_back(make_int4(BATCH_PASS_B, b, n2, 0));
+        if (desc[b].L2 > 1) {
+            const int run = (int)std::max<int64_t>(1, std::min<int64_t>(desc[b].L2, batch_pass_b_points() / desc[b].L1));
+            for (int n2 = 0; n2 < desc[b].L2; n2 += run)
+                tk.push_back(make_int4(BATCH_PASS_B, b, n2, (int)std::min<int64_t>(run, desc[b].L2 - n2)));
+        }
     p->bntasks = (int)tk.size();
     Factors<R> *dfac = (Factors<R> *)p->alloc(B * sizeof(Factors<R>));
     p->bdesc = p->alloc(B * sizeof(BatchDesc<R>));

@@ -36,6 +36,7 @@ size_t batch_lds_bytes(int L, int L1, int L2, bool fp32);
 int batch_threads();
 int batch_small_chunk();
 int batch_pass_a_cols(int L2);
+int batch_pass_b_points();     // grid points per PASS_B task (runs of whole tiles)
 template <typename R>
 hipError_t batch_launch(const BatchDesc<R> *descs, const int4 *tasks, int ntasks, BatchCtl *ctl,
                         const cx_t<R> *const *cs, cx_t<R> *const *fs, int grid, size_t lds, hipStream_t s);

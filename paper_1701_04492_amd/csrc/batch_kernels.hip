@@ -5,21 +5,30 @@
 //   SMALL tasks (L_b <= 4096: scale, all K FFTs in LDS and a slice of the
 //   samples, as the one-workgroup kernel does), or
 //   PASS_A tasks (a group of columns of the two-pass split) followed, after
-//   every phase-1 task of the batch, by PASS_B tasks (one output tile each).
-// Workgroups claim tasks in table order from an atomic counter.  A PASS_B
-// task waits until every PASS_A task of its transform has finished (counter
-// per transform, device-scope release/acquire).  Because all phase-1 tasks
-// precede all PASS_B tasks in the table and a phase-1 task never waits, every
-// wait ends: each unfinished PASS_A task the waiter depends on is already
-// held by a running workgroup.  The last workgroup to leave resets the
-// counters, so the launch can be replayed (HIP graph) without any memset.
+//   every phase-1 task of the batch, by PASS_B tasks (a run of consecutive
+//   output tiles, about 2048 grid points, so that the per-task set-up is
+//   amortised over many small tiles).
+// Workgroups claim tasks in table order from an atomic counter, one task
+// ahead of the one they run.  A PASS_B task waits until every PASS_A task of
+// its transform has finished (counter per transform, device-scope
+// release/acquire).  Because all phase-1 tasks precede all PASS_B tasks in the
+// table and a phase-1 task never waits, every wait ends: each unfinished
+// PASS_A task the waiter depends on is held, as its current or next task, by
+// a running workgroup whose current task does not wait.  The last workgroup
+// to leave resets the counters, so the launch can be replayed (HIP graph)
+// without any memset.
 #include "batch.h"
 #include "fused_common.h"
 
 namespace nufft {
 
 #define BNT 256              // threads per workgroup of the persistent kernel
+#ifndef BSLOTS
 #define BSLOTS 8             // sample slots per thread in SMALL tasks
+#endif
+#ifndef NUFFT_BATCH_WAVES
+#define NUFFT_BATCH_WAVES 2  // waves per SIMD the register allocation targets
+#endif
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -119,6 +128,12 @@ __device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, in
 #pragma unroll
     for (int q = 0; q < 16; ++q) cv[q] = buf[g * P + lds_pad(lt + q * TPF)];
     const ZMap zm = zmap(d.N);
+    C wt[16];   // inter-pass twiddles of this thread's output positions, the same for every rank
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = tid + e * BNT;
+        wt[e] = tw_big<C, -1>(d.hi, d.lo, (k1_0 + i % G) * (int64_t)(i / G));
+    }
     for (int r = 0; r < K; ++r) {
         C v[16];
 #pragma unroll
@@ -127,12 +142,11 @@ __device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, in
         __syncthreads();
         block_fft_regs<C, L2, -1>(buf + g * P, tw, lt, v);
         C *Yr = d.Y + (int64_t)r * L + k1_0;
-#pragma unroll 4
+#pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * BNT;
             const int gg = i % G, n2 = i / G;
-            const C w = tw_big<C, -1>(d.hi, d.lo, (k1_0 + gg) * (int64_t)n2);
-            Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], w);
+            Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], wt[e]);
         }
     }
     __syncthreads();   // LDS is reused by the next task
@@ -140,7 +154,7 @@ __device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, in
 
 // ---- PASS_B: one tile n2, RC = 4096 / L1 ranks side by side ------------------------------
 template <typename R, int L1, int S>
-__device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2, char *lds)
+__device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2_first, int n2_count, char *lds)
 {
     using C = cx_t<R>;
     constexpr int TPF = L1 / 16;
@@ -155,6 +169,7 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2, 
     const int64_t L = d.L;
     const Factors<R> &fac = *d.fac;
     const int K = fac.K;
+    for (int n2 = n2_first; n2 < n2_first + n2_count; ++n2) {
     const int64_t tile_lo = d.off[(int64_t)n2 * L1], tile_hi = d.off[(int64_t)(n2 + 1) * L1];
     const C *Yrow = d.Y + (int64_t)n2 * L1 + lt;
     for (int64_t c0 = tile_lo; c0 < tile_hi; c0 += CAP) {
@@ -209,24 +224,30 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2, 
         }
         __syncthreads();
     }
+    }
 }
 
 template <typename R>
-__global__ void __launch_bounds__(BNT)
+__global__ void __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(NUFFT_BATCH_WAVES)))
 k_batch(const BatchDesc<R> *__restrict__ descs, const int4 *__restrict__ tasks, int ntasks, BatchCtl *ctl,
         const cx_t<R> *const *__restrict__ cs, cx_t<R> *const *__restrict__ fs, int64_t spin_limit)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ int s_task;
     const int tid = threadIdx.x;
+    // Claim-ahead: the next task is claimed while the current one runs.  A
+    // PASS_B task held as "next" never blocks a PASS_A task it depends on:
+    // every PASS_A task precedes every PASS_B task in the table, so a
+    // workgroup whose current task waits holds only PASS_B tasks.
+    if (tid == 0) s_task = atomicAdd(&ctl->next, 1);
+    __syncthreads();
+    int t = uniform(s_task);
     for (;;) {
-        if (tid == 0) s_task = atomicAdd(&ctl->next, 1);
-        __syncthreads();
-        const int t = uniform(s_task);
         __syncthreads();   // s_task is rewritten only after everyone has read it
         if (t >= ntasks) break;
+        if (tid == 0) s_task = atomicAdd(&ctl->next, 1);
         const int4 tk = tasks[t];
-        const int type = uniform(tk.x), b = uniform(tk.y), par = uniform(tk.z);
+        const int type = uniform(tk.x), b = uniform(tk.y), par = uniform(tk.z), par2 = uniform(tk.w);
         const BatchDesc<R> &d = descs[b];
         if (type == BATCH_PASS_B) {
             if (tid == 0) {
@@ -264,14 +285,15 @@ k_batch(const BatchDesc<R> *__restrict__ descs, const int4 *__restrict__ tasks, 
             break;
         default:
             switch (d.L1) {
-#define BB(LL, SS) case LL: b_passB<R, LL, SS>(d, fs[b], par, lds); break;
+#define BB(LL, SS) case LL: b_passB<R, LL, SS>(d, fs[b], par, par2, lds); break;
                 BB(128, 1) BB(256, 2) BB(512, 3) BB(1024, 5)
 #undef BB
             default: break;
             }
             break;
         }
-        __syncthreads();
+        __syncthreads();   // the task is done; s_task holds the next claim
+        t = uniform(s_task);
     }
     // the last workgroup out resets the queue for the next launch
     if (tid == 0) {
@@ -301,6 +323,7 @@ size_t batch_lds_bytes(int L, int L1, int L2, bool fp32)
 int batch_threads() { return BNT; }
 int batch_small_chunk() { return BNT * BSLOTS; }
 int batch_pass_a_cols(int L2) { return BNT / (L2 / 16); }
+int batch_pass_b_points() { return 2048; }
 
 template <typename R>
 hipError_t batch_launch(const BatchDesc<R> *descs, const int4 *tasks, int ntasks, BatchCtl *ctl,

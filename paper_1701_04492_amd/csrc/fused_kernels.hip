@@ -437,26 +437,30 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
     if (nst > 0) {
         // stage the tile's samples: all index/value loads of a thread in flight
         // together (clamped indices), then the dependent loads of c, one wait each
-        constexpr int SU = (SCAP + NT - 1) / NT;
-        R xv[SU];
-        uint32_t kv[SU];
-        C cj[SU];
+        constexpr int SU = (SCAP + NT - 1) / NT;   // staging rounds per thread
+        constexpr int SB = SU < 8 ? SU : 8;          // rounds whose loads are in flight together
+        for (int u0 = 0; u0 < SU; u0 += SB) {
+            if (u0 * NT >= nst) break;
+            R xv[SB];
+            uint32_t kv[SB];
+            C cj[SB];
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int i = tile_lo + min(tid + u * NT, nst - 1);
-            xv[u] = Xs[i];
-            kv[u] = keys[i];
-            cj[u] = csort[i];
-        }
+            for (int u = 0; u < SB; ++u) {
+                const int i = tile_lo + min(tid + (u0 + u) * NT, nst - 1);
+                xv[u] = Xs[i];
+                kv[u] = keys[i];
+                cj[u] = csort[i];
+            }
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int i = tid + u * NT;
-            if (i < nst) {
-                R sn, cs;
-                sincospi_r(xv[u], &sn, &cs);
-                sval[i] = cmul(cmake<C>(cs, dir * sn), cj[u]);
-                sz[i] = xv[u] * fac.inv_gamma;
-                spos[i] = (unsigned short)(kv[u] & (uint32_t)(L1 - 1));
+            for (int u = 0; u < SB; ++u) {
+                const int i = tid + (u0 + u) * NT;
+                if (i < nst) {
+                    R sn, cs;
+                    sincospi_r(xv[u], &sn, &cs);
+                    sval[i] = cmul(cmake<C>(cs, dir * sn), cj[u]);
+                    sz[i] = xv[u] * fac.inv_gamma;
+                    spos[i] = (unsigned short)(kv[u] & (uint32_t)(L1 - 1));
+                }
             }
         }
     }
@@ -804,8 +808,8 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         PBA(256, 16, 384, 8, 384, false)
         PBA(512, 8, 768, 4, 768, false)
         PBA(1024, 4, 1280, 4, 1280, false)
-        PBA(2048, 2, 2304, 2, 1280, true)
-        PBA(4096, 1, 2304, 1, 256, true)
+        PBA(2048, 2, 2304, 2, 2304, true)
+        PBA(4096, 1, 5120, 1, 2560, true)
 #undef PBA
     default: return hipErrorInvalidValue;
     }

@@ -16,6 +16,11 @@ struct Args2D {
     const int32_t *off;       // Gx * Gy + 1 first sorted position per key
     const int4 *tasks;        // forward pass-B tasks (column n2, first, end)
     int ntasks;
+    const int4 *atasks;       // adjoint pass-B' tasks (column n2, first, end, partial slot or -1)
+    int natasks;
+    const int4 *rtasks;       // split columns (n2, first slot, slots)
+    int nrtasks;
+    cx_t<R> *Zp;              // partial rows of split columns: slots x Ky x Gx
     cx_t<R> *H;               // Ky x Gy x Gx intermediate [r2][n2][k1]
     const cx_t<R> *twx, *twxi, *twy, *twyi;   // FFT tables, both signs
     Profiler *prof;
@@ -26,6 +31,7 @@ hipError_t fused_2d(const Args2D<R> &a, const cx_t<R> *Cin, cx_t<R> *f, hipStrea
 template <typename R>
 hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, hipStream_t s);
 int pass_b2d_cap(int GX, bool fp32);
+int pass_b2d_adj_cap(int GX, bool fp32);
 template <typename R>
 hipError_t launch_assign2d(const double *x, const double *y, int64_t M, int64_t GX, int64_t GY, double sx,
                            double sy, R *Xx, R *Xy, uint32_t *key, int32_t *hist, unsigned long long *gbits,

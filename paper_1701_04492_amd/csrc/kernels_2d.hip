@@ -169,18 +169,20 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
     }
 }
 
-// ---- adjoint pass B': one column n2 -> Z_r2[n2][k1] -----------------------------
-// The column's samples are staged in LDS (exp(+i pi (Xx + Xy)) g_j, zx, zy, tx);
-// for each r2 and chunk of RC ranks r1 the samples are summed per grid point
-// (each thread walks the contiguous run of samples of its own grid points),
-// transformed along n1 (inverse sign), weighted by v^x_r1(k1) and summed over r1
-// in registers; the row Z_r2[n2][:] is written once per r2.
+// ---- adjoint pass B': one column n2 (or a slice of its samples) -> Z_r2[n2][k1] ----
+// Task = (n2, first, end, slot): the sorted samples [first, end) of column n2,
+// at most SCAP of them, staged once in LDS (exp(+i pi (Xx + Xy)) g_j, zx, zy,
+// tx).  For each r2 and chunk of RC ranks r1 they are summed per grid point
+// (balanced segmented sum, deterministic), transformed along n1 (inverse
+// sign), weighted by v^x_r1(k1) and summed over r1 in registers; the row for
+// r2 is written once: to Z_r2[n2][:] when the task holds the whole column
+// (slot < 0), else to partial row `slot` of Zp, which k_2d_sum_parts adds up.
 template <typename R, int GX, int RC, int SCAP, bool TWG>
 __global__ void __launch_bounds__(RC * GX / 16)
-k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const int32_t *__restrict__ perm,
-               const uint32_t *__restrict__ keys, const R *__restrict__ Xxs, const R *__restrict__ Xys,
-               const int32_t *__restrict__ off, Factors<R> fx, Factors<R> fy, const cx_t<R> *__restrict__ twi_g,
-               cx_t<R> *__restrict__ Z)
+k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const int4 *__restrict__ tasks, int ntasks,
+               const int32_t *__restrict__ perm, const uint32_t *__restrict__ keys, const R *__restrict__ Xxs,
+               const R *__restrict__ Xys, Factors<R> fx, Factors<R> fy, const cx_t<R> *__restrict__ twi_g,
+               cx_t<R> *__restrict__ Z, cx_t<R> *__restrict__ Zp)
 {
     using C = cx_t<R>;
     constexpr int TPF = GX / 16;
@@ -195,43 +197,47 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     __shared__ C hv[RC * NT], tv[RC * NT];
     __shared__ int hix[NT], tix[NT];
     const C *tw = TWG ? twi_g : tw_s;
-    const int task = xcd_task((int)GY);
+    const int task = xcd_task(ntasks);
     if (task < 0) return;
+    const int4 tk = tasks[task];
     const int tid = threadIdx.x;
     if (!TWG) load_tw_s<C, GX, -1, NT>(tw_s, twi_g);   // twi_g already has the + sign
     const int g = tid / TPF, lt = tid % TPF;
-    const int64_t n2 = task;
-    const int tile_lo = off[n2 * GX];
-    const int cnt = off[(n2 + 1) * GX] - tile_lo;
-    const int nst = min(cnt, SCAP);
-    if (nst > 0) {
-        // stage the column's samples: index/value loads of a thread issued
-        // together (clamped indices), then the dependent loads of g
+    const int64_t n2 = tk.x;
+    const int tile_lo = tk.y;
+    const int cnt = min(tk.z - tk.y, SCAP);   // the plan never makes a task larger than SCAP
+    if (cnt > 0) {
+        // stage the samples: index/value loads of a thread issued together
+        // (clamped indices), then the dependent loads of g
         constexpr int SU = (SCAP + NT - 1) / NT;
-        R ax[SU], ay[SU];
-        int32_t jv[SU];
-        uint32_t kv[SU];
+        constexpr int SB = SU < 8 ? SU : 8;
+        for (int u0 = 0; u0 < SU; u0 += SB) {
+            if (u0 * NT >= cnt) break;
+            R ax[SB], ay[SB];
+            int32_t jv[SB];
+            uint32_t kv[SB];
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int i = tile_lo + min(tid + u * NT, nst - 1);
-            ax[u] = Xxs[i];
-            ay[u] = Xys[i];
-            jv[u] = perm[i];
-            kv[u] = keys[i];
-        }
-        C gv[SU];
+            for (int u = 0; u < SB; ++u) {
+                const int i = tile_lo + min(tid + (u0 + u) * NT, cnt - 1);
+                ax[u] = Xxs[i];
+                ay[u] = Xys[i];
+                jv[u] = perm[i];
+                kv[u] = keys[i];
+            }
+            C gv[SB];
 #pragma unroll
-        for (int u = 0; u < SU; ++u) gv[u] = gin[jv[u]];
+            for (int u = 0; u < SB; ++u) gv[u] = gin[jv[u]];
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int i = tid + u * NT;
-            if (i < nst) {
-                R sn, cs;
-                sincospi_r(ax[u] + ay[u], &sn, &cs);
-                sval[i] = cmul(cmake<C>(cs, sn), gv[u]);
-                szx[i] = ax[u] * fx.inv_gamma;
-                szy[i] = ay[u] * fy.inv_gamma;
-                spos[i] = (unsigned short)(kv[u] & (uint32_t)(GX - 1));
+            for (int u = 0; u < SB; ++u) {
+                const int i = tid + (u0 + u) * NT;
+                if (i < cnt) {
+                    R sn, cs;
+                    sincospi_r(ax[u] + ay[u], &sn, &cs);
+                    sval[i] = cmul(cmake<C>(cs, sn), gv[u]);
+                    szx[i] = ax[u] * fx.inv_gamma;
+                    szy[i] = ay[u] * fy.inv_gamma;
+                    spos[i] = (unsigned short)(kv[u] & (uint32_t)(GX - 1));
+                }
             }
         }
     }
@@ -240,7 +246,7 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
         __syncthreads();   // staging done / previous readers of spy done
         {
             const RankPoly<R> uy = rank_poly(fy, r2);
-            for (int i = tid; i < nst; i += NT) spy[i] = rank_eval(uy, szy[i]);
+            for (int i = tid; i < cnt; i += NT) spy[i] = rank_eval(uy, szy[i]);
         }
         __syncthreads();
         C za[ZA];
@@ -250,21 +256,12 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
             const int nr = min(RC, fx.K - r0);
             for (int m = tid; m < RC * P; m += NT) buf[m] = cmake<C>(0, 0);
             __syncthreads();
-            auto pos = [&](int i) -> int {
-                return i < SCAP ? (int)spos[i] : (int)(keys[tile_lo + i] & (uint32_t)(GX - 1));
-            };
+            auto pos = [&](int i) -> int { return (int)spos[i]; };
             RankPoly<R> ux[RC];
 #pragma unroll
             for (int gg = 0; gg < RC; ++gg) ux[gg] = rank_poly(fx, min(r0 + gg, fx.K - 1));
             auto contrib = [&](int i, int gg) -> C {
-                const int r1 = r0 + gg;
-                if (i < SCAP) return crot(cscale(sval[i], rank_eval(ux[gg], szx[i]) * spy[i]), -(r1 + r2));
-                const R ax = Xxs[tile_lo + i], ay = Xys[tile_lo + i];
-                R sn, cs;
-                sincospi_r(ax + ay, &sn, &cs);
-                const C val = cmul(cmake<C>(cs, sn), gin[perm[tile_lo + i]]);
-                return crot(cscale(val, upoly(fx, r1, ax * fx.inv_gamma) * upoly(fy, r2, ay * fy.inv_gamma)),
-                            -(r1 + r2));
+                return crot(cscale(sval[i], rank_eval(ux[gg], szx[i]) * spy[i]), -(r0 + gg + r2));
             };
             seg_spread<C, RC, NT>(cnt, nr, pos, contrib, buf, P, hv, tv, hix, tix);
             __syncthreads();
@@ -278,9 +275,27 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
             }
             __syncthreads();
         }
-        C *Zrow = Z + ((int64_t)r2 * GY + n2) * GX;
+        C *Zrow = tk.w < 0 ? Z + ((int64_t)r2 * GY + n2) * GX : Zp + ((int64_t)tk.w * fy.K + r2) * GX;
 #pragma unroll
         for (int m = 0; m < ZA; ++m) Zrow[tid + m * NT] = za[m];
+    }
+}
+
+// Columns whose samples were split over several pass-B' tasks: task t = (n2,
+// first slot, number of slots) adds the partial rows in slot order (a fixed
+// order: the result does not depend on timing).  Block = (t, r2).
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_2d_sum_parts(const int4 *__restrict__ rtasks, const cx_t<R> *__restrict__ Zp, int64_t GX, int64_t GY, int Ky,
+               cx_t<R> *__restrict__ Z)
+{
+    using C = cx_t<R>;
+    const int4 rt = rtasks[blockIdx.x];
+    const int r2 = blockIdx.y;
+    for (int64_t k1 = threadIdx.x; k1 < GX; k1 += blockDim.x) {
+        C a = Zp[((int64_t)rt.y * Ky + r2) * GX + k1];
+        for (int q = 1; q < rt.z; ++q) a = cadd(a, Zp[((int64_t)(rt.y + q) * Ky + r2) * GX + k1]);
+        Z[((int64_t)r2 * GY + rt.x) * GX + k1] = a;
     }
 }
 
@@ -419,9 +434,9 @@ hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, h
 #define BA2(GG, RF, SCF, RD, SCD, TG)                                                                        \
     case GG: {                                                                                              \
         constexpr int RR = F ? RF : RD, SC = F ? SCF : SCD;                                                 \
-        hipLaunchKernelGGL((k_2d_passB_adj<R, GG, RR, SC, TG>), dim3(xcd_grid(a.Gy)), dim3(RR * GG / 16), 0, \
-                           s, gin, a.N1, (int64_t)a.Gy, a.perm, a.keys, a.Xxs, a.Xys, a.off, a.fx, a.fy,     \
-                           a.twxi, a.H);                                                                    \
+        hipLaunchKernelGGL((k_2d_passB_adj<R, GG, RR, SC, TG>), dim3(xcd_grid(a.natasks)), dim3(RR * GG / 16), \
+                           0, s, gin, a.N1, (int64_t)a.Gy, a.atasks, a.natasks, a.perm, a.keys, a.Xxs, a.Xys,  \
+                           a.fx, a.fy, a.twxi, a.H, a.Zp);                                                   \
         break;                                                                                              \
     }
         BA2(16, 16, 256, 16, 256, false)
@@ -430,12 +445,18 @@ hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, h
         BA2(128, 16, 512, 8, 512, false)
         BA2(256, 16, 512, 8, 512, false)
         BA2(512, 8, 1024, 4, 768, false)
-        BA2(1024, 4, 2048, 4, 768, false)
+        BA2(1024, 4, 1024, 4, 768, true)
         BA2(2048, 2, 2304, 2, 1280, true)
 #undef BA2
     default: return hipErrorInvalidValue;
     }
     prof_end(a.prof, s);
+    if (a.nrtasks > 0) {
+        prof_begin(a.prof, "adj2d_sum", s);
+        hipLaunchKernelGGL(k_2d_sum_parts<R>, dim3(a.nrtasks, a.fy.K), dim3(256), 0, s, a.rtasks,
+                           (const cx_t<R> *)a.Zp, (int64_t)a.Gx, (int64_t)a.Gy, a.fy.K, a.H);
+        prof_end(a.prof, s);
+    }
     prof_begin(a.prof, "adj2d_passA", s);
     switch (a.Gy) {
 #define AA2(GG, GF, GD)                                                                                     \
@@ -459,6 +480,19 @@ hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, h
     }
     prof_end(a.prof, s);
     return hipGetLastError();
+}
+
+// Samples per adjoint pass-B' task (the LDS staging capacity of the instantiation above).
+int pass_b2d_adj_cap(int GX, bool fp32)
+{
+    switch (GX) {
+    case 16: case 32: case 64: return 256;
+    case 128: case 256: return 512;
+    case 512: return fp32 ? 1024 : 768;
+    case 1024: return fp32 ? 1024 : 768;
+    case 2048: return fp32 ? 2304 : 1280;
+    default: return 0;
+    }
 }
 
 // Samples per forward pass-B task (threads x slots of the instantiation above).

@@ -54,6 +54,9 @@ struct nufft_plan_s {
     void *Xxs = nullptr, *Xys = nullptr;
     int4 *tasks = nullptr;
     int ntasks = 0;
+    int4 *atasks = nullptr, *rtasks = nullptr;   // adjoint pass-B' tasks, split columns
+    int natasks = 0, nrtasks = 0;
+    void *Zp = nullptr;                          // partial rows of split columns
     void *twx = nullptr, *twxi = nullptr, *twy = nullptr, *twyi = nullptr;
 
     // batch plans: member plans are the children
