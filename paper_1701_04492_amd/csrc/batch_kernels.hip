@@ -69,7 +69,8 @@ __device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx
         for (int q = 0; q < 16; ++q)
             v[q] = r < K ? cscale(v[q], cheb_v<R>(r, zcoord<R>(lt + q * TPF, zm))) : cmake<C>(0, 0);
         __syncthreads();
-        block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L, -1, fft_wave_sync<L>>(buf + g * P, tw, lt, v);
+        fft_publish<L>();
         const int nr = min(RC, K - r0);
         for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
             const int rr = r0 + gg;
@@ -140,7 +141,8 @@ __device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, in
         for (int q = 0; q < 16; ++q)
             v[q] = cscale(cv[q], cheb_v<R>(r, zcoord<R>((k1_0 + g) + L1 * (int64_t)(lt + q * TPF), zm)));
         __syncthreads();
-        block_fft_regs<C, L2, -1>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L2, -1, fft_wave_sync<L2>>(buf + g * P, tw, lt, v);
+        fft_publish<L2>();
         C *Yr = d.Y + (int64_t)r * L + k1_0;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -199,7 +201,8 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2_f
                 for (int q = 0; q < 16; ++q) vn[q] = rn < K ? Yrow[(int64_t)rn * L + q * TPF] : cmake<C>(0, 0);
             }
             __syncthreads();
-            block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
+            block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v);
+            fft_publish<L1>();
             const int nr = min(RC, K - r0);
             for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
                 const int rr = r0 + gg;

@@ -201,6 +201,20 @@ __device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt)
 
 }  // namespace fftk
 
+// Transforms of at most 1024 points are held by at most 64 threads, i.e. each
+// lies inside one wavefront (transforms start at multiples of L/16 threads,
+// which divides 64).  Their stages then need only wave-level ordering, and
+// the waves of a workgroup do not wait for each other inside the FFT.  A
+// caller that reads transforms of other waves afterwards calls fft_publish<L>()
+// (a workgroup barrier when the stages were wave-synchronous).
+template <int L>
+inline constexpr bool fft_wave_sync = (L <= 1024);
+template <int L>
+__device__ __forceinline__ void fft_publish()
+{
+    if constexpr (fft_wave_sync<L>) __syncthreads();
+}
+
 // Full transform whose input is already in LDS (natural order, padded).
 // Result: natural order in the same buffer.  Called by all threads of the
 // workgroup; lt in [0, L/16) is this thread's lane within the transform.

@@ -69,7 +69,8 @@ k_small_fwd(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, const int32_t *
         for (int q = 0; q < 16; ++q) v[q] = r < fac.K ? cscale(v[q], cheb_v<R>(r, zcoord<R>(lt + q * TPF, zm)))
                                                       : cmake<C>(0, 0);
         __syncthreads();   // previous gather finished with buf
-        block_fft_regs<C, L, -1>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L, -1, fft_wave_sync<L>>(buf + g * P, tw, lt, v);
+        fft_publish<L>();
         const int nr = min(RC, fac.K - r0);
         // rank outer (coefficients loaded once), samples inner
         for (int gg = 0; gg < nr; ++gg) {
@@ -155,7 +156,8 @@ k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
             v[q] = a;
         }
         __syncthreads();
-        block_fft_regs<C, L, DIR>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L, DIR, fft_wave_sync<L>>(buf + g * P, tw, lt, v);
+        fft_publish<L>();
         const int nr = min(RC, fac.K - r0);
 #pragma unroll
         for (int m = 0; m < OPT; ++m) {
@@ -276,7 +278,8 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
 #pragma unroll
         for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], cheb_v<R>(r, zk[q]));
         __syncthreads();   // earlier readers of buf are done
-        block_fft_regs<C, L2, -1>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L2, -1, fft_wave_sync<L2>>(buf + g * P, tw, lt, v);
+        fft_publish<L2>();
         C *Yr = Y + (int64_t)r * L + k1_0;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -344,7 +347,8 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
                 for (int q = 0; q < 16; ++q) vn[q] = (rn < fac.K) ? Yrow[(int64_t)rn * L + q * TPF] : cmake<C>(0, 0);
             }
             __syncthreads();
-            block_fft_regs<C, L1, -1>(buf + g * P, tw, lt, v);
+            block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v);
+            fft_publish<L1>();
             const int nr = min(RC, fac.K - r0);
             // rank outer (its coefficients loaded once), samples inner
 #pragma unroll
@@ -524,7 +528,7 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
                 if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -dir * (r0 + gg));
         }
         __syncthreads();
-        block_fft_lds<C, L1, dir>(buf + g * P, tw, lt);
+        block_fft_lds<C, L1, dir, fft_wave_sync<L1>>(buf + g * P, tw, lt);   // each thread then reads only its own transform
         const int r = r0 + g;
         if (r < fac.K) {
             C *Zr = Z + (int64_t)r * L + n2 * L1;
@@ -586,7 +590,8 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
             }
         }
         __syncthreads();
-        block_fft_lds<C, L2, DIR>(buf + g * P, tw, lt);
+        block_fft_lds<C, L2, DIR, fft_wave_sync<L2>>(buf + g * P, tw, lt);
+        fft_publish<L2>();
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;

@@ -57,7 +57,8 @@ k_2d_passA(const cx_t<R> *__restrict__ Cin, int64_t N1, int64_t N2, int64_t GX, 
 #pragma unroll
         for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], cheb_v<R>(r, zk[q]));
         __syncthreads();
-        block_fft_regs<C, GY, -1>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, GY, -1, fft_wave_sync<GY>>(buf + g * P, tw, lt, v);
+        fft_publish<GY>();
         C *Hr = H + (int64_t)r * GY * GX + k1_0;
 #pragma unroll 4
         for (int e = 0; e < 16; ++e) {
@@ -139,7 +140,8 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
             for (int q = 0; q < 16; ++q)
                 v[q] = r1 < fx.K ? cscale(hrow[lt + q * TPF], cheb_v<R>(r1, zcoord<R>(lt + q * TPF, zm)))
                                  : cmake<C>(0, 0);
-            block_fft_regs<C, GX, -1>(buf + g * P, tw, lt, v);
+            block_fft_regs<C, GX, -1, fft_wave_sync<GX>>(buf + g * P, tw, lt, v);
+            fft_publish<GX>();
             const int nr = min(RC, fx.K - r0);
             for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
                 const int rr = r0 + gg;
@@ -265,7 +267,8 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
             };
             seg_spread<C, RC, NT>(cnt, nr, pos, contrib, buf, P, hv, tv, hix, tix);
             __syncthreads();
-            block_fft_lds<C, GX, 1>(buf + g * P, tw, lt);
+            block_fft_lds<C, GX, 1, fft_wave_sync<GX>>(buf + g * P, tw, lt);
+            fft_publish<GX>();
 #pragma unroll
             for (int m = 0; m < ZA; ++m) {
                 const int k1 = tid + m * NT;
@@ -344,7 +347,8 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
             }
         }
         __syncthreads();
-        block_fft_lds<C, GY, 1>(buf + g * P, tw, lt);
+        block_fft_lds<C, GY, 1, fft_wave_sync<GY>>(buf + g * P, tw, lt);
+        fft_publish<GY>();
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;
