@@ -100,7 +100,48 @@ def test_n2p20_sampled(dtype):
     check_type1(x, g, N, dtype, -1, kq=kq, label="2^20 type I")
 
 
+def test_n2p23_max_size_sampled():
+    """Largest supported grid (N = 2^23, L1 = 4096 tiles): adjoint on sampled outputs."""
+    N = 1 << 23
+    x, g = W.type2_case(27, N)
+    kq = np.sort(np.random.default_rng(6).choice(N, 48, replace=False))
+    kq = np.concatenate([[0, 1, N - 1], kq])
+    check_type1(x, g, N, C64, +1, kq=kq, label="2^23 adjoint")
+
+
 # ---- gradients --------------------------------------------------------------
+
+def test_n2p22_backward_sampled():
+    """The backward of the bench step exactly as timed (N = M = 2^22, complex64,
+    eps 1e-6, nufft2_backward): dL/dc on sampled modes, dL/dx on sampled samples
+    (seeded random ones, every wrap sample, the largest |delta|)."""
+    N = 1 << 22
+    x, c = W.type2_case(3, N)
+    g = W.complex_normal(W.rng_for(28), N)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS[C64], C64)
+    ct, gt = _t(c, C64), _t(g, C64)
+    gc, gx = P.nufft2_backward(plan, ct, gt)
+    torch.cuda.synchronize()
+    gc, gx = gc.cpu().numpy(), gx.cpu().numpy()
+    cc, gg = ct.cpu().numpy().astype(np.complex128), gt.cpu().numpy().astype(np.complex128)
+    kq = np.sort(np.random.default_rng(11).choice(N, 64, replace=False))
+    kq = np.concatenate([[0, 1, N - 1], kq])
+    ref_c = D.nudft1(x, gg, N, k=kq, sign=+1)
+    err_c = np.abs(gc[kq] - ref_c).max() / np.abs(gg).sum()
+    rng = np.random.default_rng(12)
+    s, _, d = D.grid_assign(x, N)
+    rows = set(rng.choice(N, 64, replace=False).tolist())
+    rows.update(np.nonzero(s == N)[0][:16].tolist())
+    rows.update(np.argsort(-np.abs(d))[:16].tolist())
+    rows = np.array(sorted(rows), dtype=np.int64)
+    ref_x = D.grad_x(x[rows], cc, gg[rows])
+    bound = 4 * EPS[C64] * np.abs(gg[rows]) * 2 * np.pi * (np.arange(N) * np.abs(cc)).sum()
+    _say("2^22 backward: K=%d dL/dc err/||g||_1 %.3e, dL/dx max err/bound %.3e"
+         % (plan.K, err_c, (np.abs(gx[rows] - ref_x) / bound).max()))
+    assert np.all(np.isfinite(gc)) and np.all(np.isfinite(gx))
+    assert err_c <= 4 * EPS[C64]
+    assert np.all(np.abs(gx[rows] - ref_x) <= bound)
+
 
 @pytest.mark.parametrize("dtype", [C64, C128])
 def test_grad_x_pass(dtype):

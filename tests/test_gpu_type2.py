@@ -185,6 +185,20 @@ def test_n2p22_fp32_sampled():
     check_type2(x, c, N, C64, rows=rows, label="2^22")
 
 
+def test_n2p23_max_size_sampled():
+    """Largest supported grid: N = 2^23 (L1 = 4096 tiles), complex64, sampled rows."""
+    N = 1 << 23
+    x, c = W.type2_case(27, N)
+    rows = _rows_subset(x, N, N, 48, 10)
+    check_type2(x, c, N, C64, rows=rows, label="2^23")
+
+
+def test_beyond_max_size_rejected():
+    x = torch.zeros(4, dtype=torch.float64, device=DEV)
+    with pytest.raises(P.NufftError):
+        P.nufft2_plan(x, (1 << 23) + 1, 1e-6, C64)
+
+
 def test_kernel_profiling_hook():
     N = 1 << 16
     x, c = W.type2_case(26, N)
