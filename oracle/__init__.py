@@ -11,4 +11,7 @@ nothing from the product: the two share no code.
   coefficients (Sec. 2.1.2), choice of K, factors u_r / v_r, the vectorized
   two-step form (Sec. 2.3), type I (Sec. 3.1), type III (Sec. 3.2) and the
   2-D transform (Sec. 4).
+* ``oracle.inverse`` -- the inverse type-II transform of Sec. 3.3: conjugate
+  gradients on the normal equations with the Toeplitz product through a 2N
+  circulant embedding, and a dense least-squares reference for small sizes.
 """

@@ -688,6 +688,9 @@ static hipError_t run_small_adj(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R>
 #ifndef NUFFT_F32_PB2048_S
 #define NUFFT_F32_PB2048_S 5
 #endif
+#ifndef NUFFT_F32_PBA2048_RC
+#define NUFFT_F32_PBA2048_RC 2  // adjoint pass B' at L1 = 2048: ranks side by side
+#endif
 #ifndef NUFFT_F32_PB1024_RC
 #define NUFFT_F32_PB1024_RC 4
 #endif
@@ -813,7 +816,7 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         PBA(256, 16, 384, 8, 384, false)
         PBA(512, 8, 768, 4, 768, false)
         PBA(1024, 4, 1280, 4, 1280, false)
-        PBA(2048, 2, 2304, 2, 2304, true)
+        PBA(2048, NUFFT_F32_PBA2048_RC, 2304, 2, 2304, true)
         PBA(4096, 1, 5120, 1, 2560, true)
 #undef PBA
     default: return hipErrorInvalidValue;
