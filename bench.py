@@ -231,6 +231,27 @@ def bench_batch(P, W, torch, dev):
             "speedup_vs_separate_plain": round(t_plain / t_graph, 2)}
 
 
+def bench_solve(P, W, torch, dev):
+    """Inverse type II (Sec. 3.3) at N = M = 2^20, complex64, perturbed equispaced samples
+    x_j = (j + U(-1/8, 1/8))/N, f = F2 c for c complex N(0,1): CG to a residual of 1e-5."""
+    import numpy as np
+    N = 1 << 20
+    rng = W.rng_for(6)
+    x = (np.arange(N) + 0.125 * rng.uniform(-1.0, 1.0, N)) / N
+    c = torch.from_numpy(W.complex_normal(rng, N)).to(torch.complex64).to(dev)
+    plan = P.nufft2_plan(torch.from_numpy(x).to(dev), N, 1e-6, torch.complex64)
+    f = P.nufft2_exec(plan, c)
+    P.nufft2_solve(plan, f, tol=1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol, it, res = P.nufft2_solve(plan, f, tol=1e-5)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err = (sol - c).abs().max().item() / c.abs().max().item()
+    return {"N": N, "gamma": 0.125, "iterations": it, "residual": res, "ms": round(dt * 1e3, 2),
+            "ms_per_iteration": round(dt * 1e3 / max(it, 1), 3), "max_rel_err_vs_c": err}
+
+
 def bench_2d(P, W, torch, dev):
     """2-D type II and adjoint, 1024 x 1024 coefficients, 2^20 polar samples, eps 1e-6 FP32."""
     x, y, C = W.polar_case(5)
@@ -399,6 +420,7 @@ def main():
     if not args.no_secondary:
         out["batch_512"] = bench_batch(P, W, torch, dev)
         out["polar_2d"] = bench_2d(P, W, torch, dev)
+        out["inverse_2p20"] = bench_solve(P, W, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, c_np, N, args.cpu_seconds)

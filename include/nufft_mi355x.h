@@ -121,6 +121,24 @@ nufft_status nufft2_grad_x(nufft_plan_t plan, const void *c_dev, const void *g_d
 nufft_status nufft2_backward(nufft_plan_t plan, const void *c_dev, const void *g_dev,
                              void *gc_dev, double *gx_dev, void *stream);
 
+/* Inverse type II (Sec. 3.3): c_dev ~ argmin ||F2 c - f||_2 for the plan's
+ * samples (M >= N; F2 of eq. (2), applied through the plan's low-rank
+ * transforms), by conjugate gradients on the normal equations
+ * F2^* F2 c = F2^* f.  F2^* F2 is Hermitian Toeplitz with first column
+ * tau = F2^* 1 (one adjoint transform); each iteration multiplies by it
+ * through a circulant embedding of size Lc >= 2N (two DFTs of size Lc).
+ * Starts from c = 0 and stops when ||F2^* (f - F2 c)|| <= tol ||F2^* f||
+ * (the recursively updated residual) or after max_iter iterations.
+ *   f_dev: M complex (read), c_dev: N complex (written).
+ *   iters, resid: optional host outputs (iterations done, final relative
+ *   residual of the normal equations).
+ * N up to 2^22 (NUFFT_ERR_UNSUPPORTED beyond).  Allocates its temporaries and
+ * synchronises `stream` twice per iteration (not graph capturable).  The
+ * iteration count grows with the perturbation gamma (Sec. 3.3: small for
+ * gamma < 1/4, unbounded as gamma -> 1/2). */
+nufft_status nufft2_solve(nufft_plan_t plan, const void *f_dev, void *c_dev, double tol, int max_iter,
+                          int *iters, double *resid, void *stream);
+
 /* ---- type III ---------------------------------------------------------- */
 
 /* Type III (Sec. 3.2): f_dev[j] ~ sum_{k<N} c_dev[k] exp(-2 pi i x_j w_k), j < M,

@@ -39,6 +39,7 @@ _sig = {
     "nufft1_exec": [_vp, _vp, _vp, _int, _vp],
     "nufft2_grad_x": [_vp, _vp, _vp, _vp, _vp],
     "nufft2_backward": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "nufft2_solve": [_vp, _vp, _vp, _dbl, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _vp],
     "nufft3_exec": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
     "nufft2d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _dbl, _int, _u32, _vp],
     "nufft2d_exec": [_vp, _vp, _vp, _int, _vp],
@@ -178,6 +179,19 @@ def nufft2_backward(plan, c, g, gc=None, gx=None, need_c=True, need_x=True):
                                _dev_tensor(gx, torch.float64, plan.M, "gx") if need_x else None,
                                _stream(plan.device)), "nufft2_backward")
     return (gc if need_c else None), (gx if need_x else None)
+
+
+def nufft2_solve(plan, f, c=None, tol=1e-6, max_iter=200):
+    """Inverse type II (Sec. 3.3): least-squares c with F2 c ~ f, by CG on the normal
+    equations.  Returns (c, iterations, relative residual of the normal equations)."""
+    if c is None:
+        c = torch.empty(plan.N, dtype=plan.dtype, device=plan.device)
+    it = _int()
+    res = _dbl()
+    _check(lib.nufft2_solve(plan.handle, _dev_tensor(f, plan.dtype, plan.M, "f"),
+                            _dev_tensor(c, plan.dtype, plan.N, "c"), float(tol), int(max_iter),
+                            ctypes.byref(it), ctypes.byref(res), _stream(plan.device)), "nufft2_solve")
+    return c, it.value, res.value
 
 
 def nufft3_exec(x, w, c, eps, f=None):

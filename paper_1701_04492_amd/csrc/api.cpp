@@ -9,6 +9,7 @@
 #include "kernels.h"
 #include "plan.h"
 #include "kernels_2d.h"
+#include "solve.h"
 #include "batch.h"
 
 using namespace nufft;
@@ -398,6 +399,100 @@ static nufft_status type3(int64_t M, const double *x, int64_t N, const double *w
         if (any_wrap) NUFFT_HIP_CHECK(fused_type1<R>(ia, c2, y2, -1, s));
         NUFFT_HIP_CHECK(t3_accum<R>(d, t, wrap, M, fac, r, y, any_wrap ? y2 : nullptr, (C *)f, s));
     }
+    return NUFFT_OK;
+}
+
+// ---- inverse type II (Sec. 3.3) -------------------------------------------------
+
+// Conjugate gradients on F2^* F2 c = F2^* f.  F2^* F2 is Hermitian Toeplitz with
+// first column tau = F2^* 1; its product with a vector is a circulant product of
+// size Lc >= 2N (two DFTs and a pointwise product with the circulant's
+// eigenvalues lam = DFT(column)).  The loop runs on the host: two FP64 dot
+// products are read back per iteration.
+template <typename R>
+static nufft_status solve_impl(Plan *p, const void *f, void *c, double tol, int max_iter, int *iters_out,
+                               double *resid_out, hipStream_t s)
+{
+    using C = cx_t<R>;
+    const int64_t N = p->N, M = p->M;
+    int64_t Lc = 16;
+    while (Lc < 2 * N) Lc <<= 1;
+    Plan tmp;   // owns the temporaries
+    struct SyncGuard {   // destroyed before tmp: no temporary is freed under a running kernel
+        hipStream_t s;
+        ~SyncGuard() { (void)hipStreamSynchronize(s); }
+    } guard{s};
+    Plan *circ = new (std::nothrow) Plan();
+    if (!circ) return NUFFT_ERR_ALLOC;
+    tmp.children.push_back(circ);
+    circ->dtype = p->dtype;
+    circ->N = Lc;
+    if (!choose_grid(Lc, &circ->L, &circ->L1, &circ->L2)) return NUFFT_ERR_UNSUPPORTED;
+    nufft_status st = upload_twiddles<R>(circ, s);
+    if (st) return st;
+    C *ones = (C *)tmp.alloc(M * sizeof(C));
+    C *tau = (C *)tmp.alloc(N * sizeof(C));
+    C *b = (C *)tmp.alloc(N * sizeof(C));
+    C *r = (C *)tmp.alloc(N * sizeof(C));
+    C *pv = (C *)tmp.alloc(N * sizeof(C));
+    C *ap = (C *)tmp.alloc(N * sizeof(C));
+    C *lam1 = (C *)tmp.alloc(Lc * sizeof(C));
+    C *lam2 = (C *)tmp.alloc(Lc * sizeof(C));
+    C *q1 = (C *)tmp.alloc(Lc * sizeof(C));
+    C *q2 = (C *)tmp.alloc(Lc * sizeof(C));
+    double2 *part = (double2 *)tmp.alloc(SOLVE_DOT_BLOCKS * sizeof(double2));
+    double2 *dd = (double2 *)tmp.alloc(sizeof(double2));
+    if (!ones || !tau || !b || !r || !pv || !ap || !lam1 || !lam2 || !q1 || !q2 || !part || !dd)
+        return NUFFT_ERR_ALLOC;
+    const FusedArgs<R> a = fused_args<R>(p);
+    const C *tw1 = (const C *)circ->tw1, *tw2 = (const C *)circ->tw2;
+    const C *hi = (const C *)circ->hi, *lo = (const C *)circ->lo;
+    auto dot = [&](const C *u, const C *v, double *re) -> nufft_status {
+        NUFFT_HIP_CHECK(solve_dot<R>(u, v, N, part, dd, s));
+        double2 h;
+        NUFFT_HIP_CHECK(hipMemcpyAsync(&h, dd, sizeof(h), hipMemcpyDeviceToHost, s));
+        NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+        *re = h.x;
+        return NUFFT_OK;
+    };
+    // eigenvalues of the circulant embedding
+    NUFFT_HIP_CHECK(solve_fill<R>(ones, M, 1.0, 0.0, s));
+    NUFFT_HIP_CHECK(fused_type1<R>(a, ones, tau, +1, s));
+    NUFFT_HIP_CHECK(solve_circulant_column<R>(tau, N, Lc, lam1, s));
+    C *lam;
+    NUFFT_HIP_CHECK(plain_fft<R>(Lc, circ->L1, circ->L2, lam1, lam2, tw1, tw2, hi, lo, &lam, s));
+    // right-hand side and the CG iteration from c = 0
+    NUFFT_HIP_CHECK(fused_type1<R>(a, (const C *)f, b, +1, s));
+    C *x = (C *)c;
+    NUFFT_HIP_CHECK(solve_fill<R>(x, N, 0.0, 0.0, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(r, b, N * sizeof(C), hipMemcpyDeviceToDevice, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(pv, b, N * sizeof(C), hipMemcpyDeviceToDevice, s));
+    double rs;
+    if ((st = dot(r, r, &rs))) return st;
+    const double bn = std::sqrt(rs);
+    int it = 0;
+    while (bn > 0.0 && it < max_iter && std::sqrt(rs) > tol * bn) {
+        // ap = (F2^* F2) pv = first N of conj(DFT(conj(lam o DFT([pv, 0])) / Lc))
+        C *res1, *res2;
+        NUFFT_HIP_CHECK(solve_pad<R>(pv, N, Lc, q1, s));
+        NUFFT_HIP_CHECK(plain_fft<R>(Lc, circ->L1, circ->L2, q1, q2, tw1, tw2, hi, lo, &res1, s));
+        NUFFT_HIP_CHECK(solve_circulant_scale<R>(res1, lam, Lc, s));
+        NUFFT_HIP_CHECK(plain_fft<R>(Lc, circ->L1, circ->L2, res1, res1 == q1 ? q2 : q1, tw1, tw2, hi, lo,
+                                     &res2, s));
+        NUFFT_HIP_CHECK(solve_take_conj<R>(res2, N, ap, s));
+        double pap;
+        if ((st = dot(pv, ap, &pap))) return st;
+        if (!(pap > 0.0)) break;   // breakdown: the normal matrix is singular on this direction
+        const double alpha = rs / pap;
+        NUFFT_HIP_CHECK(solve_step<R>(x, r, pv, ap, alpha, N, s));
+        double rs_new;
+        if ((st = dot(r, r, &rs_new))) return st;
+        NUFFT_HIP_CHECK(solve_direction<R>(pv, r, rs_new / rs, N, s));
+        rs = rs_new;
+        ++it;
+    }
+    if (iters_out) *iters_out = it;
+    if (resid_out) *resid_out = bn > 0.0 ? std::sqrt(rs) / bn : 0.0;
     return NUFFT_OK;
 }
 
@@ -808,6 +903,16 @@ nufft_status nufft2_grad_x(nufft_plan_t plan, const void *c, const void *g, doub
     hipStream_t s = (hipStream_t)stream;
     return from_hip(plan->dtype == NUFFT_C64 ? exec_type2<float>(plan, c, nullptr, 1, g, gx, s)
                                              : exec_type2<double>(plan, c, nullptr, 1, g, gx, s));
+}
+
+nufft_status nufft2_solve(nufft_plan_t plan, const void *f, void *c, double tol, int max_iter, int *iters,
+                          double *resid, void *stream)
+{
+    if (!plan || plan->kind != PLAN_1D || !f || !c || !(tol > 0.0) || max_iter < 0) return NUFFT_ERR_INVALID_ARG;
+    if (plan->N > (int64_t(1) << 22)) return NUFFT_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    return plan->dtype == NUFFT_C64 ? solve_impl<float>(plan, f, c, tol, max_iter, iters, resid, s)
+                                    : solve_impl<double>(plan, f, c, tol, max_iter, iters, resid, s);
 }
 
 nufft_status nufft2_backward(nufft_plan_t plan, const void *c, const void *g, void *gc, double *gx, void *stream)

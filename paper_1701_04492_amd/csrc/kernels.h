@@ -109,6 +109,12 @@ template <typename R>
 hipError_t plain_build_U(const R *X, int64_t M, const Factors<R> &fac, cx_t<R> *U, hipStream_t s);
 template <typename R>
 hipError_t plain_exec(const PlainArgs<R> &a, hipStream_t s);
+// Forward DFT of one vector of length L = L1 * L2 (the split and tables of a
+// plan with that grid).  L2 == 1: in place in `data`; otherwise `data` is
+// overwritten and the result is written to `out`.  *result: where it is.
+template <typename R>
+hipError_t plain_fft(int64_t L, int L1, int L2, cx_t<R> *data, cx_t<R> *out, const cx_t<R> *tw1,
+                     const cx_t<R> *tw2, const cx_t<R> *hi, const cx_t<R> *lo, cx_t<R> **result, hipStream_t s);
 
 // ---- fused online stage -------------------------------------------------------
 template <typename R>

@@ -274,6 +274,27 @@ hipError_t plain_exec(const PlainArgs<R> &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t plain_fft(int64_t L, int L1, int L2, cx_t<R> *data, cx_t<R> *out, const cx_t<R> *tw1,
+                     const cx_t<R> *tw2, const cx_t<R> *hi, const cx_t<R> *lo, cx_t<R> **result, hipStream_t s)
+{
+    bool ok;
+    if (L2 == 1) {
+        ok = dispatch_rows<R, -1, 0>((int)L, data, data, 1, 1, tw1, s);
+        *result = data;
+    } else {
+        ok = dispatch_cols<R, -1>(L2, data, L1, 1, tw2, hi, lo, s);
+        ok = ok && dispatch_rows<R, -1, 1>(L1, data, out, L2, 1, tw1, s);
+        *result = out;
+    }
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template hipError_t plain_fft<float>(int64_t, int, int, float2 *, float2 *, const float2 *, const float2 *,
+                                     const float2 *, const float2 *, float2 **, hipStream_t);
+template hipError_t plain_fft<double>(int64_t, int, int, double2 *, double2 *, const double2 *, const double2 *,
+                                      const double2 *, const double2 *, double2 **, hipStream_t);
 template hipError_t plain_build_U<float>(const float *, int64_t, const Factors<float> &, float2 *, hipStream_t);
 template hipError_t plain_build_U<double>(const double *, int64_t, const Factors<double> &, double2 *,
                                           hipStream_t);

@@ -1,0 +1,116 @@
+"""GPU parity of the inverse type-II transform (Sec. 3.3, nufft2_solve) against the
+FP64 oracle: the solution of F2 c = f and the CG iteration count."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import inverse as I
+from oracle import nudft as D
+from paper_1701_04492_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1701_04492_amd")
+DEV = torch.device("cuda:0")
+C64, C128 = torch.complex64, torch.complex128
+
+
+def _t(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _jittered(n, gamma, seed):
+    rng = np.random.default_rng(seed)
+    return (np.arange(n) + gamma * rng.uniform(-1.0, 1.0, n)) / n
+
+
+@pytest.mark.parametrize("n", [500, 4096])
+def test_square_fp64_against_oracle(n):
+    x = _jittered(n, 1 / 8, 40)
+    c = W.complex_normal(W.rng_for(41), n)
+    f = D.nudft2(x, c)
+    plan = P.nufft2_plan(_t(x, torch.float64), n, 1e-12, C128)
+    sol, it, res = P.nufft2_solve(plan, _t(f, C128), tol=1e-12, max_iter=200)
+    sol = sol.cpu().numpy()
+    ref, it_ref, _ = I.cg_normal(x, f, n, tol=1e-12, max_iter=200)
+    err = np.abs(sol - c).max() / np.abs(c).max()
+    _say("solve n=%d fp64: iterations %d (oracle %d), residual %.2e, err %.2e" % (n, it, it_ref, res, err))
+    assert res <= 1e-12
+    assert err <= 1e-8
+    assert np.abs(sol - ref).max() <= 1e-8 * np.abs(ref).max()
+    assert abs(it - it_ref) <= 2
+
+
+def test_overdetermined_fp64_least_squares():
+    n, m = 300, 700
+    x = np.random.default_rng(42).random(m)
+    f = W.complex_normal(W.rng_for(43), m)            # not in the range of F2: a true least-squares problem
+    plan = P.nufft2_plan(_t(x, torch.float64), n, 1e-12, C128)
+    sol, it, res = P.nufft2_solve(plan, _t(f, C128), tol=1e-12, max_iter=2000)
+    sol = sol.cpu().numpy()
+    ref = I.lstsq(x, f, n)
+    err = np.abs(sol - ref).max() / np.abs(ref).max()
+    _say("least squares n=%d m=%d: iterations %d, residual %.2e, err %.2e" % (n, m, it, res, err))
+    assert res <= 1e-12
+    assert err <= 1e-7
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_equispaced_is_one_iteration(dtype):
+    n = 1024
+    x = np.arange(n) / n
+    c = W.complex_normal(W.rng_for(44), n)
+    f = D.nudft2(x, c)
+    plan = P.nufft2_plan(_t(x, torch.float64), n, 1e-6 if dtype == C64 else 1e-12, dtype)
+    sol, it, res = P.nufft2_solve(plan, _t(f, dtype), tol=1e-5 if dtype == C64 else 1e-12)
+    sol = sol.cpu().numpy()
+    _say("equispaced", dtype, "iterations", it)
+    assert it == 1
+    assert np.abs(sol - c).max() <= (1e-5 if dtype == C64 else 1e-10) * np.abs(c).max()
+
+
+def test_fp32_against_oracle():
+    n = 2000
+    x = _jittered(n, 1 / 8, 45)
+    c = W.complex_normal(W.rng_for(46), n)
+    f = D.nudft2(x, c)
+    plan = P.nufft2_plan(_t(x, torch.float64), n, 1e-6, C64)
+    sol, it, res = P.nufft2_solve(plan, _t(f, C64), tol=1e-5, max_iter=200)
+    err = np.abs(sol.cpu().numpy() - c).max() / np.abs(c).max()
+    _say("solve n=%d fp32: iterations %d residual %.2e err %.2e" % (n, it, res, err))
+    assert res <= 1e-5
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_two_pass_round_trip(dtype):
+    """N = 2^16 (two-pass plans, circulant of 2^17): solve(F2 c) returns c, and the
+    iteration count stays small for gamma = 1/8 (Sec. 3.3)."""
+    n = 1 << 16
+    x = _jittered(n, 1 / 8, 47)
+    c = W.complex_normal(W.rng_for(48), n)
+    plan = P.nufft2_plan(_t(x, torch.float64), n, 1e-6 if dtype == C64 else 1e-12, dtype)
+    ct = _t(c, dtype)
+    f = P.nufft2_exec(plan, ct)
+    tol = 1e-5 if dtype == C64 else 1e-11
+    sol, it, res = P.nufft2_solve(plan, f, tol=tol, max_iter=200)
+    err = (sol - ct).abs().max().item() / ct.abs().max().item()
+    _say("round trip n=2^16", dtype, "iterations %d residual %.2e err %.2e" % (it, res, err))
+    assert res <= tol
+    assert it <= 40
+    assert err <= (1e-4 if dtype == C64 else 1e-8)
+
+
+def test_solve_argument_errors():
+    x = _t(np.arange(64) / 64, torch.float64)
+    plan = P.nufft2_plan(x, 64, 1e-6, C64)
+    f = torch.zeros(64, dtype=C64, device=DEV)
+    with pytest.raises(P.NufftError):
+        P.nufft2_solve(plan, f, tol=0.0)
+    # zero right-hand side: zero solution, no iteration
+    sol, it, res = P.nufft2_solve(plan, f)
+    assert it == 0 and torch.count_nonzero(sol).item() == 0
