@@ -169,14 +169,15 @@ def cpu_baseline(x, c, N, seconds):
     import numpy as np
     from oracle import nudft as D
     cores = D.max_threads()
-    rows = 8
-    t0 = time.perf_counter()
-    D.nudft2(x[:rows], c)
-    dt = time.perf_counter() - t0
-    rows = int(min(4096, max(8, rows * seconds / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    D.nudft2(x[:rows], c)
-    dt = time.perf_counter() - t0
+    D.nudft2(x[:cores], c)            # warm-up: thread pool, first touch of c
+    rows = 2 * cores
+    while True:                       # grow the sample until it takes about `seconds`
+        t0 = time.perf_counter()
+        D.nudft2(x[:rows], c)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * seconds or rows >= 8192:
+            break
+        rows = int(min(8192, rows * max(2.0, seconds / max(dt, 1e-3))))
     # the step needs three N-term sums per point: f_j, (F2^H g)_k and the x-derivative
     return {
         "value": rows / dt / 3.0,
