@@ -1,4 +1,4 @@
-"""The inverse type-II transform of Sec. 3.3, in plain numpy FP64.
+"""The inverse type-II and type-I transforms of Sec. 3.3, in plain numpy FP64.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Steps in the paper's
 order:
@@ -14,11 +14,17 @@ order:
 * A Toeplitz matrix-vector product is one FFT and one inverse FFT of size 2N
   through the circulant matrix whose first column is
   [tau_0, ..., tau_{N-1}, 0, conj(tau_{N-1}), ..., conj(tau_1)].
+* Inverse type I: F1 = F2^T (type I of Sec. 3.1 with x_j = w_j / N) maps M
+  values to N; for M >= N its inverse (minimum-norm when M > N) is
+  F1^* (F1 F1^*)^{-1}, and F1 F1^* = conj(F2^* F2) is again Hermitian
+  Toeplitz, with first column conj(tau).  CG runs on F1 F1^* y = f and
+  c = F1^* y.
 
 Readings (listed in the design doc): the embedding uses 2N points with one zero
 (any value there gives the same product); CG stops when the residual of the
 normal equations falls below tol times the norm of their right-hand side
-F2^* f, or after max_iter iterations, and starts from c = 0.
+F2^* f, or after max_iter iterations, and starts from c = 0; the type-I
+solve stops on ||f - F1 F1^* y|| <= tol ||f|| and starts from y = 0.
 """
 import numpy as np
 
@@ -55,6 +61,28 @@ def toeplitz_matvec(lam, c):
     return np.fft.ifft(lam * np.fft.fft(pad))[:n]
 
 
+def _cg(apply, b, tol, max_iter):
+    """Plain conjugate gradients for a Hermitian positive definite operator, from zero."""
+    y = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rs = np.vdot(r, r).real
+    bn = np.sqrt(np.vdot(b, b).real)
+    it = 0
+    if bn == 0.0:
+        return y, 0, 0.0
+    while it < max_iter and np.sqrt(rs) > tol * bn:
+        ap = apply(p)
+        alpha = rs / np.vdot(p, ap).real
+        y = y + alpha * p
+        r = r - alpha * ap
+        rs_new = np.vdot(r, r).real
+        p = r + (rs_new / rs) * p
+        rs = rs_new
+        it += 1
+    return y, it, np.sqrt(rs) / bn
+
+
 def cg_normal(x, f, n_modes, tol=1e-12, max_iter=500):
     """Sec. 3.3: conjugate gradients on F2^* F2 c = F2^* f with the fast Toeplitz product.
     Returns (c, iterations, relative residual of the normal equations)."""
@@ -62,26 +90,32 @@ def cg_normal(x, f, n_modes, tol=1e-12, max_iter=500):
     f = np.asarray(f, np.complex128)
     b = _direct.nudft1(x, f, n_modes, sign=+1)
     lam = circulant_eigenvalues(toeplitz_column(x, n_modes))
-    c = np.zeros(n_modes, np.complex128)
-    r = b.copy()
-    p = r.copy()
-    rs = np.vdot(r, r).real
-    bn = np.sqrt(np.vdot(b, b).real)
-    it = 0
-    if bn == 0.0:
-        return c, 0, 0.0
-    while it < max_iter and np.sqrt(rs) > tol * bn:
-        ap = toeplitz_matvec(lam, p)
-        alpha = rs / np.vdot(p, ap).real
-        c = c + alpha * p
-        r = r - alpha * ap
-        rs_new = np.vdot(r, r).real
-        p = r + (rs_new / rs) * p
-        rs = rs_new
-        it += 1
-    return c, it, np.sqrt(rs) / bn
+    return _cg(lambda v: toeplitz_matvec(lam, v), b, tol, max_iter)
 
 
 def lstsq(x, f, n_modes):
     """Least-squares solution of F2 c = f from the dense matrix (small sizes only)."""
     return np.linalg.lstsq(dense_matrix(x, n_modes), np.asarray(f, np.complex128), rcond=None)[0]
+
+
+def dense_matrix_type1(x, n_modes):
+    """F1 = F2^T, the type I of Sec. 3.1: (F1)_{kj} = exp(-2 pi i x_j k) (small sizes only)."""
+    return dense_matrix(x, n_modes).T
+
+
+def cg_type1(x, f, n_modes, tol=1e-12, max_iter=500):
+    """Sec. 3.3, the type-I analogue: c = F1^* y with F1 F1^* y = f solved by CG; F1 F1^* =
+    conj(F2^* F2) is applied through the circulant embedding of conj(tau).
+    Returns (c, iterations, relative residual ||f - F1 F1^* y|| / ||f||)."""
+    x = np.asarray(x, np.float64)
+    f = np.asarray(f, np.complex128)
+    lam = circulant_eigenvalues(np.conj(toeplitz_column(x, n_modes)))
+    y, it, res = _cg(lambda v: toeplitz_matvec(lam, v), f, tol, max_iter)
+    # c_j = sum_k y_k exp(+2 pi i x_j k) = conj of the type II of conj(y)
+    c = np.conj(_direct.nudft2(x, np.conj(y)))
+    return c, it, res
+
+
+def lstsq_type1(x, f, n_modes):
+    """Minimum-norm solution of F1 c = f from the dense matrix (small sizes only)."""
+    return np.linalg.lstsq(dense_matrix_type1(x, n_modes), np.asarray(f, np.complex128), rcond=None)[0]

@@ -197,12 +197,13 @@ int oracle_nudft2d(int64_t N1, int64_t N2, const double *C, int64_t M,
     return 0;
 }
 
-/* Adjoint of 2-D type II, evaluated at the requested coefficient indices:
- *   out_q = sum_{j<M} g_j exp(+2 pi i (k1_q x_j + k2_q y_j)). */
+/* Adjoint (sign = +1) or 2-D type I (sign = -1, the transpose) of the 2-D
+ * type II, evaluated at the requested coefficient indices:
+ *   out_q = sum_{j<M} g_j exp(sign 2 pi i (k1_q x_j + k2_q y_j)). */
 int oracle_nudft2d_adj(int64_t M, const double *x, const double *y, const double *g,
-                       int64_t nq, const int64_t *k1, const int64_t *k2, double *out)
+                       int64_t nq, const int64_t *k1, const int64_t *k2, int sign, double *out)
 {
-    if (M < 0 || nq < 0) return -1;
+    if (M < 0 || nq < 0 || (sign != 1 && sign != -1)) return -1;
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t q = 0; q < nq; ++q) {
         acc2 re = {0.0, 0.0}, im = {0.0, 0.0};
@@ -210,6 +211,7 @@ int oracle_nudft2d_adj(int64_t M, const double *x, const double *y, const double
             double phi = phase_mod1(x[j], (double)k1[q]) + phase_mod1(y[j], (double)k2[q]);
             double co, si;
             cis2pi(phi - nearbyint(phi), &co, &si);
+            si *= (double)sign;
             double gr = g[2 * j], gi = g[2 * j + 1];
             acc2_add_prod(&re, gr, co);
             acc2_add_prod(&re, -gi, si);

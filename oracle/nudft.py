@@ -26,7 +26,7 @@ def _load():
         lib.oracle_nudft1.argtypes = [_i64, _dp, _dp, _i64, _ip, ctypes.c_int, _dp]
         lib.oracle_nudft3.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         lib.oracle_nudft2d.argtypes = [_i64, _i64, _dp, _i64, _dp, _dp, _dp]
-        lib.oracle_nudft2d_adj.argtypes = [_i64, _dp, _dp, _dp, _i64, _ip, _ip, _dp]
+        lib.oracle_nudft2d_adj.argtypes = [_i64, _dp, _dp, _dp, _i64, _ip, _ip, ctypes.c_int, _dp]
         lib.oracle_grid_assign.argtypes = [_i64, _i64, _dp, _ip, _ip, _dp]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
@@ -103,15 +103,15 @@ def nudft2d(x, y, C):
     return f
 
 
-def nudft2d_adj(x, y, g, k1, k2):
-    """Adjoint of 2-D type II at coefficient indices (k1_q, k2_q):
-    out_q = sum_j g_j exp(+2 pi i (k1_q x_j + k2_q y_j))."""
+def nudft2d_adj(x, y, g, k1, k2, sign=+1):
+    """Adjoint of 2-D type II (sign=+1), or the 2-D type I, its transpose (sign=-1),
+    at coefficient indices (k1_q, k2_q): out_q = sum_j g_j exp(sign 2 pi i (k1_q x_j + k2_q y_j))."""
     x, y, g = _f64(x), _f64(y), _c128(g)
     k1 = np.ascontiguousarray(k1, dtype=np.int64)
     k2 = np.ascontiguousarray(k2, dtype=np.int64)
     out = np.empty(k1.shape[0], np.complex128)
     rc = _load().oracle_nudft2d_adj(x.shape[0], _p(x), _p(y), _p(g.view(np.float64)),
-                                    k1.shape[0], _pi(k1), _pi(k2), _p(out.view(np.float64)))
+                                    k1.shape[0], _pi(k1), _pi(k2), int(sign), _p(out.view(np.float64)))
     assert rc == 0
     return out
 

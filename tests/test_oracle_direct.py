@@ -76,10 +76,28 @@ def test_2d_vs_mpmath():
         assert abs(f[j] - ref) <= 4e-16 * np.abs(C).sum()
     g = _rand(rng, M)
     k1 = np.array([0, 1, 3, 2]); k2 = np.array([0, 4, 1, 2])
-    a = D.nudft2d_adj(x, y, g, k1, k2)
-    for q in range(4):
-        ph = [mpmath.mpf(x[j]) * int(k1[q]) + mpmath.mpf(y[j]) * int(k2[q]) for j in range(M)]
-        assert abs(a[q] - _mp_sum(ph, g)) <= 4e-16 * np.abs(g).sum()
+    for sign in (+1, -1):     # adjoint and 2-D type I
+        a = D.nudft2d_adj(x, y, g, k1, k2, sign=sign)
+        for q in range(4):
+            ph = [sign * (mpmath.mpf(x[j]) * int(k1[q]) + mpmath.mpf(y[j]) * int(k2[q])) for j in range(M)]
+            assert abs(a[q] - _mp_sum(ph, g)) <= 4e-16 * np.abs(g).sum()
+
+
+def test_2d_type1_is_transpose_and_adjoint_is_conjugate_transpose():
+    """sum_j g_j (F C)_j = sum_k C_k (F^T g)_k and <g, F C> = <F^H g, C> (2-D)."""
+    rng = np.random.default_rng(17)
+    n1, n2, M = 6, 7, 33
+    x, y = rng.random(M) * 3 - 1, rng.random(M)
+    C = _rand(rng, n1 * n2).reshape(n1, n2)
+    g = _rand(rng, M)
+    f = D.nudft2d(x, y, C)
+    k1, k2 = np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")
+    t1 = D.nudft2d_adj(x, y, g, k1.ravel(), k2.ravel(), sign=-1)
+    ad = D.nudft2d_adj(x, y, g, k1.ravel(), k2.ravel(), sign=+1)
+    scale = np.abs(C).sum() * np.abs(g).sum()
+    assert abs(np.sum(g * f) - np.sum(C.ravel() * t1)) <= 1e-14 * scale
+    assert abs(np.vdot(g, f) - np.vdot(ad, C.ravel())) <= 1e-14 * scale
+    assert np.abs(t1 - ad).max() > 1e-2          # the two signs differ for generic samples
 
 
 def test_large_phase_exact_reduction():

@@ -90,3 +90,60 @@ def test_iterations_stay_small_for_small_perturbation():
         assert res <= 1e-12
         its.append(it)
     assert max(its) <= 40
+
+
+# ---- inverse type I (Sec. 3.3, the type-I analogue) ------------------------------
+
+def test_type1_gram_matrix_is_conjugate_toeplitz():
+    """F1 F1^* = conj(F2^* F2): Hermitian Toeplitz with first column conj(tau)."""
+    n, m = 29, 41
+    x = np.random.default_rng(11).random(m)
+    F1 = I.dense_matrix_type1(x, n)
+    G = F1 @ F1.conj().T
+    tau = I.toeplitz_column(x, n)
+    assert np.allclose(G[:, 0], np.conj(tau), rtol=0, atol=1e-11)
+    F2 = I.dense_matrix(x, n)
+    assert np.allclose(G, np.conj(F2.conj().T @ F2), rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("n,m,gamma", [(64, 64, 1 / 8), (90, 160, 0.3), (256, 256, 1 / 32)])
+def test_cg_type1_matches_dense_minimum_norm(n, m, gamma):
+    if m == n:
+        x = _jittered(n, gamma, 12)
+    else:
+        x = np.sort(np.random.default_rng(12).random(m))
+    f = W.complex_normal(W.rng_for(13), n)
+    sol, it, res = I.cg_type1(x, f, n, tol=1e-13, max_iter=2000)
+    ref = I.lstsq_type1(x, f, n)
+    assert res <= 1e-13
+    assert np.abs(sol - ref).max() <= 1e-8 * np.abs(ref).max()
+    # it solves the system (to the conditioning of the random-sample Gram matrix),
+    # and (M > N) the solution lies in the range of F1^*
+    F1 = I.dense_matrix_type1(x, n)
+    assert np.abs(F1 @ sol - f).max() <= 1e-7 * np.abs(f).max()
+    if m > n:
+        z = np.linalg.lstsq(F1.conj().T, sol, rcond=None)[0]
+        assert np.abs(F1.conj().T @ z - sol).max() <= 1e-9 * np.abs(sol).max()
+
+
+def test_type1_equispaced_is_inverse_fft():
+    """gamma = 0: F1 = F (the DFT), F F^* = N I, one CG iteration and c = ifft(f)."""
+    n = 128
+    x = np.arange(n) / n
+    f = W.complex_normal(W.rng_for(14), n)
+    sol, it, _ = I.cg_type1(x, f, n, tol=1e-12)
+    assert it == 1
+    assert np.abs(sol - np.fft.ifft(f)).max() <= 1e-13 * np.abs(f).max()
+
+
+def test_type1_unconjugated_column_fails():
+    """Planted mistake: the type-II column tau (instead of conj(tau)) gives a wrong Gram product."""
+    n, m = 24, 40
+    x = np.random.default_rng(15).random(m)
+    y = W.complex_normal(W.rng_for(16), n)
+    F1 = I.dense_matrix_type1(x, n)
+    right = F1 @ (F1.conj().T @ y)
+    good = I.toeplitz_matvec(I.circulant_eigenvalues(np.conj(I.toeplitz_column(x, n))), y)
+    wrong = I.toeplitz_matvec(I.circulant_eigenvalues(I.toeplitz_column(x, n)), y)
+    assert np.abs(good - right).max() <= 1e-10 * np.abs(right).max()
+    assert np.abs(wrong - right).max() > 1e-3 * np.abs(right).max()
