@@ -249,12 +249,24 @@ def bench_solve(P, W, torch, dev):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     err = (sol - c).abs().max().item() / c.abs().max().item()
-    return {"N": N, "gamma": 0.125, "iterations": it, "residual": res, "ms": round(dt * 1e3, 2),
-            "ms_per_iteration": round(dt * 1e3 / max(it, 1), 3), "max_rel_err_vs_c": err}
+    out = {"N": N, "gamma": 0.125, "iterations": it, "residual": res, "ms": round(dt * 1e3, 2),
+           "ms_per_iteration": round(dt * 1e3 / max(it, 1), 3), "max_rel_err_vs_c": err}
+    # inverse type I on the same samples: f1 = F1 c, then solve F1 c = f1
+    f1 = P.nufft1_exec(plan, c, sign=-1)
+    P.nufft1_solve(plan, f1, tol=1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol, it, res = P.nufft1_solve(plan, f1, tol=1e-5)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err = (sol - c).abs().max().item() / c.abs().max().item()
+    out["type1"] = {"iterations": it, "residual": res, "ms": round(dt * 1e3, 2),
+                    "ms_per_iteration": round(dt * 1e3 / max(it, 1), 3), "max_rel_err_vs_c": err}
+    return out
 
 
 def bench_2d(P, W, torch, dev):
-    """2-D type II and adjoint, 1024 x 1024 coefficients, 2^20 polar samples, eps 1e-6 FP32."""
+    """2-D type II, adjoint and type I, 1024 x 1024 coefficients, 2^20 polar samples, eps 1e-6 FP32."""
     x, y, C = W.polar_case(5)
     xt, yt = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
     Ct = torch.from_numpy(C.ravel()).to(torch.complex64).to(dev)
@@ -263,15 +275,18 @@ def bench_2d(P, W, torch, dev):
     plan = P.nufft2d_plan(xt, yt, 1024, 1024, 1e-6, torch.complex64)
     t_f = time_loop(lambda: P.nufft2d_exec(plan, Ct, f, 0), 10, 2, torch)
     t_a = time_loop(lambda: P.nufft2d_exec(plan, Co, f, 1), 10, 2, torch)
-    P.nufft_plan_profile(plan, 1, reserve=64)
+    t_1 = time_loop(lambda: P.nufft2d_type1_exec(plan, f, Co, -1), 10, 2, torch)
+    P.nufft_plan_profile(plan, 1, reserve=96)
     for _ in range(5):
         P.nufft2d_exec(plan, Ct, f, 0)
         P.nufft2d_exec(plan, Co, f, 1)
+        P.nufft2d_type1_exec(plan, f, Co, -1)
     torch.cuda.synchronize()
     kern = {k: round(ms / n * 1e3, 1) for k, (n, ms) in P.nufft_plan_profile_read(plan).items()}
     P.nufft_plan_profile(plan, 0)
     return {"Kx": plan.K, "forward_us": round(t_f * 1e3, 1), "adjoint_us": round(t_a * 1e3, 1),
-            "forward_pts_per_s": x.shape[0] / (t_f * 1e-3), "kernels_avg_us": kern}
+            "type1_us": round(t_1 * 1e3, 1), "forward_pts_per_s": x.shape[0] / (t_f * 1e-3),
+            "kernels_avg_us": kern}
 
 
 def main():

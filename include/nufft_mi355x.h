@@ -139,6 +139,21 @@ nufft_status nufft2_backward(nufft_plan_t plan, const void *c_dev, const void *g
 nufft_status nufft2_solve(nufft_plan_t plan, const void *f_dev, void *c_dev, double tol, int max_iter,
                           int *iters, double *resid, void *stream);
 
+/* Inverse type I (Sec. 3.3, the type-I analogue): solves F1 c = f with
+ * F1 = F2^T (f_k = sum_j c_j exp(-2 pi i x_j k), k < N) for the plan's
+ * samples, M >= N, returning the minimum-norm solution c = F1^* y where
+ * (F1 F1^*) y = f.  F1 F1^* = conj(F2^* F2) is Hermitian Toeplitz (first
+ * column conj(tau), tau = F2^* 1), applied through the same circulant
+ * embedding as nufft2_solve; CG starts from y = 0 and stops when
+ * ||f - F1 F1^* y|| <= tol ||f|| (the recursively updated residual) or after
+ * max_iter iterations; then c = conj(F2 conj(y)) by one type-II transform.
+ *   f_dev: N complex (read), c_dev: M complex (written).
+ *   iters, resid: optional host outputs (iterations, final relative residual).
+ * N up to 2^22.  Allocates its temporaries and synchronises `stream` twice
+ * per iteration (not graph capturable). */
+nufft_status nufft1_solve(nufft_plan_t plan, const void *f_dev, void *c_dev, double tol, int max_iter,
+                          int *iters, double *resid, void *stream);
+
 /* ---- type III ---------------------------------------------------------- */
 
 /* Type III (Sec. 3.2): f_dev[j] ~ sum_{k<N} c_dev[k] exp(-2 pi i x_j w_k), j < M,
@@ -163,6 +178,17 @@ nufft_status nufft2d_plan(nufft_plan_t *out, int64_t n1, int64_t n2, int64_t n_p
  * C_dev: n1*n2 complex, row-major; f_dev: M complex.  The output is overwritten. */
 nufft_status nufft2d_exec(nufft_plan_t plan, void *C_dev, void *f_dev, int adjoint,
                           void *stream);
+
+/* 2-D type I (Sec. 3.1 taken along both axes; the transpose of the 2-D
+ * type II of Sec. 4) on the plan's samples:
+ *   sign = -1: F_dev[k1*n2+k2] ~ sum_j c_dev[j] exp(-2 pi i (k1 x_j + k2 y_j)),
+ *   sign = +1: the same with exp(+...), i.e. nufft2d_exec with adjoint = 1.
+ * c_dev: M complex; F_dev: n1*n2 complex, row-major, overwritten.  Same
+ * error bound as the type II, eps * ||c||_1 per output.  Allocates nothing
+ * and never synchronises.  Returns INVALID_ARG for a non-2-D plan, a NULL
+ * pointer or sign not in {-1, +1}. */
+nufft_status nufft2d_type1_exec(nufft_plan_t plan, const void *c_dev, void *F_dev, int sign,
+                                void *stream);
 
 /* ---- batches of independent 1-D type II transforms ---------------------- */
 

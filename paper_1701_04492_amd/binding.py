@@ -40,9 +40,11 @@ _sig = {
     "nufft2_grad_x": [_vp, _vp, _vp, _vp, _vp],
     "nufft2_backward": [_vp, _vp, _vp, _vp, _vp, _vp],
     "nufft2_solve": [_vp, _vp, _vp, _dbl, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _vp],
+    "nufft1_solve": [_vp, _vp, _vp, _dbl, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _vp],
     "nufft3_exec": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
     "nufft2d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _dbl, _int, _u32, _vp],
     "nufft2d_exec": [_vp, _vp, _vp, _int, _vp],
+    "nufft2d_type1_exec": [_vp, _vp, _vp, _int, _vp],
     "nufft_batch_plan": [ctypes.POINTER(_vp), _int, _vp, _vp, _vp, _dbl, _int, _u32, _vp],
     "nufft_batch_exec": [_vp, _vp, _vp, _vp],
     "nufft_plan_info": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl), ctypes.POINTER(_i64)],
@@ -194,6 +196,19 @@ def nufft2_solve(plan, f, c=None, tol=1e-6, max_iter=200):
     return c, it.value, res.value
 
 
+def nufft1_solve(plan, f, c=None, tol=1e-6, max_iter=200):
+    """Inverse type I (Sec. 3.3): the minimum-norm c with F1 c ~ f (F1 = F2^T), by CG on
+    F1 F1^* y = f and c = F1^* y.  Returns (c, iterations, relative residual)."""
+    if c is None:
+        c = torch.empty(plan.M, dtype=plan.dtype, device=plan.device)
+    it = _int()
+    res = _dbl()
+    _check(lib.nufft1_solve(plan.handle, _dev_tensor(f, plan.dtype, plan.N, "f"),
+                            _dev_tensor(c, plan.dtype, plan.M, "c"), float(tol), int(max_iter),
+                            ctypes.byref(it), ctypes.byref(res), _stream(plan.device)), "nufft1_solve")
+    return c, it.value, res.value
+
+
 def nufft3_exec(x, w, c, eps, f=None):
     M, N = x.numel(), w.numel()
     if f is None:
@@ -217,6 +232,16 @@ def nufft2d_exec(plan, C, f, adjoint=0):
     _check(lib.nufft2d_exec(plan.handle, _dev_tensor(C, plan.dtype, plan.n1 * plan.n2, "C"),
                             _dev_tensor(f, plan.dtype, plan.M, "f"), int(adjoint), _stream(plan.device)),
            "nufft2d_exec")
+
+
+def nufft2d_type1_exec(plan, c, F=None, sign=-1):
+    """2-D type I (sign -1) or adjoint (sign +1) on the plan's samples: c (M) -> F (n1*n2)."""
+    if F is None:
+        F = torch.empty(plan.n1 * plan.n2, dtype=plan.dtype, device=plan.device)
+    _check(lib.nufft2d_type1_exec(plan.handle, _dev_tensor(c, plan.dtype, plan.M, "c"),
+                                  _dev_tensor(F, plan.dtype, plan.n1 * plan.n2, "F"), int(sign),
+                                  _stream(plan.device)), "nufft2d_type1_exec")
+    return F
 
 
 def nufft_batch_plan(n_modes, xs, eps, dtype=torch.complex64, flags=0):

@@ -402,14 +402,18 @@ static nufft_status type3(int64_t M, const double *x, int64_t N, const double *w
     return NUFFT_OK;
 }
 
-// ---- inverse type II (Sec. 3.3) -------------------------------------------------
+// ---- inverse type II and type I (Sec. 3.3) -----------------------------------------
 
-// Conjugate gradients on F2^* F2 c = F2^* f.  F2^* F2 is Hermitian Toeplitz with
-// first column tau = F2^* 1; its product with a vector is a circulant product of
-// size Lc >= 2N (two DFTs and a pointwise product with the circulant's
-// eigenvalues lam = DFT(column)).  The loop runs on the host: two FP64 dot
-// products are read back per iteration.
-template <typename R>
+// Type II (T1 = false): conjugate gradients on F2^* F2 c = F2^* f.  F2^* F2 is
+// Hermitian Toeplitz with first column tau = F2^* 1; its product with a vector
+// is a circulant product of size Lc >= 2N (two DFTs and a pointwise product
+// with the circulant's eigenvalues lam = DFT(column)).
+// Type I (T1 = true), F1 = F2^T: c = F1^* y with F1 F1^* y = f.  F1 F1^* =
+// conj(F2^* F2) is Hermitian Toeplitz with first column conj(tau); CG runs on
+// it with the same circulant product, and c = conj(F2 conj(y)) is one type-II
+// transform.  The loop runs on the host: two FP64 dot products are read back
+// per iteration.
+template <typename R, bool T1>
 static nufft_status solve_impl(Plan *p, const void *f, void *c, double tol, int max_iter, int *iters_out,
                                double *resid_out, hipStream_t s)
 {
@@ -458,15 +462,25 @@ static nufft_status solve_impl(Plan *p, const void *f, void *c, double tol, int 
     // eigenvalues of the circulant embedding
     NUFFT_HIP_CHECK(solve_fill<R>(ones, M, 1.0, 0.0, s));
     NUFFT_HIP_CHECK(fused_type1<R>(a, ones, tau, +1, s));
-    NUFFT_HIP_CHECK(solve_circulant_column<R>(tau, N, Lc, lam1, s));
+    if (T1) {   // first column of conj(F2^* F2)
+        NUFFT_HIP_CHECK(solve_take_conj<R>(tau, N, ap, s));
+        NUFFT_HIP_CHECK(solve_circulant_column<R>(ap, N, Lc, lam1, s));
+    } else {
+        NUFFT_HIP_CHECK(solve_circulant_column<R>(tau, N, Lc, lam1, s));
+    }
     C *lam;
     NUFFT_HIP_CHECK(plain_fft<R>(Lc, circ->L1, circ->L2, lam1, lam2, tw1, tw2, hi, lo, &lam, s));
-    // right-hand side and the CG iteration from c = 0
-    NUFFT_HIP_CHECK(fused_type1<R>(a, (const C *)f, b, +1, s));
-    C *x = (C *)c;
+    // right-hand side (F2^* f, or f itself for the type I) and the CG
+    // iteration from zero; x is c itself for the type II, y (in b) for the type I
+    const C *rhs = (const C *)f;
+    if (!T1) {
+        NUFFT_HIP_CHECK(fused_type1<R>(a, (const C *)f, b, +1, s));
+        rhs = b;
+    }
+    C *x = T1 ? b : (C *)c;
     NUFFT_HIP_CHECK(solve_fill<R>(x, N, 0.0, 0.0, s));
-    NUFFT_HIP_CHECK(hipMemcpyAsync(r, b, N * sizeof(C), hipMemcpyDeviceToDevice, s));
-    NUFFT_HIP_CHECK(hipMemcpyAsync(pv, b, N * sizeof(C), hipMemcpyDeviceToDevice, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(r, rhs, N * sizeof(C), hipMemcpyDeviceToDevice, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(pv, rhs, N * sizeof(C), hipMemcpyDeviceToDevice, s));
     double rs;
     if ((st = dot(r, r, &rs))) return st;
     const double bn = std::sqrt(rs);
@@ -490,6 +504,11 @@ static nufft_status solve_impl(Plan *p, const void *f, void *c, double tol, int 
         NUFFT_HIP_CHECK(solve_direction<R>(pv, r, rs_new / rs, N, s));
         rs = rs_new;
         ++it;
+    }
+    if (T1) {   // c = F1^* y = conj(F2 conj(y)); r and ones are free here
+        NUFFT_HIP_CHECK(solve_take_conj<R>(x, N, r, s));
+        NUFFT_HIP_CHECK(exec_type2<R>(p, r, ones, 0, nullptr, nullptr, s));
+        NUFFT_HIP_CHECK(solve_take_conj<R>(ones, M, (C *)c, s));
     }
     if (iters_out) *iters_out = it;
     if (resid_out) *resid_out = bn > 0.0 ? std::sqrt(rs) / bn : 0.0;
@@ -911,8 +930,18 @@ nufft_status nufft2_solve(nufft_plan_t plan, const void *f, void *c, double tol,
     if (!plan || plan->kind != PLAN_1D || !f || !c || !(tol > 0.0) || max_iter < 0) return NUFFT_ERR_INVALID_ARG;
     if (plan->N > (int64_t(1) << 22)) return NUFFT_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
-    return plan->dtype == NUFFT_C64 ? solve_impl<float>(plan, f, c, tol, max_iter, iters, resid, s)
-                                    : solve_impl<double>(plan, f, c, tol, max_iter, iters, resid, s);
+    return plan->dtype == NUFFT_C64 ? solve_impl<float, false>(plan, f, c, tol, max_iter, iters, resid, s)
+                                    : solve_impl<double, false>(plan, f, c, tol, max_iter, iters, resid, s);
+}
+
+nufft_status nufft1_solve(nufft_plan_t plan, const void *f, void *c, double tol, int max_iter, int *iters,
+                          double *resid, void *stream)
+{
+    if (!plan || plan->kind != PLAN_1D || !f || !c || !(tol > 0.0) || max_iter < 0) return NUFFT_ERR_INVALID_ARG;
+    if (plan->N > (int64_t(1) << 22)) return NUFFT_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    return plan->dtype == NUFFT_C64 ? solve_impl<float, true>(plan, f, c, tol, max_iter, iters, resid, s)
+                                    : solve_impl<double, true>(plan, f, c, tol, max_iter, iters, resid, s);
 }
 
 nufft_status nufft2_backward(nufft_plan_t plan, const void *c, const void *g, void *gc, double *gx, void *stream)
@@ -993,14 +1022,23 @@ nufft_status nufft2d_exec(nufft_plan_t plan, void *C, void *f, int adjoint, void
     hipError_t e;
     if (plan->dtype == NUFFT_C64) {
         const Args2D<float> a = args_2d<float>(plan);
-        e = adjoint ? fused_2d_adj<float>(a, (const float2 *)f, (float2 *)C, s)
+        e = adjoint ? fused_2d_adj<float>(a, (const float2 *)f, (float2 *)C, 1, s)
                     : fused_2d<float>(a, (const float2 *)C, (float2 *)f, s);
     } else {
         const Args2D<double> a = args_2d<double>(plan);
-        e = adjoint ? fused_2d_adj<double>(a, (const double2 *)f, (double2 *)C, s)
+        e = adjoint ? fused_2d_adj<double>(a, (const double2 *)f, (double2 *)C, 1, s)
                     : fused_2d<double>(a, (const double2 *)C, (double2 *)f, s);
     }
     return from_hip(e);
+}
+
+nufft_status nufft2d_type1_exec(nufft_plan_t plan, const void *c, void *F, int sign, void *stream)
+{
+    if (!plan || plan->kind != PLAN_2D || !c || !F || (sign != 1 && sign != -1)) return NUFFT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->dtype == NUFFT_C64)
+        return from_hip(fused_2d_adj<float>(args_2d<float>(plan), (const float2 *)c, (float2 *)F, sign, s));
+    return from_hip(fused_2d_adj<double>(args_2d<double>(plan), (const double2 *)c, (double2 *)F, sign, s));
 }
 
 nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_modes, const int64_t *n_pts,

@@ -28,8 +28,10 @@ struct Args2D {
 
 template <typename R>
 hipError_t fused_2d(const Args2D<R> &a, const cx_t<R> *Cin, cx_t<R> *f, hipStream_t s);
+// sign = +1: the adjoint, C = sum_j g_j exp(+2 pi i (k1 x_j + k2 y_j));
+// sign = -1: the 2-D type I, C = sum_j g_j exp(-2 pi i (k1 x_j + k2 y_j)).
 template <typename R>
-hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, hipStream_t s);
+hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, int sign, hipStream_t s);
 int pass_b2d_cap(int GX, bool fp32);
 int pass_b2d_adj_cap(int GX, bool fp32);
 template <typename R>

@@ -11,7 +11,10 @@
 //   pass B (per column n2 and sample range): for every r2, r1:
 //     X = F_{Gx}(v^x_r1 o H_r2[n2][:]) and f_j += u^x_r1 u^y_r2 X[tx_j] for
 //     the samples with ty_j = n2 (sorted there by the plan).
-// The adjoint runs the two passes in reverse with the conjugate factors.
+// The adjoint runs the two passes in reverse with the conjugate factors; the
+// 2-D type I (Sec. 3.1 applied per axis, the transpose of the type II) runs
+// the same two passes with the factors unconjugated and forward-sign FFTs.
+// Both are instantiated from one template on the sign DIR of the exponent.
 #include "fused_common.h"
 #include "kernels_2d.h"
 
@@ -171,19 +174,19 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
     }
 }
 
-// ---- adjoint pass B': one column n2 (or a slice of its samples) -> Z_r2[n2][k1] ----
+// ---- adjoint / type-I pass B': one column n2 (or a slice of its samples) -> Z_r2[n2][k1] ----
 // Task = (n2, first, end, slot): the sorted samples [first, end) of column n2,
-// at most SCAP of them, staged once in LDS (exp(+i pi (Xx + Xy)) g_j, zx, zy,
-// tx).  For each r2 and chunk of RC ranks r1 they are summed per grid point
-// (balanced segmented sum, deterministic), transformed along n1 (inverse
-// sign), weighted by v^x_r1(k1) and summed over r1 in registers; the row for
+// at most SCAP of them, staged once in LDS (exp(DIR i pi (Xx + Xy)) g_j, zx,
+// zy, tx).  For each r2 and chunk of RC ranks r1 they are summed per grid point
+// (balanced segmented sum, deterministic), transformed along n1 (sign DIR),
+// weighted by v^x_r1(k1) and summed over r1 in registers; the row for
 // r2 is written once: to Z_r2[n2][:] when the task holds the whole column
 // (slot < 0), else to partial row `slot` of Zp, which k_2d_sum_parts adds up.
-template <typename R, int GX, int RC, int SCAP, bool TWG>
+template <typename R, int GX, int RC, int SCAP, bool TWG, int DIR>
 __global__ void __launch_bounds__(RC * GX / 16)
 k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const int4 *__restrict__ tasks, int ntasks,
                const int32_t *__restrict__ perm, const uint32_t *__restrict__ keys, const R *__restrict__ Xxs,
-               const R *__restrict__ Xys, Factors<R> fx, Factors<R> fy, const cx_t<R> *__restrict__ twi_g,
+               const R *__restrict__ Xys, Factors<R> fx, Factors<R> fy, const cx_t<R> *__restrict__ twd_g,
                cx_t<R> *__restrict__ Z, cx_t<R> *__restrict__ Zp)
 {
     using C = cx_t<R>;
@@ -198,12 +201,12 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     __shared__ unsigned short spos[SCAP];
     __shared__ C hv[RC * NT], tv[RC * NT];
     __shared__ int hix[NT], tix[NT];
-    const C *tw = TWG ? twi_g : tw_s;
+    const C *tw = TWG ? twd_g : tw_s;
     const int task = xcd_task(ntasks);
     if (task < 0) return;
     const int4 tk = tasks[task];
     const int tid = threadIdx.x;
-    if (!TWG) load_tw_s<C, GX, -1, NT>(tw_s, twi_g);   // twi_g already has the + sign
+    if (!TWG) load_tw_s<C, GX, -1, NT>(tw_s, twd_g);   // twd_g already has the sign DIR
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t n2 = tk.x;
     const int tile_lo = tk.y;
@@ -235,7 +238,7 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
                 if (i < cnt) {
                     R sn, cs;
                     sincospi_r(ax[u] + ay[u], &sn, &cs);
-                    sval[i] = cmul(cmake<C>(cs, sn), gv[u]);
+                    sval[i] = cmul(cmake<C>(cs, DIR * sn), gv[u]);   // exp(DIR i pi (Xx + Xy))
                     szx[i] = ax[u] * fx.inv_gamma;
                     szy[i] = ay[u] * fy.inv_gamma;
                     spos[i] = (unsigned short)(kv[u] & (uint32_t)(GX - 1));
@@ -263,11 +266,12 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
 #pragma unroll
             for (int gg = 0; gg < RC; ++gg) ux[gg] = rank_poly(fx, min(r0 + gg, fx.K - 1));
             auto contrib = [&](int i, int gg) -> C {
-                return crot(cscale(sval[i], rank_eval(ux[gg], szx[i]) * spy[i]), -(r0 + gg + r2));
+                // i^(r1 + r2) for the type I, i^-(r1 + r2) for the adjoint
+                return crot(cscale(sval[i], rank_eval(ux[gg], szx[i]) * spy[i]), -DIR * (r0 + gg + r2));
             };
             seg_spread<C, RC, NT>(cnt, nr, pos, contrib, buf, P, hv, tv, hix, tix);
             __syncthreads();
-            block_fft_lds<C, GX, 1, fft_wave_sync<GX>>(buf + g * P, tw, lt);
+            block_fft_lds<C, GX, DIR, fft_wave_sync<GX>>(buf + g * P, tw, lt);
             fft_publish<GX>();
 #pragma unroll
             for (int m = 0; m < ZA; ++m) {
@@ -302,11 +306,11 @@ k_2d_sum_parts(const int4 *__restrict__ rtasks, const cx_t<R> *__restrict__ Zp, 
     }
 }
 
-// ---- adjoint pass A': G rows k1, FFT along n2 -> k2, weighted sum over r2 --------
-template <typename R, int GY, int G>
+// ---- adjoint / type-I pass A': G rows k1, FFT along n2 -> k2 (sign DIR), weighted sum over r2 ----
+template <typename R, int GY, int G, int DIR>
 __global__ void __launch_bounds__(G * GY / 16)
 k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX, int Ky,
-               const cx_t<R> *__restrict__ twi_g, cx_t<R> *__restrict__ Cout)
+               const cx_t<R> *__restrict__ twd_g, cx_t<R> *__restrict__ Cout)
 {
     using C = cx_t<R>;
     constexpr int TPF = GY / 16;
@@ -318,7 +322,7 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
     const int task = xcd_task(ncg);
     if (task < 0) return;
     const int tid = threadIdx.x;
-    load_tw_s<C, GY, -1, NT>(tw, twi_g);   // twi_g already has the + sign
+    load_tw_s<C, GY, -1, NT>(tw, twd_g);   // twd_g already has the sign DIR
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)task * G;
     const ZMap zm = zmap(N2);
@@ -347,7 +351,7 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
             }
         }
         __syncthreads();
-        block_fft_lds<C, GY, 1, fft_wave_sync<GY>>(buf + g * P, tw, lt);
+        block_fft_lds<C, GY, DIR, fft_wave_sync<GY>>(buf + g * P, tw, lt);
         fft_publish<GY>();
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -429,18 +433,19 @@ hipError_t fused_2d(const Args2D<R> &a, const cx_t<R> *Cin, cx_t<R> *f, hipStrea
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, hipStream_t s)
+template <typename R, int DIR>
+static hipError_t fused_2d_t1_dir(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, hipStream_t s)
 {
     constexpr bool F = sizeof(R) == 4;
-    prof_begin(a.prof, "adj2d_passB", s);
+    const cx_t<R> *twx = DIR < 0 ? a.twx : a.twxi, *twy = DIR < 0 ? a.twy : a.twyi;
+    prof_begin(a.prof, DIR > 0 ? "adj2d_passB" : "type1_2d_passB", s);
     switch (a.Gx) {
 #define BA2(GG, RF, SCF, RD, SCD, TG)                                                                        \
     case GG: {                                                                                              \
         constexpr int RR = F ? RF : RD, SC = F ? SCF : SCD;                                                 \
-        hipLaunchKernelGGL((k_2d_passB_adj<R, GG, RR, SC, TG>), dim3(xcd_grid(a.natasks)), dim3(RR * GG / 16), \
-                           0, s, gin, a.N1, (int64_t)a.Gy, a.atasks, a.natasks, a.perm, a.keys, a.Xxs, a.Xys,  \
-                           a.fx, a.fy, a.twxi, a.H, a.Zp);                                                   \
+        hipLaunchKernelGGL((k_2d_passB_adj<R, GG, RR, SC, TG, DIR>), dim3(xcd_grid(a.natasks)),             \
+                           dim3(RR * GG / 16), 0, s, gin, a.N1, (int64_t)a.Gy, a.atasks, a.natasks, a.perm,   \
+                           a.keys, a.Xxs, a.Xys, a.fx, a.fy, twx, a.H, a.Zp);                               \
         break;                                                                                              \
     }
         BA2(16, 16, 256, 16, 256, false)
@@ -456,19 +461,19 @@ hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, h
     }
     prof_end(a.prof, s);
     if (a.nrtasks > 0) {
-        prof_begin(a.prof, "adj2d_sum", s);
+        prof_begin(a.prof, DIR > 0 ? "adj2d_sum" : "type1_2d_sum", s);
         hipLaunchKernelGGL(k_2d_sum_parts<R>, dim3(a.nrtasks, a.fy.K), dim3(256), 0, s, a.rtasks,
                            (const cx_t<R> *)a.Zp, (int64_t)a.Gx, (int64_t)a.Gy, a.fy.K, a.H);
         prof_end(a.prof, s);
     }
-    prof_begin(a.prof, "adj2d_passA", s);
+    prof_begin(a.prof, DIR > 0 ? "adj2d_passA" : "type1_2d_passA", s);
     switch (a.Gy) {
 #define AA2(GG, GF, GD)                                                                                     \
     case GG: {                                                                                              \
         constexpr int G = F ? GF : GD;                                                                      \
         const int ncg = (int)((a.N1 + G - 1) / G);                                                          \
-        hipLaunchKernelGGL((k_2d_passA_adj<R, GG, G>), dim3(xcd_grid(ncg)), dim3(G * GG / 16), 0, s,         \
-                           (const cx_t<R> *)a.H, a.N1, a.N2, (int64_t)a.Gx, a.fy.K, a.twyi, Cout);          \
+        hipLaunchKernelGGL((k_2d_passA_adj<R, GG, G, DIR>), dim3(xcd_grid(ncg)), dim3(G * GG / 16), 0, s,    \
+                           (const cx_t<R> *)a.H, a.N1, a.N2, (int64_t)a.Gx, a.fy.K, twy, Cout);             \
         break;                                                                                              \
     }
         AA2(16, 8, 8)
@@ -484,6 +489,12 @@ hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, h
     }
     prof_end(a.prof, s);
     return hipGetLastError();
+}
+
+template <typename R>
+hipError_t fused_2d_adj(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R> *Cout, int sign, hipStream_t s)
+{
+    return sign < 0 ? fused_2d_t1_dir<R, -1>(a, gin, Cout, s) : fused_2d_t1_dir<R, 1>(a, gin, Cout, s);
 }
 
 // Samples per adjoint pass-B' task (the LDS staging capacity of the instantiation above).
@@ -569,8 +580,8 @@ hipError_t launch_assign2d(const double *x, const double *y, int64_t M, int64_t 
 
 template hipError_t fused_2d<float>(const Args2D<float> &, const float2 *, float2 *, hipStream_t);
 template hipError_t fused_2d<double>(const Args2D<double> &, const double2 *, double2 *, hipStream_t);
-template hipError_t fused_2d_adj<float>(const Args2D<float> &, const float2 *, float2 *, hipStream_t);
-template hipError_t fused_2d_adj<double>(const Args2D<double> &, const double2 *, double2 *, hipStream_t);
+template hipError_t fused_2d_adj<float>(const Args2D<float> &, const float2 *, float2 *, int, hipStream_t);
+template hipError_t fused_2d_adj<double>(const Args2D<double> &, const double2 *, double2 *, int, hipStream_t);
 template hipError_t launch_assign2d<float>(const double *, const double *, int64_t, int64_t, int64_t, double,
                                            double, float *, float *, uint32_t *, int32_t *, unsigned long long *,
                                            int *, hipStream_t);

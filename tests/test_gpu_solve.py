@@ -114,3 +114,68 @@ def test_solve_argument_errors():
     # zero right-hand side: zero solution, no iteration
     sol, it, res = P.nufft2_solve(plan, f)
     assert it == 0 and torch.count_nonzero(sol).item() == 0
+
+
+# ---- inverse type I (nufft1_solve) ------------------------------------------------
+
+@pytest.mark.parametrize("n,m", [(500, 500), (300, 700)])
+def test_type1_fp64_against_oracle(n, m):
+    x = _jittered(n, 1 / 8, 60) if m == n else np.random.default_rng(60).random(m)
+    f = W.complex_normal(W.rng_for(61), n)
+    plan = P.nufft2_plan(_t(x, torch.float64), n, 1e-12, C128)
+    sol, it, res = P.nufft1_solve(plan, _t(f, C128), tol=1e-12, max_iter=2000)
+    sol = sol.cpu().numpy()
+    assert sol.shape == (m,)
+    ref = I.lstsq_type1(x, f, n)
+    _, it_ref, _ = I.cg_type1(x, f, n, tol=1e-12, max_iter=2000)
+    err = np.abs(sol - ref).max() / np.abs(ref).max()
+    back = D.nudft1(x, sol, n, sign=-1)
+    _say("type-I solve n=%d m=%d fp64: iterations %d (oracle %d), residual %.2e, err %.2e"
+         % (n, m, it, it_ref, res, err))
+    assert res <= 1e-12
+    assert err <= 1e-7
+    assert np.abs(back - f).max() <= 1e-7 * np.abs(f).max()
+    if m == n:
+        assert abs(it - it_ref) <= 2
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_type1_equispaced_is_inverse_fft(dtype):
+    n = 1024
+    x = np.arange(n) / n
+    f = W.complex_normal(W.rng_for(62), n)
+    plan = P.nufft2_plan(_t(x, torch.float64), n, 1e-6 if dtype == C64 else 1e-12, dtype)
+    sol, it, _ = P.nufft1_solve(plan, _t(f, dtype), tol=1e-5 if dtype == C64 else 1e-12)
+    sol = sol.cpu().numpy()
+    _say("type-I equispaced", dtype, "iterations", it)
+    assert it == 1
+    ref = np.fft.ifft(f)
+    assert np.abs(sol - ref).max() <= (1e-5 if dtype == C64 else 1e-12) * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_type1_two_pass_round_trip(dtype):
+    """N = 2^16: solve(F1 c) for c in the range of F1^* returns c (square, gamma = 1/8)."""
+    n = 1 << 16
+    x = _jittered(n, 1 / 8, 63)
+    c = W.complex_normal(W.rng_for(64), n)
+    plan = P.nufft2_plan(_t(x, torch.float64), n, 1e-6 if dtype == C64 else 1e-12, dtype)
+    ct = _t(c, dtype)
+    f = P.nufft1_exec(plan, ct, sign=-1)
+    tol = 1e-5 if dtype == C64 else 1e-11
+    sol, it, res = P.nufft1_solve(plan, f, tol=tol, max_iter=200)
+    err = (sol - ct).abs().max().item() / ct.abs().max().item()
+    _say("type-I round trip n=2^16", dtype, "iterations %d residual %.2e err %.2e" % (it, res, err))
+    assert res <= tol
+    assert it <= 40
+    assert err <= (1e-4 if dtype == C64 else 1e-8)
+
+
+def test_type1_solve_argument_errors():
+    x = _t(np.arange(64) / 64, torch.float64)
+    plan = P.nufft2_plan(x, 64, 1e-6, C64)
+    f = torch.zeros(64, dtype=C64, device=DEV)
+    with pytest.raises(P.NufftError):
+        P.nufft1_solve(plan, f, max_iter=-1)
+    sol, it, res = P.nufft1_solve(plan, f)
+    assert it == 0 and torch.count_nonzero(sol).item() == 0
