@@ -33,10 +33,11 @@ def _fail_multi(n):
     sys.exit(2)
 
 
-def kernel_bytes(name, K, N, M, L, cs):
+def kernel_bytes(name, K, N, M, L, cs, ys=None):
     """Algorithmic bytes moved by one launch of a fused kernel: compulsory I/O plus the
-    K-wide intermediate written by the first pass and read by the second."""
-    inter = K * L * cs
+    K-wide intermediate written by the first pass and read by the second (ys bytes per
+    intermediate value: cs, or 4 for the half-precision exchange)."""
+    inter = K * L * (cs if ys is None else ys)
     plan_pts = M * (4 + 4 + 4)           # sorted key, perturbation X (f32), sample index
     table = {
         "fwd_passA": N * cs + inter,
@@ -230,6 +231,35 @@ def bench_batch(P, W, torch, dev):
             "separate_fused_launches_us": round(t_sep * 1e3, 1),
             "separate_plain_launches_us": round(t_plain * 1e3, 1),
             "speedup_vs_separate_plain": round(t_plain / t_graph, 2)}
+
+
+def bench_half(P, torch, x, c, y, N, M, steps, warmup):
+    """The same forward+backward step at Table 1's half precision, eps = 2^-10, with the
+    half-precision exchange (fp16 intermediate between the two passes)."""
+    plan = P.nufft2_plan(x, N, 2.0 ** -10, torch.complex64, P.NUFFT_FLAG_HALF_EXCHANGE)
+    xg = x.clone().requires_grad_(True)
+    cg = c.clone().requires_grad_(True)
+
+    def step():
+        xg.grad = None
+        cg.grad = None
+        loss = torch.view_as_real(P.nufft2(xg, cg, plan) - y).pow(2).sum()
+        loss.backward()
+
+    ms = time_loop(step, steps, warmup, torch)
+    P.nufft_plan_profile(plan, 1, reserve=8 * (steps + 1))
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    kern = {}
+    for name, (calls, tot) in P.nufft_plan_profile_read(plan).items():
+        avg = tot / calls
+        by = kernel_bytes(name, plan.K, N, M, plan.grid, 8, ys=4)
+        kern[name] = {"avg_us": round(avg * 1e3, 2),
+                      "GBs": None if by is None else round(by / (avg * 1e-3) / 1e9, 1)}
+    P.nufft_plan_profile(plan, 0)
+    return {"eps": 2.0 ** -10, "K": plan.K, "ms_per_step": round(ms, 4), "pts_per_s": M / (ms * 1e-3),
+            "kernels": kern}
 
 
 def bench_solve(P, W, torch, dev):
@@ -434,6 +464,7 @@ def main():
         out["forward_2p20"] = sec
 
     if not args.no_secondary:
+        out["fwd_bwd_2p22_half"] = bench_half(P, torch, xg.detach(), c, y, N, M, args.steps, args.warmup)
         out["batch_512"] = bench_batch(P, W, torch, dev)
         out["polar_2d"] = bench_2d(P, W, torch, dev)
         out["inverse_2p20"] = bench_solve(P, W, torch, dev)

@@ -69,7 +69,17 @@ enum {
     NUFFT_FLAG_PLAIN = 2u,
     /* Batches only: time the persistent launch at a few grid sizes while
      * planning and keep the fastest (reported as `grid` by nufft_plan_info). */
-    NUFFT_FLAG_AUTOTUNE = 4u
+    NUFFT_FLAG_AUTOTUNE = 4u,
+    /* 1-D complex64 plans only, eps >= 2^-10 (Table 1's "half" precision):
+     * the K x L intermediate that the two passes exchange through HBM
+     * (N > 4096) is stored as fp16 pairs, 4 bytes per value instead of 8,
+     * with one power-of-two scale per column (type II) or row (type I /
+     * adjoint) so that no value overflows.  Arithmetic stays FP32.  The
+     * storage rounding adds at most about 2^-11 * sum_r |u_r| * ||c||_1 to
+     * each output, inside the 4 eps ||c||_1 bound for eps >= 2^-10.
+     * Combined with NUFFT_FLAG_PLAIN: NUFFT_ERR_INVALID_ARG; with complex128
+     * or a smaller eps: NUFFT_ERR_UNSUPPORTED. */
+    NUFFT_FLAG_HALF_EXCHANGE = 8u
 };
 
 /* ---- 1-D type II / type I / adjoint ----------------------------------- */

@@ -205,7 +205,12 @@ nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
         NUFFT_HIP_CHECK(plain_build_U<R>((const R *)p->X, M, fac, (cx_t<R> *)p->U, s));
     }
     if (p->L2 > 1) {
-        p->Y = p->alloc((size_t)p->K * L * cs);
+        const bool half = (p->flags & NUFFT_FLAG_HALF_EXCHANGE) != 0;
+        p->Y = p->alloc((size_t)p->K * L * (half ? 4 : cs));
+        if (half) {
+            p->E = (int8_t *)p->alloc((size_t)p->K * std::max(p->L1, p->L2));
+            if (!p->E) return NUFFT_ERR_ALLOC;
+        }
         p->sinv = (int32_t *)p->alloc((size_t)M * sizeof(int32_t));
         p->gsort = p->alloc((size_t)M * cs);
         if (!p->Y || !p->sinv || !p->gsort) return NUFFT_ERR_ALLOC;
@@ -246,6 +251,8 @@ FusedArgs<R> fused_args(const Plan *p)
     a.t = p->t;
     a.X = (const R *)p->X;
     a.Y = (cx_t<R> *)p->Y;
+    a.half = sizeof(R) == 4 && (p->flags & NUFFT_FLAG_HALF_EXCHANGE) && p->L2 > 1;
+    a.E = p->E;
     a.tw1 = (const cx_t<R> *)p->tw1;
     a.tw1i = (const cx_t<R> *)p->tw1i;
     a.tw2i = (const cx_t<R> *)p->tw2i;
@@ -881,10 +888,14 @@ nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, cons
     *out = nullptr;
     if (n_modes < 1 || n_pts < 1 || !x_dev) return NUFFT_ERR_INVALID_ARG;
     if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_PLAIN)) return NUFFT_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_PLAIN | NUFFT_FLAG_HALF_EXCHANGE))
+        return NUFFT_ERR_INVALID_ARG;
+    if ((flags & NUFFT_FLAG_HALF_EXCHANGE) && (flags & NUFFT_FLAG_PLAIN)) return NUFFT_ERR_INVALID_ARG;
     if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
     nufft_status st;
     if (!eps_ok(eps, dtype, &st)) return st;
+    // fp16 storage rounding (2^-11 relative) must fit the error budget
+    if ((flags & NUFFT_FLAG_HALF_EXCHANGE) && (dtype != NUFFT_C64 || eps < 0x1p-10)) return NUFFT_ERR_UNSUPPORTED;
     Plan *p = new (std::nothrow) Plan();
     if (!p) return NUFFT_ERR_ALLOC;
     p->kind = PLAN_1D;

@@ -1,10 +1,51 @@
 // Device helpers shared by the fused kernels (1-D, 2-D, batched).
 #pragma once
 
+#include <hip/hip_fp16.h>
+
+#include <type_traits>
+
 #include "fft.h"
 #include "kernels.h"
 
 namespace nufft {
+
+// ---- half-precision exchange (FP32 plans with NUFFT_FLAG_HALF_EXCHANGE) ----
+// The K x L intermediate of the two-pass split is stored as two fp16 per
+// complex value (4 bytes instead of 8) with one power-of-two scale 2^s per
+// block of values that one pass writes together: a column of pass A, a row of
+// pass B'.  s maps the block's largest |re|, |im| into [2^14, 2^15), below the
+// fp16 maximum 65504; every value above 2^-28 of the block maximum keeps the
+// relative rounding 2^-11 of fp16, smaller ones an absolute error below 2^-39
+// of the maximum.  The scaling itself is exact (ldexp).
+__device__ __forceinline__ int hx_exponent(float m)
+{
+    if (!(m > 0.0f) || !(m <= 3.4e38f)) return 0;   // all-zero block, or inf / NaN: stored unscaled
+    const int s = 14 - ilogbf(m);
+    return s > 127 ? 127 : s;                        // fits int8 (s >= -113)
+}
+__device__ __forceinline__ __half2 hx_pack(float2 v, int s)
+{
+    return __floats2half2_rn(ldexpf(v.x, s), ldexpf(v.y, s));
+}
+__device__ __forceinline__ float2 hx_unpack(__half2 h, int s)
+{
+    const float2 f = __half22float2(h);
+    return make_float2(ldexpf(f.x, -s), ldexpf(f.y, -s));
+}
+__device__ __forceinline__ float cmaxabs(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
+// max over the lanes of a wave whose lane index agrees modulo S (S a power of two)
+__device__ __forceinline__ float wave_max_mod(float m, int S)
+{
+    for (int o = S; o < 64; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+    return m;
+}
+// max over each aligned group of S consecutive lanes (S a power of two)
+__device__ __forceinline__ float wave_max_group(float m, int S)
+{
+    for (int o = 1; o < S && o < 64; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+    return m;
+}
 
 // Copies the length-L FFT twiddle table (conjugated for DIR = +1) into LDS
 // with the workgroup's NT threads.  Every load is issued before the first

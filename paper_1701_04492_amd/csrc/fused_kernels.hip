@@ -221,18 +221,22 @@ hipError_t fused_sort_input(const FusedArgs<R> &a, const cx_t<R> *in, const char
 // (k2 = lt + q L2/16); for each rank of the chunk it is scaled by v_r,
 // transformed, multiplied by exp(-2 pi i k1 n2 / L) and stored as
 // Y_r[n2][k1] (G-element runs).
-template <typename R, int L2, int G, bool TWG>
+// H (FP32 only): Y in fp16 pairs with one scale exponent per (rank, column),
+// E[r * L1 + k1] (the half-precision exchange).
+template <typename R, int L2, int G, bool TWG, bool H>
 __global__ void __launch_bounds__(G * L2 / 16)
 k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, int mode,
         const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
-        cx_t<R> *__restrict__ Y)
+        cx_t<R> *__restrict__ Y, int8_t *__restrict__ E)
 {
     using C = cx_t<R>;
     constexpr int TPF = L2 / 16;
     constexpr int NT = G * TPF;
     constexpr int P = fft_pitch_g(L2, G);
+    static_assert(!H || sizeof(R) == 4, "the half-precision exchange is an FP32 path");
     __shared__ C buf[G * P];
     __shared__ C tw_s[TWG ? 1 : L2];
+    __shared__ unsigned smax[H ? 2 * G : 1];   // per-column block maxima (float bits), two parities
     const C *tw = TWG ? tw_g : tw_s;
     const int nrc = (K + RCA - 1) / RCA;
     const int task = xcd_task((int)(L1 / G) * nrc);
@@ -244,6 +248,7 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)cg * G;
     const int64_t L = L1 * L2;
+    if (H && tid < 2 * G) smax[tid] = 0;
     {
         C cl[16];   // all 16 loads in flight before the first LDS store
 #pragma unroll
@@ -280,12 +285,40 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
         __syncthreads();   // earlier readers of buf are done
         block_fft_regs<C, L2, -1, fft_wave_sync<L2>>(buf + g * P, tw, lt, v);
         fft_publish<L2>();
-        C *Yr = Y + (int64_t)r * L + k1_0;
+        if constexpr (H) {
+            // this thread's 16 outputs all lie in column gg = tid % G (NT is a multiple of G)
+            C o[16];
+            float m = 0.0f;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int i = tid + e * NT;
-            const int gg = i % G, n2 = i / G;
-            Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], wt[e]);
+            for (int e = 0; e < 16; ++e) {
+                const int i = tid + e * NT;
+                o[e] = cmul(buf[(i % G) * P + lds_pad(i / G)], wt[e]);
+                m = fmaxf(m, cmaxabs(o[e]));
+            }
+            m = wave_max_mod(m, G);
+            unsigned *sm = smax + (r & 1) * G;
+            if ((tid & 63) < G) atomicMax(&sm[tid & 63], __float_as_uint(m));
+            __syncthreads();
+            const int gg = tid % G;
+            const int ex = hx_exponent(__uint_as_float(sm[gg]));
+            if (tid < G) {
+                E[(int64_t)r * L1 + k1_0 + tid] = (int8_t)ex;
+                smax[((r + 1) & 1) * G + tid] = 0;   // its last readers finished before this rank's first barrier
+            }
+            __half2 *Yr = reinterpret_cast<__half2 *>(Y) + (int64_t)r * L + k1_0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int n2 = (tid + e * NT) / G;
+                Yr[(int64_t)n2 * L1 + gg] = hx_pack(o[e], ex);
+            }
+        } else {
+            C *Yr = Y + (int64_t)r * L + k1_0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int i = tid + e * NT;
+                const int gg = i % G, n2 = i / G;
+                Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], wt[e]);
+            }
         }
     }
 }
@@ -295,12 +328,13 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
 // registers while the current chunk is transformed and gathered.  Every
 // sample of the tile (up to NT*S per round) gathers its RC spectrum values
 // from LDS and accumulates u_r(j) X_r[t_j] in registers.
-template <typename R, int L1, int RC, int S, bool TWG>
+// H: Y holds fp16 pairs scaled per (rank, column) by 2^E[r * L1 + k1].
+template <typename R, int L1, int RC, int S, bool TWG, bool H>
 __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
         const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
         Factors<R> fac, const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ f, int mode,
-        const cx_t<R> *__restrict__ gup, double *__restrict__ gx)
+        const cx_t<R> *__restrict__ gup, double *__restrict__ gx, const int8_t *__restrict__ E)
 {
     using C = cx_t<R>;
     constexpr int TPF = L1 / 16;
@@ -319,6 +353,31 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     const int64_t L = (int64_t)L1 * L2;
     const int64_t tile_lo = off[n2 * L1], tile_hi = off[(n2 + 1) * L1];
     const C *Yrow = Y + n2 * L1 + lt;
+    const __half2 *Yhrow = reinterpret_cast<const __half2 *>(Y) + n2 * L1 + lt;
+    // Rank row rr of the tile, the lanes' 16 elements (zero for rr >= K), in
+    // two steps so that a prefetch stays in flight: fetch issues the loads
+    // into raw registers (fp16 pairs and exponents for H), take decodes them.
+    using Raw = typename std::conditional<H, __half2, C>::type;
+    // (a rank beyond K loads nothing: its lanes are zero and its transform is discarded)
+    auto fetch = [&](int rr, Raw (&w)[16], int8_t (&ev)[16]) {
+        const bool in = rr < fac.K;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if constexpr (H) {
+                w[q] = in ? Yhrow[(int64_t)rr * L + q * TPF] : __half2{};
+                ev[q] = in ? E[(int64_t)rr * L1 + lt + q * TPF] : (int8_t)0;
+            } else {
+                w[q] = in ? Yrow[(int64_t)rr * L + q * TPF] : cmake<C>(0, 0);
+            }
+        }
+    };
+    auto take = [&](const Raw (&w)[16], const int8_t (&ev)[16], C (&v)[16]) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if constexpr (H) v[q] = hx_unpack(w[q], ev[q]);
+            else v[q] = w[q];
+        }
+    };
 
     for (int64_t c0 = tile_lo; c0 < tile_hi; c0 += CAP) {
         // the round's sample data: every load issued before any is used
@@ -331,21 +390,16 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             kv[s] = keys[i];
             xs[s] = Xs[i];
         }
-        C vn[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) vn[q] = (g < fac.K) ? Yrow[(int64_t)g * L + q * TPF] : cmake<C>(0, 0);
+        Raw vn[16];
+        int8_t en[16];
+        fetch(g, vn, en);
         C acc[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[s] = cmake<C>(0, 0);
         for (int r0 = 0; r0 < fac.K; r0 += RC) {
             C v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = vn[q];
-            const int rn = r0 + RC + g;
-            if (r0 + RC < fac.K) {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) vn[q] = (rn < fac.K) ? Yrow[(int64_t)rn * L + q * TPF] : cmake<C>(0, 0);
-            }
+            take(vn, en, v);
+            if (r0 + RC < fac.K) fetch(r0 + RC + g, vn, en);
             __syncthreads();
             block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v);
             fft_publish<L1>();
@@ -400,12 +454,14 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
 // and multiplied by exp(DIR 2 pi i n2 k1 / L): Z_r[n2][k1].
 // TWG: read the FFT twiddles (already of sign DIR) from global memory instead
 // of an LDS copy, for the sizes where LDS would otherwise cap occupancy.
-template <typename R, int L1, int RC, int SCAP, int dir, bool TWG>
+// H (FP32 only): Z in fp16 pairs with one scale exponent per (rank, row),
+// E[r * L2 + n2] (the half-precision exchange).
+template <typename R, int L1, int RC, int SCAP, int dir, bool TWG, bool H>
 __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__ Xs,
             const uint32_t *__restrict__ keys, const int32_t *__restrict__ off,
             Factors<R> fac, const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi,
-            const cx_t<R> *__restrict__ lo, cx_t<R> *__restrict__ Z)
+            const cx_t<R> *__restrict__ lo, cx_t<R> *__restrict__ Z, int8_t *__restrict__ E)
 {
     using C = cx_t<R>;
     constexpr int TPF = L1 / 16;
@@ -419,9 +475,12 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
     __shared__ R sz[SCAP];
     __shared__ unsigned short spos[SCAP];
     __shared__ int soff[L1 + 1];
+    __shared__ unsigned smax[H ? 2 * RC : 1];   // per-row block maxima (float bits), two parities
+    static_assert(!H || sizeof(R) == 4, "the half-precision exchange is an FP32 path");
     const int task = xcd_task((int)L2);
     if (task < 0) return;
     const int tid = threadIdx.x;
+    if (H && tid < 2 * RC) smax[tid] = 0;
     if (!TWG) load_tw_s<C, L1, -1, NT>(tw_s, tw_g);   // tw_g already has the sign DIR
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t n2 = task;
@@ -530,7 +589,28 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
         __syncthreads();
         block_fft_lds<C, L1, dir, fft_wave_sync<L1>>(buf + g * P, tw, lt);   // each thread then reads only its own transform
         const int r = r0 + g;
-        if (r < fac.K) {
+        if constexpr (H) {
+            // row g's block maximum over its TPF threads (whole waves when TPF >= 64)
+            C o[16];
+            float m = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                o[q] = cmul(buf[g * P + lds_pad(lt + q * TPF)], wt[q]);
+                m = fmaxf(m, cmaxabs(o[q]));
+            }
+            m = wave_max_group(m, TPF);
+            const int par = (r0 / RC) & 1;
+            if ((lt & 63) == 0) atomicMax(&smax[par * RC + g], __float_as_uint(m));
+            __syncthreads();
+            const int ex = hx_exponent(__uint_as_float(smax[par * RC + g]));
+            if (tid < RC) smax[(par ^ 1) * RC + tid] = 0;   // its last readers finished at the previous chunk's end
+            if (r < fac.K) {
+                __half2 *Zr = reinterpret_cast<__half2 *>(Z) + (int64_t)r * L + n2 * L1;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) Zr[lt + q * TPF] = hx_pack(o[q], ex);
+                if (lt == 0) E[(int64_t)r * L2 + n2] = (int8_t)ex;
+            }
+        } else if (r < fac.K) {
             C *Zr = Z + (int64_t)r * L + n2 * L1;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -546,10 +626,11 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
 // columns Z_r[:][k1] (the next rank's block is loaded into registers while
 // this one is transformed) are transformed along n2 -> k2 and accumulated
 // with weight v_r(k1 + L1 k2) in registers; the sum over r is written once.
-template <typename R, int L2, int G, int DIR, bool TWG>
+// H: Z holds fp16 pairs scaled per (rank, row) by 2^E[r * L2 + n2].
+template <typename R, int L2, int G, int DIR, bool TWG, bool H>
 __global__ void __launch_bounds__(G * L2 / 16)
 k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const cx_t<R> *__restrict__ tw_g,
-            cx_t<R> *__restrict__ out)
+            cx_t<R> *__restrict__ out, const int8_t *__restrict__ E)
 {
     using C = cx_t<R>;
     constexpr int TPF = L2 / 16;
@@ -567,28 +648,47 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
     const int64_t L = L1 * L2;
     const ZMap zm = zmap(N);
     C acc[16];
-    C zn[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int i = tid + e * NT;
-        acc[e] = cmake<C>(0, 0);
-        zn[e] = Z[k1_0 + (i % G) + (int64_t)(i / G) * L1];
-    }
-    for (int r = 0; r < K; ++r) {
-        __syncthreads();   // previous readers of buf are done
+    // rank r's block of G columns in raw registers (fp16 pairs for H); for H the
+    // rank's L2 row exponents go through LDS (L2 / NT = 16 / G bytes per thread,
+    // one load), which keeps 16 exponent registers out of this register-bound kernel
+    using Raw = typename std::conditional<H, __half2, C>::type;
+    constexpr int EB = 16 / G;   // exponent bytes per thread
+    using EWord = typename std::conditional<EB == 8, uint2, typename std::conditional<EB == 4, uint32_t,
+                                            uint16_t>::type>::type;
+    static_assert(!H || (EB == 2 || EB == 4 || EB == 8), "G must be 2, 4 or 8 for the half exchange");
+    __shared__ EWord sexp[H ? 2 * NT : 1];
+    Raw zn[16];
+    auto fetch = [&](int r) {
+        if constexpr (H) {   // the exponent word first, so that its wait leaves the values in flight
+            const EWord ew = reinterpret_cast<const EWord *>(E + (int64_t)r * L2)[tid];
+            sexp[(r & 1) * NT + tid] = ew;
+        }
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;
-            buf[(i % G) * P + lds_pad(i / G)] = zn[e];
+            const int64_t at = (int64_t)r * L + k1_0 + (i % G) + (int64_t)(i / G) * L1;
+            if constexpr (H) zn[e] = reinterpret_cast<const __half2 *>(Z)[at];
+            else zn[e] = Z[at];
         }
-        if (r + 1 < K) {
-            const C *Zr = Z + (int64_t)(r + 1) * L + k1_0;
+    };
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int i = tid + e * NT;
-                zn[e] = Zr[(int64_t)(i / G) * L1 + (i % G)];
+    for (int e = 0; e < 16; ++e) acc[e] = cmake<C>(0, 0);
+    fetch(0);
+    for (int r = 0; r < K; ++r) {
+        __syncthreads();   // previous readers of buf are done; rank r's exponents are visible
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + e * NT;
+            C v;
+            if constexpr (H) {
+                const int8_t *ex = reinterpret_cast<const int8_t *>(sexp + (r & 1) * NT);
+                v = hx_unpack(zn[e], ex[i / G]);
+            } else {
+                v = zn[e];
             }
+            buf[(i % G) * P + lds_pad(i / G)] = v;
         }
+        if (r + 1 < K) fetch(r + 1);   // its exponents go to the other parity, last read at rank r - 1
         __syncthreads();
         block_fft_lds<C, L2, DIR, fft_wave_sync<L2>>(buf + g * P, tw, lt);
         fft_publish<L2>();
@@ -612,6 +712,24 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
 // ============================================================================
 
 static inline int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
+
+// Launches CALL with the compile-time flag HX = a.half (FP32 plans with the
+// half-precision exchange), HX = false otherwise.
+#define HX_DISPATCH(CALL)                                                                                  \
+    do {                                                                                                   \
+        auto go_ = [&](auto hc_) {                                                                         \
+            constexpr bool HX = decltype(hc_)::value;                                                      \
+            CALL;                                                                                          \
+        };                                                                                                 \
+        bool done_ = false;                                                                                \
+        if constexpr (sizeof(R) == 4) {                                                                    \
+            if (a.half) {                                                                                  \
+                go_(std::true_type{});                                                                     \
+                done_ = true;                                                                              \
+            }                                                                                              \
+        }                                                                                                  \
+        if (!done_) go_(std::false_type{});                                                                \
+    } while (0)
 
 template <typename R, int L>
 static void run_small_fwd(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int mode,
@@ -747,9 +865,9 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
         constexpr int G = GG;                                                                              \
         const int ncg = a.L1 / G, rca = pass_a_ranks(a.fac.K, ncg);                                        \
         const int T = ncg * ((a.fac.K + rca - 1) / rca);                                                   \
-        hipLaunchKernelGGL((k_passA<R, LL, G, false>), dim3(xcd_grid(T)), dim3(G * LL / 16), 0, s, c, \
-                           a.N,                                                                            \
-                           (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);                     \
+        HX_DISPATCH(hipLaunchKernelGGL((k_passA<R, LL, G, false, HX>), dim3(xcd_grid(T)), dim3(G * LL / 16), \
+                                       0, s, c, a.N, (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo,   \
+                                       a.Y, a.E));                                                          \
         break;                                                                                             \
     }
         PA(64, 8)
@@ -770,10 +888,9 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     case LL: {                                                                                             \
         constexpr bool F = sizeof(R) == 4;                                                                 \
         constexpr int RR = F ? RF : RD, SS = F ? SF : SD;                                                  \
-        hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false>), dim3(xcd_grid(a.L2)), dim3(RR * LL / 16),  \
-                           0, s,                                                                           \
-                           (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,     \
-                           a.tw1, f, mode, g, gx);                                                          \
+        HX_DISPATCH(hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false, HX>), dim3(xcd_grid(a.L2)),            \
+                                       dim3(RR * LL / 16), 0, s, (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M,   \
+                                       a.keys, a.perm, a.Xs, a.off, a.fac, a.tw1, f, mode, g, gx, a.E));     \
         break;                                                                                             \
     }
         PB(128, 16, 1, 8, 2)
@@ -807,9 +924,9 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
     case LL: {                                                                                             \
         constexpr bool F = sizeof(R) == 4;                                                                 \
         constexpr int RR = F ? RF : RD, SC = F ? SCF : SCD;                                                \
-        hipLaunchKernelGGL((k_passB_adj<R, LL, RR, SC, DIR, TG>), dim3(xcd_grid(a.L2)), dim3(RR * LL / 16), \
-                           0, s, a.gsort, (int64_t)a.L2, a.Xs, a.keys, a.off, a.fac,                        \
-                           DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, a.Y);                                     \
+        HX_DISPATCH(hipLaunchKernelGGL((k_passB_adj<R, LL, RR, SC, DIR, TG, HX>), dim3(xcd_grid(a.L2)),      \
+                                       dim3(RR * LL / 16), 0, s, a.gsort, (int64_t)a.L2, a.Xs, a.keys,       \
+                                       a.off, a.fac, DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, a.Y, a.E));      \
         break;                                                                                             \
     }
         PBA(128, 16, 256, 8, 256, false)
@@ -827,9 +944,9 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
 #define PAA(LL, GG)                                                                                        \
     case LL: {                                                                                             \
         constexpr int G = GG;                                                                              \
-        hipLaunchKernelGGL((k_passA_adj<R, LL, G, DIR, false>), dim3(xcd_grid(a.L1 / G)),            \
-                           dim3(G * LL / 16), 0, s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K,      \
-                           DIR < 0 ? a.tw2 : a.tw2i, f);                                                   \
+        HX_DISPATCH(hipLaunchKernelGGL((k_passA_adj<R, LL, G, DIR, false, HX>), dim3(xcd_grid(a.L1 / G)),    \
+                                       dim3(G * LL / 16), 0, s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1,    \
+                                       a.fac.K, DIR < 0 ? a.tw2 : a.tw2i, f, a.E));                          \
         break;                                                                                             \
     }
         PAA(64, 8)

@@ -132,6 +132,8 @@ struct FusedArgs {
     const int32_t *t;        // M grid indices, sample order
     const R *X;              // M perturbations, sample order
     cx_t<R> *Y;              // K x L intermediate of the two-pass split
+    int half;                // FP32 only: Y in fp16 pairs with block exponents E (half-precision exchange)
+    int8_t *E;               // K x max(L1, L2) block exponents of the half-precision exchange
     const cx_t<R> *tw1, *tw2, *hi, *lo;
     const cx_t<R> *tw1i, *tw2i;   // inverse-sign twiddles of lengths L1, L2
     cx_t<R> *part;           // scratch for partial sums of the one-workgroup adjoint

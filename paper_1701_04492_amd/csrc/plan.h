@@ -39,7 +39,8 @@ struct nufft_plan_s {
     int32_t *sinv = nullptr;        // M sorted position per sample (two-pass)
     void *gsort = nullptr;          // M complex: sample-ordered input in sorted order (two-pass)
     void *U = nullptr, *W = nullptr, *W2 = nullptr;   // plain path
-    void *Y = nullptr;              // K x L two-pass intermediate
+    void *Y = nullptr;              // K x L two-pass intermediate (fp16 pairs with NUFFT_FLAG_HALF_EXCHANGE)
+    int8_t *E = nullptr;            // K x max(L1, L2) block exponents of the half-precision exchange
     void *tw1 = nullptr, *tw2 = nullptr, *hi = nullptr, *lo = nullptr;
     void *tw1i = nullptr, *tw2i = nullptr;   // inverse-sign tables
     void *part = nullptr;           // partial sums of the one-workgroup adjoint

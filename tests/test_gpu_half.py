@@ -1,0 +1,137 @@
+"""GPU parity of the half-precision exchange (NUFFT_FLAG_HALF_EXCHANGE, Table 1's
+"half" precision eps = 2^-10) against the FP64 oracle.
+
+The two passes of the split exchange the K x L intermediate as fp16 pairs with
+one power-of-two scale per column (type II) or row (type I / adjoint).  Storage
+rounding adds at most 2^-11 sum_{p,r} w_p w_r |b_pr| ||c||_1 to an output
+(|Y_r| <= w_r ||c||_1 per column sum, |u_r| <= sum_p w_p |b_pr|), on top of the
+truncation eps: the bar stays 4 eps ||c||_1, and the derived bound is checked too.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lowrank as Lr
+from oracle import nudft as D
+from paper_1701_04492_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1701_04492_amd")
+DEV = torch.device("cuda:0")
+C64, C128 = torch.complex64, torch.complex128
+EPS = 2.0 ** -10
+HALF = P.NUFFT_FLAG_HALF_EXCHANGE
+
+
+def _t(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _storage_bound(gamma, K):
+    b = np.abs(Lr.chebyshev_coefficients(gamma, K))
+    w = np.ones(K)
+    w[0] = 0.5
+    return 2.0 ** -11 * float((b * w[:, None] * w[None, :]).sum())
+
+
+def _rows(M, n, seed):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([rng.choice(M, size=min(n, M), replace=False), [0, M - 1]]))
+
+
+def _check(label, got, ref, l1, plan):
+    err = np.abs(got - ref).max() / l1
+    bound = EPS + _storage_bound(plan.gamma, plan.K) + 1e-5
+    _say("   %s K=%d err/||c||_1 = %.3e (derived bound %.3e, bar %.3e)" % (label, plan.K, err, bound, 4 * EPS))
+    assert np.all(np.isfinite(got))
+    assert err <= bound and err <= 4 * EPS
+    return err
+
+
+@pytest.mark.parametrize("N,M,dist", [(8192, 8192, "iid"), (20000, 23000, "iid"), (1 << 16, 1 << 16, "jitter")])
+def test_half_all_directions(N, M, dist):
+    x, c = W.type2_case(70, N, M, dist)
+    g = W.complex_normal(W.rng_for(71), M)
+    _say("half exchange N=%d M=%d %s" % (N, M, dist))
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS, C64, HALF)
+    ct, gt = _t(c, C64), _t(g, C64)
+    cc, gg = ct.cpu().numpy().astype(np.complex128), gt.cpu().numpy().astype(np.complex128)
+    rows = _rows(M, 512, 72)
+    f = P.nufft2_exec(plan, ct).cpu().numpy()
+    e2 = _check("type II", f[rows], D.nudft2(x[rows], cc), np.abs(cc).sum(), plan)
+    ks = _rows(N, 512, 73)
+    for sign in (-1, +1):
+        h = P.nufft1_exec(plan, gt, sign=sign).cpu().numpy()
+        _check("type I" if sign < 0 else "adjoint", h[ks], D.nudft1(x, gg, N, k=ks, sign=sign),
+               np.abs(gg).sum(), plan)
+    gc, gx = P.nufft2_backward(plan, ct, gt)
+    gx = gx.cpu().numpy()
+    ref = D.grad_x(x[rows], cc, gg[rows])
+    scale = np.abs(gg[rows]) * 2 * np.pi * (np.arange(N) * np.abs(cc)).sum()
+    gerr = (np.abs(gx[rows] - ref) / scale).max()
+    _say("   grad_x err / (|g_j| 2 pi sum_k k |c_k|) = %.3e" % gerr)
+    assert gerr <= 4 * EPS
+    if N >= (1 << 16):
+        assert e2 < 2e-4      # regression gate: random data sits far inside the bound
+
+
+def test_half_is_inert_for_one_pass_sizes():
+    """N <= 4096 runs in one workgroup with no HBM exchange: the flag changes nothing."""
+    x, c = W.type2_case(74, 3000, 5000)
+    xt, ct = _t(x, torch.float64), _t(c, C64)
+    a = P.nufft2_exec(P.nufft2_plan(xt, 3000, EPS, C64, HALF), ct)
+    b = P.nufft2_exec(P.nufft2_plan(xt, 3000, EPS, C64, 0), ct)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("scale", [1e30, 1e-30])
+def test_half_block_scaling_range(scale):
+    """Inputs far outside fp16's range: the per-block power-of-two scales keep every
+    stored value finite and normal, so the relative error is that of unit inputs."""
+    N = 1 << 14
+    x, c = W.type2_case(75, N)
+    c = c * scale
+    c[17] *= 1e3                     # one dominant coefficient: columns of very different size
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS, C64, HALF)
+    ct = _t(c, C64)
+    cc = ct.cpu().numpy().astype(np.complex128)
+    rows = _rows(N, 256, 76)
+    f = P.nufft2_exec(plan, ct).cpu().numpy()
+    _check("type II scale %g" % scale, f[rows], D.nudft2(x[rows], cc), np.abs(cc).sum(), plan)
+    g = P.nufft1_exec(plan, ct[:N], sign=+1).cpu().numpy()
+    ks = _rows(N, 256, 77)
+    _check("adjoint scale %g" % scale, g[ks], D.nudft1(x, cc, N, k=ks, sign=+1), np.abs(cc).sum(), plan)
+
+
+def test_half_full_size_sampled():
+    """N = M = 2^22 (the forward+backward workload's shape) at eps = 2^-10, sampled rows."""
+    N = 1 << 22
+    x, c = W.type2_case(3, N)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS, C64, HALF)
+    assert plan.K == 7
+    ct = _t(c, C64)
+    cc = ct.cpu().numpy().astype(np.complex128)
+    rows = _rows(N, 48, 78)
+    f = P.nufft2_exec(plan, ct).cpu().numpy()
+    _check("2^22 type II", f[rows], D.nudft2(x[rows], cc), np.abs(cc).sum(), plan)
+    ks = _rows(N, 24, 79)
+    h = P.nufft1_exec(plan, ct, sign=+1).cpu().numpy()
+    _check("2^22 adjoint", h[ks], D.nudft1(x, cc, N, k=ks, sign=+1), np.abs(cc).sum(), plan)
+
+
+def test_half_flag_validation():
+    x = _t(np.linspace(0, 1, 100), torch.float64)
+    with pytest.raises(P.NufftError) as e:
+        P.nufft2_plan(x, 10000, EPS, C128, HALF)
+    assert e.value.status == 2
+    with pytest.raises(P.NufftError) as e:
+        P.nufft2_plan(x, 10000, 1e-4, C64, HALF)
+    assert e.value.status == 2
+    with pytest.raises(P.NufftError) as e:
+        P.nufft2_plan(x, 10000, EPS, C64, HALF | P.NUFFT_FLAG_PLAIN)
+    assert e.value.status == 1
