@@ -262,6 +262,26 @@ def bench_half(P, torch, x, c, y, N, M, steps, warmup):
             "kernels": kern}
 
 
+def bench_oversampling(P, W, torch, dev):
+    """Autotuned oversampling (Sec. 2.3): N = 2^14 modes, M = 2^22 iid samples, complex64,
+    eps 1e-6; the default grid L0 = N against the plan's timed choice of L0 or 2 L0."""
+    N, M = 1 << 14, 1 << 22
+    rng = W.rng_for(7)
+    c = torch.from_numpy(W.complex_normal(rng, N)).to(torch.complex64).to(dev)
+    x = torch.from_numpy(W.iid_samples(rng, M)).to(dev)
+    f = torch.empty(M, dtype=torch.complex64, device=dev)
+    out = {"N": N, "M": M}
+    for label, fl in (("default", 0), ("autotuned", P.NUFFT_FLAG_AUTOTUNE)):
+        pl = P.nufft2_plan(x, N, 1e-6, torch.complex64, fl)
+        t = time_loop(lambda: P.nufft2_exec(pl, c, f), 20, 3, torch)
+        ta = time_loop(lambda: P.nufft1_exec(pl, f, +1, c), 10, 2, torch)
+        out[label] = {"grid": pl.grid, "K": pl.K, "gamma": round(pl.gamma, 4), "us": round(t * 1e3, 2),
+                      "pts_per_s": M / (t * 1e-3), "adjoint_us": round(ta * 1e3, 2)}
+        del pl
+    out["speedup"] = round(out["default"]["us"] / out["autotuned"]["us"], 3)
+    return out
+
+
 def bench_solve(P, W, torch, dev):
     """Inverse type II (Sec. 3.3) at N = M = 2^20, complex64, perturbed equispaced samples
     x_j = (j + U(-1/8, 1/8))/N, f = F2 c for c complex N(0,1): CG to a residual of 1e-5."""
@@ -468,6 +488,7 @@ def main():
         out["batch_512"] = bench_batch(P, W, torch, dev)
         out["polar_2d"] = bench_2d(P, W, torch, dev)
         out["inverse_2p20"] = bench_solve(P, W, torch, dev)
+        out["oversampling_2p14_modes_2p22_samples"] = bench_oversampling(P, W, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, c_np, N, args.cpu_seconds)

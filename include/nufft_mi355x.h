@@ -67,8 +67,13 @@ enum {
      * passes over a K x L buffer, a stored U table (Sec. 2.3, "Planning the
      * transform") and a separate gather/row-sum kernel.  Default is fused. */
     NUFFT_FLAG_PLAIN = 2u,
-    /* Batches only: time the persistent launch at a few grid sizes while
-     * planning and keep the fastest (reported as `grid` by nufft_plan_info). */
+    /* Autotuning at plan time (reported as `grid` by nufft_plan_info).
+     * 1-D plans: oversampling (Sec. 2.3) -- the plan is built on the grid
+     * L0 (smallest power of two >= max(16, N)) and on 2 L0, where
+     * gamma <= N / (4 L0) lowers K; one type-II transform of each is timed
+     * on a scratch input and the faster plan is kept (up to L = 2^23).
+     * Batches: the persistent launch is timed at a few grid sizes and the
+     * fastest kept.  Results do not depend on the choice beyond eps. */
     NUFFT_FLAG_AUTOTUNE = 4u,
     /* 1-D complex64 plans only, eps >= 2^-10 (Table 1's "half" precision):
      * the K x L intermediate that the two passes exchange through HBM

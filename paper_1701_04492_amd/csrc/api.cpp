@@ -871,6 +871,68 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
 
 static nufft_status from_hip(hipError_t e) { return e == hipSuccess ? NUFFT_OK : NUFFT_ERR_HIP; }
 
+// Oversampling choice.  Sec. 2.3 leaves the grid free as long as it has at least
+// N points; a larger grid lowers gamma_eff = max|X| <= N / (2L) and with it K,
+// at the price of longer FFTs.  With NUFFT_FLAG_AUTOTUNE the plan is built on
+// the smallest power-of-two grid L0 >= N and on 2 L0 (gamma_eff <= 1/4), one
+// type-II transform of each is timed on a scratch input, and the faster plan
+// is kept.  The larger grid wins when the per-sample work K M outweighs the
+// FFT work K L log L, e.g. for many more samples than modes.
+template <typename R>
+static nufft_status time_type2(Plan *p, hipStream_t s, float *ms_out)
+{
+    Plan scratch;
+    void *c = scratch.alloc((size_t)p->N * 2 * sizeof(R));
+    void *f = scratch.alloc((size_t)p->M * 2 * sizeof(R));
+    if (!c || !f) return NUFFT_ERR_ALLOC;
+    NUFFT_HIP_CHECK(hipMemsetAsync(c, 0, (size_t)p->N * 2 * sizeof(R), s));
+    hipEvent_t e0, e1;
+    NUFFT_HIP_CHECK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return NUFFT_ERR_HIP;
+    }
+    hipError_t e = exec_type2<R>(p, c, f, 0, nullptr, nullptr, s);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = exec_type2<R>(p, c, f, 0, nullptr, nullptr, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms_out, e0, e1);
+    (void)hipStreamSynchronize(s);   // nothing may still use the scratch buffers freed on return
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return from_hip(e);
+}
+
+template <typename R>
+static nufft_status autotune_grid(Plan **pp, const double *x, hipStream_t s)
+{
+    Plan *p = *pp;
+    if (2 * p->L > (int64_t(1) << 23)) return NUFFT_OK;   // the larger grid is not supported
+    Plan *q = new (std::nothrow) Plan();
+    if (!q) return NUFFT_ERR_ALLOC;
+    q->kind = PLAN_1D;
+    q->dtype = p->dtype;
+    q->flags = p->flags;
+    q->N = p->N;
+    q->M = p->M;
+    q->eps = p->eps;
+    nufft_status st = NUFFT_OK;
+    if (!choose_grid(2 * p->L, &q->L, &q->L1, &q->L2)) st = NUFFT_ERR_UNSUPPORTED;
+    if (!st) st = build_1d<R>(q, x, s);
+    float t0 = 0, t1 = 0;
+    if (!st) st = time_type2<R>(p, s, &t0);
+    if (!st) st = time_type2<R>(q, s, &t1);
+    if (st || !(t1 < t0)) {
+        (void)hipStreamSynchronize(s);
+        delete q;
+        return st;
+    }
+    delete p;
+    *pp = q;
+    return NUFFT_OK;
+}
+
 static bool eps_ok(double eps, nufft_dtype dt, nufft_status *st)
 {
     if (!(eps > 0.0 && eps < 1.0)) { *st = NUFFT_ERR_INVALID_ARG; return false; }
@@ -888,7 +950,8 @@ nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, cons
     *out = nullptr;
     if (n_modes < 1 || n_pts < 1 || !x_dev) return NUFFT_ERR_INVALID_ARG;
     if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_PLAIN | NUFFT_FLAG_HALF_EXCHANGE))
+    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_PLAIN | NUFFT_FLAG_HALF_EXCHANGE |
+                            NUFFT_FLAG_AUTOTUNE))
         return NUFFT_ERR_INVALID_ARG;
     if ((flags & NUFFT_FLAG_HALF_EXCHANGE) && (flags & NUFFT_FLAG_PLAIN)) return NUFFT_ERR_INVALID_ARG;
     if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
@@ -910,6 +973,8 @@ nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, cons
     }
     hipStream_t s = (hipStream_t)stream;
     st = dtype == NUFFT_C64 ? build_1d<float>(p, x_dev, s) : build_1d<double>(p, x_dev, s);
+    if (st == NUFFT_OK && (flags & NUFFT_FLAG_AUTOTUNE))
+        st = dtype == NUFFT_C64 ? autotune_grid<float>(&p, x_dev, s) : autotune_grid<double>(&p, x_dev, s);
     if (st != NUFFT_OK) {
         (void)hipStreamSynchronize(s);
         delete p;

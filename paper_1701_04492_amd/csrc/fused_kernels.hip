@@ -20,6 +20,8 @@
 // point's samples one contiguous segment: a deterministic sum, no atomics),
 // transformed along n1, and pass A' transforms along n2, scales by v_r and
 // sums over r in registers.
+#include <algorithm>
+
 #include "fused_common.h"
 
 namespace nufft {
@@ -327,14 +329,19 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
 // side by side (L1/16 threads each); the next chunk's rows are loaded into
 // registers while the current chunk is transformed and gathered.  Every
 // sample of the tile (up to NT*S per round) gathers its RC spectrum values
-// from LDS and accumulates u_r(j) X_r[t_j] in registers.
+// from LDS and accumulates u_r(j) X_r[t_j] in registers.  When K <= RC the
+// transforms are done once per task and serve every round of its samples;
+// otherwise each round repeats them (rounds are rare then: S is sized so
+// that one round holds about 1.25 L1 samples, the mean tile when M = N).
+// With many more samples than grid points, `splits` tasks share a tile, each
+// transforming its rows and taking an equal slice of the tile's samples.
 // H: Y holds fp16 pairs scaled per (rank, column) by 2^E[r * L1 + k1].
 template <typename R, int L1, int RC, int S, bool TWG, bool H>
 __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
         const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
         Factors<R> fac, const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ f, int mode,
-        const cx_t<R> *__restrict__ gup, double *__restrict__ gx, const int8_t *__restrict__ E)
+        const cx_t<R> *__restrict__ gup, double *__restrict__ gx, const int8_t *__restrict__ E, int splits)
 {
     using C = cx_t<R>;
     constexpr int TPF = L1 / 16;
@@ -344,14 +351,17 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     __shared__ C buf[RC * P];
     __shared__ C tw_s[TWG ? 1 : L1];
     const C *tw = TWG ? tw_g : tw_s;
-    const int task = xcd_task((int)L2);
+    const int task = xcd_task((int)L2 * splits);
     if (task < 0) return;
     if (!TWG) load_tw_s<C, L1, -1, NT>(tw_s, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
-    const int64_t n2 = task;
+    const int64_t n2 = task / splits;
+    const int part = task % splits;
     const int64_t L = (int64_t)L1 * L2;
-    const int64_t tile_lo = off[n2 * L1], tile_hi = off[(n2 + 1) * L1];
+    // this task's share of the tile's samples (the whole tile unless splits > 1)
+    const int64_t t_lo = off[n2 * L1], t_cnt = off[(n2 + 1) * L1] - t_lo;
+    const int64_t tile_lo = t_lo + t_cnt * part / splits, tile_hi = t_lo + t_cnt * (part + 1) / splits;
     const C *Yrow = Y + n2 * L1 + lt;
     const __half2 *Yhrow = reinterpret_cast<const __half2 *>(Y) + n2 * L1 + lt;
     // Rank row rr of the tile, the lanes' 16 elements (zero for rr >= K), in
@@ -359,7 +369,7 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     // into raw registers (fp16 pairs and exponents for H), take decodes them.
     using Raw = typename std::conditional<H, __half2, C>::type;
     // (a rank beyond K loads nothing: its lanes are zero and its transform is discarded)
-    auto fetch = [&](int rr, Raw (&w)[16], int8_t (&ev)[16]) {
+    auto fetch = [&](int rr, Raw (&w)[16], int8_t (&ev)[16]) __attribute__((always_inline)) {
         const bool in = rr < fac.K;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -371,13 +381,35 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             }
         }
     };
-    auto take = [&](const Raw (&w)[16], const int8_t (&ev)[16], C (&v)[16]) {
+    auto take = [&](const Raw (&w)[16], const int8_t (&ev)[16], C (&v)[16]) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             if constexpr (H) v[q] = hx_unpack(w[q], ev[q]);
             else v[q] = w[q];
         }
     };
+
+    // gather of ranks r0 .. r0 + nr - 1 from the spectra in buf into the sample sums
+    auto gather = [&](int r0, int nr, int64_t c0, const uint32_t (&kv)[S], const R (&xs)[S], C (&acc)[S]) __attribute__((always_inline)) {
+        // rank outer (its coefficients loaded once), samples inner
+#pragma unroll
+        for (int gg = 0; gg < RC; ++gg) {
+            if (gg < nr) {
+                const int rr = r0 + gg;
+                const RankPoly<R> up = rank_poly(fac, rr);
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    if (c0 + s * NT < tile_hi) {   // else no lane has a sample in this slot
+                        const C xv = buf[gg * P + lds_pad((int)(kv[s] & (uint32_t)(L1 - 1)))];
+                        acc[s] = cadd(acc[s], crot(cscale(xv, rank_eval(up, xs[s] * fac.inv_gamma)), rr));
+                    }
+                }
+            }
+        }
+    };
+    // K <= RC: every rank is transformed in the first round, and the spectra
+    // stay in LDS for all later rounds of the tile (many samples per tile: M >> N)
+    const bool once = fac.K <= RC;
 
     for (int64_t c0 = tile_lo; c0 < tile_hi; c0 += CAP) {
         // the round's sample data: every load issued before any is used
@@ -390,35 +422,23 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             kv[s] = keys[i];
             xs[s] = Xs[i];
         }
-        Raw vn[16];
-        int8_t en[16];
-        fetch(g, vn, en);
         C acc[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[s] = cmake<C>(0, 0);
+        const bool transform = !once || c0 == tile_lo;
+        Raw vn[16];
+        int8_t en[16];
+        if (transform) fetch(g, vn, en);
         for (int r0 = 0; r0 < fac.K; r0 += RC) {
-            C v[16];
-            take(vn, en, v);
-            if (r0 + RC < fac.K) fetch(r0 + RC + g, vn, en);
-            __syncthreads();
-            block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v);
-            fft_publish<L1>();
-            const int nr = min(RC, fac.K - r0);
-            // rank outer (its coefficients loaded once), samples inner
-#pragma unroll
-            for (int gg = 0; gg < RC; ++gg) {
-                if (gg < nr) {
-                    const int rr = r0 + gg;
-                    const RankPoly<R> up = rank_poly(fac, rr);
-#pragma unroll
-                    for (int s = 0; s < S; ++s) {
-                        if (c0 + s * NT < tile_hi) {   // else no lane has a sample in this slot
-                            const C xv = buf[gg * P + lds_pad((int)(kv[s] & (uint32_t)(L1 - 1)))];
-                            acc[s] = cadd(acc[s], crot(cscale(xv, rank_eval(up, xs[s] * fac.inv_gamma)), rr));
-                        }
-                    }
-                }
+            if (transform) {
+                C v[16];
+                take(vn, en, v);
+                if (r0 + RC < fac.K) fetch(r0 + RC + g, vn, en);
+                __syncthreads();
+                block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v);
+                fft_publish<L1>();
             }
+            gather(r0, min(RC, fac.K - r0), c0, kv, xs, acc);
         }
         int32_t jv[S];   // output positions: loaded together once the sums are done
         C gj[S];         // derivative pass: g in sorted order (contiguous)
@@ -438,7 +458,7 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
                 else gx[jv[s]] = (double)(gj[s].x * out.x + gj[s].y * out.y);
             }
         }
-        __syncthreads();
+        if (!once) __syncthreads();   // the next round's transforms overwrite buf
     }
 }
 
@@ -713,6 +733,17 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
 
 static inline int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
 
+// Tasks per tile of pass B: 1 while a tile holds about one round of samples
+// (M ~ N); with many more samples than grid points the tiles are split so that
+// each task keeps about max(CAP, L1) samples (the row transforms it repeats
+// are then a small part of its work), at most 64 ways.
+static int pass_b_splits(int64_t M, int L2, int L1, int cap)
+{
+    const int64_t per = std::max<int64_t>(cap, L1);
+    const int64_t want = (M + (int64_t)L2 * per - 1) / ((int64_t)L2 * per);
+    return (int)std::min<int64_t>(64, std::max<int64_t>(1, want));
+}
+
 // Launches CALL with the compile-time flag HX = a.half (FP32 plans with the
 // half-precision exchange), HX = false otherwise.
 #define HX_DISPATCH(CALL)                                                                                  \
@@ -888,9 +919,10 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     case LL: {                                                                                             \
         constexpr bool F = sizeof(R) == 4;                                                                 \
         constexpr int RR = F ? RF : RD, SS = F ? SF : SD;                                                  \
-        HX_DISPATCH(hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false, HX>), dim3(xcd_grid(a.L2)),            \
+        const int sp = pass_b_splits(a.M, a.L2, LL, RR * (LL / 16) * SS);                                   \
+        HX_DISPATCH(hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false, HX>), dim3(xcd_grid(a.L2 * sp)),       \
                                        dim3(RR * LL / 16), 0, s, (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M,   \
-                                       a.keys, a.perm, a.Xs, a.off, a.fac, a.tw1, f, mode, g, gx, a.E));     \
+                                       a.keys, a.perm, a.Xs, a.off, a.fac, a.tw1, f, mode, g, gx, a.E, sp)); \
         break;                                                                                             \
     }
         PB(128, 16, 1, 8, 2)

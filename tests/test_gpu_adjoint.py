@@ -160,6 +160,28 @@ def test_grad_x_pass(dtype):
     assert np.all(np.abs(gx - ref) <= bound)
 
 
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_many_samples_per_grid_point(dtype):
+    """M = 256 N (thousands of samples per output tile): adjoint on sampled k and the
+    derivative pass on sampled samples, against the oracle."""
+    N, M = 1 << 13, 1 << 21
+    rng = W.rng_for(36)
+    x = rng.random(M)
+    c, g = W.complex_normal(rng, N), W.complex_normal(rng, M)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS[dtype], dtype)
+    ct, gt = _t(c, dtype), _t(g, dtype)
+    cc, gg = ct.cpu().numpy().astype(np.complex128), gt.cpu().numpy().astype(np.complex128)
+    gc, gx = P.nufft2_backward(plan, ct, gt)
+    kq = np.unique(np.concatenate([rng.choice(N, 40, replace=False), [0, N - 1]]))
+    err = np.abs(gc.cpu().numpy()[kq] - D.nudft1(x, gg, N, k=kq, sign=+1)).max() / np.abs(gg).sum()
+    rows = np.unique(np.concatenate([rng.choice(M, 300, replace=False), [0, M - 1]]))
+    ref = D.grad_x(x[rows], cc, gg[rows])
+    bound = 4 * EPS[dtype] * np.abs(gg[rows]) * 2 * np.pi * (np.arange(N) * np.abs(cc)).sum()
+    gerr = (np.abs(gx.cpu().numpy()[rows] - ref) / bound).max()
+    _say("M = 256 N", dtype, "adjoint err/||g||_1 %.3e, grad_x err/bound %.3e" % (err, gerr))
+    assert err <= 4 * EPS[dtype] and gerr <= 1.0
+
+
 @pytest.mark.parametrize("N,M", [(3000, 2500), (20000, 17000), (1 << 16, 1 << 16)])
 @pytest.mark.parametrize("dtype", [C64, C128])
 def test_backward_matches_separate_calls(N, M, dtype):

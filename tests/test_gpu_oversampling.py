@@ -1,0 +1,78 @@
+"""Autotuned oversampling (NUFFT_FLAG_AUTOTUNE on 1-D plans, Sec. 2.3): the plan is
+built on the grids L0 and 2 L0, the faster type-II transform is kept.  Whatever it
+picks, the result must meet the 4 eps ||c||_1 bar against the FP64 direct sums, and
+K and gamma must be those of the grid it picked."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lowrank as Lr
+from oracle import nudft as D
+from paper_1701_04492_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1701_04492_amd")
+DEV = torch.device("cuda:0")
+C64, C128 = torch.complex64, torch.complex128
+EPS = {C64: 1e-6, C128: 1e-12}
+
+
+def _t(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _next_pow2(n):
+    l = 16
+    while l < n:
+        l *= 2
+    return l
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+@pytest.mark.parametrize("N,M", [(1 << 14, 1 << 22), (3000, 1 << 20), (1 << 16, 1 << 16), (20000, 30000)])
+def test_autotune_grid_parity(dtype, N, M):
+    x, c = W.type2_case(80, N, M)
+    g = W.complex_normal(W.rng_for(81), M)
+    eps = EPS[dtype]
+    plan = P.nufft2_plan(_t(x, torch.float64), N, eps, dtype, P.NUFFT_FLAG_AUTOTUNE)
+    L0 = _next_pow2(N)
+    _say("autotune N=%d M=%d %s: grid %d (L0 %d), K=%d gamma=%.4f" % (N, M, dtype, plan.grid, L0, plan.K, plan.gamma))
+    assert plan.grid in (L0, 2 * L0)
+    # gamma and K belong to the chosen grid: X_j = (L x_j - s_j) N / L
+    _, _, d = D.grid_assign(x, plan.grid)
+    gam = np.abs(d).max() * N / plan.grid
+    assert plan.gamma == pytest.approx(gam, rel=1e-12, abs=1e-15)
+    assert plan.K == Lr.choose_K(eps, plan.gamma)
+    ct, gt = _t(c, dtype), _t(g, dtype)
+    cc = ct.cpu().numpy().astype(np.complex128)
+    gg = gt.cpu().numpy().astype(np.complex128)
+    rng = np.random.default_rng(82)
+    rows = np.unique(np.concatenate([rng.choice(M, size=min(M, 300), replace=False), [0, M - 1]]))
+    f = P.nufft2_exec(plan, ct).cpu().numpy()
+    err = np.abs(f[rows] - D.nudft2(x[rows], cc)).max() / np.abs(cc).sum()
+    ks = np.unique(np.concatenate([rng.choice(N, size=min(N, 300), replace=False), [0, N - 1]]))
+    a = P.nufft1_exec(plan, gt, sign=+1).cpu().numpy()
+    aerr = np.abs(a[ks] - D.nudft1(x, gg, N, k=ks, sign=+1)).max() / np.abs(gg).sum()
+    _say("   type II err %.3e, adjoint err %.3e" % (err, aerr))
+    assert err <= 4 * eps and aerr <= 4 * eps
+
+
+def test_autotune_matches_fixed_grid_choice():
+    """The autotuned plan computes what a plan on its grid computes: same K, and the
+    type II equal to the default plan's within the bar (both are eps-accurate)."""
+    N, M = 1 << 12, 1 << 21
+    x, c = W.type2_case(83, N, M)
+    xt, ct = _t(x, torch.float64), _t(c, C64)
+    pa = P.nufft2_plan(xt, N, 1e-6, C64, P.NUFFT_FLAG_AUTOTUNE)
+    pd = P.nufft2_plan(xt, N, 1e-6, C64)
+    fa = P.nufft2_exec(pa, ct)
+    fd = P.nufft2_exec(pd, ct)
+    diff = (fa - fd).abs().max().item() / ct.abs().sum().item()
+    _say("N=2^12 M=2^21: autotuned grid %d (K=%d), default grid %d (K=%d), diff %.3e"
+         % (pa.grid, pa.K, pd.grid, pd.K, diff))
+    assert diff <= 8e-6

@@ -193,6 +193,16 @@ def test_n2p23_max_size_sampled():
     check_type2(x, c, N, C64, rows=rows, label="2^23")
 
 
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_many_samples_per_tile(dtype):
+    """M = 256 N: each output tile holds thousands of samples and pass B splits it over
+    several workgroups (each with its own share, the tile's transforms repeated)."""
+    N, M = 1 << 13, 1 << 21
+    x, c = W.type2_case(28, N, M)
+    rows = _rows_subset(x, N, N, 256, 11)
+    check_type2(x, c, N, dtype, rows=rows, label="M = 256 N")
+
+
 def test_beyond_max_size_rejected():
     x = torch.zeros(4, dtype=torch.float64, device=DEV)
     with pytest.raises(P.NufftError):
