@@ -155,47 +155,56 @@ __device__ __forceinline__ void dft(C *v)
 // of the 16/R butterflies b = lt + i*(L/16) this thread owns, the R inputs
 // x[b + q*L/R].  Applies the stage twiddles, the radix-R DFT, and writes the
 // outputs to LDS in auto-sorted order.
+// `active` false: the thread's transform is not needed (its threads form whole
+// waves); it skips the arithmetic and the LDS traffic but still takes part in
+// every barrier of the stage sequence.
 template <typename C, int L, int DIR, int NS, int R, bool WS>
-__device__ __forceinline__ void stage_compute_store(C *buf, const C *tw, int lt, C *v)
+__device__ __forceinline__ void stage_compute_store(C *buf, const C *tw, int lt, C *v, bool active)
 {
     constexpr int BPT = 16 / R;
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-        const int b = lt + i * (L / 16);
-        if constexpr (NS > 1) {
-            const int k = b % NS;
+        for (int i = 0; i < BPT; ++i) {
+            const int b = lt + i * (L / 16);
+            if constexpr (NS > 1) {
+                const int k = b % NS;
 #pragma unroll
-            for (int q = 1; q < R; ++q)
-                v[i * R + q] = cmul(v[i * R + q], tw[(NS - 1) + k * (R - 1) + (q - 1)]);
+                for (int q = 1; q < R; ++q)
+                    v[i * R + q] = cmul(v[i * R + q], tw[(NS - 1) + k * (R - 1) + (q - 1)]);
+            }
+            dft<R, C, DIR>(v + i * R);
         }
-        dft<R, C, DIR>(v + i * R);
     }
     stage_sync<WS>();   // every thread has read its inputs of this stage
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-        const int b = lt + i * (L / 16);
-        const int base = (b / NS) * NS * R + (b % NS);
+        for (int i = 0; i < BPT; ++i) {
+            const int b = lt + i * (L / 16);
+            const int base = (b / NS) * NS * R + (b % NS);
 #pragma unroll
-        for (int q = 0; q < R; ++q) buf[lds_pad(base + q * NS)] = v[i * R + q];
+            for (int q = 0; q < R; ++q) buf[lds_pad(base + q * NS)] = v[i * R + q];
+        }
     }
     stage_sync<WS>();
 }
 
 template <typename C, int L, int DIR, int NS, bool WS>
-__device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt)
+__device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt, bool active)
 {
     if constexpr (NS < L) {
         constexpr int R = (L / NS >= 16) ? 16 : (L / NS);
         constexpr int BPT = 16 / R;
         C v[16];
+        if (active) {
 #pragma unroll
-        for (int i = 0; i < BPT; ++i) {
-            const int b = lt + i * (L / 16);
+            for (int i = 0; i < BPT; ++i) {
+                const int b = lt + i * (L / 16);
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[i * R + q] = buf[lds_pad(b + q * (L / R))];
+                for (int q = 0; q < R; ++q) v[i * R + q] = buf[lds_pad(b + q * (L / R))];
+            }
         }
-        stage_compute_store<C, L, DIR, NS, R, WS>(buf, tw, lt, v);
-        stages_from<C, L, DIR, NS * R, WS>(buf, tw, lt);
+        stage_compute_store<C, L, DIR, NS, R, WS>(buf, tw, lt, v, active);
+        stages_from<C, L, DIR, NS * R, WS>(buf, tw, lt, active);
     }
 }
 
@@ -219,27 +228,31 @@ __device__ __forceinline__ void fft_publish()
 // Result: natural order in the same buffer.  Called by all threads of the
 // workgroup; lt in [0, L/16) is this thread's lane within the transform.
 template <typename C, int L, int DIR, bool WS = false>
-__device__ __forceinline__ void block_fft_lds(C *buf, const C *tw, int lt)
+__device__ __forceinline__ void block_fft_lds(C *buf, const C *tw, int lt, bool active = true)
 {
     static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "unsupported FFT length");
     static_assert(!WS || L <= 1024, "a wave-synchronous transform must fit one wavefront");
-    fftk::stages_from<C, L, DIR, 1, WS>(buf, tw, lt);
+    fftk::stages_from<C, L, DIR, 1, WS>(buf, tw, lt, active);
 }
 
 // Full transform whose input is in registers: v[q] = x[lt + q*L/16], q < 16
 // (exactly the operands of the first radix-16 stage, so that stage skips the
 // LDS round trip).  The caller must have finished every earlier read of buf
 // (a __syncthreads() since the last use).  Result: natural order in buf.
+// `active` false (uniform over whole waves): the transform is skipped, the
+// barriers are still taken, and its part of buf is left as it was.
 template <typename C, int L, int DIR, bool WS = false>
-__device__ __forceinline__ void block_fft_regs(C *buf, const C *tw, int lt, C *v)
+__device__ __forceinline__ void block_fft_regs(C *buf, const C *tw, int lt, C *v, bool active = true)
 {
     static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "unsupported FFT length");
     static_assert(!WS || L <= 1024, "a wave-synchronous transform must fit one wavefront");
     // first stage: NS = 1, R = 16, one butterfly per thread, no twiddles
-    fftk::dft<16, C, DIR>(v);
-    const int base = lt * 16;
+    if (active) {
+        fftk::dft<16, C, DIR>(v);
+        const int base = lt * 16;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) buf[lds_pad(base + q)] = v[q];
+        for (int q = 0; q < 16; ++q) buf[lds_pad(base + q)] = v[q];
+    }
     fftk::stage_sync<WS>();
-    fftk::stages_from<C, L, DIR, 16, WS>(buf, tw, lt);
+    fftk::stages_from<C, L, DIR, 16, WS>(buf, tw, lt, active);
 }

@@ -86,6 +86,40 @@ __device__ __forceinline__ R cheb_v(int r, R z)
     return b;
 }
 
+// Unhalved Chebyshev pairs (T_r(z_e), T_{r+1}(z_e)) for E values by the
+// three-term recurrence.  One loop advances all E chains per step, so their
+// dependent steps interleave (E separate calls of cheb_v would run E serial
+// loops of r - 1 dependent steps each).
+template <typename R, int E>
+__device__ __forceinline__ void cheb_pair_many(int r, const R (&z)[E], R (&t0)[E], R (&t1)[E])
+{
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        t0[e] = 1;
+        t1[e] = z[e];
+    }
+    for (int q = 0; q < r; ++q) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const R c = 2 * z[e] * t1[e] - t0[e];
+            t0[e] = t1[e];
+            t1[e] = c;
+        }
+    }
+}
+
+// v_r(z_e) = T_r(z_e) (halved for r = 0) for E values at once.
+template <typename R, int E>
+__device__ __forceinline__ void cheb_v_many(int r, const R (&z)[E], R (&out)[E])
+{
+    R t1[E];
+    cheb_pair_many<R, E>(r, z, out, t1);
+    if (r == 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) out[e] = (R)0.5;
+    }
+}
+
 // c_k, or -2 pi i k c_k for the derivative pass; zero for k >= N.  The load
 // itself is unconditional (from a clamped index), so that a run of such
 // loads is issued back to back and waited for once.

@@ -67,9 +67,12 @@ k_small_fwd(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, const int32_t *
         C v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) v[q] = load_coef<R>(c, lt + q * TPF, N, mode);
+        R zq[16], wq[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = r < fac.K ? cscale(v[q], cheb_v<R>(r, zcoord<R>(lt + q * TPF, zm)))
-                                                      : cmake<C>(0, 0);
+        for (int q = 0; q < 16; ++q) zq[q] = zcoord<R>(lt + q * TPF, zm);
+        cheb_v_many<R, 16>(r < fac.K ? r : 0, zq, wq);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = r < fac.K ? cscale(v[q], wq[q]) : cmake<C>(0, 0);
         __syncthreads();   // previous gather finished with buf
         block_fft_regs<C, L, -1, fft_wave_sync<L>>(buf + g * P, tw, lt, v);
         fft_publish<L>();
@@ -161,13 +164,20 @@ k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
         block_fft_regs<C, L, DIR, fft_wave_sync<L>>(buf + g * P, tw, lt, v);
         fft_publish<L>();
         const int nr = min(RC, fac.K - r0);
+        // T_{r0 + gg} for the consecutive ranks of the chunk by the recurrence
+        R zq[OPT], t0[OPT], t1[OPT];
 #pragma unroll
-        for (int m = 0; m < OPT; ++m) {
-            const int k = tid + m * SMALL_NT;
-            if (k < N && k < L) {
-                const R z = zcoord<R>(k, zm);
-                for (int gg = 0; gg < nr; ++gg)
-                    oacc[m] = cadd(oacc[m], cscale(buf[gg * P + lds_pad(k)], cheb_v<R>(r0 + gg, z)));
+        for (int m = 0; m < OPT; ++m) zq[m] = zcoord<R>(tid + m * SMALL_NT, zm);
+        cheb_pair_many<R, OPT>(r0, zq, t0, t1);
+        for (int gg = 0; gg < nr; ++gg) {
+#pragma unroll
+            for (int m = 0; m < OPT; ++m) {
+                const int k = tid + m * SMALL_NT;
+                const R w = (r0 + gg == 0) ? (R)0.5 : t0[m];
+                if (k < N && k < L) oacc[m] = cadd(oacc[m], cscale(buf[gg * P + lds_pad(k)], w));
+                const R c = 2 * zq[m] * t1[m] - t0[m];
+                t0[m] = t1[m];
+                t1[m] = c;
             }
         }
     }
@@ -282,8 +292,12 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     }
     for (int r = r_lo; r < r_hi; ++r) {
         C v[16];
+        {
+            R wq[16];
+            cheb_v_many<R, 16>(r, zk, wq);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], cheb_v<R>(r, zk[q]));
+            for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], wq[q]);
+        }
         __syncthreads();   // earlier readers of buf are done
         block_fft_regs<C, L2, -1, fft_wave_sync<L2>>(buf + g * P, tw, lt, v);
         fft_publish<L2>();
@@ -435,7 +449,8 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
                 take(vn, en, v);
                 if (r0 + RC < fac.K) fetch(r0 + RC + g, vn, en);
                 __syncthreads();
-                block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v);
+                // a rank slot beyond K (the last chunk of ranks) skips its transform
+                block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v, r0 + g < fac.K);
                 fft_publish<L1>();
             }
             gather(r0, min(RC, fac.K - r0), c0, kv, xs, acc);
@@ -713,10 +728,19 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
         block_fft_lds<C, L2, DIR, fft_wave_sync<L2>>(buf + g * P, tw, lt);
         fft_publish<L2>();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int i = tid + e * NT;
-            const R z = zcoord<R>(k1_0 + (i % G) + L1 * (int64_t)(i / G), zm);
-            acc[e] = cadd(acc[e], cscale(buf[(i % G) * P + lds_pad(i / G)], cheb_v<R>(r, z)));
+        for (int h = 0; h < 16; h += 8) {   // two halves of 8: bounded transient registers
+            R zq[8], wq[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int i = tid + (h + e) * NT;
+                zq[e] = zcoord<R>(k1_0 + (i % G) + L1 * (int64_t)(i / G), zm);
+            }
+            cheb_v_many<R, 8>(r, zq, wq);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int i = tid + (h + e) * NT;
+                acc[h + e] = cadd(acc[h + e], cscale(buf[(i % G) * P + lds_pad(i / G)], wq[e]));
+            }
         }
     }
 #pragma unroll

@@ -57,8 +57,12 @@ k_2d_passA(const cx_t<R> *__restrict__ Cin, int64_t N1, int64_t N2, int64_t GX, 
     }
     for (int r = r_lo; r < r_hi; ++r) {
         C v[16];
+        {
+            R wq[16];
+            cheb_v_many<R, 16>(r, zk, wq);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], cheb_v<R>(r, zk[q]));
+            for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], wq[q]);
+        }
         __syncthreads();
         block_fft_regs<C, GY, -1, fft_wave_sync<GY>>(buf + g * P, tw, lt, v);
         fft_publish<GY>();
@@ -139,11 +143,15 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
             const int r1 = r0 + g;
             __syncthreads();   // the row is staged; the previous gather is finished with buf
             C v[16];
+            {
+                R zq[16], wq[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                v[q] = r1 < fx.K ? cscale(hrow[lt + q * TPF], cheb_v<R>(r1, zcoord<R>(lt + q * TPF, zm)))
-                                 : cmake<C>(0, 0);
-            block_fft_regs<C, GX, -1, fft_wave_sync<GX>>(buf + g * P, tw, lt, v);
+                for (int q = 0; q < 16; ++q) zq[q] = zcoord<R>(lt + q * TPF, zm);
+                cheb_v_many<R, 16>(r1 < fx.K ? r1 : 0, zq, wq);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) v[q] = r1 < fx.K ? cscale(hrow[lt + q * TPF], wq[q]) : cmake<C>(0, 0);
+            }
+            block_fft_regs<C, GX, -1, fft_wave_sync<GX>>(buf + g * P, tw, lt, v, r1 < fx.K);
             fft_publish<GX>();
             const int nr = min(RC, fx.K - r0);
             for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
@@ -273,12 +281,21 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
             __syncthreads();
             block_fft_lds<C, GX, DIR, fft_wave_sync<GX>>(buf + g * P, tw, lt);
             fft_publish<GX>();
+            // T_{r0 + gg} for the consecutive ranks of the chunk by the recurrence
+            R zq[ZA], t0[ZA], t1[ZA];
 #pragma unroll
-            for (int m = 0; m < ZA; ++m) {
-                const int k1 = tid + m * NT;
-                const R z = zcoord<R>(k1, zm);
-                for (int gg = 0; gg < nr; ++gg)
-                    za[m] = cadd(za[m], cscale(buf[gg * P + lds_pad(k1)], cheb_v<R>(r0 + gg, z)));
+            for (int m = 0; m < ZA; ++m) zq[m] = zcoord<R>(tid + m * NT, zm);
+            cheb_pair_many<R, ZA>(r0, zq, t0, t1);
+            for (int gg = 0; gg < nr; ++gg) {
+#pragma unroll
+                for (int m = 0; m < ZA; ++m) {
+                    const int k1 = tid + m * NT;
+                    const R w = (r0 + gg == 0) ? (R)0.5 : t0[m];
+                    za[m] = cadd(za[m], cscale(buf[gg * P + lds_pad(k1)], w));
+                    const R c = 2 * zq[m] * t1[m] - t0[m];
+                    t0[m] = t1[m];
+                    t1[m] = c;
+                }
             }
             __syncthreads();
         }
@@ -354,10 +371,16 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
         block_fft_lds<C, GY, DIR, fft_wave_sync<GY>>(buf + g * P, tw, lt);
         fft_publish<GY>();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int i = tid + e * NT;
-            const R z = zcoord<R>(i / G, zm);
-            acc[e] = cadd(acc[e], cscale(buf[(i % G) * P + lds_pad(i / G)], cheb_v<R>(r, z)));
+        for (int h = 0; h < 16; h += 8) {   // two halves of 8: bounded transient registers
+            R zq[8], wq[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) zq[e] = zcoord<R>((tid + (h + e) * NT) / G, zm);
+            cheb_v_many<R, 8>(r, zq, wq);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int i = tid + (h + e) * NT;
+                acc[h + e] = cadd(acc[h + e], cscale(buf[(i % G) * P + lds_pad(i / G)], wq[e]));
+            }
         }
     }
     // transpose through LDS so that rows of C are written contiguously
