@@ -191,6 +191,7 @@ nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
     if (p->gamma > 0.5) p->gamma = 0.5;
     p->K = choose_rank(p->eps, p->gamma);
     if (p->K < 0) return NUFFT_ERR_UNSUPPORTED;
+    if (p->dtype == NUFFT_C64 && p->K > NUFFT_KMAX_F32) return NUFFT_ERR_UNSUPPORTED;   // FP32 rank polynomials
     if (p->dtype == NUFFT_C64) fill_factors(p->facf, p->gamma, p->K);
     else fill_factors(p->facd, p->gamma, p->K);
     nufft_status st = upload_twiddles<R>(p, s);
@@ -586,6 +587,7 @@ nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
     p->Kx = choose_rank(p->eps / 2.0, p->gammax);
     p->Ky = choose_rank(p->eps / 2.0, p->gammay);
     if (p->Kx < 0 || p->Ky < 0) return NUFFT_ERR_UNSUPPORTED;
+    if (p->dtype == NUFFT_C64 && (p->Kx > NUFFT_KMAX_F32 || p->Ky > NUFFT_KMAX_F32)) return NUFFT_ERR_UNSUPPORTED;
     p->K = p->Kx;
     p->gamma = p->gammax;
     if (p->dtype == NUFFT_C64) {

@@ -166,22 +166,27 @@ static inline unsigned xcd_grid(int T) { return (unsigned)(8 * ((T + 7) / 8)); }
 
 
 // Deterministic segmented sum of per-sample contributions into RC grids in LDS.
-// The cnt samples of a tile are sorted by grid point; thread t takes the
-// balanced slice [t*cnt/NT, (t+1)*cnt/NT), sums contrib(i, gg) over runs of
-// equal grid point and stores every run that starts and ends inside its slice
-// straight into grid gg.  A run that crosses a slice boundary leaves one
-// partial per thread in head/tail slots; the thread in whose slice the run
-// starts adds the partials of the following threads in thread order.  The
-// result does not depend on timing, and one heavily populated grid point is
-// spread over many threads instead of being walked by one.
+// The cnt samples of a tile are sorted by grid point; thread t takes a
+// balanced slice of them (empty slices, when cnt < NT, only at the end), sums
+// contrib(i, gg) over runs of equal grid point and stores every run that
+// starts and ends inside its slice straight into grid gg.  A run that crosses
+// slice boundaries leaves one partial per thread in head/tail slots; the
+// thread in whose slice the run starts adds the partials of the following
+// slices.  With few crossing runs it walks them in thread order; when many
+// slices are wholly inside one run (a heavily populated grid point) the sums
+// over the following slices come from a segmented suffix sum by pointer
+// jumping (log2 NT barrier steps) instead of a walk over hundreds of slices.
+// Either way the order of the additions is fixed: the result does not depend
+// on timing.
 // Grids must be zero on entry where no sample falls; the caller synchronises
-// before reading them.  Scratch: hv, tv (RC*NT values), hi, ti (NT ints).
+// before reading them.  Scratch: hv, tv (RC*NT values), hix, tix, nxa, nxb (NT ints).
 template <typename C, int RC, int NT, typename PosF, typename ContribF>
 __device__ __forceinline__ void seg_spread(int cnt, int nr, PosF pos, ContribF contrib, C *grid, int pitch,
-                                           C *hv, C *tv, int *hix, int *tix)
+                                           C *hv, C *tv, int *hix, int *tix, int *nxa, int *nxb)
 {
     const int tid = threadIdx.x;
-    const int i0 = (int)(((int64_t)tid * cnt) / NT), i1 = (int)(((int64_t)(tid + 1) * cnt) / NT);
+    const int per = cnt / NT, rem = cnt % NT;
+    const int i0 = tid * per + min(tid, rem), i1 = i0 + per + (tid < rem ? 1 : 0);
     C a[RC];
 #pragma unroll
     for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
@@ -209,7 +214,7 @@ __device__ __forceinline__ void seg_spread(int cnt, int nr, PosF pos, ContribF c
         for (int gg = 0; gg < RC; ++gg)
             if (gg < nr) a[gg] = cadd(a[gg], contrib(i, gg));
     }
-    // the last run of the slice (possibly also its first)
+    // the last run of the slice (possibly also its first); a keeps its sum
     if (ncur >= 0) {
         if (ncur == nfirst) {
 #pragma unroll
@@ -221,32 +226,68 @@ __device__ __forceinline__ void seg_spread(int cnt, int nr, PosF pos, ContribF c
     hix[tid] = nfirst;   // -1 for an empty slice
     tix[tid] = ncur;
     __syncthreads();
-    // runs crossing into later slices: owned by the slice where they start
+    // link: this slice lies wholly inside one run that continues into the next slice
+    const bool link = nfirst >= 0 && nfirst == ncur && tid + 1 < NT && hix[tid + 1] == ncur;
+    const bool jump = __syncthreads_count(link) >= 16;
+    bool head_starts_here = false, last_starts_here = false;
     if (nfirst >= 0) {
-        const bool head_starts_here = (i0 == 0) || pos(i0 - 1) != nfirst;
+        head_starts_here = (i0 == 0) || pos(i0 - 1) != nfirst;
         // the first run: complete here unless it is also the last run (then handled below)
         if (head_starts_here && nfirst != ncur) {
-            // the first run ended inside this slice: it is complete
 #pragma unroll
             for (int gg = 0; gg < RC; ++gg)
                 if (gg < nr) grid[gg * pitch + lds_pad(nfirst)] = hv[gg * NT + tid];
         }
-        const bool last_starts_here = (nfirst != ncur) || head_starts_here;
-        if (last_starts_here) {
-            C sum[RC];
+        last_starts_here = (nfirst != ncur) || head_starts_here;
+    }
+    const bool cont = nfirst >= 0 && tid + 1 < NT && hix[tid + 1] == ncur;   // the last run goes on
+    if (jump) {
+        // S_u = H_u + (link_u ? S_{u+1} : 0) by pointer jumping; tv becomes the
+        // second buffer (this thread's tail sum stays in a)
+        C *X = hv, *Y = tv;
+        int *nx = nxa, *ny = nxb;
+        nx[tid] = link ? tid + 1 : -1;
+        __syncthreads();
+        for (int d = 1; d < NT; d <<= 1) {
+            const int n = nx[tid];
+            C v[RC];
 #pragma unroll
-            for (int gg = 0; gg < RC; ++gg) sum[gg] = tv[gg * NT + tid];
-            for (int u = tid + 1; u < NT; ++u) {
-                if (hix[u] < 0) continue;               // empty slice
-                if (hix[u] != ncur) break;
+            for (int gg = 0; gg < RC; ++gg) v[gg] = X[gg * NT + tid];
+            if (n >= 0) {
 #pragma unroll
-                for (int gg = 0; gg < RC; ++gg) sum[gg] = cadd(sum[gg], hv[gg * NT + u]);
-                if (tix[u] != ncur) break;               // the run ends inside slice u
+                for (int gg = 0; gg < RC; ++gg) v[gg] = cadd(v[gg], X[gg * NT + n]);
             }
 #pragma unroll
-            for (int gg = 0; gg < RC; ++gg)
-                if (gg < nr) grid[gg * pitch + lds_pad(ncur)] = sum[gg];
+            for (int gg = 0; gg < RC; ++gg) Y[gg * NT + tid] = v[gg];
+            ny[tid] = n >= 0 ? nx[n] : -1;
+            __syncthreads();
+            C *t = X;
+            X = Y;
+            Y = t;
+            int *tn = nx;
+            nx = ny;
+            ny = tn;
         }
+        if (last_starts_here) {
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg) {
+                const C sum = cont ? cadd(a[gg], X[gg * NT + tid + 1]) : a[gg];
+                if (gg < nr) grid[gg * pitch + lds_pad(ncur)] = sum;
+            }
+        }
+    } else if (last_starts_here) {
+        C sum[RC];
+#pragma unroll
+        for (int gg = 0; gg < RC; ++gg) sum[gg] = a[gg];
+        for (int u = tid + 1; u < NT; ++u) {
+            if (hix[u] != ncur) break;                   // (empty slices only follow the last sample)
+#pragma unroll
+            for (int gg = 0; gg < RC; ++gg) sum[gg] = cadd(sum[gg], hv[gg * NT + u]);
+            if (tix[u] != ncur) break;                   // the run ends inside slice u
+        }
+#pragma unroll
+        for (int gg = 0; gg < RC; ++gg)
+            if (gg < nr) grid[gg * pitch + lds_pad(ncur)] = sum[gg];
     }
 }
 }  // namespace nufft

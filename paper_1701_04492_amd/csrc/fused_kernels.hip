@@ -586,22 +586,9 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
 #pragma unroll
         for (int gg = 0; gg < RC; ++gg) up[gg] = rank_poly(fac, min(r0 + gg, fac.K - 1));
         int ncur = -1;
-        for (int i = i0; i < i1; ++i) {
-            C val;
-            R z;
-            int n1;
-            if (i < SCAP) {
-                val = sval[i];
-                z = sz[i];
-                n1 = spos[i];
-            } else {
-                const R Xi = Xs[tile_lo + i];
-                R sn, cs;
-                sincospi_r(Xi, &sn, &cs);
-                val = cmul(cmake<C>(cs, dir * sn), csort[tile_lo + i]);
-                z = Xi * fac.inv_gamma;
-                n1 = (int)(keys[tile_lo + i] & (uint32_t)(L1 - 1));
-            }
+        // one sample of the walk: store the finished grid value when the grid
+        // point changes, then add this sample's terms
+        auto step = [&](const C &val, R z, int n1) __attribute__((always_inline)) {
             if (n1 != ncur) {
                 if (ncur >= 0) {
 #pragma unroll
@@ -615,6 +602,36 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
 #pragma unroll
             for (int gg = 0; gg < RC; ++gg)
                 if (gg < nr) a[gg] = cadd(a[gg], cscale(val, rank_eval(up[gg], z)));
+        };
+        if (i1 <= SCAP) {
+            // the whole slice is staged: its LDS reads go out four samples at a time
+            for (int i = i0; i < i1; i += 4) {
+                C vv[4];
+                R zz[4];
+                int nn[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = min(i + u, i1 - 1);
+                    vv[u] = sval[j];
+                    zz[u] = sz[j];
+                    nn[u] = spos[j];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i + u < i1) step(vv[u], zz[u], nn[u]);
+            }
+        } else {
+            for (int i = i0; i < i1; ++i) {
+                if (i < SCAP) {
+                    step(sval[i], sz[i], spos[i]);
+                } else {
+                    const R Xi = Xs[tile_lo + i];
+                    R sn, cs;
+                    sincospi_r(Xi, &sn, &cs);
+                    step(cmul(cmake<C>(cs, dir * sn), csort[tile_lo + i]), Xi * fac.inv_gamma,
+                         (int)(keys[tile_lo + i] & (uint32_t)(L1 - 1)));
+                }
+            }
         }
         if (ncur >= 0) {
 #pragma unroll

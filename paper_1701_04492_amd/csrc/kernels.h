@@ -24,12 +24,18 @@ __device__ __forceinline__ R upoly(const Factors<R> &fac, int r, R z)
 // The same polynomial for one rank r that is uniform across the workgroup,
 // with its coefficients loaded once into registers and reused for every
 // sample (a per-term load inside the evaluation would wait for each term).
-// Since K <= NUFFT_KMAX, no rank has more than NUFFT_KMAX / 2 terms and the
-// table is zero past nterm[r]: a fixed-length Horner chain over the first
-// NUFFT_KMAX / 2 coefficients gives the same value with no branch or select.
+// A rank of K has at most ceil(K / 2) terms and the table is zero past
+// nterm[r]: a fixed-length Horner chain over the first rank_terms<R>
+// coefficients gives the same value with no branch or select.  FP32 plans
+// have K <= NUFFT_KMAX_F32 (eps >= 1e-7, or 5e-8 per axis in 2-D, gives
+// K <= 12 at gamma = 1/2; the plan builders reject more), so 6 terms; FP64
+// plans use the full NUFFT_KMAX / 2.
+#define NUFFT_KMAX_F32 12
+template <typename R>
+inline constexpr int rank_terms = sizeof(R) == 4 ? NUFFT_KMAX_F32 / 2 : NUFFT_KMAX / 2;
 template <typename R>
 struct RankPoly {
-    R c[NUFFT_KMAX / 2];
+    R c[rank_terms<R>];
     int odd;
 };
 template <typename R>
@@ -37,7 +43,7 @@ __device__ __forceinline__ RankPoly<R> rank_poly(const Factors<R> &fac, int r)
 {
     RankPoly<R> p;
 #pragma unroll
-    for (int m = 0; m < NUFFT_KMAX / 2; ++m) p.c[m] = fac.ucoef[r * NUFFT_UCOEF_STRIDE + m];
+    for (int m = 0; m < rank_terms<R>; ++m) p.c[m] = fac.ucoef[r * NUFFT_UCOEF_STRIDE + m];
     p.odd = r & 1;
     return p;
 }
@@ -45,9 +51,9 @@ template <typename R>
 __device__ __forceinline__ R rank_eval(const RankPoly<R> &p, R z)
 {
     const R w = z * z;
-    R acc = p.c[NUFFT_KMAX / 2 - 1];
+    R acc = p.c[rank_terms<R> - 1];
 #pragma unroll
-    for (int m = NUFFT_KMAX / 2 - 2; m >= 0; --m) acc = acc * w + p.c[m];
+    for (int m = rank_terms<R> - 2; m >= 0; --m) acc = acc * w + p.c[m];
     return p.odd ? acc * z : acc;
 }
 

@@ -208,7 +208,7 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     __shared__ R szx[SCAP], szy[SCAP], spy[SCAP];
     __shared__ unsigned short spos[SCAP];
     __shared__ C hv[RC * NT], tv[RC * NT];
-    __shared__ int hix[NT], tix[NT];
+    __shared__ int hix[NT], tix[NT], nxa[NT], nxb[NT];
     const C *tw = TWG ? twd_g : tw_s;
     const int task = xcd_task(ntasks);
     if (task < 0) return;
@@ -277,7 +277,7 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
                 // i^(r1 + r2) for the type I, i^-(r1 + r2) for the adjoint
                 return crot(cscale(sval[i], rank_eval(ux[gg], szx[i]) * spy[i]), -DIR * (r0 + gg + r2));
             };
-            seg_spread<C, RC, NT>(cnt, nr, pos, contrib, buf, P, hv, tv, hix, tix);
+            seg_spread<C, RC, NT>(cnt, nr, pos, contrib, buf, P, hv, tv, hix, tix, nxa, nxb);
             __syncthreads();
             block_fft_lds<C, GX, DIR, fft_wave_sync<GX>>(buf + g * P, tw, lt);
             fft_publish<GX>();
