@@ -191,8 +191,9 @@ def cpu_baseline(x, c, N, seconds):
 
 
 def bench_batch(P, W, torch, dev):
-    """512 type-II transforms, N_b = round(2^U(8,16)), eps 1e-6 FP32: one persistent launch
-    (eager and replayed from a HIP graph) against 512 separate launches."""
+    """512 type-II transforms, N_b = round(2^U(8,16)), eps 1e-6 FP32: the autotuned batch
+    (three phased launches or one persistent launch; eager and replayed from a HIP graph),
+    each launch mode on its own, against 512 separate launches."""
     Ns, xs_np, cs_np = W.batch_case(4)
     Ns = [int(n) for n in Ns]
     xs = [torch.from_numpy(x).to(dev) for x in xs_np]
@@ -204,6 +205,11 @@ def bench_batch(P, W, torch, dev):
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     t_batch = time_loop(lambda: P.nufft_batch_exec(plan, cs, fs), 20, 3, torch)
+    modes = {}
+    for label, fl in (("phased", 0), ("persistent", P.NUFFT_FLAG_BATCH_PERSISTENT)):
+        pm = P.nufft_batch_plan(Ns, xs, 1e-6, torch.complex64, fl)
+        modes[label + "_us"] = round(time_loop(lambda: P.nufft_batch_exec(pm, cs, fs), 20, 3, torch) * 1e3, 1)
+        del pm
     g = torch.cuda.CUDAGraph()
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
@@ -224,9 +230,10 @@ def bench_batch(P, W, torch, dev):
             P.nufft2_exec(pl, c, f)
     t_plain = time_loop(run_plains, 5, 1, torch)
     del plains
-    return {"members": len(Ns), "points": pts, "K_max": plan.K, "persistent_grid": plan.grid,
+    return {"members": len(Ns), "points": pts, "K_max": plan.K, "autotuned_grid": plan.grid,
             "plan_s": round(plan_s, 2),
-            "persistent_us": round(t_batch * 1e3, 1), "persistent_pts_per_s": pts / (t_batch * 1e-3),
+            "autotuned_us": round(t_batch * 1e3, 1), "autotuned_pts_per_s": pts / (t_batch * 1e-3),
+            "launch_modes": modes,
             "graph_replay_us": round(t_graph * 1e3, 1),
             "separate_fused_launches_us": round(t_sep * 1e3, 1),
             "separate_plain_launches_us": round(t_plain * 1e3, 1),

@@ -84,7 +84,11 @@ enum {
      * each output, inside the 4 eps ||c||_1 bound for eps >= 2^-10.
      * Combined with NUFFT_FLAG_PLAIN: NUFFT_ERR_INVALID_ARG; with complex128
      * or a smaller eps: NUFFT_ERR_UNSUPPORTED. */
-    NUFFT_FLAG_HALF_EXCHANGE = 8u
+    NUFFT_FLAG_HALF_EXCHANGE = 8u,
+    /* Batches only: run each exec as one persistent launch over a task queue
+     * (workgroups claim tasks; a pass-B task waits on its transform's pass-A
+     * tasks) instead of three plain launches, one per task type. */
+    NUFFT_FLAG_BATCH_PERSISTENT = 16u
 };
 
 /* ---- 1-D type II / type I / adjoint ----------------------------------- */
@@ -212,9 +216,14 @@ nufft_status nufft2d_type1_exec(nufft_plan_t plan, const void *c_dev, void *F_de
  * host array of device pointers).  Each transform uses the grid
  * L_b = next power of two >= N_b (oversampling, Sec. 2.3) and its own rank
  * K_b(eps, gamma_b).  Transforms with L_b <= 4096 run whole in one
- * workgroup; larger ones run as a two-pass split; all of them go into one
- * persistent launch per exec, tasks in decreasing order of size.
- * Flags: NUFFT_FLAG_FIX_GAMMA_HALF, NUFFT_FLAG_AUTOTUNE. */
+ * workgroup; larger ones run as a two-pass split.  An exec is three plain
+ * launches (whole small transforms, pass-A column groups, pass-B tiles; one
+ * workgroup per task, tasks in decreasing order of size), or one persistent
+ * launch with NUFFT_FLAG_BATCH_PERSISTENT.
+ * Flags: NUFFT_FLAG_FIX_GAMMA_HALF, NUFFT_FLAG_AUTOTUNE (times the
+ * persistent launch at 1..4 workgroups per CU and, unless
+ * NUFFT_FLAG_BATCH_PERSISTENT, the phased launches; keeps the fastest),
+ * NUFFT_FLAG_BATCH_PERSISTENT. */
 nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_modes_host,
                               const int64_t *n_pts_host, const double *const *x_dev_host,
                               double eps, nufft_dtype dtype, uint32_t flags, void *stream);
@@ -231,7 +240,8 @@ nufft_status nufft_batch_exec(nufft_plan_t plan, const void *const *c_dev_host,
 
 /* Any output pointer may be NULL.  For 2-D plans K and gamma describe the
  * x axis and grid is Gx * Gy; for batches K is the largest rank, gamma the
- * largest gamma and grid the number of workgroups of the persistent launch. */
+ * largest gamma and grid the number of workgroups of the persistent launch,
+ * or of the three phased launches together (one per task). */
 nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *grid);
 
 /* Copies the plan's sorted sample order to host memory: perm_host[i] is the

@@ -6,7 +6,8 @@ The transforms run in hand-written HIP kernels for gfx950 behind the C ABI of
 ``autograd`` wraps the type-II transform for torch.autograd.
 """
 from .binding import (  # noqa: F401
-    NUFFT_FLAG_AUTOTUNE, NUFFT_FLAG_FIX_GAMMA_HALF, NUFFT_FLAG_HALF_EXCHANGE, NUFFT_FLAG_PLAIN, NufftError, Plan,
+    NUFFT_FLAG_AUTOTUNE, NUFFT_FLAG_BATCH_PERSISTENT, NUFFT_FLAG_FIX_GAMMA_HALF, NUFFT_FLAG_HALF_EXCHANGE,
+    NUFFT_FLAG_PLAIN, NufftError, Plan,
     nufft1_exec, nufft1_solve, nufft2_backward, nufft2_exec, nufft2_grad_x, nufft2_plan, nufft2_solve,
     nufft2d_exec, nufft2d_plan, nufft2d_type1_exec, nufft3_exec,
     nufft_batch_exec, nufft_batch_plan, nufft_bessel_coefficients, nufft_choose_rank, nufft_destroy,

@@ -21,6 +21,7 @@ NUFFT_FLAG_FIX_GAMMA_HALF = 1
 NUFFT_FLAG_PLAIN = 2
 NUFFT_FLAG_AUTOTUNE = 4
 NUFFT_FLAG_HALF_EXCHANGE = 8
+NUFFT_FLAG_BATCH_PERSISTENT = 16
 STATUS = {0: "NUFFT_OK", 1: "NUFFT_ERR_INVALID_ARG", 2: "NUFFT_ERR_UNSUPPORTED", 3: "NUFFT_ERR_ALLOC",
           4: "NUFFT_ERR_NONFINITE", 5: "NUFFT_ERR_HIP"}
 

@@ -720,8 +720,11 @@ static nufft_status batch_upload_ptrs(Plan *p, const void *const *cs, void *cons
 }
 
 template <typename R>
-static hipError_t batch_run(const Plan *p, int grid, hipStream_t s)
+static hipError_t batch_run(const Plan *p, int mode, int grid, hipStream_t s)
 {
+    if (mode == 1)
+        return batch_launch_phased<R>((const BatchDesc<R> *)p->bdesc, (const int4 *)p->btasks3, p->bcnt,
+                                      (const cx_t<R> *const *)p->bcs, (cx_t<R> *const *)p->bfs, p->blds, s);
     return batch_launch<R>((const BatchDesc<R> *)p->bdesc, (const int4 *)p->btasks, p->bntasks, (BatchCtl *)p->bctl,
                            (const cx_t<R> *const *)p->bcs, (cx_t<R> *const *)p->bfs, grid, p->blds, s);
 }
@@ -797,9 +800,18 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
                 tk.push_back(make_int4(BATCH_PASS_B, b, n2, (int)std::min<int64_t>(run, desc[b].L2 - n2)));
         }
     p->bntasks = (int)tk.size();
+    // the same tasks grouped by type for the phased mode (each group keeps the order above)
+    std::vector<int4> tk3;
+    for (int type : {BATCH_SMALL, BATCH_PASS_A, BATCH_PASS_B}) {
+        for (const int4 &t : tk)
+            if (t.x == type) tk3.push_back(t);
+        p->bcnt[type] = (int)tk3.size() - (type > 0 ? p->bcnt[0] + (type > 1 ? p->bcnt[1] : 0) : 0);
+    }
     Factors<R> *dfac = (Factors<R> *)p->alloc(B * sizeof(Factors<R>));
     p->bdesc = p->alloc(B * sizeof(BatchDesc<R>));
     p->btasks = p->alloc(tk.size() * sizeof(int4));
+    p->btasks3 = p->alloc(tk3.size() * sizeof(int4));
+    if (!p->btasks3) return NUFFT_ERR_ALLOC;
     const size_t ctl_bytes = sizeof(BatchCtl) + (size_t)B * sizeof(int);
     p->bctl = p->alloc(ctl_bytes);
     p->bcs = (void **)p->alloc(B * sizeof(void *));
@@ -811,13 +823,17 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
     NUFFT_HIP_CHECK(hipMemcpyAsync(dfac, facs.data(), B * sizeof(Factors<R>), hipMemcpyHostToDevice, s));
     NUFFT_HIP_CHECK(hipMemcpyAsync(p->bdesc, desc.data(), B * sizeof(BatchDesc<R>), hipMemcpyHostToDevice, s));
     NUFFT_HIP_CHECK(hipMemcpyAsync(p->btasks, tk.data(), tk.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(p->btasks3, tk3.data(), tk3.size() * sizeof(int4), hipMemcpyHostToDevice, s));
     NUFFT_HIP_CHECK(hipMemcpyAsync(p->bctl, ctl.data(), ctl_bytes, hipMemcpyHostToDevice, s));
     NUFFT_HIP_CHECK(hipStreamSynchronize(s));
     NUFFT_HIP_CHECK(batch_set_lds_limit<R>(lds));
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    p->bgrid = 2 * cus;
+    // default: the three phased launches; NUFFT_FLAG_BATCH_PERSISTENT: one persistent launch
+    const bool persistent = (p->flags & NUFFT_FLAG_BATCH_PERSISTENT) != 0;
+    p->bmode = persistent ? 0 : 1;
+    p->bgrid = persistent ? 2 * cus : p->bntasks;
     if (p->flags & NUFFT_FLAG_AUTOTUNE) {
         // time the launch at 1..4 workgroups per CU on scratch inputs, keep the fastest
         int64_t nc = 0, nf = 0;
@@ -844,11 +860,13 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
         NUFFT_HIP_CHECK(hipEventCreate(&e0));
         NUFFT_HIP_CHECK(hipEventCreate(&e1));
         float best = 1e30f;
-        for (int wpc = 1; wpc <= 4; ++wpc) {
-            const int grid = wpc * cus;
-            NUFFT_HIP_CHECK(batch_run<R>(p, grid, s));   // warm-up
+        // candidates: the persistent launch at 1..4 workgroups per CU, and the phased launches
+        // (with NUFFT_FLAG_BATCH_PERSISTENT only the persistent grid sizes)
+        for (int cand = 1; cand <= (persistent ? 4 : 5); ++cand) {
+            const int mode = cand == 5 ? 1 : 0, grid = cand == 5 ? p->bntasks : cand * cus;
+            NUFFT_HIP_CHECK(batch_run<R>(p, mode, grid, s));   // warm-up
             NUFFT_HIP_CHECK(hipEventRecord(e0, s));
-            for (int rep = 0; rep < 3; ++rep) NUFFT_HIP_CHECK(batch_run<R>(p, grid, s));
+            for (int rep = 0; rep < 3; ++rep) NUFFT_HIP_CHECK(batch_run<R>(p, mode, grid, s));
             NUFFT_HIP_CHECK(hipEventRecord(e1, s));
             NUFFT_HIP_CHECK(hipEventSynchronize(e1));
             float ms = 0;
@@ -856,6 +874,7 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
             if (ms < best) {
                 best = ms;
                 p->bgrid = grid;
+                p->bmode = mode;
             }
         }
         (void)hipEventDestroy(e0);
@@ -1127,7 +1146,8 @@ nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_mod
     *out = nullptr;
     if (batch < 1 || !n_modes || !n_pts || !x_dev) return NUFFT_ERR_INVALID_ARG;
     if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_AUTOTUNE)) return NUFFT_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_AUTOTUNE | NUFFT_FLAG_BATCH_PERSISTENT))
+        return NUFFT_ERR_INVALID_ARG;
     for (int b = 0; b < batch; ++b) {
         if (n_modes[b] < 1 || n_pts[b] < 1 || !x_dev[b]) return NUFFT_ERR_INVALID_ARG;
         if (n_modes[b] > (int64_t(1) << 20) || n_pts[b] > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
@@ -1162,8 +1182,8 @@ nufft_status nufft_batch_exec(nufft_plan_t plan, const void *const *c, void *con
     nufft_status st = plan->dtype == NUFFT_C64 ? batch_upload_ptrs<float>(plan, c, f, s)
                                                : batch_upload_ptrs<double>(plan, c, f, s);
     if (st) return st;
-    return from_hip(plan->dtype == NUFFT_C64 ? batch_run<float>(plan, plan->bgrid, s)
-                                             : batch_run<double>(plan, plan->bgrid, s));
+    return from_hip(plan->dtype == NUFFT_C64 ? batch_run<float>(plan, plan->bmode, plan->bgrid, s)
+                                             : batch_run<double>(plan, plan->bmode, plan->bgrid, s));
 }
 
 nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *grid)

@@ -40,6 +40,11 @@ int batch_pass_b_points();     // grid points per PASS_B task (runs of whole til
 template <typename R>
 hipError_t batch_launch(const BatchDesc<R> *descs, const int4 *tasks, int ntasks, BatchCtl *ctl,
                         const cx_t<R> *const *cs, cx_t<R> *const *fs, int grid, size_t lds, hipStream_t s);
+// The same work as three plain launches (SMALL, PASS_A, PASS_B tasks; counts[3]),
+// tasks laid out in that order, one workgroup per task.
+template <typename R>
+hipError_t batch_launch_phased(const BatchDesc<R> *descs, const int4 *tasks, const int *counts,
+                               const cx_t<R> *const *cs, cx_t<R> *const *fs, size_t lds, hipStream_t s);
 template <typename R>
 hipError_t batch_set_lds_limit(size_t lds);
 

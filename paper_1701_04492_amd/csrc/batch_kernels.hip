@@ -311,6 +311,46 @@ k_batch(const BatchDesc<R> *__restrict__ descs, const int4 *__restrict__ tasks, 
     }
 }
 
+// Phased execution of the same task table: one plain launch per task type
+// (SMALL, PASS_A, PASS_B), one workgroup per task, in stream order.  The
+// PASS_B launch starts after every PASS_A task has finished, so no task waits
+// and there is no queue state; each kernel is compiled for its own task type
+// only (fewer registers than the persistent kernel, which holds all three).
+template <typename R, int TYPE>
+__global__ void __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(NUFFT_BATCH_WAVES)))
+k_batch_phase(const BatchDesc<R> *__restrict__ descs, const int4 *__restrict__ tasks, int ntasks,
+              const cx_t<R> *const *__restrict__ cs, cx_t<R> *const *__restrict__ fs)
+{
+    extern __shared__ __align__(16) char lds[];
+    const int t = (int)blockIdx.x;
+    if (t >= ntasks) return;
+    const int4 tk = tasks[t];
+    const int b = uniform(tk.y), par = uniform(tk.z), par2 = uniform(tk.w);
+    const BatchDesc<R> &d = descs[b];
+    if constexpr (TYPE == BATCH_SMALL) {
+        switch (d.L) {
+#define BS(LL) case LL: b_small<R, LL>(d, cs[b], fs[b], par, lds); break;
+            BS(16) BS(32) BS(64) BS(128) BS(256) BS(512) BS(1024) BS(2048) BS(4096)
+#undef BS
+        default: break;
+        }
+    } else if constexpr (TYPE == BATCH_PASS_A) {
+        switch (d.L2) {
+#define BA(LL) case LL: b_passA<R, LL>(d, cs[b], par, lds); break;
+            BA(64) BA(128) BA(256) BA(512) BA(1024)
+#undef BA
+        default: break;
+        }
+    } else {
+        switch (d.L1) {
+#define BB(LL, SS) case LL: b_passB<R, LL, SS>(d, fs[b], par, par2, lds); break;
+            BB(128, 1) BB(256, 2) BB(512, 3) BB(1024, 5)
+#undef BB
+        default: break;
+        }
+    }
+}
+
 size_t batch_lds_bytes(int L, int L1, int L2, bool fp32)
 {
     const size_t es = fp32 ? 8 : 16;
@@ -338,15 +378,44 @@ hipError_t batch_launch(const BatchDesc<R> *descs, const int4 *tasks, int ntasks
 }
 
 template <typename R>
+hipError_t batch_launch_phased(const BatchDesc<R> *descs, const int4 *tasks, const int *counts,
+                               const cx_t<R> *const *cs, cx_t<R> *const *fs, size_t lds, hipStream_t s)
+{
+    const int4 *t = tasks;
+    if (counts[0] > 0)
+        hipLaunchKernelGGL((k_batch_phase<R, BATCH_SMALL>), dim3(counts[0]), dim3(BNT), lds, s, descs, t, counts[0],
+                           cs, fs);
+    t += counts[0];
+    if (counts[1] > 0)
+        hipLaunchKernelGGL((k_batch_phase<R, BATCH_PASS_A>), dim3(counts[1]), dim3(BNT), lds, s, descs, t,
+                           counts[1], cs, fs);
+    t += counts[1];
+    if (counts[2] > 0)
+        hipLaunchKernelGGL((k_batch_phase<R, BATCH_PASS_B>), dim3(counts[2]), dim3(BNT), lds, s, descs, t,
+                           counts[2], cs, fs);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t batch_set_lds_limit(size_t lds)
 {
-    return hipFuncSetAttribute((const void *)k_batch<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *fns[] = {(const void *)k_batch<R>, (const void *)k_batch_phase<R, BATCH_SMALL>,
+                         (const void *)k_batch_phase<R, BATCH_PASS_A>, (const void *)k_batch_phase<R, BATCH_PASS_B>};
+    for (const void *fn : fns) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template hipError_t batch_launch<float>(const BatchDesc<float> *, const int4 *, int, BatchCtl *,
                                         const float2 *const *, float2 *const *, int, size_t, hipStream_t);
 template hipError_t batch_launch<double>(const BatchDesc<double> *, const int4 *, int, BatchCtl *,
                                          const double2 *const *, double2 *const *, int, size_t, hipStream_t);
+template hipError_t batch_launch_phased<float>(const BatchDesc<float> *, const int4 *, const int *,
+                                               const float2 *const *, float2 *const *, size_t, hipStream_t);
+template hipError_t batch_launch_phased<double>(const BatchDesc<double> *, const int4 *, const int *,
+                                                const double2 *const *, double2 *const *, size_t, hipStream_t);
 template hipError_t batch_set_lds_limit<float>(size_t);
 template hipError_t batch_set_lds_limit<double>(size_t);
 

@@ -66,6 +66,9 @@ struct nufft_plan_s {
     std::vector<const void *> hcs;                   // last uploaded pointers
     std::vector<void *> hfs;
     int bntasks = 0, bgrid = 0;
+    int bmode = 0;                  // 0: one persistent launch; 1: three phased launches
+    void *btasks3 = nullptr;        // the tasks ordered SMALL, PASS_A, PASS_B (phased mode)
+    int bcnt[3] = {0, 0, 0};        // their counts
     size_t blds = 0;
 
     Profiler prof;

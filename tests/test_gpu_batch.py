@@ -1,4 +1,5 @@
-"""GPU parity of batched type-II transforms of uneven sizes (one persistent launch)."""
+"""GPU parity of batched type-II transforms of uneven sizes (three phased launches by
+default, one persistent launch with NUFFT_FLAG_BATCH_PERSISTENT)."""
 import numpy as np
 import pytest
 import torch
@@ -63,6 +64,23 @@ def test_batch_mixed_sizes(dtype):
     assert all(torch.equal(a, b) for a, b in zip(f0, fs))
 
 
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_batch_persistent_equals_phased(dtype):
+    """The two launch modes run the same per-task code: bit-identical results."""
+    Ns = [1, 100, 4096, 4097, 9000, 40000, 65536, 777]
+    Ms = [5, 300, 4096, 5000, 9000, 40000, 65536, 2000]
+    xs, cs, fs = _make(Ns, Ms, 64, dtype)
+    pa = P.nufft_batch_plan(Ns, xs, EPS[dtype], dtype)
+    pb = P.nufft_batch_plan(Ns, xs, EPS[dtype], dtype, P.NUFFT_FLAG_BATCH_PERSISTENT)
+    P.nufft_batch_exec(pa, cs, fs)
+    fa = [f.clone() for f in fs]
+    for _ in range(2):   # the persistent queue resets itself between launches
+        P.nufft_batch_exec(pb, cs, fs)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(fa, fs))
+    _check_members(Ns, xs, cs, fs, dtype)
+
+
 def test_batch_matches_single_plans():
     Ns = [300, 5000, 70000 // 2]
     xs, cs, fs = _make(Ns, Ns, 61, C64)
@@ -73,10 +91,11 @@ def test_batch_matches_single_plans():
         assert (single - f).abs().max().item() <= 1e-5 * c.abs().sum().item() / n ** 0.5
 
 
-def test_batch_graph_replay():
+@pytest.mark.parametrize("flags", [0, 16])   # phased (three launches); 16 = NUFFT_FLAG_BATCH_PERSISTENT
+def test_batch_graph_replay(flags):
     Ns = [500, 3000, 12000, 50000]
     xs, cs, fs = _make(Ns, Ns, 62, C64)
-    plan = P.nufft_batch_plan(Ns, xs, 1e-6, C64, P.NUFFT_FLAG_AUTOTUNE)
+    plan = P.nufft_batch_plan(Ns, xs, 1e-6, C64, P.NUFFT_FLAG_AUTOTUNE | flags)
     assert plan.grid >= 1
     P.nufft_batch_exec(plan, cs, fs)          # uploads the pointers; the capture holds the kernel only
     torch.cuda.synchronize()
