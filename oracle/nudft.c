@@ -224,6 +224,32 @@ int oracle_nudft2d_adj(int64_t M, const double *x, const double *y, const double
     return 0;
 }
 
+/* 2-D type III: f_j = sum_{k<Q} c_k exp(-2 pi i (x_j w1_k + y_j w2_k)).  Both products
+ * are non-integer; each is reduced modulo 1 exactly and the two are added. */
+int oracle_nudft3_2d(int64_t Q, const double *w1, const double *w2, const double *c, int64_t M,
+                     const double *x, const double *y, double *f)
+{
+    if (Q < 0 || M < 0) return -1;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t j = 0; j < M; ++j) {
+        acc2 re = {0.0, 0.0}, im = {0.0, 0.0};
+        for (int64_t k = 0; k < Q; ++k) {
+            double phi = phase_mod1(x[j], w1[k]) + phase_mod1(y[j], w2[k]);
+            double co, si;
+            cis2pi(phi - nearbyint(phi), &co, &si);
+            si = -si;
+            double cr = c[2 * k], ci = c[2 * k + 1];
+            acc2_add_prod(&re, cr, co);
+            acc2_add_prod(&re, -ci, si);
+            acc2_add_prod(&im, cr, si);
+            acc2_add_prod(&im, ci, co);
+        }
+        f[2 * j] = re.s + re.t;
+        f[2 * j + 1] = im.s + im.t;
+    }
+    return 0;
+}
+
 /* Nearest-grid assignment on a grid of n points (Sec. 2.2):
  *   s_j = round(n x_j)  (round-to-nearest-even of the rounded product),
  *   t_j = s_j mod n     (Euclidean, so negative x wraps too),

@@ -27,6 +27,7 @@ def _load():
         lib.oracle_nudft3.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         lib.oracle_nudft2d.argtypes = [_i64, _i64, _dp, _i64, _dp, _dp, _dp]
         lib.oracle_nudft2d_adj.argtypes = [_i64, _dp, _dp, _dp, _i64, _ip, _ip, ctypes.c_int, _dp]
+        lib.oracle_nudft3_2d.argtypes = [_i64, _dp, _dp, _dp, _i64, _dp, _dp, _dp]
         lib.oracle_grid_assign.argtypes = [_i64, _i64, _dp, _ip, _ip, _dp]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
@@ -88,6 +89,16 @@ def nudft3(x, w, c):
     f = np.empty(x.shape[0], np.complex128)
     rc = _load().oracle_nudft3(w.shape[0], _p(w), _p(c.view(np.float64)), x.shape[0], _p(x),
                                _p(f.view(np.float64)))
+    assert rc == 0
+    return f
+
+
+def nudft3_2d(x, y, w1, w2, c):
+    """2-D type III (Sec. 3.2 per axis): f_j = sum_k c_k exp(-2 pi i (x_j w1_k + y_j w2_k))."""
+    x, y, w1, w2, c = _f64(x), _f64(y), _f64(w1), _f64(w2), _c128(c)
+    f = np.empty(x.shape[0], np.complex128)
+    rc = _load().oracle_nudft3_2d(w1.shape[0], _p(w1), _p(w2), _p(c.view(np.float64)), x.shape[0], _p(x), _p(y),
+                                  _p(f.view(np.float64)))
     assert rc == 0
     return f
 

@@ -80,6 +80,23 @@ def test_half_all_directions(N, M, dist):
         assert e2 < 2e-4      # regression gate: random data sits far inside the bound
 
 
+def test_half_many_samples_per_tile():
+    """M = 128 N: the adjoint's dense tiles are split and their partial rows summed in full
+    precision before the fp16 store; the type II splits its tiles too."""
+    N, M = 1 << 13, 1 << 20
+    x, c = W.type2_case(84, N, M)
+    g = W.complex_normal(W.rng_for(85), M)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS, C64, HALF)
+    ct, gt = _t(c, C64), _t(g, C64)
+    cc, gg = ct.cpu().numpy().astype(np.complex128), gt.cpu().numpy().astype(np.complex128)
+    rows = _rows(M, 256, 86)
+    f = P.nufft2_exec(plan, ct).cpu().numpy()
+    _check("dense type II", f[rows], D.nudft2(x[rows], cc), np.abs(cc).sum(), plan)
+    ks = _rows(N, 128, 87)
+    a = P.nufft1_exec(plan, gt, sign=+1).cpu().numpy()
+    _check("dense adjoint", a[ks], D.nudft1(x, gg, N, k=ks, sign=+1), np.abs(gg).sum(), plan)
+
+
 def test_half_is_inert_for_one_pass_sizes():
     """N <= 4096 runs in one workgroup with no HBM exchange: the flag changes nothing."""
     x, c = W.type2_case(74, 3000, 5000)

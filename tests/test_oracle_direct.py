@@ -100,6 +100,39 @@ def test_2d_type1_is_transpose_and_adjoint_is_conjugate_transpose():
     assert np.abs(t1 - ad).max() > 1e-2          # the two signs differ for generic samples
 
 
+def test_type3_2d_vs_mpmath():
+    rng = np.random.default_rng(18)
+    M, Q = 5, 7
+    x, y = rng.random(M), rng.random(M)
+    w1, w2 = rng.random(Q) * 9.0, rng.random(Q) * 5.0
+    c = _rand(rng, Q)
+    f = D.nudft3_2d(x, y, w1, w2, c)
+    for j in range(M):
+        ph = [-(mpmath.mpf(x[j]) * mpmath.mpf(w1[k]) + mpmath.mpf(y[j]) * mpmath.mpf(w2[k])) for k in range(Q)]
+        assert abs(f[j] - _mp_sum(ph, c)) <= 4e-16 * np.abs(c).sum()
+
+
+def test_type3_2d_reduces_to_type2_and_separates():
+    """Integer frequencies: the 2-D type II of the coefficients placed at them.  A product
+    set of frequencies with a product coefficient: the product of two 1-D type IIIs."""
+    rng = np.random.default_rng(19)
+    M, n1, n2 = 40, 6, 5
+    x, y = rng.random(M), rng.random(M)
+    k1, k2 = rng.integers(0, n1, 30), rng.integers(0, n2, 30)
+    c = _rand(rng, 30)
+    C = np.zeros((n1, n2), np.complex128)
+    np.add.at(C, (k1, k2), c)
+    f = D.nudft3_2d(x, y, k1.astype(np.float64), k2.astype(np.float64), c)
+    assert np.abs(f - D.nudft2d(x, y, C)).max() <= 1e-13 * np.abs(c).sum()
+    a1, a2 = rng.random(4) * 7.3, rng.random(3) * 2.9
+    ca, cb = _rand(rng, 4), _rand(rng, 3)
+    W1, W2 = np.meshgrid(a1, a2, indexing="ij")
+    CC = np.outer(ca, cb)
+    g = D.nudft3_2d(x, y, W1.ravel(), W2.ravel(), CC.ravel())
+    ref = D.nudft3(x, a1, ca) * D.nudft3(y, a2, cb)
+    assert np.abs(g - ref).max() <= 1e-13 * np.abs(CC).sum()
+
+
 def test_large_phase_exact_reduction():
     """At k ~ 2^20 a plain fl(x*k) loses ~1e-10 of phase; the oracle must not."""
     rng = np.random.default_rng(14)
