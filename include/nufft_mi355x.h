@@ -209,6 +209,21 @@ nufft_status nufft2d_exec(nufft_plan_t plan, void *C_dev, void *f_dev, int adjoi
 nufft_status nufft2d_type1_exec(nufft_plan_t plan, const void *c_dev, void *F_dev, int sign,
                                 void *stream);
 
+/* 2-D type III (Sec. 3.2 applied per axis):
+ *   f_dev[j] ~ sum_{k<Q} c_dev[k] exp(-2 pi i (x_j w1_k + y_j w2_k)),  j < M,
+ * x_dev, y_dev: M doubles in [0, 1); w1_dev, w2_dev: Q doubles with
+ * w1 in [0, n1), w2 in [0, n2) (n1, n2 >= 1, n1 + 1 and n2 + 1 at most 2048).
+ * Each axis is factored as in the 1-D type III (rank K(eps/4, gamma_axis));
+ * the Kx * Ky inner transforms are 2-D type I on the samples
+ * (w1/n1, w2/n2) with n1 + 1 by n2 + 1 modes, read at
+ * (round(n1 x_j), round(n2 y_j)).  c_dev: Q complex, f_dev: M complex.
+ * Error ~ eps * ||c||_1 per output.  Plans, allocates and synchronises
+ * internally (not graph capturable); INVALID_ARG for samples or
+ * frequencies out of range or not finite. */
+nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_dev, int64_t n_freq,
+                           const double *w1_dev, const double *w2_dev, int64_t n1, int64_t n2,
+                           const void *c_dev, void *f_dev, double eps, nufft_dtype dtype, void *stream);
+
 /* ---- batches of independent 1-D type II transforms ---------------------- */
 
 /* Plan B independent type-II transforms of sizes N_b (modes, 1 <= N_b <= 2^20)

@@ -44,6 +44,7 @@ _sig = {
     "nufft2_solve": [_vp, _vp, _vp, _dbl, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _vp],
     "nufft1_solve": [_vp, _vp, _vp, _dbl, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _vp],
     "nufft3_exec": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
+    "nufft2d3_exec": [_i64, _vp, _vp, _i64, _vp, _vp, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
     "nufft2d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _dbl, _int, _u32, _vp],
     "nufft2d_exec": [_vp, _vp, _vp, _int, _vp],
     "nufft2d_type1_exec": [_vp, _vp, _vp, _int, _vp],
@@ -218,6 +219,19 @@ def nufft3_exec(x, w, c, eps, f=None):
     _check(lib.nufft3_exec(M, _dev_tensor(x, torch.float64, M, "x"), N, _dev_tensor(w, torch.float64, N, "w"),
                            _dev_tensor(c, c.dtype, N, "c"), _dev_tensor(f, c.dtype, M, "f"), float(eps),
                            _cdtype(c.dtype), _stream(c.device)), "nufft3_exec")
+    return f
+
+
+def nufft2d3_exec(x, y, w1, w2, n1, n2, c, eps, f=None):
+    """2-D type III: f_j = sum_k c_k exp(-2 pi i (x_j w1_k + y_j w2_k)); x, y in [0, 1),
+    w1 in [0, n1), w2 in [0, n2)."""
+    M, Q = x.numel(), w1.numel()
+    if f is None:
+        f = torch.empty(M, dtype=c.dtype, device=c.device)
+    _check(lib.nufft2d3_exec(M, _dev_tensor(x, torch.float64, M, "x"), _dev_tensor(y, torch.float64, M, "y"), Q,
+                             _dev_tensor(w1, torch.float64, Q, "w1"), _dev_tensor(w2, torch.float64, Q, "w2"),
+                             int(n1), int(n2), _dev_tensor(c, c.dtype, Q, "c"), _dev_tensor(f, c.dtype, M, "f"),
+                             float(eps), _cdtype(c.dtype), _stream(c.device)), "nufft2d3_exec")
     return f
 
 

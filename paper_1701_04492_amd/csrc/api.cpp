@@ -331,6 +331,38 @@ hipError_t t3_scale(const cx_t<R> *c, const double *w, int64_t N, int r, int wit
 template <typename R>
 hipError_t t3_accum(const double *d, const int32_t *t, const int32_t *wrap, int64_t M, const Factors<double> &fac,
                     int r, const cx_t<R> *y, const cx_t<R> *y2, cx_t<R> *f, hipStream_t s);
+hipError_t t3d_assign(const double *x, const double *y, int64_t M, int64_t n1, int64_t n2, int32_t *sx, int32_t *sy,
+                      double *dx, double *dy, unsigned long long *gbits, int *flags, hipStream_t s);
+hipError_t t3d_freq(const double *w1, const double *w2, int64_t Q, int64_t n1, int64_t n2, double *xs, double *ys,
+                    int *flags, hipStream_t s);
+template <typename R>
+hipError_t t3d_scale(const cx_t<R> *c, const double *w1, const double *w2, int64_t Q, int64_t n1, int64_t n2, int r1,
+                     int r2, cx_t<R> *c1, hipStream_t s);
+template <typename R>
+hipError_t t3d_accum(const double *dx, const double *dy, const int32_t *sx, const int32_t *sy, int64_t M,
+                     const Factors<double> &fx, const Factors<double> &fy, int r1, int r2, const cx_t<R> *F,
+                     int64_t ld, int first, cx_t<R> *f, hipStream_t s);
+
+// FP64 factors u_r of the type-III expansion (monomial form of Sec. 2.1.2) and
+// sum_{p,r} w_p |b_pr|, the bound on sum_r |u_r| that weighs the inner errors.
+static void t3_factors(double gamma, int K, Factors<double> &fac, double *su_out)
+{
+    std::memset(&fac, 0, sizeof(fac));
+    double mono[NUFFT_KMAX * NUFFT_KMAX];
+    u_monomials(gamma, K, mono);
+    for (int r = 0; r < K; ++r) {
+        int n = 0;
+        for (int m = (r & 1); m < K; m += 2) fac.ucoef[r * NUFFT_UCOEF_STRIDE + n++] = mono[r * K + m];
+        fac.nterm[r] = n;
+    }
+    fac.K = K;
+    fac.inv_gamma = gamma > 0 ? 1.0 / gamma : 0.0;
+    double b[NUFFT_KMAX * NUFFT_KMAX], su = 0.0;
+    bessel_b(gamma, K, b);
+    for (int p = 0; p < K; ++p)
+        for (int r = 0; r < K; ++r) su += (p == 0 ? 0.5 : 1.0) * std::fabs(b[p * K + r]);
+    *su_out = su;
+}
 
 template <typename R>
 static nufft_status type3(int64_t M, const double *x, int64_t N, const double *w, const void *c, void *f,
@@ -369,22 +401,8 @@ static nufft_status type3(int64_t M, const double *x, int64_t N, const double *w
     const int K = choose_rank(eps / 2.0, gamma);
     if (K < 0) return NUFFT_ERR_UNSUPPORTED;
     Factors<double> fac;
-    {
-        std::memset(&fac, 0, sizeof(fac));
-        double mono[NUFFT_KMAX * NUFFT_KMAX];
-        u_monomials(gamma, K, mono);
-        for (int r = 0; r < K; ++r) {
-            int n = 0;
-            for (int m = (r & 1); m < K; m += 2) fac.ucoef[r * NUFFT_UCOEF_STRIDE + n++] = mono[r * K + m];
-            fac.nterm[r] = n;
-        }
-        fac.K = K;
-        fac.inv_gamma = gamma > 0 ? 1.0 / gamma : 0.0;
-    }
-    double b[NUFFT_KMAX * NUFFT_KMAX], su = 0.0;
-    bessel_b(gamma, K, b);
-    for (int p = 0; p < K; ++p)
-        for (int r = 0; r < K; ++r) su += (p == 0 ? 0.5 : 1.0) * std::fabs(b[p * K + r]);
+    double su;
+    t3_factors(gamma, K, fac, &su);
     const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
     double eps_i = eps / (2.0 * (su > 1.0 ? su : 1.0));
     if (eps_i < floor_eps) eps_i = floor_eps;
@@ -884,6 +902,84 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
     }
     return NUFFT_OK;
 }
+// 2-D type III (Sec. 3.2 applied per axis; the composition is stated with the
+// kernels): Kx * Ky inner 2-D type-I transforms on the frequencies.
+template <typename R>
+static nufft_status type3_2d(int64_t M, const double *x, const double *y, int64_t Q, const double *w1,
+                             const double *w2, int64_t n1, int64_t n2, const void *c, void *f, double eps,
+                             nufft_dtype dt, hipStream_t s)
+{
+    using C = cx_t<R>;
+    Plan tmp;   // owns the temporaries
+    struct SyncGuard {   // destroyed before tmp: no temporary is freed under a running kernel
+        hipStream_t s;
+        ~SyncGuard() { (void)hipStreamSynchronize(s); }
+    } guard{s};
+    const int64_t ld = n2 + 1;
+    int32_t *sx = (int32_t *)tmp.alloc(M * sizeof(int32_t));
+    int32_t *sy = (int32_t *)tmp.alloc(M * sizeof(int32_t));
+    double *dx = (double *)tmp.alloc(M * sizeof(double));
+    double *dy = (double *)tmp.alloc(M * sizeof(double));
+    double *xs = (double *)tmp.alloc(Q * sizeof(double));
+    double *ys = (double *)tmp.alloc(Q * sizeof(double));
+    unsigned long long *flags = (unsigned long long *)tmp.alloc(3 * sizeof(unsigned long long));
+    C *c1 = (C *)tmp.alloc(Q * sizeof(C));
+    C *F = (C *)tmp.alloc((n1 + 1) * ld * sizeof(C));
+    if (!sx || !sy || !dx || !dy || !xs || !ys || !flags || !c1 || !F) return NUFFT_ERR_ALLOC;
+    NUFFT_HIP_CHECK(hipMemsetAsync(flags, 0, 3 * sizeof(unsigned long long), s));
+    NUFFT_HIP_CHECK(t3d_assign(x, y, M, n1, n2, sx, sy, dx, dy, flags, (int *)(flags + 2), s));
+    NUFFT_HIP_CHECK(t3d_freq(w1, w2, Q, n1, n2, xs, ys, (int *)(flags + 2), s));
+    unsigned long long h[3];
+    NUFFT_HIP_CHECK(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    if ((int)h[2] & 5) return NUFFT_ERR_INVALID_ARG;   // samples outside [0,1)^2 / frequencies outside [0,n)
+    double gx, gy;
+    std::memcpy(&gx, &h[0], sizeof(double));
+    std::memcpy(&gy, &h[1], sizeof(double));
+    gx = std::min(gx, 0.5);
+    gy = std::min(gy, 0.5);
+    // half of eps for the factorisation, shared by the two axes
+    // (|A^x A^y - A^x_K A^y_K| <= eps_x + eps_y + eps_x eps_y), half for the inner
+    // transforms, whose errors are weighted by sum |u^x_r1| |u^y_r2| <= su_x su_y
+    const int Kx = choose_rank(eps / 4.0, gx), Ky = choose_rank(eps / 4.0, gy);
+    if (Kx < 0 || Ky < 0) return NUFFT_ERR_UNSUPPORTED;
+    Factors<double> fx, fy;
+    double sux, suy;
+    t3_factors(gx, Kx, fx, &sux);
+    t3_factors(gy, Ky, fy, &suy);
+    const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
+    double eps_i = eps / (2.0 * std::max(sux, 1.0) * std::max(suy, 1.0));
+    if (eps_i < floor_eps) eps_i = floor_eps;
+    // inner 2-D type-I plan on the samples (w1/n1, w2/n2) with n1+1 by n2+1 modes
+    Plan *inner = new (std::nothrow) Plan();
+    if (!inner) return NUFFT_ERR_ALLOC;
+    tmp.children.push_back(inner);
+    inner->kind = PLAN_2D;
+    inner->dtype = dt;
+    inner->N1 = n1 + 1;
+    inner->N2 = n2 + 1;
+    inner->N = (n1 + 1) * (n2 + 1);
+    inner->M = Q;
+    inner->eps = eps_i;
+    int gxs = 16, gys = 16;
+    while (gxs < n1 + 1) gxs <<= 1;
+    while (gys < n2 + 1) gys <<= 1;
+    if (gxs > 2048 || gys > 2048) return NUFFT_ERR_UNSUPPORTED;
+    inner->Gx = gxs;
+    inner->Gy = gys;
+    inner->L = (int64_t)gxs * gys;
+    nufft_status st = build_2d<R>(inner, xs, ys, s);
+    if (st) return st;
+    const Args2D<R> ia = args_2d<R>(inner);
+    for (int r1 = 0; r1 < Kx; ++r1)
+        for (int r2 = 0; r2 < Ky; ++r2) {
+            NUFFT_HIP_CHECK(t3d_scale<R>((const C *)c, w1, w2, Q, n1, n2, r1, r2, c1, s));
+            NUFFT_HIP_CHECK(fused_2d_adj<R>(ia, c1, F, -1, s));
+            NUFFT_HIP_CHECK(t3d_accum<R>(dx, dy, sx, sy, M, fx, fy, r1, r2, F, ld, r1 == 0 && r2 == 0, (C *)f, s));
+        }
+    return NUFFT_OK;
+}
+
 }  // namespace nufft
 
 // ============================================================================
@@ -1069,6 +1165,24 @@ nufft_status nufft3_exec(int64_t n_pts, const double *x, int64_t n_freq, const d
     hipStream_t s = (hipStream_t)stream;
     st = dtype == NUFFT_C64 ? type3<float>(n_pts, x, n_freq, w, c, f, eps, dtype, s)
                             : type3<double>(n_pts, x, n_freq, w, c, f, eps, dtype, s);
+    if (st != NUFFT_OK) (void)hipStreamSynchronize(s);
+    return st;
+}
+
+nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_dev, int64_t n_freq,
+                           const double *w1_dev, const double *w2_dev, int64_t n1, int64_t n2, const void *c,
+                           void *f, double eps, nufft_dtype dtype, void *stream)
+{
+    if (n_pts < 1 || n_freq < 1 || n1 < 1 || n2 < 1 || !x_dev || !y_dev || !w1_dev || !w2_dev || !c || !f)
+        return NUFFT_ERR_INVALID_ARG;
+    if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
+    if (n_pts > (int64_t(1) << 30) || n_freq > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
+    nufft_status st;
+    if (!eps_ok(eps, dtype, &st)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = dtype == NUFFT_C64 ? type3_2d<float>(n_pts, x_dev, y_dev, n_freq, w1_dev, w2_dev, n1, n2, c, f, eps, dtype, s)
+                            : type3_2d<double>(n_pts, x_dev, y_dev, n_freq, w1_dev, w2_dev, n1, n2, c, f, eps, dtype,
+                                               s);
     if (st != NUFFT_OK) (void)hipStreamSynchronize(s);
     return st;
 }

@@ -56,3 +56,54 @@ def test_type3_rejects_out_of_range():
     w = np.array([0.5, 2.5])       # w must lie in [0, N)
     with pytest.raises(P.NufftError):
         P.nufft3_exec(_t(x, torch.float64), _t(w, torch.float64), _t(np.ones(2), C64), 1e-6)
+
+
+# ---- 2-D type III (nufft2d3_exec) --------------------------------------------------
+
+@pytest.mark.parametrize("dtype,eps", [(C64, 1e-6), (C128, 1e-9)])
+@pytest.mark.parametrize("M,Q,n1,n2", [(1, 1, 1, 1), (300, 200, 16, 24), (2000, 1500, 60, 33), (4000, 3000, 128, 100)])
+def test_type3_2d_against_oracle(dtype, eps, M, Q, n1, n2):
+    rng = W.rng_for(42)
+    x, y = rng.random(M), rng.random(M)
+    # samples that round to s = n (the last mode row / column of the inner transform)
+    x[: min(2, M)] = 1.0 - rng.random(min(2, M)) * 0.4 / n1
+    y[-min(2, M):] = 1.0 - rng.random(min(2, M)) * 0.4 / n2
+    w1, w2 = rng.uniform(0, n1, Q), rng.uniform(0, n2, Q)
+    c = W.complex_normal(rng, Q)
+    print("type3 2-D M=%d Q=%d n=%dx%d %s eps %g" % (M, Q, n1, n2, dtype, eps), flush=True)
+    ct = _t(c, dtype)
+    f = P.nufft2d3_exec(_t(x, torch.float64), _t(y, torch.float64), _t(w1, torch.float64), _t(w2, torch.float64),
+                        n1, n2, ct, eps).cpu().numpy()
+    cc = ct.cpu().numpy().astype(np.complex128)
+    ref = D.nudft3_2d(x, y, w1, w2, cc)
+    err = np.abs(f - ref).max() / np.abs(cc).sum()
+    print("   err/||c||_1 = %.3e" % err, flush=True)
+    assert np.all(np.isfinite(f)) and err <= 4 * eps
+
+
+def test_type3_2d_integer_frequencies_match_2d_type2():
+    """Integer frequencies on the n1 x n2 grid: the 2-D type II of the coefficients placed there."""
+    rng = W.rng_for(43)
+    n1, n2, M, Q = 40, 30, 900, 500
+    x, y = rng.random(M), rng.random(M)
+    k1, k2 = rng.integers(0, n1, Q), rng.integers(0, n2, Q)
+    c = W.complex_normal(rng, Q)
+    f3 = P.nufft2d3_exec(_t(x, torch.float64), _t(y, torch.float64), _t(k1.astype(np.float64), torch.float64),
+                         _t(k2.astype(np.float64), torch.float64), n1, n2, _t(c, C128), 1e-11)
+    C = np.zeros((n1, n2), np.complex128)
+    np.add.at(C, (k1, k2), c)
+    plan = P.nufft2d_plan(_t(x, torch.float64), _t(y, torch.float64), n1, n2, 1e-11, C128)
+    f2 = torch.empty(M, dtype=C128, device=DEV)
+    P.nufft2d_exec(plan, _t(C.ravel(), C128), f2, 0)
+    assert (f3 - f2).abs().max().item() <= 8e-11 * np.abs(c).sum()
+
+
+def test_type3_2d_rejects_out_of_range():
+    x = _t(np.array([0.1, 0.5]), torch.float64)
+    yb = _t(np.array([0.1, 1.0]), torch.float64)
+    w = _t(np.array([0.5, 3.0]), torch.float64)
+    c = _t(np.ones(2), C64)
+    with pytest.raises(P.NufftError):
+        P.nufft2d3_exec(x, yb, w, w, 4, 4, c, 1e-6)          # y = 1 is outside [0, 1)
+    with pytest.raises(P.NufftError):
+        P.nufft2d3_exec(x, x, w, w, 2, 4, c, 1e-6)           # w1 = 3 is outside [0, 2)
