@@ -289,6 +289,27 @@ def bench_oversampling(P, W, torch, dev):
     return out
 
 
+def bench_type3(P, W, torch, dev):
+    """Type III (Sec. 3.2), planning included (each call plans its inner transforms):
+    1-D with M = N = 2^20, and 2-D with M = Q = 2^16 on 256 x 256 frequency boxes;
+    complex64, eps 1e-6, iid samples and frequencies."""
+    rng = W.rng_for(8)
+    out = {}
+    N = 1 << 20
+    x = torch.from_numpy(W.iid_samples(rng, N)).to(dev)
+    w = torch.from_numpy(rng.uniform(0, N, N)).to(dev)
+    c = torch.from_numpy(W.complex_normal(rng, N)).to(torch.complex64).to(dev)
+    t = time_loop(lambda: P.nufft3_exec(x, w, c, 1e-6), 5, 1, torch)
+    out["1d_2p20"] = {"ms": round(t, 3), "pts_per_s": N / (t * 1e-3)}
+    M, n = 1 << 16, 256
+    x, y = (torch.from_numpy(W.iid_samples(rng, M)).to(dev) for _ in range(2))
+    w1, w2 = (torch.from_numpy(rng.uniform(0, n, M)).to(dev) for _ in range(2))
+    c = torch.from_numpy(W.complex_normal(rng, M)).to(torch.complex64).to(dev)
+    t = time_loop(lambda: P.nufft2d3_exec(x, y, w1, w2, n, n, c, 1e-6), 3, 1, torch)
+    out["2d_2p16_256x256"] = {"ms": round(t, 3), "pts_per_s": M / (t * 1e-3)}
+    return out
+
+
 def bench_solve(P, W, torch, dev):
     """Inverse type II (Sec. 3.3) at N = M = 2^20, complex64, perturbed equispaced samples
     x_j = (j + U(-1/8, 1/8))/N, f = F2 c for c complex N(0,1): CG to a residual of 1e-5."""
@@ -496,6 +517,7 @@ def main():
         out["polar_2d"] = bench_2d(P, W, torch, dev)
         out["inverse_2p20"] = bench_solve(P, W, torch, dev)
         out["oversampling_2p14_modes_2p22_samples"] = bench_oversampling(P, W, torch, dev)
+        out["type3"] = bench_type3(P, W, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, c_np, N, args.cpu_seconds)
