@@ -224,6 +224,38 @@ int oracle_nudft2d_adj(int64_t M, const double *x, const double *y, const double
     return 0;
 }
 
+/* 3-D type II: f_j = sum_{k1<N1, k2<N2, k3<N3} C[(k1*N2+k2)*N3+k3]
+ *   exp(-2 pi i (k1 x_j + k2 y_j + k3 z_j)); the three phases reduced modulo 1 separately. */
+int oracle_nudft3d(int64_t N1, int64_t N2, int64_t N3, const double *C, int64_t M,
+                   const double *x, const double *y, const double *z, double *f)
+{
+    if (N1 < 0 || N2 < 0 || N3 < 0 || M < 0) return -1;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t j = 0; j < M; ++j) {
+        acc2 re = {0.0, 0.0}, im = {0.0, 0.0};
+        for (int64_t k1 = 0; k1 < N1; ++k1) {
+            double p1 = phase_mod1(x[j], (double)k1);
+            for (int64_t k2 = 0; k2 < N2; ++k2) {
+                double p12 = p1 + phase_mod1(y[j], (double)k2);
+                for (int64_t k3 = 0; k3 < N3; ++k3) {
+                    double phi = p12 + phase_mod1(z[j], (double)k3);
+                    double co, si;
+                    cis2pi(phi - nearbyint(phi), &co, &si);
+                    si = -si;
+                    const double *cc = C + 2 * ((k1 * N2 + k2) * N3 + k3);
+                    acc2_add_prod(&re, cc[0], co);
+                    acc2_add_prod(&re, -cc[1], si);
+                    acc2_add_prod(&im, cc[0], si);
+                    acc2_add_prod(&im, cc[1], co);
+                }
+            }
+        }
+        f[2 * j] = re.s + re.t;
+        f[2 * j + 1] = im.s + im.t;
+    }
+    return 0;
+}
+
 /* 2-D type III: f_j = sum_{k<Q} c_k exp(-2 pi i (x_j w1_k + y_j w2_k)).  Both products
  * are non-integer; each is reduced modulo 1 exactly and the two are added. */
 int oracle_nudft3_2d(int64_t Q, const double *w1, const double *w2, const double *c, int64_t M,

@@ -28,6 +28,7 @@ def _load():
         lib.oracle_nudft2d.argtypes = [_i64, _i64, _dp, _i64, _dp, _dp, _dp]
         lib.oracle_nudft2d_adj.argtypes = [_i64, _dp, _dp, _dp, _i64, _ip, _ip, ctypes.c_int, _dp]
         lib.oracle_nudft3_2d.argtypes = [_i64, _dp, _dp, _dp, _i64, _dp, _dp, _dp]
+        lib.oracle_nudft3d.argtypes = [_i64, _i64, _i64, _dp, _i64, _dp, _dp, _dp, _dp]
         lib.oracle_grid_assign.argtypes = [_i64, _i64, _dp, _ip, _ip, _dp]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
@@ -89,6 +90,18 @@ def nudft3(x, w, c):
     f = np.empty(x.shape[0], np.complex128)
     rc = _load().oracle_nudft3(w.shape[0], _p(w), _p(c.view(np.float64)), x.shape[0], _p(x),
                                _p(f.view(np.float64)))
+    assert rc == 0
+    return f
+
+
+def nudft3d(x, y, z, C):
+    """3-D type II (Sec. 4's construction with a third axis):
+    f_j = sum_{k1,k2,k3} C[k1,k2,k3] exp(-2 pi i (k1 x_j + k2 y_j + k3 z_j))."""
+    x, y, z, C = _f64(x), _f64(y), _f64(z), _c128(C)
+    n1, n2, n3 = C.shape
+    f = np.empty(x.shape[0], np.complex128)
+    rc = _load().oracle_nudft3d(n1, n2, n3, _p(C.view(np.float64)), x.shape[0], _p(x), _p(y), _p(z),
+                                _p(f.view(np.float64)))
     assert rc == 0
     return f
 

@@ -133,6 +133,26 @@ def test_type3_2d_reduces_to_type2_and_separates():
     assert np.abs(g - ref).max() <= 1e-13 * np.abs(CC).sum()
 
 
+def test_3d_vs_mpmath_and_separable():
+    rng = np.random.default_rng(20)
+    n1, n2, n3, M = 3, 4, 2, 5
+    x, y, z = rng.random(M) * 2 - 0.5, rng.random(M), rng.random(M)
+    C = _rand(rng, n1 * n2 * n3).reshape(n1, n2, n3)
+    f = D.nudft3d(x, y, z, C)
+    for j in range(M):
+        ph = [-(mpmath.mpf(x[j]) * a + mpmath.mpf(y[j]) * b + mpmath.mpf(z[j]) * c)
+              for a in range(n1) for b in range(n2) for c in range(n3)]
+        assert abs(f[j] - _mp_sum(ph, C.ravel())) <= 4e-16 * np.abs(C).sum()
+    # a product coefficient gives the product of three 1-D type IIs
+    a, b, c = _rand(rng, 5), _rand(rng, 3), _rand(rng, 4)
+    P3 = np.einsum("i,j,k->ijk", a, b, c)
+    g = D.nudft3d(x, y, z, P3)
+    assert np.abs(g - D.nudft2(x, a) * D.nudft2(y, b) * D.nudft2(z, c)).max() <= 1e-14 * np.abs(P3).sum()
+    # one mode along z: the 2-D type II
+    C1 = _rand(rng, 12).reshape(3, 4, 1)
+    assert np.abs(D.nudft3d(x, y, z, C1) - D.nudft2d(x, y, C1[:, :, 0])).max() <= 1e-14 * np.abs(C1).sum()
+
+
 def test_large_phase_exact_reduction():
     """At k ~ 2^20 a plain fl(x*k) loses ~1e-10 of phase; the oracle must not."""
     rng = np.random.default_rng(14)
