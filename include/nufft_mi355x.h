@@ -224,6 +224,20 @@ nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_d
                            const double *w1_dev, const double *w2_dev, int64_t n1, int64_t n2,
                            const void *c_dev, void *f_dev, double eps, nufft_dtype dtype, void *stream);
 
+/* ---- 3-D type II --------------------------------------------------------- */
+
+/* 3-D type II (Sec. 4's construction with a third axis):
+ *   f_dev[j] ~ sum_{k1<n1,k2<n2,k3<n3} C_dev[(k1*n2+k2)*n3+k3] exp(-2 pi i (k1 x_j + k2 y_j + k3 z_j)).
+ * x_dev, y_dev, z_dev: M doubles each, any finite reals; C_dev: n1*n2*n3 complex,
+ * row-major; f_dev: M complex.  The z axis is factored with rank K(eps/2, gamma_z)
+ * on a grid of Gz >= n3 points (Gz <= 1024), and each z slice of the samples
+ * gets one 2-D type-II plan (n1, n2 up to 2048).  Error ~ eps * ||C||_1 per
+ * output.  Plans (one 2-D plan per non-empty slice), allocates and
+ * synchronises internally (not graph capturable); NONFINITE for a non-finite z. */
+nufft_status nufft3d_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev,
+                          int64_t n1, int64_t n2, int64_t n3, const void *C_dev, void *f_dev, double eps,
+                          nufft_dtype dtype, void *stream);
+
 /* ---- batches of independent 1-D type II transforms ---------------------- */
 
 /* Plan B independent type-II transforms of sizes N_b (modes, 1 <= N_b <= 2^20)

@@ -45,6 +45,7 @@ _sig = {
     "nufft1_solve": [_vp, _vp, _vp, _dbl, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _vp],
     "nufft3_exec": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
     "nufft2d3_exec": [_i64, _vp, _vp, _i64, _vp, _vp, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
+    "nufft3d_exec": [_i64, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
     "nufft2d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _dbl, _int, _u32, _vp],
     "nufft2d_exec": [_vp, _vp, _vp, _int, _vp],
     "nufft2d_type1_exec": [_vp, _vp, _vp, _int, _vp],
@@ -232,6 +233,21 @@ def nufft2d3_exec(x, y, w1, w2, n1, n2, c, eps, f=None):
                              _dev_tensor(w1, torch.float64, Q, "w1"), _dev_tensor(w2, torch.float64, Q, "w2"),
                              int(n1), int(n2), _dev_tensor(c, c.dtype, Q, "c"), _dev_tensor(f, c.dtype, M, "f"),
                              float(eps), _cdtype(c.dtype), _stream(c.device)), "nufft2d3_exec")
+    return f
+
+
+def nufft3d_exec(x, y, z, C, eps, f=None):
+    """3-D type II: f_j = sum_{k1,k2,k3} C[k1,k2,k3] exp(-2 pi i (k1 x_j + k2 y_j + k3 z_j)); C is
+    an (n1, n2, n3) complex tensor (row-major)."""
+    M = x.numel()
+    n1, n2, n3 = C.shape
+    Cf = C.reshape(-1)   # held here for the duration of the call
+    if f is None:
+        f = torch.empty(M, dtype=C.dtype, device=C.device)
+    _check(lib.nufft3d_exec(M, _dev_tensor(x, torch.float64, M, "x"), _dev_tensor(y, torch.float64, M, "y"),
+                            _dev_tensor(z, torch.float64, M, "z"), int(n1), int(n2), int(n3),
+                            _dev_tensor(Cf, C.dtype, n1 * n2 * n3, "C"), _dev_tensor(f, C.dtype, M, "f"),
+                            float(eps), _cdtype(C.dtype), _stream(C.device)), "nufft3d_exec")
     return f
 
 

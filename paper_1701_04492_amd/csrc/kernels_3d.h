@@ -1,0 +1,25 @@
+// 3-D type II (Sec. 4's construction with a third axis): device launchers.
+#pragma once
+
+#include "kernels.h"
+
+namespace nufft {
+
+// t = round(Gz z) mod Gz and X = (Gz z - round(Gz z)) n3 / Gz per sample; max |X| into gbits
+// (bits of a non-negative double); flags |= 1 for a non-finite z.
+template <typename R>
+hipError_t launch_3d_assign(const double *z, int64_t M, int64_t n3, int64_t Gz, int32_t *t, R *X,
+                            unsigned long long *gbits, int *flags, hipStream_t s);
+// out[i] = in[perm[i]], i < M
+hipError_t launch_3d_gather(const double *in, const int32_t *perm, int64_t M, double *out, hipStream_t s);
+// D[m * rows + row] = sum_{k3 < n3} v_r(k3) Cin[row * n3 + k3] exp(-2 pi i k3 m / Gz), m < Gz (16..1024);
+// tw: the stage-major length-Gz twiddle table
+template <typename R>
+hipError_t launch_3d_zfft(const cx_t<R> *Cin, int64_t rows, int64_t n3, int64_t Gz, int r, const cx_t<R> *tw,
+                          cx_t<R> *D, hipStream_t s);
+// f[perm[i]] = (r == 0 ? 0 : f[perm[i]]) + u_r(Xs[i]) fs[i]
+template <typename R>
+hipError_t launch_3d_accum(const cx_t<R> *fs, const int32_t *perm, const R *Xs, int64_t M, const Factors<R> &fac,
+                           int r, cx_t<R> *f, hipStream_t s);
+
+}  // namespace nufft

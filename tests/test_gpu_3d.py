@@ -1,0 +1,58 @@
+"""GPU parity of the 3-D type II (Sec. 4's construction with a third axis) against the
+FP64 direct sum, with the bar 4 eps ||C||_1."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nudft as D
+from paper_1701_04492_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1701_04492_amd")
+DEV = torch.device("cuda:0")
+C64, C128 = torch.complex64, torch.complex128
+EPS = {C64: 1e-6, C128: 1e-12}
+
+
+def _t(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+@pytest.mark.parametrize("n1,n2,n3,M", [(1, 1, 1, 3), (8, 6, 5, 300), (16, 16, 16, 2000), (20, 12, 33, 3000),
+                                        (32, 32, 64, 4000)])
+def test_3d_against_oracle(dtype, n1, n2, n3, M):
+    rng = W.rng_for(90)
+    x, y, z = rng.random(M) * 2 - 0.5, rng.random(M), rng.random(M) * 3 - 1.0
+    C = W.complex_normal(rng, n1 * n2 * n3).reshape(n1, n2, n3)
+    print("3-D n=%dx%dx%d M=%d %s" % (n1, n2, n3, M, dtype), flush=True)
+    Ct = _t(C, dtype)
+    f = P.nufft3d_exec(_t(x, torch.float64), _t(y, torch.float64), _t(z, torch.float64), Ct, EPS[dtype]).cpu().numpy()
+    Cc = Ct.cpu().numpy().astype(np.complex128)
+    rows = np.arange(M) if M * n1 * n2 * n3 <= 2e7 else np.unique(np.concatenate(
+        [np.random.default_rng(91).choice(M, 400, replace=False), [0, M - 1]]))
+    ref = D.nudft3d(x[rows], y[rows], z[rows], Cc)
+    err = np.abs(f[rows] - ref).max() / np.abs(Cc).sum()
+    print("   err/||C||_1 = %.3e" % err, flush=True)
+    assert np.all(np.isfinite(f)) and err <= 4 * EPS[dtype]
+
+
+def test_3d_one_z_mode_is_2d():
+    """n3 = 1: the 3-D transform is the 2-D type II of C[:, :, 0]."""
+    rng = W.rng_for(92)
+    n1, n2, M = 24, 40, 5000
+    x, y, z = rng.random(M), rng.random(M), rng.random(M)
+    C = W.complex_normal(rng, n1 * n2).reshape(n1, n2, 1)
+    f3 = P.nufft3d_exec(_t(x, torch.float64), _t(y, torch.float64), _t(z, torch.float64), _t(C, C128), 1e-12)
+    plan = P.nufft2d_plan(_t(x, torch.float64), _t(y, torch.float64), n1, n2, 1e-12, C128)
+    f2 = torch.empty(M, dtype=C128, device=DEV)
+    P.nufft2d_exec(plan, _t(C[:, :, 0].ravel(), C128), f2, 0)
+    assert (f3 - f2).abs().max().item() <= 8e-12 * np.abs(C).sum()
+
+
+def test_3d_rejects_nonfinite():
+    x = _t(np.array([0.1, 0.2]), torch.float64)
+    z = _t(np.array([0.1, np.nan]), torch.float64)
+    with pytest.raises(P.NufftError):
+        P.nufft3d_exec(x, x, z, _t(np.ones((2, 2, 2)), C64), 1e-6)
