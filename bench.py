@@ -316,6 +316,17 @@ def bench_type3(P, W, torch, dev):
     return out
 
 
+def bench_3d(P, W, torch, dev):
+    """3-D type II, 64^3 modes, M = 2^18 iid samples in [0, 1)^3, complex64, eps 1e-6; each call
+    plans (one 2-D plan per z slice) and transforms."""
+    rng = W.rng_for(9)
+    n, M = 64, 1 << 18
+    x, y, z = (torch.from_numpy(W.iid_samples(rng, M)).to(dev) for _ in range(3))
+    C = torch.from_numpy(W.complex_normal(rng, n ** 3).reshape(n, n, n)).to(torch.complex64).to(dev)
+    t = time_loop(lambda: P.nufft3d_exec(x, y, z, C, 1e-6), 3, 1, torch)
+    return {"modes": [n, n, n], "M": M, "ms": round(t, 3), "pts_per_s": M / (t * 1e-3)}
+
+
 def bench_solve(P, W, torch, dev):
     """Inverse type II (Sec. 3.3) at N = M = 2^20, complex64, perturbed equispaced samples
     x_j = (j + U(-1/8, 1/8))/N, f = F2 c for c complex N(0,1): CG to a residual of 1e-5."""
@@ -524,6 +535,7 @@ def main():
         out["inverse_2p20"] = bench_solve(P, W, torch, dev)
         out["oversampling_2p14_modes_2p22_samples"] = bench_oversampling(P, W, torch, dev)
         out["type3"] = bench_type3(P, W, torch, dev)
+        out["type2_3d"] = bench_3d(P, W, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, c_np, N, args.cpu_seconds)
