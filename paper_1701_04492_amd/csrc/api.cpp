@@ -213,6 +213,11 @@ nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
             p->E = (int8_t *)p->alloc((size_t)p->K * std::max(p->L1, p->L2));
             if (!p->E) return NUFFT_ERR_ALLOC;
         }
+        const int sp = pass_b_adj_splits(M, p->L2, p->L1, sizeof(R) == 4);
+        if (sp > 0) {   // partial rows of the dense-tile adjoint pass B'
+            p->Zp = p->alloc((size_t)sp * p->K * L * cs);
+            if (!p->Zp) return NUFFT_ERR_ALLOC;
+        }
         p->sinv = (int32_t *)p->alloc((size_t)M * sizeof(int32_t));
         p->gsort = p->alloc((size_t)M * cs);
         if (!p->Y || !p->sinv || !p->gsort) return NUFFT_ERR_ALLOC;
@@ -253,6 +258,7 @@ FusedArgs<R> fused_args(const Plan *p)
     a.t = p->t;
     a.X = (const R *)p->X;
     a.Y = (cx_t<R> *)p->Y;
+    a.Zp = (cx_t<R> *)p->Zp;
     a.half = sizeof(R) == 4 && (p->flags & NUFFT_FLAG_HALF_EXCHANGE) && p->L2 > 1;
     a.E = p->E;
     a.tw1 = (const cx_t<R> *)p->tw1;

@@ -178,11 +178,14 @@ static inline unsigned xcd_grid(int T) { return (unsigned)(8 * ((T + 7) / 8)); }
 // jumping (log2 NT barrier steps) instead of a walk over hundreds of slices.
 // Either way the order of the additions is fixed: the result does not depend
 // on timing.
+// load(i) returns sample i (a struct whose member n is its grid point); the
+// loads of four samples are issued together.  contrib(sample, gg) is its term
+// for grid gg; pos(i) is sample i's grid point alone.
 // Grids must be zero on entry where no sample falls; the caller synchronises
 // before reading them.  Scratch: hv, tv (RC*NT values), hix, tix, nxa, nxb (NT ints).
-template <typename C, int RC, int NT, typename PosF, typename ContribF>
-__device__ __forceinline__ void seg_spread(int cnt, int nr, PosF pos, ContribF contrib, C *grid, int pitch,
-                                           C *hv, C *tv, int *hix, int *tix, int *nxa, int *nxb)
+template <typename C, int RC, int NT, typename PosF, typename LoadF, typename ContribF>
+__device__ __forceinline__ void seg_spread(int cnt, int nr, PosF pos, LoadF load, ContribF contrib, C *grid,
+                                           int pitch, C *hv, C *tv, int *hix, int *tix, int *nxa, int *nxb)
 {
     const int tid = threadIdx.x;
     const int per = cnt / NT, rem = cnt % NT;
@@ -191,28 +194,37 @@ __device__ __forceinline__ void seg_spread(int cnt, int nr, PosF pos, ContribF c
 #pragma unroll
     for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
     int ncur = -1, nfirst = -1;
-    for (int i = i0; i < i1; ++i) {
-        const int n = pos(i);
-        if (n != ncur) {
-            if (ncur >= 0) {
-                if (ncur == nfirst) {
+    using Sample = decltype(load(0));
+    for (int i = i0; i < i1; i += 4) {
+        Sample sm[4];
 #pragma unroll
-                    for (int gg = 0; gg < RC; ++gg) hv[gg * NT + tid] = a[gg];
-                } else {
+        for (int u = 0; u < 4; ++u) sm[u] = load(min(i + u, i1 - 1));
 #pragma unroll
-                    for (int gg = 0; gg < RC; ++gg)
-                        if (gg < nr) grid[gg * pitch + lds_pad(ncur)] = a[gg];
+        for (int u = 0; u < 4; ++u) {
+            if (i + u < i1) {
+                const int n = sm[u].n;
+                if (n != ncur) {
+                    if (ncur >= 0) {
+                        if (ncur == nfirst) {
+#pragma unroll
+                            for (int gg = 0; gg < RC; ++gg) hv[gg * NT + tid] = a[gg];
+                        } else {
+#pragma unroll
+                            for (int gg = 0; gg < RC; ++gg)
+                                if (gg < nr) grid[gg * pitch + lds_pad(ncur)] = a[gg];
+                        }
+                    } else {
+                        nfirst = n;
+                    }
+#pragma unroll
+                    for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+                    ncur = n;
                 }
-            } else {
-                nfirst = n;
+#pragma unroll
+                for (int gg = 0; gg < RC; ++gg)
+                    if (gg < nr) a[gg] = cadd(a[gg], contrib(sm[u], gg));
             }
-#pragma unroll
-            for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
-            ncur = n;
         }
-#pragma unroll
-        for (int gg = 0; gg < RC; ++gg)
-            if (gg < nr) a[gg] = cadd(a[gg], contrib(i, gg));
     }
     // the last run of the slice (possibly also its first); a keeps its sum
     if (ncur >= 0) {

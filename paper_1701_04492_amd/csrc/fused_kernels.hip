@@ -674,6 +674,146 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
     }
 }
 
+// Adjoint / type-I pass B' for tiles with many more samples than grid points
+// (M >> N): task = (tile n2, slice `part` of its sorted samples), splits slices
+// per tile.  The slice's samples (up to SCAPD staged in LDS, the rest read from
+// global memory) are spread with the balanced segmented sum, so a grid point
+// holding hundreds of samples is shared by many threads; each slice's RC
+// grids are transformed and written as partial rows to Zp, which
+// k_sum_split_rows adds in slice order.
+template <typename R, int L1, int RC, int SCAPD, int dir, bool TWG>
+__global__ void __launch_bounds__(RC * L1 / 16)
+k_passB_adj_dense(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__ Xs,
+                  const uint32_t *__restrict__ keys, const int32_t *__restrict__ off, Factors<R> fac,
+                  const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
+                  int splits, cx_t<R> *__restrict__ Zp)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L1 / 16;
+    constexpr int NT = RC * TPF;
+    constexpr int P = fft_pitch(L1);
+    __shared__ C buf[RC * P];
+    __shared__ C tw_s[TWG ? 1 : L1];
+    const C *tw = TWG ? tw_g : tw_s;
+    __shared__ C sval[SCAPD];
+    __shared__ R sz[SCAPD];
+    __shared__ unsigned short spos[SCAPD];
+    __shared__ C hv[RC * NT], tv[RC * NT];
+    __shared__ int hix[NT], tix[NT], nxa[NT], nxb[NT];
+    const int task = xcd_task((int)L2 * splits);
+    if (task < 0) return;
+    const int tid = threadIdx.x;
+    if (!TWG) load_tw_s<C, L1, -1, NT>(tw_s, tw_g);   // tw_g already has the sign DIR
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t n2 = task / splits;
+    const int part = task % splits;
+    const int t_lo = off[n2 * L1], t_cnt = off[(n2 + 1) * L1] - t_lo;
+    const int base = t_lo + (int)((int64_t)t_cnt * part / splits);
+    const int cnt = t_lo + (int)((int64_t)t_cnt * (part + 1) / splits) - base;
+    const int nst = min(cnt, SCAPD);
+    for (int i = tid; i < nst; i += NT) {
+        const R xv = Xs[base + i];
+        R sn, cs;
+        sincospi_r(xv, &sn, &cs);
+        sval[i] = cmul(cmake<C>(cs, dir * sn), csort[base + i]);
+        sz[i] = xv * fac.inv_gamma;
+        spos[i] = (unsigned short)(keys[base + i] & (uint32_t)(L1 - 1));
+    }
+    C wt[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const C w = tw_big<C, -1>(hi, lo, n2 * (int64_t)(lt + q * TPF));
+        wt[q] = dir > 0 ? cconj(w) : w;
+    }
+    __syncthreads();
+    struct Sample {
+        int n;
+        C val;
+        R z;
+    };
+    auto load = [&](int i) -> Sample {
+        if (i < SCAPD) return Sample{(int)spos[i], sval[i], sz[i]};
+        const R xv = Xs[base + i];
+        R sn, cs;
+        sincospi_r(xv, &sn, &cs);
+        return Sample{(int)(keys[base + i] & (uint32_t)(L1 - 1)), cmul(cmake<C>(cs, dir * sn), csort[base + i]),
+                      xv * fac.inv_gamma};
+    };
+    auto pos = [&](int i) -> int { return load(i).n; };
+    for (int r0 = 0; r0 < fac.K; r0 += RC) {
+        const int nr = min(RC, fac.K - r0);
+        for (int m = tid; m < RC * P; m += NT) buf[m] = cmake<C>(0, 0);
+        __syncthreads();
+        RankPoly<R> up[RC];
+#pragma unroll
+        for (int gg = 0; gg < RC; ++gg) up[gg] = rank_poly(fac, min(r0 + gg, fac.K - 1));
+        // i^r for the type I, i^-r for the adjoint: a constant factor, applied after the transform
+        auto contrib = [&](const Sample &sm, int gg) -> C { return cscale(sm.val, rank_eval(up[gg], sm.z)); };
+        seg_spread<C, RC, NT>(cnt, nr, pos, load, contrib, buf, P, hv, tv, hix, tix, nxa, nxb);
+        __syncthreads();
+        block_fft_lds<C, L1, dir, fft_wave_sync<L1>>(buf + g * P, tw, lt);   // each thread then reads only its own transform
+        const int r = r0 + g;
+        if (r < fac.K) {
+            C *Zr = Zp + (((int64_t)n2 * splits + part) * fac.K + r) * L1;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k1 = lt + q * TPF;
+                Zr[k1] = crot(cmul(buf[g * P + lds_pad(k1)], wt[q]), -dir * r);
+            }
+        }
+        __syncthreads();   // the next chunk overwrites buf
+    }
+}
+
+// Rows of the adjoint pass B' whose tile was split over `splits` tasks: the
+// partial rows are added in slice order (a fixed order: deterministic) into
+// Z_r[n2][:]; with the half-precision exchange the row gets its block
+// exponent here.  Block = (n2, r), L1 <= 4096 = 256 x 16.
+template <typename R, bool H>
+__global__ void __launch_bounds__(256)
+k_sum_split_rows(const cx_t<R> *__restrict__ Zp, int splits, int K, int L1, int64_t L2, cx_t<R> *__restrict__ Z,
+                 int8_t *__restrict__ E)
+{
+    using C = cx_t<R>;
+    const int64_t n2 = blockIdx.x;
+    const int r = blockIdx.y;
+    const int64_t L = (int64_t)L1 * L2;
+    C acc[16];
+    float m = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int k1 = threadIdx.x + e * 256;
+        acc[e] = cmake<C>(0, 0);
+        if (k1 < L1) {
+            for (int q = 0; q < splits; ++q) acc[e] = cadd(acc[e], Zp[((n2 * splits + q) * K + r) * L1 + k1]);
+            if constexpr (H) m = fmaxf(m, cmaxabs(acc[e]));
+        }
+    }
+    if constexpr (H) {
+        __shared__ unsigned smax;
+        if (threadIdx.x == 0) smax = 0;
+        __syncthreads();
+        m = wave_max_group(m, 64);
+        if ((threadIdx.x & 63) == 0) atomicMax(&smax, __float_as_uint(m));
+        __syncthreads();
+        const int ex = hx_exponent(__uint_as_float(smax));
+        __half2 *Zr = reinterpret_cast<__half2 *>(Z) + (int64_t)r * L + n2 * L1;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int k1 = threadIdx.x + e * 256;
+            if (k1 < L1) Zr[k1] = hx_pack(acc[e], ex);
+        }
+        if (threadIdx.x == 0) E[(int64_t)r * L2 + n2] = (int8_t)ex;
+    } else {
+        C *Zr = Z + (int64_t)r * L + n2 * L1;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int k1 = threadIdx.x + e * 256;
+            if (k1 < L1) Zr[k1] = acc[e];
+        }
+    }
+}
+
 // Pass A' of type I / adjoint.  Task = G adjacent columns k1.  For each r the
 // columns Z_r[:][k1] (the next rank's block is loaded into registers while
 // this one is transformed) are transformed along n2 -> k2 and accumulated
@@ -783,6 +923,30 @@ static int pass_b_splits(int64_t M, int L2, int L1, int cap)
     const int64_t per = std::max<int64_t>(cap, L1);
     const int64_t want = (M + (int64_t)L2 * per - 1) / ((int64_t)L2 * per);
     return (int)std::min<int64_t>(64, std::max<int64_t>(1, want));
+}
+
+// Samples staged in LDS by one adjoint pass-B' workgroup (SCAP of the
+// instantiations below), per row length L1 and precision.
+static constexpr int pba_cap(int L1, bool fp32)
+{
+    return L1 <= 128 ? 256 : L1 == 256 ? 384 : L1 == 512 ? 768 : L1 == 1024 ? 1280 : L1 == 2048 ? 2304
+                                                                                                 : (fp32 ? 5120 : 2560);
+}
+// Samples staged per task of the dense-tile adjoint pass B' (measured: the
+// smaller staging lets two workgroups share a CU at L1 = 128).
+static constexpr int pba_dense_cap(int L1, bool fp32) { return (L1 <= 128 ? 1024 : 2048) / (fp32 ? 1 : 2); }
+
+// Dense-tile adjoint pass B': 0 (not used) while the tiles hold at most twice
+// the staging capacity of the per-grid-point walk on average; else the number
+// of slices per tile, about one dense staging load each, at most 64.  The
+// plan sizes Zp (slices x K x L partial rows) by the same rule.
+int pass_b_adj_splits(int64_t M, int L2, int L1, bool fp32)
+{
+    if (L2 <= 1) return 0;
+    const int64_t avg = M / L2;
+    if (avg <= 2 * (int64_t)pba_cap(L1, fp32)) return 0;
+    const int64_t cap = pba_dense_cap(L1, fp32);
+    return (int)std::min<int64_t>(64, std::max<int64_t>(1, (avg + cap - 1) / cap));
 }
 
 // Launches CALL with the compile-time flag HX = a.half (FP32 plans with the
@@ -991,27 +1155,41 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         const hipError_t e = fused_sort_input<R>(a, c, DIR > 0 ? "adj_sort" : "type1_sort", s);
         if (e != hipSuccess) return e;
     }
+    const int sp = pass_b_adj_splits(a.M, a.L2, a.L1, sizeof(R) == 4);
+    if (sp > 0 && !a.Zp) return hipErrorInvalidValue;   // the plan sizes Zp by the same rule
     prof_begin(a.prof, DIR > 0 ? "adj_passB" : "type1_passB", s);
     switch (a.L1) {
-#define PBA(LL, RF, SCF, RD, SCD, TG)                                                                      \
+#define PBA(LL, RF, RD, TG)                                                                                \
     case LL: {                                                                                             \
         constexpr bool F = sizeof(R) == 4;                                                                 \
-        constexpr int RR = F ? RF : RD, SC = F ? SCF : SCD;                                                \
-        HX_DISPATCH(hipLaunchKernelGGL((k_passB_adj<R, LL, RR, SC, DIR, TG, HX>), dim3(xcd_grid(a.L2)),      \
-                                       dim3(RR * LL / 16), 0, s, a.gsort, (int64_t)a.L2, a.Xs, a.keys,       \
-                                       a.off, a.fac, DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, a.Y, a.E));      \
+        constexpr int RR = F ? RF : RD, SC = pba_cap(LL, F);                                               \
+        if (sp > 0) {                                                                                      \
+            hipLaunchKernelGGL((k_passB_adj_dense<R, LL, RR, pba_dense_cap(LL, F), DIR, TG>),              \
+                               dim3(xcd_grid(a.L2 * sp)), dim3(RR * LL / 16), 0, s, a.gsort, (int64_t)a.L2,  \
+                               a.Xs, a.keys, a.off, a.fac, DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, sp, a.Zp);  \
+        } else {                                                                                           \
+            HX_DISPATCH(hipLaunchKernelGGL((k_passB_adj<R, LL, RR, SC, DIR, TG, HX>), dim3(xcd_grid(a.L2)),  \
+                                           dim3(RR * LL / 16), 0, s, a.gsort, (int64_t)a.L2, a.Xs, a.keys,   \
+                                           a.off, a.fac, DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, a.Y, a.E));  \
+        }                                                                                                  \
         break;                                                                                             \
     }
-        PBA(128, 16, 256, 8, 256, false)
-        PBA(256, 16, 384, 8, 384, false)
-        PBA(512, 8, 768, 4, 768, false)
-        PBA(1024, 4, 1280, 4, 1280, false)
-        PBA(2048, NUFFT_F32_PBA2048_RC, 2304, 2, 2304, true)
-        PBA(4096, 1, 5120, 1, 2560, true)
+        PBA(128, 16, 8, false)
+        PBA(256, 16, 8, false)
+        PBA(512, 8, 4, false)
+        PBA(1024, 4, 4, false)
+        PBA(2048, NUFFT_F32_PBA2048_RC, 2, true)
+        PBA(4096, 1, 1, true)
 #undef PBA
     default: return hipErrorInvalidValue;
     }
     prof_end(a.prof, s);
+    if (sp > 0) {
+        prof_begin(a.prof, DIR > 0 ? "adj_sum" : "type1_sum", s);
+        HX_DISPATCH(hipLaunchKernelGGL((k_sum_split_rows<R, HX>), dim3(a.L2, a.fac.K), dim3(256), 0, s,
+                                       (const cx_t<R> *)a.Zp, sp, a.fac.K, a.L1, (int64_t)a.L2, a.Y, a.E));
+        prof_end(a.prof, s);
+    }
     prof_begin(a.prof, DIR > 0 ? "adj_passA" : "type1_passA", s);
     switch (a.L2) {
 #define PAA(LL, GG)                                                                                        \

@@ -138,6 +138,7 @@ struct FusedArgs {
     const int32_t *t;        // M grid indices, sample order
     const R *X;              // M perturbations, sample order
     cx_t<R> *Y;              // K x L intermediate of the two-pass split
+    cx_t<R> *Zp;             // partial rows of the dense-tile adjoint pass B' (else null)
     int half;                // FP32 only: Y in fp16 pairs with block exponents E (half-precision exchange)
     int8_t *E;               // K x max(L1, L2) block exponents of the half-precision exchange
     const cx_t<R> *tw1, *tw2, *hi, *lo;
@@ -154,6 +155,8 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
 // sign -1: f = F2^T c (type I); sign +1: f = F2^H c (adjoint)
 template <typename R>
 hipError_t fused_type1(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int sign, hipStream_t s);
+// slices per tile of the dense-tile adjoint pass B' (0: not used; tiles of about M / L2 samples)
+int pass_b_adj_splits(int64_t M, int L2, int L1, bool fp32);
 // a sample-ordered M-vector into a.gsort (two-pass plans); `name` labels it for the profiler
 template <typename R>
 hipError_t fused_sort_input(const FusedArgs<R> &a, const cx_t<R> *in, const char *name, hipStream_t s);

@@ -273,11 +273,17 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
             RankPoly<R> ux[RC];
 #pragma unroll
             for (int gg = 0; gg < RC; ++gg) ux[gg] = rank_poly(fx, min(r0 + gg, fx.K - 1));
-            auto contrib = [&](int i, int gg) -> C {
-                // i^(r1 + r2) for the type I, i^-(r1 + r2) for the adjoint
-                return crot(cscale(sval[i], rank_eval(ux[gg], szx[i]) * spy[i]), -DIR * (r0 + gg + r2));
+            struct Sample {
+                int n;
+                C w;   // exp(DIR i pi (Xx + Xy)) g_j P^y_r2(zy_j)
+                R zx;
             };
-            seg_spread<C, RC, NT>(cnt, nr, pos, contrib, buf, P, hv, tv, hix, tix, nxa, nxb);
+            auto load = [&](int i) -> Sample { return Sample{(int)spos[i], cscale(sval[i], spy[i]), szx[i]}; };
+            auto contrib = [&](const Sample &sm, int gg) -> C {
+                // i^(r1 + r2) for the type I, i^-(r1 + r2) for the adjoint
+                return crot(cscale(sm.w, rank_eval(ux[gg], sm.zx)), -DIR * (r0 + gg + r2));
+            };
+            seg_spread<C, RC, NT>(cnt, nr, pos, load, contrib, buf, P, hv, tv, hix, tix, nxa, nxb);
             __syncthreads();
             block_fft_lds<C, GX, DIR, fft_wave_sync<GX>>(buf + g * P, tw, lt);
             fft_publish<GX>();

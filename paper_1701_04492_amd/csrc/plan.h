@@ -57,7 +57,7 @@ struct nufft_plan_s {
     int ntasks = 0;
     int4 *atasks = nullptr, *rtasks = nullptr;   // adjoint pass-B' tasks, split columns
     int natasks = 0, nrtasks = 0;
-    void *Zp = nullptr;                          // partial rows of split columns
+    void *Zp = nullptr;                          // partial rows: split 2-D columns, or dense 1-D adjoint tiles
     void *twx = nullptr, *twxi = nullptr, *twy = nullptr, *twyi = nullptr;
 
     // batch plans: member plans are the children
