@@ -34,7 +34,7 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 
 // ---- SMALL: whole transform in LDS, samples [chunk * BNT * BSLOTS, ...) -----------------
 template <typename R, int L>
-__device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx_t<R> *__restrict__ f, int chunk,
+__device__ __forceinline__ void b_small_body(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx_t<R> *__restrict__ f, int chunk,
                         char *lds)
 {
     using C = cx_t<R>;
@@ -69,7 +69,7 @@ __device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx
         for (int q = 0; q < 16; ++q)
             v[q] = r < K ? cscale(v[q], cheb_v<R>(r, zcoord<R>(lt + q * TPF, zm))) : cmake<C>(0, 0);
         __syncthreads();
-        block_fft_regs<C, L, -1, fft_wave_sync<L>>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L, -1, fft_wave_sync<L>>(buf + g * P, tw, lt, v, r < K);   // idle rank slots skip
         fft_publish<L>();
         const int nr = min(RC, K - r0);
         for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
@@ -96,7 +96,7 @@ __device__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx
 
 // ---- PASS_A: G = 4096 / L2 adjacent columns, all K ranks -------------------------------
 template <typename R, int L2>
-__device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, int cg, char *lds)
+__device__ __forceinline__ void b_passA_body(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, int cg, char *lds)
 {
     using C = cx_t<R>;
     constexpr int TPF = L2 / 16;
@@ -156,7 +156,7 @@ __device__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, in
 
 // ---- PASS_B: one tile n2, RC = 4096 / L1 ranks side by side ------------------------------
 template <typename R, int L1, int S>
-__device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2_first, int n2_count, char *lds)
+__device__ __forceinline__ void b_passB_body(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2_first, int n2_count, char *lds)
 {
     using C = cx_t<R>;
     constexpr int TPF = L1 / 16;
@@ -201,7 +201,7 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2_f
                 for (int q = 0; q < 16; ++q) vn[q] = rn < K ? Yrow[(int64_t)rn * L + q * TPF] : cmake<C>(0, 0);
             }
             __syncthreads();
-            block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v);
+            block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v, r0 + g < K);   // idle slots skip
             fft_publish<L1>();
             const int nr = min(RC, K - r0);
             for (int gg = 0; gg < nr; ++gg) {   // rank outer (coefficients loaded once), samples inner
@@ -228,6 +228,26 @@ __device__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2_f
         __syncthreads();
     }
     }
+}
+
+// The persistent kernel calls the task bodies as functions (inlining all of
+// them into one kernel spills); the phased kernels inline the one they run.
+template <typename R, int L>
+__device__ __noinline__ void b_small(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, cx_t<R> *__restrict__ f,
+                                     int chunk, char *lds)
+{
+    b_small_body<R, L>(d, c, f, chunk, lds);
+}
+template <typename R, int L2>
+__device__ __noinline__ void b_passA(const BatchDesc<R> &d, const cx_t<R> *__restrict__ c, int cg, char *lds)
+{
+    b_passA_body<R, L2>(d, c, cg, lds);
+}
+template <typename R, int L1, int S>
+__device__ __noinline__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict__ f, int n2_first, int n2_count,
+                                     char *lds)
+{
+    b_passB_body<R, L1, S>(d, f, n2_first, n2_count, lds);
 }
 
 template <typename R>
@@ -329,21 +349,21 @@ k_batch_phase(const BatchDesc<R> *__restrict__ descs, const int4 *__restrict__ t
     const BatchDesc<R> &d = descs[b];
     if constexpr (TYPE == BATCH_SMALL) {
         switch (d.L) {
-#define BS(LL) case LL: b_small<R, LL>(d, cs[b], fs[b], par, lds); break;
+#define BS(LL) case LL: b_small_body<R, LL>(d, cs[b], fs[b], par, lds); break;
             BS(16) BS(32) BS(64) BS(128) BS(256) BS(512) BS(1024) BS(2048) BS(4096)
 #undef BS
         default: break;
         }
     } else if constexpr (TYPE == BATCH_PASS_A) {
         switch (d.L2) {
-#define BA(LL) case LL: b_passA<R, LL>(d, cs[b], par, lds); break;
+#define BA(LL) case LL: b_passA_body<R, LL>(d, cs[b], par, lds); break;
             BA(64) BA(128) BA(256) BA(512) BA(1024)
 #undef BA
         default: break;
         }
     } else {
         switch (d.L1) {
-#define BB(LL, SS) case LL: b_passB<R, LL, SS>(d, fs[b], par, par2, lds); break;
+#define BB(LL, SS) case LL: b_passB_body<R, LL, SS>(d, fs[b], par, par2, lds); break;
             BB(128, 1) BB(256, 2) BB(512, 3) BB(1024, 5)
 #undef BB
         default: break;

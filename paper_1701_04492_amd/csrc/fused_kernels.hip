@@ -74,7 +74,7 @@ k_small_fwd(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, const int32_t *
 #pragma unroll
         for (int q = 0; q < 16; ++q) v[q] = r < fac.K ? cscale(v[q], wq[q]) : cmake<C>(0, 0);
         __syncthreads();   // previous gather finished with buf
-        block_fft_regs<C, L, -1, fft_wave_sync<L>>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L, -1, fft_wave_sync<L>>(buf + g * P, tw, lt, v, r < fac.K);   // idle rank slots skip
         fft_publish<L>();
         const int nr = min(RC, fac.K - r0);
         // rank outer (coefficients loaded once), samples inner
@@ -161,7 +161,7 @@ k_small_adj(const cx_t<R> *__restrict__ c, int64_t N, int64_t M, int64_t span,
             v[q] = a;
         }
         __syncthreads();
-        block_fft_regs<C, L, DIR, fft_wave_sync<L>>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L, DIR, fft_wave_sync<L>>(buf + g * P, tw, lt, v, r < fac.K);   // idle rank slots skip
         fft_publish<L>();
         const int nr = min(RC, fac.K - r0);
         // T_{r0 + gg} for the consecutive ranks of the chunk by the recurrence
