@@ -14,6 +14,7 @@
  *   adjoint   f_k = sum_j c_j exp(+2 pi i x_j k)           (conjugate transpose of II)
  *   type III  f_j = sum_k c_k exp(-2 pi i x_j w_k)          (Sec. 3.2)
  *   2-D II    f_j = sum_{k1,k2} C_{k1 k2} exp(-2 pi i (k1 x_j + k2 y_j))  (Sec. 4, first display)
+ *   3-D II, I and adjoint: the same with a third axis (k3, z_j)
  * and the nearest-grid assignment of Sec. 2.2 (s = round(N x), t = s mod N).
  *
  * Two things keep the sums accurate to a few units in the last place:
@@ -252,6 +253,35 @@ int oracle_nudft3d(int64_t N1, int64_t N2, int64_t N3, const double *C, int64_t 
         }
         f[2 * j] = re.s + re.t;
         f[2 * j + 1] = im.s + im.t;
+    }
+    return 0;
+}
+
+/* Adjoint (sign = +1) or type I (sign = -1, the transpose) of the 3-D type II at the
+ * requested coefficient indices:
+ *   out_q = sum_{j<M} g_j exp(sign 2 pi i (k1_q x_j + k2_q y_j + k3_q z_j)). */
+int oracle_nudft3d_adj(int64_t M, const double *x, const double *y, const double *z, const double *g,
+                       int64_t nq, const int64_t *k1, const int64_t *k2, const int64_t *k3, int sign,
+                       double *out)
+{
+    if (M < 0 || nq < 0 || (sign != 1 && sign != -1)) return -1;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < nq; ++q) {
+        acc2 re = {0.0, 0.0}, im = {0.0, 0.0};
+        for (int64_t j = 0; j < M; ++j) {
+            double phi = phase_mod1(x[j], (double)k1[q]) + phase_mod1(y[j], (double)k2[q])
+                         + phase_mod1(z[j], (double)k3[q]);
+            double co, si;
+            cis2pi(phi - nearbyint(phi), &co, &si);
+            si *= (double)sign;
+            double gr = g[2 * j], gi = g[2 * j + 1];
+            acc2_add_prod(&re, gr, co);
+            acc2_add_prod(&re, -gi, si);
+            acc2_add_prod(&im, gr, si);
+            acc2_add_prod(&im, gi, co);
+        }
+        out[2 * q] = re.s + re.t;
+        out[2 * q + 1] = im.s + im.t;
     }
     return 0;
 }

@@ -29,6 +29,7 @@ def _load():
         lib.oracle_nudft2d_adj.argtypes = [_i64, _dp, _dp, _dp, _i64, _ip, _ip, ctypes.c_int, _dp]
         lib.oracle_nudft3_2d.argtypes = [_i64, _dp, _dp, _dp, _i64, _dp, _dp, _dp]
         lib.oracle_nudft3d.argtypes = [_i64, _i64, _i64, _dp, _i64, _dp, _dp, _dp, _dp]
+        lib.oracle_nudft3d_adj.argtypes = [_i64, _dp, _dp, _dp, _dp, _i64, _ip, _ip, _ip, ctypes.c_int, _dp]
         lib.oracle_grid_assign.argtypes = [_i64, _i64, _dp, _ip, _ip, _dp]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
@@ -104,6 +105,18 @@ def nudft3d(x, y, z, C):
                                 _p(f.view(np.float64)))
     assert rc == 0
     return f
+
+
+def nudft3d_adj(x, y, z, g, k1, k2, k3, sign=+1):
+    """Adjoint of the 3-D type II (sign=+1), or the 3-D type I, its transpose (sign=-1), at
+    coefficient indices (k1_q, k2_q, k3_q): out_q = sum_j g_j exp(sign 2 pi i (k1_q x_j + k2_q y_j + k3_q z_j))."""
+    x, y, z, g = _f64(x), _f64(y), _f64(z), _c128(g)
+    k1, k2, k3 = (np.ascontiguousarray(k, dtype=np.int64) for k in (k1, k2, k3))
+    out = np.empty(k1.shape[0], np.complex128)
+    rc = _load().oracle_nudft3d_adj(x.shape[0], _p(x), _p(y), _p(z), _p(g.view(np.float64)), k1.shape[0],
+                                    _pi(k1), _pi(k2), _pi(k3), int(sign), _p(out.view(np.float64)))
+    assert rc == 0
+    return out
 
 
 def nudft3_2d(x, y, w1, w2, c):

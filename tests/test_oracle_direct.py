@@ -153,6 +153,51 @@ def test_3d_vs_mpmath_and_separable():
     assert np.abs(D.nudft3d(x, y, z, C1) - D.nudft2d(x, y, C1[:, :, 0])).max() <= 1e-14 * np.abs(C1).sum()
 
 
+@pytest.mark.parametrize("sign", [-1, +1])
+def test_3d_type1_and_adjoint_vs_mpmath(sign):
+    rng = np.random.default_rng(21)
+    M = 6
+    x, y, z = rng.random(M) * 2 - 0.5, rng.random(M), rng.random(M) * 3
+    g = _rand(rng, M)
+    k1, k2, k3 = np.array([0, 2, 1, 3]), np.array([0, 1, 3, 2]), np.array([0, 1, 2, 4])
+    a = D.nudft3d_adj(x, y, z, g, k1, k2, k3, sign=sign)
+    for q in range(4):
+        ph = [sign * (mpmath.mpf(x[j]) * int(k1[q]) + mpmath.mpf(y[j]) * int(k2[q]) + mpmath.mpf(z[j]) * int(k3[q]))
+              for j in range(M)]
+        assert abs(a[q] - _mp_sum(ph, g)) <= 4e-16 * np.abs(g).sum()
+
+
+def test_3d_type1_transpose_adjoint_and_separable():
+    """sum_j g_j (F C)_j = sum_k C_k (F^T g)_k and <g, F C> = <F^H g, C> against the 3-D
+    type II; samples on a product grid with a product weight give the product of three
+    1-D type Is; one z mode at z = 0 gives the 2-D type I."""
+    rng = np.random.default_rng(22)
+    n1, n2, n3, M = 4, 3, 5, 29
+    x, y, z = rng.random(M) * 3 - 1, rng.random(M), rng.random(M)
+    C = _rand(rng, n1 * n2 * n3).reshape(n1, n2, n3)
+    g = _rand(rng, M)
+    K1, K2, K3 = (k.ravel() for k in np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3), indexing="ij"))
+    f = D.nudft3d(x, y, z, C)
+    t1 = D.nudft3d_adj(x, y, z, g, K1, K2, K3, sign=-1)
+    ad = D.nudft3d_adj(x, y, z, g, K1, K2, K3, sign=+1)
+    scale = np.abs(C).sum() * np.abs(g).sum()
+    assert abs(np.sum(g * f) - np.sum(C.ravel() * t1)) <= 1e-14 * scale
+    assert abs(np.vdot(g, f) - np.vdot(ad, C.ravel())) <= 1e-14 * scale
+    assert np.abs(t1 - ad).max() > 1e-2
+    xa, yb, zc = rng.random(3), rng.random(4) * 2, rng.random(2) - 0.5
+    wa, wb, wc = _rand(rng, 3), _rand(rng, 4), _rand(rng, 2)
+    X, Y, Z = (v.ravel() for v in np.meshgrid(xa, yb, zc, indexing="ij"))
+    W = np.einsum("i,j,k->ijk", wa, wb, wc).ravel()
+    for sign in (-1, +1):
+        got = D.nudft3d_adj(X, Y, Z, W, K1, K2, K3, sign=sign).reshape(n1, n2, n3)
+        ref = np.einsum("i,j,k->ijk", D.nudft1(xa, wa, n1, sign=sign), D.nudft1(yb, wb, n2, sign=sign),
+                        D.nudft1(zc, wc, n3, sign=sign))
+        assert np.abs(got - ref).max() <= 1e-14 * np.abs(W).sum()
+    k1, k2 = np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")
+    got = D.nudft3d_adj(x, y, np.zeros(M), g, k1.ravel(), k2.ravel(), np.zeros(n1 * n2, np.int64), sign=+1)
+    assert np.abs(got - D.nudft2d_adj(x, y, g, k1.ravel(), k2.ravel(), sign=+1)).max() <= 1e-14 * np.abs(g).sum()
+
+
 def test_large_phase_exact_reduction():
     """At k ~ 2^20 a plain fl(x*k) loses ~1e-10 of phase; the oracle must not."""
     rng = np.random.default_rng(14)
