@@ -317,14 +317,18 @@ def bench_type3(P, W, torch, dev):
 
 
 def bench_3d(P, W, torch, dev):
-    """3-D type II, 64^3 modes, M = 2^18 iid samples in [0, 1)^3, complex64, eps 1e-6; each call
-    plans (one 2-D plan per z slice) and transforms."""
+    """3-D type II and type I, 64^3 modes, M = 2^18 iid samples in [0, 1)^3, complex64, eps 1e-6;
+    each call plans (one 2-D plan per z slice) and transforms."""
     rng = W.rng_for(9)
     n, M = 64, 1 << 18
     x, y, z = (torch.from_numpy(W.iid_samples(rng, M)).to(dev) for _ in range(3))
     C = torch.from_numpy(W.complex_normal(rng, n ** 3).reshape(n, n, n)).to(torch.complex64).to(dev)
     t = time_loop(lambda: P.nufft3d_exec(x, y, z, C, 1e-6), 3, 1, torch)
-    return {"modes": [n, n, n], "M": M, "ms": round(t, 3), "pts_per_s": M / (t * 1e-3)}
+    c = torch.from_numpy(W.complex_normal(rng, M)).to(torch.complex64).to(dev)
+    Cout = torch.empty((n, n, n), dtype=torch.complex64, device=dev)
+    t1 = time_loop(lambda: P.nufft3d_type1_exec(x, y, z, c, (n, n, n), 1e-6, sign=-1, C=Cout), 3, 1, torch)
+    return {"modes": [n, n, n], "M": M, "ms": round(t, 3), "pts_per_s": M / (t * 1e-3),
+            "type1_ms": round(t1, 3)}
 
 
 def bench_solve(P, W, torch, dev):

@@ -224,7 +224,7 @@ nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_d
                            const double *w1_dev, const double *w2_dev, int64_t n1, int64_t n2,
                            const void *c_dev, void *f_dev, double eps, nufft_dtype dtype, void *stream);
 
-/* ---- 3-D type II --------------------------------------------------------- */
+/* ---- 3-D type II, type I and adjoint ---------------------------------------- */
 
 /* 3-D type II (Sec. 4's construction with a third axis):
  *   f_dev[j] ~ sum_{k1<n1,k2<n2,k3<n3} C_dev[(k1*n2+k2)*n3+k3] exp(-2 pi i (k1 x_j + k2 y_j + k3 z_j)).
@@ -237,6 +237,19 @@ nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_d
 nufft_status nufft3d_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev,
                           int64_t n1, int64_t n2, int64_t n3, const void *C_dev, void *f_dev, double eps,
                           nufft_dtype dtype, void *stream);
+
+/* 3-D type I (sign = -1, the transpose of the 3-D type II) or adjoint (sign = +1):
+ *   C_dev[(k1*n2+k2)*n3+k3] ~ sum_{j<M} c_dev[j] exp(sign 2 pi i (k1 x_j + k2 y_j + k3 z_j)),
+ * k1 < n1, k2 < n2, k3 < n3.  x_dev, y_dev, z_dev: M doubles each, any finite reals;
+ * c_dev: M complex; C_dev: n1*n2*n3 complex, row-major, overwritten.  The factoring of
+ * nufft3d_exec run backwards: the samples weighted by u^z_r (or its conjugate), a
+ * 2-D type I per z slice, and one length-Gz transform per (k1, k2) and rank.  Error
+ * ~ eps * ||c||_1 per output.  Plans, allocates and synchronises internally (not
+ * graph capturable); INVALID_ARG for sign not in {-1, +1}, NONFINITE for a
+ * non-finite z. */
+nufft_status nufft3d_type1_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev,
+                                int64_t n1, int64_t n2, int64_t n3, const void *c_dev, void *C_dev, int sign,
+                                double eps, nufft_dtype dtype, void *stream);
 
 /* ---- batches of independent 1-D type II transforms ---------------------- */
 

@@ -46,6 +46,7 @@ _sig = {
     "nufft3_exec": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
     "nufft2d3_exec": [_i64, _vp, _vp, _i64, _vp, _vp, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
     "nufft3d_exec": [_i64, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
+    "nufft3d_type1_exec": [_i64, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _int, _dbl, _int, _vp],
     "nufft2d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _dbl, _int, _u32, _vp],
     "nufft2d_exec": [_vp, _vp, _vp, _int, _vp],
     "nufft2d_type1_exec": [_vp, _vp, _vp, _int, _vp],
@@ -249,6 +250,20 @@ def nufft3d_exec(x, y, z, C, eps, f=None):
                             _dev_tensor(Cf, C.dtype, n1 * n2 * n3, "C"), _dev_tensor(f, C.dtype, M, "f"),
                             float(eps), _cdtype(C.dtype), _stream(C.device)), "nufft3d_exec")
     return f
+
+
+def nufft3d_type1_exec(x, y, z, c, shape, eps, sign=-1, C=None):
+    """3-D type I (sign=-1) or adjoint (sign=+1):
+    C[k1,k2,k3] = sum_j c_j exp(sign 2 pi i (k1 x_j + k2 y_j + k3 z_j)), shape = (n1, n2, n3)."""
+    M = x.numel()
+    n1, n2, n3 = (int(v) for v in shape)
+    if C is None:
+        C = torch.empty((n1, n2, n3), dtype=c.dtype, device=c.device)
+    _check(lib.nufft3d_type1_exec(M, _dev_tensor(x, torch.float64, M, "x"), _dev_tensor(y, torch.float64, M, "y"),
+                                  _dev_tensor(z, torch.float64, M, "z"), n1, n2, n3,
+                                  _dev_tensor(c, c.dtype, M, "c"), _dev_tensor(C, c.dtype, n1 * n2 * n3, "C"),
+                                  int(sign), float(eps), _cdtype(c.dtype), _stream(c.device)), "nufft3d_type1_exec")
+    return C
 
 
 def nufft2d_plan(x, y, n1, n2, eps, dtype=torch.complex64, flags=0):

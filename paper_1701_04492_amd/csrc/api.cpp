@@ -909,40 +909,49 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
     }
     return NUFFT_OK;
 }
-// 3-D type II: the z axis factored as in Sec. 2.1-2.2 (rank K3 on a grid of Gz
-// points), one length-Gz FFT per (k1, k2) and rank, and for each z slice of
-// the samples one 2-D type II (Sec. 4) of that slice of the transformed
-// coefficients; the composition is stated with the kernels.  Half of eps goes
-// to the z factorisation, half to the 2-D transforms, whose errors are
-// weighted by sum_r |u^z_r| w_r <= sum_{p,r} w_p w_r |b_pr|.
+// 3-D transforms: the z axis factored as in Sec. 2.1-2.2 (rank K3 on a grid of
+// Gz points), one length-Gz FFT per (k1, k2) and rank, and for each z slice of
+// the samples one 2-D transform (Sec. 4) of that slice; the compositions are
+// stated with the kernels.  Half of eps goes to the z factorisation, half to
+// the 2-D transforms, whose errors are weighted by
+// sum_r |u^z_r| w_r <= sum_{p,r} w_p w_r |b_pr| (the same bound serves type I,
+// whose inner inputs are u^z_r c or its conjugate).
 template <typename R>
-static nufft_status type2_3d(int64_t M, const double *x, const double *y, const double *z, int64_t n1, int64_t n2,
-                             int64_t n3, const void *Cin, void *f, double eps, nufft_dtype dt, hipStream_t s)
+struct Slices3D {
+    int64_t Gz = 0, rows = 0;
+    int K3 = 0;
+    Factors<R> fz;
+    int32_t *perm = nullptr;      // slice-sorted order -> sample index
+    R *Xs = nullptr;              // z perturbations in slice order
+    std::vector<int32_t> off;     // slice m holds sorted samples [off[m], off[m+1])
+    std::vector<Plan *> sl;       // 2-D plan of each non-empty slice
+    cx_t<R> *D = nullptr;         // Gz x rows, slice-major
+    void *tw = nullptr;           // length-Gz twiddles, -1 direction
+};
+
+template <typename R>
+static nufft_status setup_3d(Plan &tmp, int64_t M, const double *x, const double *y, const double *z, int64_t n1,
+                             int64_t n2, int64_t n3, double eps, nufft_dtype dt, hipStream_t s, Slices3D<R> &o)
 {
     using C = cx_t<R>;
-    Plan tmp;   // owns the temporaries and the slice plans
-    struct SyncGuard {   // destroyed before tmp: no temporary is freed under a running kernel
-        hipStream_t s;
-        ~SyncGuard() { (void)hipStreamSynchronize(s); }
-    } guard{s};
     int64_t Gz = 16;
     while (Gz < n3) Gz <<= 1;
     int gx = 16, gy = 16;
     while (gx < n1) gx <<= 1;
     while (gy < n2) gy <<= 1;
     if (Gz > 1024 || gx > 2048 || gy > 2048) return NUFFT_ERR_UNSUPPORTED;
-    const int64_t rows = n1 * n2;
+    o.Gz = Gz;
+    o.rows = n1 * n2;
     int32_t *tz = (int32_t *)tmp.alloc(M * sizeof(int32_t));
     R *X = (R *)tmp.alloc(M * sizeof(R));
-    R *Xs = (R *)tmp.alloc(M * sizeof(R));
-    int32_t *perm = (int32_t *)tmp.alloc(M * sizeof(int32_t));
+    o.Xs = (R *)tmp.alloc(M * sizeof(R));
+    o.perm = (int32_t *)tmp.alloc(M * sizeof(int32_t));
     double *xs = (double *)tmp.alloc(M * sizeof(double));
     double *ys = (double *)tmp.alloc(M * sizeof(double));
     double *zs = (double *)tmp.alloc(M * sizeof(double));
     unsigned long long *flags = (unsigned long long *)tmp.alloc(2 * sizeof(unsigned long long));
-    C *fs = (C *)tmp.alloc(M * sizeof(C));
-    C *D = (C *)tmp.alloc(Gz * rows * sizeof(C));
-    if (!tz || !X || !Xs || !perm || !xs || !ys || !zs || !flags || !fs || !D) return NUFFT_ERR_ALLOC;
+    o.D = (C *)tmp.alloc(Gz * o.rows * sizeof(C));
+    if (!tz || !X || !o.Xs || !o.perm || !xs || !ys || !zs || !flags || !o.D) return NUFFT_ERR_ALLOC;
     // z assignment, gamma_z, and the samples grouped by z slice (a stable counting sort)
     NUFFT_HIP_CHECK(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), s));
     NUFFT_HIP_CHECK(launch_3d_assign<R>(z, M, n3, Gz, tz, X, flags, (int *)(flags + 1), s));
@@ -955,30 +964,31 @@ static nufft_status type2_3d(int64_t M, const double *x, const double *y, const 
     double gz;
     std::memcpy(&gz, &h[0], sizeof(double));
     gz = std::min(gz, 0.5);
-    std::vector<int32_t> off(Gz + 1, 0), ph(M);
+    std::vector<int32_t> &off = o.off, ph(M);
+    off.assign(Gz + 1, 0);
     for (int64_t j = 0; j < M; ++j) ++off[th[j] + 1];
     for (int64_t m = 0; m < Gz; ++m) off[m + 1] += off[m];
     {
         std::vector<int32_t> pos(off.begin(), off.end() - 1);
         for (int64_t j = 0; j < M; ++j) ph[pos[th[j]]++] = (int32_t)j;
     }
-    NUFFT_HIP_CHECK(hipMemcpyAsync(perm, ph.data(), M * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    NUFFT_HIP_CHECK(launch_3d_gather(x, perm, M, xs, s));
-    NUFFT_HIP_CHECK(launch_3d_gather(y, perm, M, ys, s));
-    NUFFT_HIP_CHECK(launch_3d_gather(z, perm, M, zs, s));
-    NUFFT_HIP_CHECK(launch_3d_assign<R>(zs, M, n3, Gz, tz, Xs, flags, (int *)(flags + 1), s));   // X in slice order
-    const int K3 = choose_rank(eps / 2.0, gz);
-    if (K3 < 0 || (sizeof(R) == 4 && K3 > NUFFT_KMAX_F32)) return NUFFT_ERR_UNSUPPORTED;
-    Factors<R> fz;
-    fill_factors(fz, gz, K3);
+    NUFFT_HIP_CHECK(hipMemcpyAsync(o.perm, ph.data(), M * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    NUFFT_HIP_CHECK(launch_3d_gather(x, o.perm, M, xs, s));
+    NUFFT_HIP_CHECK(launch_3d_gather(y, o.perm, M, ys, s));
+    NUFFT_HIP_CHECK(launch_3d_gather(z, o.perm, M, zs, s));
+    NUFFT_HIP_CHECK(launch_3d_assign<R>(zs, M, n3, Gz, tz, o.Xs, flags, (int *)(flags + 1), s));   // slice order
+    o.K3 = choose_rank(eps / 2.0, gz);
+    if (o.K3 < 0 || (sizeof(R) == 4 && o.K3 > NUFFT_KMAX_F32)) return NUFFT_ERR_UNSUPPORTED;
+    fill_factors(o.fz, gz, o.K3);
     double b[NUFFT_KMAX * NUFFT_KMAX], S = 0.0;
-    bessel_b(gz, K3, b);
-    for (int p = 0; p < K3; ++p)
-        for (int r = 0; r < K3; ++r) S += (p == 0 ? 0.5 : 1.0) * (r == 0 ? 0.5 : 1.0) * std::fabs(b[p * K3 + r]);
+    bessel_b(gz, o.K3, b);
+    for (int p = 0; p < o.K3; ++p)
+        for (int r = 0; r < o.K3; ++r)
+            S += (p == 0 ? 0.5 : 1.0) * (r == 0 ? 0.5 : 1.0) * std::fabs(b[p * o.K3 + r]);
     const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
     const double eps2 = std::max(floor_eps, eps / (2.0 * std::max(S, 1.0)));
-    // one 2-D type-II plan per non-empty z slice, on that slice's samples
-    std::vector<Plan *> sl(Gz, nullptr);
+    // one 2-D plan per non-empty z slice, on that slice's samples
+    o.sl.assign(Gz, nullptr);
     for (int64_t m = 0; m < Gz; ++m) {
         const int64_t cnt = off[m + 1] - off[m];
         if (cnt == 0) continue;
@@ -989,7 +999,7 @@ static nufft_status type2_3d(int64_t M, const double *x, const double *y, const 
         q->dtype = dt;
         q->N1 = n1;
         q->N2 = n2;
-        q->N = rows;
+        q->N = o.rows;
         q->M = cnt;
         q->eps = eps2;
         q->Gx = gx;
@@ -997,18 +1007,63 @@ static nufft_status type2_3d(int64_t M, const double *x, const double *y, const 
         q->L = (int64_t)gx * gy;
         const nufft_status st = build_2d<R>(q, xs + off[m], ys + off[m], s);
         if (st) return st;
-        sl[m] = q;
+        o.sl[m] = q;
     }
     std::vector<double> t(2 * (size_t)Gz);
     fft_twiddles(Gz, -1, t.data());
-    void *tw = nullptr;
-    nufft_status st = upload_table<R>(&tmp, t, &tw, s);
+    return upload_table<R>(&tmp, t, &o.tw, s);
+}
+
+struct StreamSyncGuard {   // declared after the Plan that owns the temporaries: no temporary is freed under a running kernel
+    hipStream_t s;
+    ~StreamSyncGuard() { (void)hipStreamSynchronize(s); }
+};
+
+// 3-D type II: f = sum_r u^z_r * [2-D type II of slice t^z_j of D_r]
+template <typename R>
+static nufft_status type2_3d(int64_t M, const double *x, const double *y, const double *z, int64_t n1, int64_t n2,
+                             int64_t n3, const void *Cin, void *f, double eps, nufft_dtype dt, hipStream_t s)
+{
+    using C = cx_t<R>;
+    Plan tmp;   // owns the temporaries and the slice plans
+    StreamSyncGuard guard{s};
+    Slices3D<R> o;
+    nufft_status st = setup_3d<R>(tmp, M, x, y, z, n1, n2, n3, eps, dt, s, o);
     if (st) return st;
-    for (int r = 0; r < K3; ++r) {
-        NUFFT_HIP_CHECK(launch_3d_zfft<R>((const C *)Cin, rows, n3, Gz, r, (const C *)tw, D, s));
-        for (int64_t m = 0; m < Gz; ++m)
-            if (sl[m]) NUFFT_HIP_CHECK(fused_2d<R>(args_2d<R>(sl[m]), D + m * rows, fs + off[m], s));
-        NUFFT_HIP_CHECK(launch_3d_accum<R>(fs, perm, Xs, M, fz, r, (C *)f, s));
+    C *fs = (C *)tmp.alloc(M * sizeof(C));
+    if (!fs) return NUFFT_ERR_ALLOC;
+    for (int r = 0; r < o.K3; ++r) {
+        NUFFT_HIP_CHECK(launch_3d_zfft<R>((const C *)Cin, o.rows, n3, o.Gz, r, (const C *)o.tw, o.D, s));
+        for (int64_t m = 0; m < o.Gz; ++m)
+            if (o.sl[m]) NUFFT_HIP_CHECK(fused_2d<R>(args_2d<R>(o.sl[m]), o.D + m * o.rows, fs + o.off[m], s));
+        NUFFT_HIP_CHECK(launch_3d_accum<R>(fs, o.perm, o.Xs, M, o.fz, r, (C *)f, s));
+    }
+    return NUFFT_OK;
+}
+
+// 3-D type I (sign -1) / adjoint (sign +1): C = sum_r v^z_r * z-DFT over the slices
+// of [2-D type I of slice m, weighted by w_r c]
+template <typename R>
+static nufft_status type1_3d(int64_t M, const double *x, const double *y, const double *z, int64_t n1, int64_t n2,
+                             int64_t n3, const void *c, void *Cout, int sign, double eps, nufft_dtype dt,
+                             hipStream_t s)
+{
+    using C = cx_t<R>;
+    Plan tmp;
+    StreamSyncGuard guard{s};
+    Slices3D<R> o;
+    nufft_status st = setup_3d<R>(tmp, M, x, y, z, n1, n2, n3, eps, dt, s, o);
+    if (st) return st;
+    C *cw = (C *)tmp.alloc(M * sizeof(C));
+    if (!cw) return NUFFT_ERR_ALLOC;
+    for (int64_t m = 0; m < o.Gz; ++m)   // empty slices contribute zero
+        if (!o.sl[m]) NUFFT_HIP_CHECK(hipMemsetAsync(o.D + m * o.rows, 0, o.rows * sizeof(C), s));
+    for (int r = 0; r < o.K3; ++r) {
+        NUFFT_HIP_CHECK(launch_3d_weight<R>((const C *)c, o.perm, o.Xs, M, o.fz, r, sign, cw, s));
+        for (int64_t m = 0; m < o.Gz; ++m)
+            if (o.sl[m])
+                NUFFT_HIP_CHECK(fused_2d_adj<R>(args_2d<R>(o.sl[m]), cw + o.off[m], o.D + m * o.rows, sign, s));
+        NUFFT_HIP_CHECK(launch_3d_zfft_t<R>(o.D, o.rows, n3, o.Gz, r, sign, (const C *)o.tw, (C *)Cout, s));
     }
     return NUFFT_OK;
 }
@@ -1292,6 +1347,23 @@ nufft_status nufft3d_exec(int64_t n_pts, const double *x_dev, const double *y_de
     hipStream_t s = (hipStream_t)stream;
     st = dtype == NUFFT_C64 ? type2_3d<float>(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, C, f, eps, dtype, s)
                             : type2_3d<double>(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, C, f, eps, dtype, s);
+    if (st != NUFFT_OK) (void)hipStreamSynchronize(s);
+    return st;
+}
+
+nufft_status nufft3d_type1_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev,
+                                int64_t n1, int64_t n2, int64_t n3, const void *c, void *C, int sign, double eps,
+                                nufft_dtype dtype, void *stream)
+{
+    if (n_pts < 1 || n1 < 1 || n2 < 1 || n3 < 1 || !x_dev || !y_dev || !z_dev || !c || !C)
+        return NUFFT_ERR_INVALID_ARG;
+    if ((sign != 1 && sign != -1) || (dtype != NUFFT_C64 && dtype != NUFFT_C128)) return NUFFT_ERR_INVALID_ARG;
+    if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
+    nufft_status st;
+    if (!eps_ok(eps, dtype, &st)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = dtype == NUFFT_C64 ? type1_3d<float>(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, c, C, sign, eps, dtype, s)
+                            : type1_3d<double>(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, c, C, sign, eps, dtype, s);
     if (st != NUFFT_OK) (void)hipStreamSynchronize(s);
     return st;
 }

@@ -21,5 +21,14 @@ hipError_t launch_3d_zfft(const cx_t<R> *Cin, int64_t rows, int64_t n3, int64_t 
 template <typename R>
 hipError_t launch_3d_accum(const cx_t<R> *fs, const int32_t *perm, const R *Xs, int64_t M, const Factors<R> &fac,
                            int r, cx_t<R> *f, hipStream_t s);
+// cw[i] = w_r(i) c[perm[i]], w_r = u^z_r (sign -1) or its conjugate (sign +1), i < M
+template <typename R>
+hipError_t launch_3d_weight(const cx_t<R> *c, const int32_t *perm, const R *Xs, int64_t M, const Factors<R> &fac,
+                            int r, int sign, cx_t<R> *cw, hipStream_t s);
+// Cout[row * n3 + k3] (r == 0 ? = : +=) v_r(k3) sum_{m < Gz} E[m * rows + row] exp(sign 2 pi i k3 m / Gz),
+// k3 < n3; tw: the stage-major length-Gz table of the -1 direction
+template <typename R>
+hipError_t launch_3d_zfft_t(const cx_t<R> *E, int64_t rows, int64_t n3, int64_t Gz, int r, int sign,
+                            const cx_t<R> *tw, cx_t<R> *Cout, hipStream_t s);
 
 }  // namespace nufft

@@ -12,6 +12,12 @@
 // and the samples of one z slice m share one 2-D type-II plan.  The slices'
 // results land in slice-sorted order and `k_3d_accum` adds u^z_r times them
 // into f in sample order.
+//
+// The 3-D type I (sign -1, the transpose) and adjoint (sign +1) run the same
+// factoring backwards: with w_r(j) = u^z_r(j) (type I) or its conjugate
+// (adjoint), `k_3d_weight` forms w_r(j) c_j in slice order, each slice m
+// gets a 2-D type I of those weights, E_r[m][k1][k2], and `k_3d_zfft_t`
+// finishes C[k1][k2][k3] += v^z_r(k3) sum_m E_r[m][k1][k2] exp(sign 2 pi i k3 m / Gz).
 #include "fused_common.h"
 #include "kernels_3d.h"
 
@@ -114,6 +120,77 @@ k_3d_accum(const cx_t<R> *__restrict__ fs, const int32_t *__restrict__ perm, con
     f[j] = r == 0 ? add : cadd(f[j], add);
 }
 
+// cw[i] = w_r(i) c[perm[i]] over the slice-sorted samples i, w_r = u^z_r (DIR -1) or its
+// conjugate (DIR +1).
+template <typename R, int DIR>
+__global__ void __launch_bounds__(256)
+k_3d_weight(const cx_t<R> *__restrict__ c, const int32_t *__restrict__ perm, const R *__restrict__ Xs, int64_t M,
+            Factors<R> fac, int r, cx_t<R> *__restrict__ cw)
+{
+    using C = cx_t<R>;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const R X = Xs[i];
+    R sn, cs;
+    sincospi_r(X, &sn, &cs);
+    const RankPoly<R> up = rank_poly(fac, r);
+    C u = crot(cscale(cmake<C>(cs, -sn), rank_eval(up, X * fac.inv_gamma)), r);
+    if (DIR > 0) u = cconj(u);
+    cw[i] = cmul(u, c[perm[i]]);
+}
+
+// C[row][k3] (r == 0 ? = : +=) v^z_r(k3) sum_m E[m][row] exp(DIR 2 pi i k3 m / GZ), k3 < n3:
+// RC rows per workgroup (256 threads), E read slice-major (consecutive threads read
+// consecutive rows of one slice), C written row-major with k3 fastest.
+template <typename R, int GZ, int DIR>
+__global__ void __launch_bounds__(256)
+k_3d_zfft_t(const cx_t<R> *__restrict__ E, int64_t rows, int64_t n3, int r, const cx_t<R> *__restrict__ tw_g,
+            cx_t<R> *__restrict__ Cout)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = GZ / 16;
+    constexpr int RC = 256 / TPF;
+    constexpr int P = fft_pitch(GZ);
+    constexpr int NE = (RC * GZ) / 256;
+    __shared__ C buf[RC * P];
+    __shared__ C tw[GZ];
+    load_tw_s<C, GZ, DIR, 256>(tw, tw_g);
+    const int tid = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * RC;
+    C v[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int i = tid + e * 256;
+        const int gg = i % RC, m = i / RC;
+        const bool in = row0 + gg < rows;
+        const C x = E[(int64_t)m * rows + min(row0 + gg, rows - 1)];   // clamped: the loads issue together
+        v[e] = in ? x : cmake<C>(0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int i = tid + e * 256;
+        buf[(i % RC) * P + lds_pad(i / RC)] = v[e];
+    }
+    __syncthreads();   // the rows and the twiddle table are in LDS
+    block_fft_lds<C, GZ, DIR, fft_wave_sync<GZ>>(buf + (tid / TPF) * P, tw, tid % TPF);
+    __syncthreads();   // the row-major store reads other transforms
+    const ZMap zm = zmap(n3);
+    R zq[NE], wq[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) zq[e] = zcoord<R>((tid + e * 256) % GZ, zm);
+    cheb_v_many<R, NE>(r, zq, wq);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int i = tid + e * 256;
+        const int gg = i / GZ, k3 = i % GZ;
+        if (k3 < n3 && row0 + gg < rows) {
+            C *o = Cout + (row0 + gg) * n3 + k3;
+            const C add = cscale(buf[gg * P + lds_pad(k3)], wq[e]);
+            *o = r == 0 ? add : cadd(*o, add);
+        }
+    }
+}
+
 template <typename R>
 hipError_t launch_3d_assign(const double *z, int64_t M, int64_t n3, int64_t Gz, int32_t *t, R *X,
                             unsigned long long *gbits, int *flags, hipStream_t s)
@@ -157,6 +234,40 @@ hipError_t launch_3d_accum(const cx_t<R> *fs, const int32_t *perm, const R *Xs, 
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_3d_weight(const cx_t<R> *c, const int32_t *perm, const R *Xs, int64_t M, const Factors<R> &fac,
+                            int r, int sign, cx_t<R> *cw, hipStream_t s)
+{
+    const dim3 g((unsigned)((M + 255) / 256));
+    if (sign < 0)
+        hipLaunchKernelGGL((k_3d_weight<R, -1>), g, dim3(256), 0, s, c, perm, Xs, M, fac, r, cw);
+    else
+        hipLaunchKernelGGL((k_3d_weight<R, 1>), g, dim3(256), 0, s, c, perm, Xs, M, fac, r, cw);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_3d_zfft_t(const cx_t<R> *E, int64_t rows, int64_t n3, int64_t Gz, int r, int sign,
+                            const cx_t<R> *tw, cx_t<R> *Cout, hipStream_t s)
+{
+    switch (Gz) {
+#define ZT(GG)                                                                                                   \
+    case GG: {                                                                                                   \
+        constexpr int RC = 256 / (GG / 16);                                                                      \
+        const dim3 g((unsigned)((rows + RC - 1) / RC));                                                          \
+        if (sign < 0)                                                                                            \
+            hipLaunchKernelGGL((k_3d_zfft_t<R, GG, -1>), g, dim3(256), 0, s, E, rows, n3, r, tw, Cout);         \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_3d_zfft_t<R, GG, 1>), g, dim3(256), 0, s, E, rows, n3, r, tw, Cout);          \
+        break;                                                                                                   \
+    }
+        ZT(16) ZT(32) ZT(64) ZT(128) ZT(256) ZT(512) ZT(1024)
+#undef ZT
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template hipError_t launch_3d_assign<float>(const double *, int64_t, int64_t, int64_t, int32_t *, float *,
                                             unsigned long long *, int *, hipStream_t);
 template hipError_t launch_3d_assign<double>(const double *, int64_t, int64_t, int64_t, int32_t *, double *,
@@ -169,5 +280,14 @@ template hipError_t launch_3d_accum<float>(const float2 *, const int32_t *, cons
                                            const Factors<float> &, int, float2 *, hipStream_t);
 template hipError_t launch_3d_accum<double>(const double2 *, const int32_t *, const double *, int64_t,
                                             const Factors<double> &, int, double2 *, hipStream_t);
+
+template hipError_t launch_3d_weight<float>(const float2 *, const int32_t *, const float *, int64_t,
+                                            const Factors<float> &, int, int, float2 *, hipStream_t);
+template hipError_t launch_3d_weight<double>(const double2 *, const int32_t *, const double *, int64_t,
+                                             const Factors<double> &, int, int, double2 *, hipStream_t);
+template hipError_t launch_3d_zfft_t<float>(const float2 *, int64_t, int64_t, int64_t, int, int, const float2 *,
+                                            float2 *, hipStream_t);
+template hipError_t launch_3d_zfft_t<double>(const double2 *, int64_t, int64_t, int64_t, int, int,
+                                             const double2 *, double2 *, hipStream_t);
 
 }  // namespace nufft

@@ -56,3 +56,58 @@ def test_3d_rejects_nonfinite():
     z = _t(np.array([0.1, np.nan]), torch.float64)
     with pytest.raises(P.NufftError):
         P.nufft3d_exec(x, x, z, _t(np.ones((2, 2, 2)), C64), 1e-6)
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+@pytest.mark.parametrize("sign", [-1, 1])
+@pytest.mark.parametrize("n1,n2,n3,M", [(1, 1, 1, 3), (8, 6, 5, 300), (16, 16, 16, 2000), (20, 12, 33, 3000),
+                                        (32, 32, 64, 4000)])
+def test_3d_type1_against_oracle(dtype, sign, n1, n2, n3, M):
+    """3-D type I (sign -1) and adjoint (sign +1) against the direct sum, bar 4 eps ||c||_1."""
+    rng = W.rng_for(93)
+    x, y, z = rng.random(M) * 2 - 0.5, rng.random(M), rng.random(M) * 3 - 1.0
+    c = W.complex_normal(rng, M)
+    print("3-D type I sign=%+d n=%dx%dx%d M=%d %s" % (sign, n1, n2, n3, M, dtype), flush=True)
+    ct = _t(c, dtype)
+    C = P.nufft3d_type1_exec(_t(x, torch.float64), _t(y, torch.float64), _t(z, torch.float64), ct, (n1, n2, n3),
+                             EPS[dtype], sign=sign).cpu().numpy().ravel()
+    cc = ct.cpu().numpy().astype(np.complex128)
+    n = n1 * n2 * n3
+    q = np.arange(n) if n * M <= 2e7 else np.unique(np.concatenate(
+        [np.random.default_rng(94).choice(n, 500, replace=False), [0, n - 1, n3 - 1, n2 * n3 - 1]]))
+    k1, k2, k3 = q // (n2 * n3), (q // n3) % n2, q % n3
+    ref = D.nudft3d_adj(x, y, z, cc, k1, k2, k3, sign=sign)
+    err = np.abs(C[q] - ref).max() / np.abs(cc).sum()
+    print("   err/||c||_1 = %.3e" % err, flush=True)
+    assert np.all(np.isfinite(C)) and err <= 4 * EPS[dtype]
+
+
+def test_3d_adjoint_identity_and_one_z_mode():
+    """<g, F C> = <F^H g, C> between nufft3d_exec and the adjoint; with n3 = 1 the type I
+    equals the 2-D type I."""
+    rng = W.rng_for(95)
+    n1, n2, n3, M = 24, 20, 12, 6000
+    x, y, z = rng.random(M) * 2 - 0.5, rng.random(M), rng.random(M)
+    X, Y, Z = (_t(v, torch.float64) for v in (x, y, z))
+    C = _t(W.complex_normal(rng, n1 * n2 * n3).reshape(n1, n2, n3), C128)
+    g = _t(W.complex_normal(rng, M), C128)
+    f = P.nufft3d_exec(X, Y, Z, C, 1e-12)
+    a = P.nufft3d_type1_exec(X, Y, Z, g, (n1, n2, n3), 1e-12, sign=1)
+    lhs = torch.vdot(g, f).item()
+    rhs = torch.vdot(a.reshape(-1), C.reshape(-1)).item()
+    assert abs(lhs - rhs) <= 1e-10 * C.abs().sum().item() * g.abs().sum().item()
+    C1 = P.nufft3d_type1_exec(X, Y, Z, g, (n1, n2, 1), 1e-12, sign=-1)
+    plan = P.nufft2d_plan(X, Y, n1, n2, 1e-12, C128)
+    F2 = torch.empty(n1 * n2, dtype=C128, device=DEV)
+    P.nufft2d_type1_exec(plan, g, F2, -1)
+    assert (C1.reshape(-1) - F2).abs().max().item() <= 8e-12 * g.abs().sum().item()
+
+
+def test_3d_type1_rejects_bad_arguments():
+    x = _t(np.array([0.1, 0.2]), torch.float64)
+    z = _t(np.array([0.1, np.nan]), torch.float64)
+    c = _t(np.ones(2), C64)
+    with pytest.raises(P.NufftError):
+        P.nufft3d_type1_exec(x, x, z, c, (2, 2, 2), 1e-6)
+    with pytest.raises(P.NufftError):
+        P.nufft3d_type1_exec(x, x, x, c, (2, 2, 2), 1e-6, sign=0)
