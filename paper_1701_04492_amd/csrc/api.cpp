@@ -594,9 +594,10 @@ nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
     unsigned long long h[3];
     std::vector<int32_t> toff((size_t)p->Gy + 1);
     NUFFT_HIP_CHECK(hipMemcpyAsync(h, dflags, sizeof(h), hipMemcpyDeviceToHost, s));
-    for (int n2 = 0; n2 <= p->Gy; ++n2)
-        NUFFT_HIP_CHECK(hipMemcpyAsync(&toff[n2], p->off + (int64_t)n2 * p->Gx, sizeof(int32_t),
-                                       hipMemcpyDeviceToHost, s));
+    // column starts off[n2 * Gx], n2 <= Gy: gathered on the device, one copy
+    // (into hist: G2 + 1 >= Gy + 1 entries, unused after the scan)
+    NUFFT_HIP_CHECK(launch_strided_i32(p->off, p->Gx, (int64_t)p->Gy + 1, hist, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(toff.data(), hist, ((size_t)p->Gy + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     NUFFT_HIP_CHECK(hipStreamSynchronize(s));
     if ((int)h[2] != 0) return NUFFT_ERR_NONFINITE;
     double gx, gy;
@@ -1019,6 +1020,56 @@ struct StreamSyncGuard {   // declared after the Plan that owns the temporaries:
     ~StreamSyncGuard() { (void)hipStreamSynchronize(s); }
 };
 
+// The slices' 2-D transforms of one rank are independent: they run on side
+// streams (slice m on stream m mod NS; a slice plan's own buffers keep its
+// launches on one stream), forked from and joined back to the caller's stream.
+// The small per-slice launches fill only a few CUs each; side by side they
+// share the chip.  Declared after the Plan that owns the temporaries, so the
+// streams are drained before anything is freed.
+struct SideStreams {
+    static constexpr int NS = 4;
+    hipStream_t main = nullptr;
+    hipStream_t st[NS] = {};
+    hipEvent_t done[NS] = {}, start = nullptr;
+    hipError_t init(hipStream_t m)
+    {
+        main = m;
+        hipError_t e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+        for (int i = 0; i < NS && e == hipSuccess; ++i) {
+            e = hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
+        }
+        return e;
+    }
+    hipStream_t operator[](int64_t m) const { return st[m % NS]; }
+    hipError_t fork()
+    {
+        hipError_t e = hipEventRecord(start, main);
+        for (int i = 0; i < NS && e == hipSuccess; ++i) e = hipStreamWaitEvent(st[i], start, 0);
+        return e;
+    }
+    hipError_t join()
+    {
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < NS && e == hipSuccess; ++i) {
+            e = hipEventRecord(done[i], st[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(main, done[i], 0);
+        }
+        return e;
+    }
+    ~SideStreams()
+    {
+        for (int i = 0; i < NS; ++i)
+            if (st[i]) {
+                (void)hipStreamSynchronize(st[i]);
+                (void)hipStreamDestroy(st[i]);
+            }
+        for (int i = 0; i < NS; ++i)
+            if (done[i]) (void)hipEventDestroy(done[i]);
+        if (start) (void)hipEventDestroy(start);
+    }
+};
+
 // 3-D type II: f = sum_r u^z_r * [2-D type II of slice t^z_j of D_r]
 template <typename R>
 static nufft_status type2_3d(int64_t M, const double *x, const double *y, const double *z, int64_t n1, int64_t n2,
@@ -1032,10 +1083,15 @@ static nufft_status type2_3d(int64_t M, const double *x, const double *y, const 
     if (st) return st;
     C *fs = (C *)tmp.alloc(M * sizeof(C));
     if (!fs) return NUFFT_ERR_ALLOC;
+    SideStreams ss;
+    NUFFT_HIP_CHECK(ss.init(s));
     for (int r = 0; r < o.K3; ++r) {
         NUFFT_HIP_CHECK(launch_3d_zfft<R>((const C *)Cin, o.rows, n3, o.Gz, r, (const C *)o.tw, o.D, s));
+        NUFFT_HIP_CHECK(ss.fork());
         for (int64_t m = 0; m < o.Gz; ++m)
-            if (o.sl[m]) NUFFT_HIP_CHECK(fused_2d<R>(args_2d<R>(o.sl[m]), o.D + m * o.rows, fs + o.off[m], s));
+            if (o.sl[m])
+                NUFFT_HIP_CHECK(fused_2d<R>(args_2d<R>(o.sl[m]), o.D + m * o.rows, fs + o.off[m], ss[m]));
+        NUFFT_HIP_CHECK(ss.join());
         NUFFT_HIP_CHECK(launch_3d_accum<R>(fs, o.perm, o.Xs, M, o.fz, r, (C *)f, s));
     }
     return NUFFT_OK;
@@ -1058,11 +1114,16 @@ static nufft_status type1_3d(int64_t M, const double *x, const double *y, const 
     if (!cw) return NUFFT_ERR_ALLOC;
     for (int64_t m = 0; m < o.Gz; ++m)   // empty slices contribute zero
         if (!o.sl[m]) NUFFT_HIP_CHECK(hipMemsetAsync(o.D + m * o.rows, 0, o.rows * sizeof(C), s));
+    SideStreams ss;
+    NUFFT_HIP_CHECK(ss.init(s));
     for (int r = 0; r < o.K3; ++r) {
         NUFFT_HIP_CHECK(launch_3d_weight<R>((const C *)c, o.perm, o.Xs, M, o.fz, r, sign, cw, s));
+        NUFFT_HIP_CHECK(ss.fork());
         for (int64_t m = 0; m < o.Gz; ++m)
             if (o.sl[m])
-                NUFFT_HIP_CHECK(fused_2d_adj<R>(args_2d<R>(o.sl[m]), cw + o.off[m], o.D + m * o.rows, sign, s));
+                NUFFT_HIP_CHECK(
+                    fused_2d_adj<R>(args_2d<R>(o.sl[m]), cw + o.off[m], o.D + m * o.rows, sign, ss[m]));
+        NUFFT_HIP_CHECK(ss.join());
         NUFFT_HIP_CHECK(launch_3d_zfft_t<R>(o.D, o.rows, n3, o.Gz, r, sign, (const C *)o.tw, (C *)Cout, s));
     }
     return NUFFT_OK;

@@ -86,6 +86,8 @@ hipError_t launch_assign(const double *x, int64_t M, int64_t L, double n_over_L,
 template <typename R>
 hipError_t launch_gather_sorted(const int32_t *perm, const R *X, int64_t n, R *Xs, hipStream_t s);
 hipError_t launch_iota(int32_t *v, int64_t n, hipStream_t s);
+// out[i] = in[i * stride], i < n
+hipError_t launch_strided_i32(const int32_t *in, int64_t stride, int64_t n, int32_t *out, hipStream_t s);
 hipError_t launch_invert_perm(const int32_t *perm, int64_t n, int32_t *sinv, hipStream_t s);
 hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);

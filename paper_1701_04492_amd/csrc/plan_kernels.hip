@@ -230,6 +230,13 @@ __global__ void k_iota(int32_t *v, int64_t n)
     if (i < n) v[i] = (int32_t)i;
 }
 
+// out[i] = in[i * stride], i < n (every stride-th entry, e.g. the first offset of each column).
+__global__ void k_strided_i32(const int32_t *__restrict__ in, int64_t stride, int64_t n, int32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i * stride];
+}
+
 // sinv[perm[i]] = i: the sorted position of every sample.
 __global__ void k_invert_perm(const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ sinv)
 {
@@ -299,6 +306,13 @@ hipError_t launch_iota(int32_t *v, int64_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_strided_i32(const int32_t *in, int64_t stride, int64_t n, int32_t *out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_strided_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, stride, n, out);
     return hipGetLastError();
 }
 
