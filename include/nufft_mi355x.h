@@ -312,6 +312,15 @@ nufft_status nufft_plan_profile(nufft_plan_t plan, int enable, int reserve);
 nufft_status nufft_plan_profile_read(nufft_plan_t plan, int index, char *name, int name_len, int *calls,
                                      double *total_ms);
 
+/* ---- failure injection (tests) ------------------------------------------- */
+
+/* For callers that test their error handling: with n >= 0, the library's
+ * device allocation n allocations from now (0: the next one) is refused, and
+ * the call that made it returns NUFFT_ERR_ALLOC after releasing what it had
+ * built; the injection then disarms itself.  n < 0 disarms it.  Process-wide
+ * state, not meant for concurrent use.  Always returns NUFFT_OK. */
+nufft_status nufft_debug_fail_alloc(int64_t n);
+
 /* ---- host-side factor generator (no GPU work) --------------------------- */
 
 /* K(eps, gamma): the smallest K whose Chebyshev truncation tail

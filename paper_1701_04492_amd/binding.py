@@ -58,6 +58,7 @@ _sig = {
     "nufft_status_string": [_int],
     "nufft_plan_profile": [_vp, _int, _int],
     "nufft_plan_profile_read": [_vp, _int, ctypes.c_char_p, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl)],
+    "nufft_debug_fail_alloc": [_i64],
     "nufft_choose_rank": [_dbl, _dbl, ctypes.POINTER(_int)],
     "nufft_bessel_coefficients": [_dbl, _int, _vp],
 }
@@ -349,6 +350,12 @@ def nufft_plan_profile_read(plan):
 
 def nufft_status_string(status):
     return lib.nufft_status_string(int(status)).decode()
+
+
+def nufft_debug_fail_alloc(n):
+    """Refuse the device allocation n allocations from now (n < 0: disarm); for tests of
+    error handling."""
+    _check(lib.nufft_debug_fail_alloc(int(n)), "nufft_debug_fail_alloc")
 
 
 def nufft_choose_rank(eps, gamma):

@@ -1,4 +1,5 @@
 // C ABI of the MI355X low-rank NUFFT: plans, dispatch, error handling.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -15,8 +16,16 @@
 
 using namespace nufft;
 
+// Failure injection for tests: >= 0 counts the device allocations left before
+// one is refused (then the countdown disarms itself); < 0: none is refused.
+static std::atomic<long long> alloc_countdown{-1};
+
 void *nufft_plan_s::alloc(size_t bytes)
 {
+    long long v = alloc_countdown.load(std::memory_order_relaxed);
+    while (v >= 0 && !alloc_countdown.compare_exchange_weak(v, v - 1, std::memory_order_relaxed)) {
+    }
+    if (v == 0) return nullptr;   // the injected failure
     if (bytes == 0) bytes = 16;
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -1642,6 +1651,12 @@ const char *nufft_status_string(nufft_status status)
     case NUFFT_ERR_HIP: return "HIP runtime error";
     default: return "unknown status";
     }
+}
+
+nufft_status nufft_debug_fail_alloc(int64_t n)
+{
+    alloc_countdown.store(n < 0 ? -1 : (long long)n, std::memory_order_relaxed);
+    return NUFFT_OK;
 }
 
 nufft_status nufft_choose_rank(double eps, double gamma, int *K)

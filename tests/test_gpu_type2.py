@@ -225,3 +225,40 @@ def test_kernel_profiling_hook():
     P.nufft_plan_profile(plan, 0)
     P.nufft2_exec(plan, ct)
     assert P.nufft_plan_profile_read(plan) == {}
+
+
+def test_allocation_failure_is_reported():
+    """Each device allocation of a plan refused in turn (failure injected from the host):
+    the call returns NUFFT_ERR_ALLOC, releases what it built, and later calls work."""
+    rng = W.rng_for(60)
+    N = M = 1 << 16
+    x = W.iid_samples(rng, M)
+    c = W.complex_normal(rng, N)
+    xt, ct = _t(x, torch.float64), _t(c, C64)
+    ref = P.nufft2_exec(P.nufft2_plan(xt, N, 1e-6, C64), ct)
+    yt = _t(W.iid_samples(rng, M), torch.float64)
+    zt = _t(np.zeros(M), torch.float64)            # one z slice: a bounded number of allocations
+    calls = [("1-D plan", lambda: P.nufft2_plan(xt, N, 1e-6, C64)),
+             ("2-D plan", lambda: P.nufft2d_plan(xt, yt, 256, 256, 1e-6, C64)),
+             ("3-D exec", lambda: P.nufft3d_exec(xt, yt, zt, _t(np.ones((8, 8, 16)), C64), 1e-6))]
+    try:
+        for label, call in calls:
+            refused = 0
+            for n in range(64):
+                _say(label, "refusing allocation", n)
+                P.nufft_debug_fail_alloc(n)
+                try:
+                    call()
+                except P.NufftError as e:
+                    assert e.status == 3, e        # NUFFT_ERR_ALLOC
+                    refused += 1
+                    continue
+                break                              # n is past the call's last allocation
+            P.nufft_debug_fail_alloc(-1)
+            torch.cuda.synchronize()
+            _say("   %s: %d allocation sites refused" % (label, refused))
+            assert 5 <= refused < 64
+    finally:
+        P.nufft_debug_fail_alloc(-1)
+    f = P.nufft2_exec(P.nufft2_plan(xt, N, 1e-6, C64), ct)
+    assert torch.equal(f, ref)
