@@ -171,8 +171,10 @@ def traffic_summary(fetch_dir, write_dir, out_path, command):
     print(json.dumps(rec, indent=1))
 
 
-def cpu_baseline(x, c, N, seconds):
-    """The FP64 direct-sum oracle on a bounded row sample of the same workload."""
+def cpu_baseline(x, c, N, seconds, f_gpu=None, eps=None):
+    """The FP64 direct-sum oracle on a bounded row sample of the same workload.  With the
+    GPU's forward output f_gpu (computed from the same c), the rows the oracle summed also
+    give the accuracy of the GPU result: returns (baseline, accuracy or None)."""
     import numpy as np
     from oracle import nudft as D
     cores = D.max_threads()
@@ -180,13 +182,13 @@ def cpu_baseline(x, c, N, seconds):
     rows = 2 * cores
     while True:                       # grow the sample until it takes about `seconds`
         t0 = time.perf_counter()
-        D.nudft2(x[:rows], c)
+        ref = D.nudft2(x[:rows], c)
         dt = time.perf_counter() - t0
         if dt >= 0.5 * seconds or rows >= 8192:
             break
         rows = int(min(8192, rows * max(2.0, seconds / max(dt, 1e-3))))
     # the step needs three N-term sums per point: f_j, (F2^H g)_k and the x-derivative
-    return {
+    base = {
         "value": rows / dt / 3.0,
         "unit": "nonuniform pts/s",
         "cores": cores,
@@ -194,6 +196,16 @@ def cpu_baseline(x, c, N, seconds):
         "sample": "%d rows of the N=M=2^22 workload, each a direct FP64 compensated sum of 2^22 "
                   "terms (%.1f s); the fwd+bwd step costs 3 such sums per point" % (rows, dt),
     }
+    acc = None
+    if f_gpu is not None:
+        d = f_gpu[:rows].astype(np.complex128) - ref
+        M = x.shape[0]
+        acc = {"rows": rows,
+               "max_err_over_c_l1": float(np.abs(d).max() / np.abs(c).sum()),
+               "bound_4eps": 4 * eps,
+               # the paper's metric ||f~ - f||_2 / ||c||_2, its sum over j estimated from the rows
+               "l2_err_over_c_l2_est": float(np.sqrt(np.mean(np.abs(d) ** 2) * M) / np.linalg.norm(c))}
+    return base, acc
 
 
 def bench_batch(P, W, torch, dev):
@@ -542,7 +554,11 @@ def main():
         out["type2_3d"] = bench_3d(P, W, torch, dev)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x_np, c_np, N, args.cpu_seconds)
+        import numpy as np
+        f_gpu = P.nufft2_exec(plan, c).cpu().numpy()
+        c_in = c.cpu().numpy().astype(np.complex128)   # the complex64 input the GPU transformed
+        out["cpu_baseline"], out["accuracy_2p22_forward"] = cpu_baseline(x_np, c_in, N, args.cpu_seconds,
+                                                                         f_gpu, eps)
     print(json.dumps(out), flush=True)
 
 
