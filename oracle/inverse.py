@@ -20,7 +20,7 @@ order:
   Toeplitz, with first column conj(tau).  CG runs on F1 F1^* y = f and
   c = F1^* y.
 
-Readings (listed in the design doc): the embedding uses 2N points with one zero
+Readings where the paper leaves a choice: the embedding uses 2N points with one zero
 (any value there gives the same product); CG stops when the residual of the
 normal equations falls below tol times the norm of their right-hand side
 F2^* f, or after max_iter iterations, and starts from c = 0; the type-I

@@ -15,7 +15,7 @@ against the text:
   f = [D_{u_0} X_0 | ... ] 1.
 * Sec. 3.1 type I as the transpose, Sec. 3.2 type III, Sec. 4 2-D type II.
 
-Readings where the paper is silent or inconsistent (all listed in the design doc):
+Readings where the paper is silent or inconsistent:
 * K is the smallest integer whose full truncation tail
   sum_{max(p,r) >= K} w_p w_r |a_pr| (w_0 = 1/2, else 1) is at most eps.  The
   tail in the proof of Lemma A.1 keeps only p >= K and r >= K, which misses the
