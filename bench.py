@@ -395,8 +395,18 @@ def bench_2d(P, W, torch, dev):
     torch.cuda.synchronize()
     kern = {k: round(ms / n * 1e3, 1) for k, (n, ms) in P.nufft_plan_profile_read(plan).items()}
     P.nufft_plan_profile(plan, 0)
+    # algorithmic flops of one direction (the ALU roofline of this ALU/LDS-bound case):
+    # Ky length-1024 FFTs per coefficient column (pass A), Kx Ky per grid column (pass B),
+    # 5 n log2 n each, plus ~8 flops per sample and rank pair for the gather/spread
+    K1 = K2 = plan.K   # gamma -> 1/2 on both axes for the polar samples: Kx = Ky
+    n, M = 1024, x.shape[0]
+    flop = 5 * n * n * 10 * (K2 + K1 * K2) + 8 * M * K1 * K2
+    peak = 157.3e12
     return {"Kx": plan.K, "forward_us": round(t_f * 1e3, 1), "adjoint_us": round(t_a * 1e3, 1),
             "type1_us": round(t_1 * 1e3, 1), "forward_pts_per_s": x.shape[0] / (t_f * 1e-3),
+            "alu_roofline": {"alg_gflop": round(flop / 1e9, 2), "peak_tflops_fp32": 157.3,
+                             "forward_frac": round(flop / (t_f * 1e-3) / peak, 4),
+                             "adjoint_frac": round(flop / (t_a * 1e-3) / peak, 4)},
             "kernels_avg_us": kern}
 
 
