@@ -566,7 +566,9 @@ template <typename R>
 nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
 {
     const int64_t M = p->M;
-    const int64_t G2 = (int64_t)p->Gx * p->Gy;
+    const int64_t cols = (int64_t)p->S * p->Gy;   // pass-B columns over the stacked problems
+    const int64_t G2 = cols * p->Gx;              // grid points, the key range
+    if (G2 > (int64_t(1) << 28)) return NUFFT_ERR_UNSUPPORTED;
     R *Xx = (R *)p->alloc(M * sizeof(R));
     R *Xy = (R *)p->alloc(M * sizeof(R));
     p->Xxs = p->alloc(M * sizeof(R));
@@ -585,8 +587,8 @@ nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
         return NUFFT_ERR_ALLOC;
     NUFFT_HIP_CHECK(hipMemsetAsync(hist, 0, (G2 + 1) * sizeof(int32_t), s));
     NUFFT_HIP_CHECK(hipMemsetAsync(dflags, 0, 3 * sizeof(unsigned long long), s));
-    NUFFT_HIP_CHECK(launch_assign2d<R>(x, y, M, p->Gx, p->Gy, (double)p->N1 / p->Gx, (double)p->N2 / p->Gy, Xx, Xy,
-                                       keys_u, hist, dflags, (int *)(dflags + 2), s));
+    NUFFT_HIP_CHECK(launch_assign2d<R>(x, y, p->slice, M, p->Gx, p->Gy, (double)p->N1 / p->Gx,
+                                       (double)p->N2 / p->Gy, Xx, Xy, keys_u, hist, dflags, (int *)(dflags + 2), s));
     NUFFT_HIP_CHECK(exclusive_scan(hist, p->off, G2 + 1, tmp, s));
     NUFFT_HIP_CHECK(launch_iota(iota, M, s));
     int key_bits = 0;
@@ -601,12 +603,12 @@ nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
     NUFFT_HIP_CHECK(launch_gather_sorted<R>(p->perm, Xx, M, (R *)p->Xxs, s));
     NUFFT_HIP_CHECK(launch_gather_sorted<R>(p->perm, Xy, M, (R *)p->Xys, s));
     unsigned long long h[3];
-    std::vector<int32_t> toff((size_t)p->Gy + 1);
+    std::vector<int32_t> toff((size_t)cols + 1);
     NUFFT_HIP_CHECK(hipMemcpyAsync(h, dflags, sizeof(h), hipMemcpyDeviceToHost, s));
-    // column starts off[n2 * Gx], n2 <= Gy: gathered on the device, one copy
-    // (into hist: G2 + 1 >= Gy + 1 entries, unused after the scan)
-    NUFFT_HIP_CHECK(launch_strided_i32(p->off, p->Gx, (int64_t)p->Gy + 1, hist, s));
-    NUFFT_HIP_CHECK(hipMemcpyAsync(toff.data(), hist, ((size_t)p->Gy + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // column starts off[n2 * Gx], n2 <= cols: gathered on the device, one copy
+    // (into hist: G2 + 1 >= cols + 1 entries, unused after the scan)
+    NUFFT_HIP_CHECK(launch_strided_i32(p->off, p->Gx, cols + 1, hist, s));
+    NUFFT_HIP_CHECK(hipMemcpyAsync(toff.data(), hist, ((size_t)cols + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     NUFFT_HIP_CHECK(hipStreamSynchronize(s));
     if ((int)h[2] != 0) return NUFFT_ERR_NONFINITE;
     double gx, gy;
@@ -646,7 +648,7 @@ nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
     const int cap = pass_b2d_cap(p->Gx, p->dtype == NUFFT_C64);
     if (cap <= 0) return NUFFT_ERR_UNSUPPORTED;
     std::vector<int4> tk;
-    for (int n2 = 0; n2 < p->Gy; ++n2)
+    for (int n2 = 0; n2 < cols; ++n2)
         for (int a = toff[n2]; a < toff[n2 + 1]; a += cap) {
             int4 v;
             v.x = n2;
@@ -668,7 +670,7 @@ nufft_status build_2d(Plan *p, const double *x, const double *y, hipStream_t s)
     if (acap <= 0) return NUFFT_ERR_UNSUPPORTED;
     std::vector<int4> at, rt;
     int nslots = 0;
-    for (int n2 = 0; n2 < p->Gy; ++n2) {
+    for (int n2 = 0; n2 < cols; ++n2) {
         const int a0 = toff[n2], a1 = toff[n2 + 1];
         if (a1 - a0 <= acap) {
             at.push_back(make_int4(n2, a0, a1, -1));   // also empty columns: their rows are zero
@@ -709,6 +711,7 @@ static Args2D<R> args_2d(const Plan *p)
     a.M = p->M;
     a.Gx = p->Gx;
     a.Gy = p->Gy;
+    a.S = p->S;
     if constexpr (sizeof(R) == 4) {
         a.fx = p->ffx;
         a.fy = p->ffy;
@@ -922,19 +925,18 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
 // 3-D transforms: the z axis factored as in Sec. 2.1-2.2 (rank K3 on a grid of
 // Gz points), one length-Gz FFT per (k1, k2) and rank, and for each z slice of
 // the samples one 2-D transform (Sec. 4) of that slice; the compositions are
-// stated with the kernels.  Half of eps goes to the z factorisation, half to
-// the 2-D transforms, whose errors are weighted by
-// sum_r |u^z_r| w_r <= sum_{p,r} w_p w_r |b_pr| (the same bound serves type I,
-// whose inner inputs are u^z_r c or its conjugate).
+// stated with the kernels.  The Gz slice transforms are the problems of one
+// stacked 2-D plan (every slice's columns in one pass-B launch).  Half of eps
+// goes to the z factorisation, half to the 2-D transforms, whose errors are
+// weighted by sum_r |u^z_r| w_r <= sum_{p,r} w_p w_r |b_pr| (the same bound
+// serves type I, whose inner inputs are u^z_r c or its conjugate).
 template <typename R>
 struct Slices3D {
     int64_t Gz = 0, rows = 0;
     int K3 = 0;
     Factors<R> fz;
-    int32_t *perm = nullptr;      // slice-sorted order -> sample index
-    R *Xs = nullptr;              // z perturbations in slice order
-    std::vector<int32_t> off;     // slice m holds sorted samples [off[m], off[m+1])
-    std::vector<Plan *> sl;       // 2-D plan of each non-empty slice
+    R *X = nullptr;               // z perturbation per sample
+    Plan *plan = nullptr;         // the stacked 2-D plan: Gz problems of n1 x n2
     cx_t<R> *D = nullptr;         // Gz x rows, slice-major
     void *tw = nullptr;           // length-Gz twiddles, -1 direction
 };
@@ -949,44 +951,24 @@ static nufft_status setup_3d(Plan &tmp, int64_t M, const double *x, const double
     int gx = 16, gy = 16;
     while (gx < n1) gx <<= 1;
     while (gy < n2) gy <<= 1;
-    if (Gz > 1024 || gx > 2048 || gy > 2048) return NUFFT_ERR_UNSUPPORTED;
+    if (Gz > 1024 || gx > 2048 || gy > 2048 || Gz * gx * gy > (int64_t(1) << 28)) return NUFFT_ERR_UNSUPPORTED;
     o.Gz = Gz;
     o.rows = n1 * n2;
     int32_t *tz = (int32_t *)tmp.alloc(M * sizeof(int32_t));
-    R *X = (R *)tmp.alloc(M * sizeof(R));
-    o.Xs = (R *)tmp.alloc(M * sizeof(R));
-    o.perm = (int32_t *)tmp.alloc(M * sizeof(int32_t));
-    double *xs = (double *)tmp.alloc(M * sizeof(double));
-    double *ys = (double *)tmp.alloc(M * sizeof(double));
-    double *zs = (double *)tmp.alloc(M * sizeof(double));
+    o.X = (R *)tmp.alloc(M * sizeof(R));
     unsigned long long *flags = (unsigned long long *)tmp.alloc(2 * sizeof(unsigned long long));
     o.D = (C *)tmp.alloc(Gz * o.rows * sizeof(C));
-    if (!tz || !X || !o.Xs || !o.perm || !xs || !ys || !zs || !flags || !o.D) return NUFFT_ERR_ALLOC;
-    // z assignment, gamma_z, and the samples grouped by z slice (a stable counting sort)
+    if (!tz || !o.X || !flags || !o.D) return NUFFT_ERR_ALLOC;
+    // z slice and perturbation per sample, and gamma_z
     NUFFT_HIP_CHECK(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), s));
-    NUFFT_HIP_CHECK(launch_3d_assign<R>(z, M, n3, Gz, tz, X, flags, (int *)(flags + 1), s));
-    std::vector<int32_t> th(M);
+    NUFFT_HIP_CHECK(launch_3d_assign<R>(z, M, n3, Gz, tz, o.X, flags, (int *)(flags + 1), s));
     unsigned long long h[2];
-    NUFFT_HIP_CHECK(hipMemcpyAsync(th.data(), tz, M * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     NUFFT_HIP_CHECK(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
     NUFFT_HIP_CHECK(hipStreamSynchronize(s));
     if ((int)h[1] != 0) return NUFFT_ERR_NONFINITE;
     double gz;
     std::memcpy(&gz, &h[0], sizeof(double));
     gz = std::min(gz, 0.5);
-    std::vector<int32_t> &off = o.off, ph(M);
-    off.assign(Gz + 1, 0);
-    for (int64_t j = 0; j < M; ++j) ++off[th[j] + 1];
-    for (int64_t m = 0; m < Gz; ++m) off[m + 1] += off[m];
-    {
-        std::vector<int32_t> pos(off.begin(), off.end() - 1);
-        for (int64_t j = 0; j < M; ++j) ph[pos[th[j]]++] = (int32_t)j;
-    }
-    NUFFT_HIP_CHECK(hipMemcpyAsync(o.perm, ph.data(), M * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    NUFFT_HIP_CHECK(launch_3d_gather(x, o.perm, M, xs, s));
-    NUFFT_HIP_CHECK(launch_3d_gather(y, o.perm, M, ys, s));
-    NUFFT_HIP_CHECK(launch_3d_gather(z, o.perm, M, zs, s));
-    NUFFT_HIP_CHECK(launch_3d_assign<R>(zs, M, n3, Gz, tz, o.Xs, flags, (int *)(flags + 1), s));   // slice order
     o.K3 = choose_rank(eps / 2.0, gz);
     if (o.K3 < 0 || (sizeof(R) == 4 && o.K3 > NUFFT_KMAX_F32)) return NUFFT_ERR_UNSUPPORTED;
     fill_factors(o.fz, gz, o.K3);
@@ -997,28 +979,26 @@ static nufft_status setup_3d(Plan &tmp, int64_t M, const double *x, const double
             S += (p == 0 ? 0.5 : 1.0) * (r == 0 ? 0.5 : 1.0) * std::fabs(b[p * o.K3 + r]);
     const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
     const double eps2 = std::max(floor_eps, eps / (2.0 * std::max(S, 1.0)));
-    // one 2-D plan per non-empty z slice, on that slice's samples
-    o.sl.assign(Gz, nullptr);
-    for (int64_t m = 0; m < Gz; ++m) {
-        const int64_t cnt = off[m + 1] - off[m];
-        if (cnt == 0) continue;
-        Plan *q = new (std::nothrow) Plan();
-        if (!q) return NUFFT_ERR_ALLOC;
-        tmp.children.push_back(q);
-        q->kind = PLAN_2D;
-        q->dtype = dt;
-        q->N1 = n1;
-        q->N2 = n2;
-        q->N = o.rows;
-        q->M = cnt;
-        q->eps = eps2;
-        q->Gx = gx;
-        q->Gy = gy;
-        q->L = (int64_t)gx * gy;
-        const nufft_status st = build_2d<R>(q, xs + off[m], ys + off[m], s);
-        if (st) return st;
-        o.sl[m] = q;
-    }
+    // one stacked 2-D plan: problem m holds the samples of z slice m
+    Plan *q = new (std::nothrow) Plan();
+    if (!q) return NUFFT_ERR_ALLOC;
+    tmp.children.push_back(q);
+    q->kind = PLAN_2D;
+    q->dtype = dt;
+    q->N1 = n1;
+    q->N2 = n2;
+    q->N = o.rows;
+    q->M = M;
+    q->eps = eps2;
+    q->Gx = gx;
+    q->Gy = gy;
+    q->L = (int64_t)gx * gy;
+    q->S = (int)Gz;
+    q->slice = tz;
+    const nufft_status st = build_2d<R>(q, x, y, s);
+    q->slice = nullptr;   // tz is not kept beyond the build
+    if (st) return st;
+    o.plan = q;
     std::vector<double> t(2 * (size_t)Gz);
     fft_twiddles(Gz, -1, t.data());
     return upload_table<R>(&tmp, t, &o.tw, s);
@@ -1029,79 +1009,24 @@ struct StreamSyncGuard {   // declared after the Plan that owns the temporaries:
     ~StreamSyncGuard() { (void)hipStreamSynchronize(s); }
 };
 
-// The slices' 2-D transforms of one rank are independent: they run on side
-// streams (slice m on stream m mod NS; a slice plan's own buffers keep its
-// launches on one stream), forked from and joined back to the caller's stream.
-// The small per-slice launches fill only a few CUs each; side by side they
-// share the chip.  Declared after the Plan that owns the temporaries, so the
-// streams are drained before anything is freed.
-struct SideStreams {
-    static constexpr int NS = 4;
-    hipStream_t main = nullptr;
-    hipStream_t st[NS] = {};
-    hipEvent_t done[NS] = {}, start = nullptr;
-    hipError_t init(hipStream_t m)
-    {
-        main = m;
-        hipError_t e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
-        for (int i = 0; i < NS && e == hipSuccess; ++i) {
-            e = hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
-        }
-        return e;
-    }
-    hipStream_t operator[](int64_t m) const { return st[m % NS]; }
-    hipError_t fork()
-    {
-        hipError_t e = hipEventRecord(start, main);
-        for (int i = 0; i < NS && e == hipSuccess; ++i) e = hipStreamWaitEvent(st[i], start, 0);
-        return e;
-    }
-    hipError_t join()
-    {
-        hipError_t e = hipSuccess;
-        for (int i = 0; i < NS && e == hipSuccess; ++i) {
-            e = hipEventRecord(done[i], st[i]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(main, done[i], 0);
-        }
-        return e;
-    }
-    ~SideStreams()
-    {
-        for (int i = 0; i < NS; ++i)
-            if (st[i]) {
-                (void)hipStreamSynchronize(st[i]);
-                (void)hipStreamDestroy(st[i]);
-            }
-        for (int i = 0; i < NS; ++i)
-            if (done[i]) (void)hipEventDestroy(done[i]);
-        if (start) (void)hipEventDestroy(start);
-    }
-};
-
 // 3-D type II: f = sum_r u^z_r * [2-D type II of slice t^z_j of D_r]
 template <typename R>
 static nufft_status type2_3d(int64_t M, const double *x, const double *y, const double *z, int64_t n1, int64_t n2,
                              int64_t n3, const void *Cin, void *f, double eps, nufft_dtype dt, hipStream_t s)
 {
     using C = cx_t<R>;
-    Plan tmp;   // owns the temporaries and the slice plans
+    Plan tmp;   // owns the temporaries and the stacked plan
     StreamSyncGuard guard{s};
     Slices3D<R> o;
     nufft_status st = setup_3d<R>(tmp, M, x, y, z, n1, n2, n3, eps, dt, s, o);
     if (st) return st;
     C *fs = (C *)tmp.alloc(M * sizeof(C));
     if (!fs) return NUFFT_ERR_ALLOC;
-    SideStreams ss;
-    NUFFT_HIP_CHECK(ss.init(s));
+    const Args2D<R> a = args_2d<R>(o.plan);
     for (int r = 0; r < o.K3; ++r) {
         NUFFT_HIP_CHECK(launch_3d_zfft<R>((const C *)Cin, o.rows, n3, o.Gz, r, (const C *)o.tw, o.D, s));
-        NUFFT_HIP_CHECK(ss.fork());
-        for (int64_t m = 0; m < o.Gz; ++m)
-            if (o.sl[m])
-                NUFFT_HIP_CHECK(fused_2d<R>(args_2d<R>(o.sl[m]), o.D + m * o.rows, fs + o.off[m], ss[m]));
-        NUFFT_HIP_CHECK(ss.join());
-        NUFFT_HIP_CHECK(launch_3d_accum<R>(fs, o.perm, o.Xs, M, o.fz, r, (C *)f, s));
+        NUFFT_HIP_CHECK(fused_2d<R>(a, o.D, fs, s));
+        NUFFT_HIP_CHECK(launch_3d_accum<R>(fs, o.X, M, o.fz, r, (C *)f, s));
     }
     return NUFFT_OK;
 }
@@ -1121,18 +1046,10 @@ static nufft_status type1_3d(int64_t M, const double *x, const double *y, const 
     if (st) return st;
     C *cw = (C *)tmp.alloc(M * sizeof(C));
     if (!cw) return NUFFT_ERR_ALLOC;
-    for (int64_t m = 0; m < o.Gz; ++m)   // empty slices contribute zero
-        if (!o.sl[m]) NUFFT_HIP_CHECK(hipMemsetAsync(o.D + m * o.rows, 0, o.rows * sizeof(C), s));
-    SideStreams ss;
-    NUFFT_HIP_CHECK(ss.init(s));
+    const Args2D<R> a = args_2d<R>(o.plan);
     for (int r = 0; r < o.K3; ++r) {
-        NUFFT_HIP_CHECK(launch_3d_weight<R>((const C *)c, o.perm, o.Xs, M, o.fz, r, sign, cw, s));
-        NUFFT_HIP_CHECK(ss.fork());
-        for (int64_t m = 0; m < o.Gz; ++m)
-            if (o.sl[m])
-                NUFFT_HIP_CHECK(
-                    fused_2d_adj<R>(args_2d<R>(o.sl[m]), cw + o.off[m], o.D + m * o.rows, sign, ss[m]));
-        NUFFT_HIP_CHECK(ss.join());
+        NUFFT_HIP_CHECK(launch_3d_weight<R>((const C *)c, o.X, M, o.fz, r, sign, cw, s));
+        NUFFT_HIP_CHECK(fused_2d_adj<R>(a, cw, o.D, sign, s));   // empty slices come out zero
         NUFFT_HIP_CHECK(launch_3d_zfft_t<R>(o.D, o.rows, n3, o.Gz, r, sign, (const C *)o.tw, (C *)Cout, s));
     }
     return NUFFT_OK;

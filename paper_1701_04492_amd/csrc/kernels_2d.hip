@@ -24,8 +24,11 @@ namespace nufft {
 template <typename R, int GY, int G>
 __global__ void __launch_bounds__(G * GY / 16)
 k_2d_passA(const cx_t<R> *__restrict__ Cin, int64_t N1, int64_t N2, int64_t GX, Factors<R> fy, int RCA,
-           const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ H)
+           const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ H, int64_t rstride)
 {
+    // stacked problems: blockIdx.y is the problem; H_r2 rows are rstride apart
+    Cin += (int64_t)blockIdx.y * N1 * N2;
+    H += (int64_t)blockIdx.y * GY * GX;
     using C = cx_t<R>;
     constexpr int TPF = GY / 16;
     constexpr int NT = G * TPF;
@@ -66,7 +69,7 @@ k_2d_passA(const cx_t<R> *__restrict__ Cin, int64_t N1, int64_t N2, int64_t GX, 
         __syncthreads();
         block_fft_regs<C, GY, -1, fft_wave_sync<GY>>(buf + g * P, tw, lt, v);
         fft_publish<GY>();
-        C *Hr = H + (int64_t)r * GY * GX + k1_0;
+        C *Hr = H + (int64_t)r * rstride + k1_0;
 #pragma unroll 4
         for (int e = 0; e < 16; ++e) {
             const int i = tid + e * NT;
@@ -333,8 +336,11 @@ k_2d_sum_parts(const int4 *__restrict__ rtasks, const cx_t<R> *__restrict__ Zp, 
 template <typename R, int GY, int G, int DIR>
 __global__ void __launch_bounds__(G * GY / 16)
 k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX, int Ky,
-               const cx_t<R> *__restrict__ twd_g, cx_t<R> *__restrict__ Cout)
+               const cx_t<R> *__restrict__ twd_g, cx_t<R> *__restrict__ Cout, int64_t rstride)
 {
+    // stacked problems: blockIdx.y is the problem; Z_r2 rows are rstride apart
+    Z += (int64_t)blockIdx.y * GY * GX;
+    Cout += (int64_t)blockIdx.y * N1 * N2;
     using C = cx_t<R>;
     constexpr int TPF = GY / 16;
     constexpr int NT = G * TPF;
@@ -365,7 +371,7 @@ k_2d_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N1, int64_t N2, int64_t GX
             buf[(i % G) * P + lds_pad(i / G)] = zn[e];
         }
         if (r + 1 < Ky) {
-            const C *Zr = Z + (int64_t)(r + 1) * GY * GX + k1_0;
+            const C *Zr = Z + (int64_t)(r + 1) * rstride + k1_0;
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int i = tid + e * NT;
@@ -411,6 +417,8 @@ template <typename R>
 hipError_t fused_2d(const Args2D<R> &a, const cx_t<R> *Cin, cx_t<R> *f, hipStream_t s)
 {
     constexpr bool F = sizeof(R) == 4;
+    const int64_t cols = (int64_t)a.S * a.Gy;   // pass-B columns over the stacked problems
+    const int64_t rstride = cols * a.Gx;         // distance between the intermediate's ranks
     prof_begin(a.prof, "fwd2d_passA", s);
     switch (a.Gy) {
 #define A2(GG, GF, GD)                                                                                      \
@@ -421,8 +429,8 @@ hipError_t fused_2d(const Args2D<R> &a, const cx_t<R> *Cin, cx_t<R> *f, hipStrea
         nrc = nrc < 1 ? 1 : (nrc > a.fy.K ? a.fy.K : nrc);                                                  \
         const int rca = (a.fy.K + nrc - 1) / nrc;                                                           \
         const int T = ncg * ((a.fy.K + rca - 1) / rca);                                                     \
-        hipLaunchKernelGGL((k_2d_passA<R, GG, G>), dim3(xcd_grid(T)), dim3(G * GG / 16), 0, s, Cin, a.N1, a.N2, \
-                           (int64_t)a.Gx, a.fy, rca, a.twy, a.H);                                           \
+        hipLaunchKernelGGL((k_2d_passA<R, GG, G>), dim3(xcd_grid(T), a.S), dim3(G * GG / 16), 0, s, Cin, a.N1,  \
+                           a.N2, (int64_t)a.Gx, a.fy, rca, a.twy, a.H, rstride);                            \
         break;                                                                                              \
     }
         A2(16, 8, 8)
@@ -443,7 +451,7 @@ hipError_t fused_2d(const Args2D<R> &a, const cx_t<R> *Cin, cx_t<R> *f, hipStrea
     case GG: {                                                                                              \
         constexpr int RR = F ? RF : RD, SS = F ? SF : SD;                                                   \
         hipLaunchKernelGGL((k_2d_passB<R, GG, RR, SS>), dim3(xcd_grid(a.ntasks)), dim3(RR * GG / 16), 0, s,   \
-                           (const cx_t<R> *)a.H, a.N1, (int64_t)a.Gy, a.tasks, a.ntasks, a.keys, a.perm,     \
+                           (const cx_t<R> *)a.H, a.N1, cols, a.tasks, a.ntasks, a.keys, a.perm,              \
                            a.Xxs, a.Xys, a.fx, a.fy, a.twx, f);                                             \
         break;                                                                                              \
     }
@@ -467,13 +475,15 @@ static hipError_t fused_2d_t1_dir(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R
 {
     constexpr bool F = sizeof(R) == 4;
     const cx_t<R> *twx = DIR < 0 ? a.twx : a.twxi, *twy = DIR < 0 ? a.twy : a.twyi;
+    const int64_t cols = (int64_t)a.S * a.Gy;   // pass-B' columns over the stacked problems
+    const int64_t rstride = cols * a.Gx;
     prof_begin(a.prof, DIR > 0 ? "adj2d_passB" : "type1_2d_passB", s);
     switch (a.Gx) {
 #define BA2(GG, RF, SCF, RD, SCD, TG)                                                                        \
     case GG: {                                                                                              \
         constexpr int RR = F ? RF : RD, SC = F ? SCF : SCD;                                                 \
         hipLaunchKernelGGL((k_2d_passB_adj<R, GG, RR, SC, TG, DIR>), dim3(xcd_grid(a.natasks)),             \
-                           dim3(RR * GG / 16), 0, s, gin, a.N1, (int64_t)a.Gy, a.atasks, a.natasks, a.perm,   \
+                           dim3(RR * GG / 16), 0, s, gin, a.N1, cols, a.atasks, a.natasks, a.perm,            \
                            a.keys, a.Xxs, a.Xys, a.fx, a.fy, twx, a.H, a.Zp);                               \
         break;                                                                                              \
     }
@@ -492,7 +502,7 @@ static hipError_t fused_2d_t1_dir(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R
     if (a.nrtasks > 0) {
         prof_begin(a.prof, DIR > 0 ? "adj2d_sum" : "type1_2d_sum", s);
         hipLaunchKernelGGL(k_2d_sum_parts<R>, dim3(a.nrtasks, a.fy.K), dim3(256), 0, s, a.rtasks,
-                           (const cx_t<R> *)a.Zp, (int64_t)a.Gx, (int64_t)a.Gy, a.fy.K, a.H);
+                           (const cx_t<R> *)a.Zp, (int64_t)a.Gx, cols, a.fy.K, a.H);
         prof_end(a.prof, s);
     }
     prof_begin(a.prof, DIR > 0 ? "adj2d_passA" : "type1_2d_passA", s);
@@ -501,8 +511,8 @@ static hipError_t fused_2d_t1_dir(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R
     case GG: {                                                                                              \
         constexpr int G = F ? GF : GD;                                                                      \
         const int ncg = (int)((a.N1 + G - 1) / G);                                                          \
-        hipLaunchKernelGGL((k_2d_passA_adj<R, GG, G, DIR>), dim3(xcd_grid(ncg)), dim3(G * GG / 16), 0, s,    \
-                           (const cx_t<R> *)a.H, a.N1, a.N2, (int64_t)a.Gx, a.fy.K, twy, Cout);             \
+        hipLaunchKernelGGL((k_2d_passA_adj<R, GG, G, DIR>), dim3(xcd_grid(ncg), a.S), dim3(G * GG / 16), 0, s, \
+                           (const cx_t<R> *)a.H, a.N1, a.N2, (int64_t)a.Gx, a.fy.K, twy, Cout, rstride);    \
         break;                                                                                              \
     }
         AA2(16, 8, 8)
@@ -555,9 +565,9 @@ int pass_b2d_cap(int GX, bool fp32)
 // ---- plan kernel: both axes at once ----------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(256)
-k_assign2d(const double *__restrict__ x, const double *__restrict__ y, int64_t M, int64_t GX, int64_t GY,
-           double sx, double sy, R *__restrict__ Xx, R *__restrict__ Xy, uint32_t *__restrict__ key,
-           int32_t *__restrict__ hist, unsigned long long *gbits, int *bad)
+k_assign2d(const double *__restrict__ x, const double *__restrict__ y, const int32_t *__restrict__ slice, int64_t M,
+           int64_t GX, int64_t GY, double sx, double sy, R *__restrict__ Xx, R *__restrict__ Xy,
+           uint32_t *__restrict__ key, int32_t *__restrict__ hist, unsigned long long *gbits, int *bad)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double ax = 0.0, ay = 0.0;
@@ -580,7 +590,8 @@ k_assign2d(const double *__restrict__ x, const double *__restrict__ y, int64_t M
             ax = fabs(dx);
             ay = fabs(dy);
         }
-        const uint32_t k = (uint32_t)ty * (uint32_t)GX + (uint32_t)tx;
+        const uint32_t sl = slice ? (uint32_t)slice[j] : 0u;   // the plan bounds S * GX * GY below 2^32
+        const uint32_t k = (sl * (uint32_t)GY + (uint32_t)ty) * (uint32_t)GX + (uint32_t)tx;
         Xx[j] = (R)dx;
         Xy[j] = (R)dy;
         key[j] = k;
@@ -598,12 +609,12 @@ k_assign2d(const double *__restrict__ x, const double *__restrict__ y, int64_t M
 }
 
 template <typename R>
-hipError_t launch_assign2d(const double *x, const double *y, int64_t M, int64_t GX, int64_t GY, double sx,
-                           double sy, R *Xx, R *Xy, uint32_t *key, int32_t *hist, unsigned long long *gbits,
-                           int *bad, hipStream_t s)
+hipError_t launch_assign2d(const double *x, const double *y, const int32_t *slice, int64_t M, int64_t GX,
+                           int64_t GY, double sx, double sy, R *Xx, R *Xy, uint32_t *key, int32_t *hist,
+                           unsigned long long *gbits, int *bad, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_assign2d<R>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, x, y, M, GX, GY, sx, sy,
-                       Xx, Xy, key, hist, gbits, bad);
+    hipLaunchKernelGGL(k_assign2d<R>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, x, y, slice, M, GX, GY,
+                       sx, sy, Xx, Xy, key, hist, gbits, bad);
     return hipGetLastError();
 }
 
@@ -611,11 +622,11 @@ template hipError_t fused_2d<float>(const Args2D<float> &, const float2 *, float
 template hipError_t fused_2d<double>(const Args2D<double> &, const double2 *, double2 *, hipStream_t);
 template hipError_t fused_2d_adj<float>(const Args2D<float> &, const float2 *, float2 *, int, hipStream_t);
 template hipError_t fused_2d_adj<double>(const Args2D<double> &, const double2 *, double2 *, int, hipStream_t);
-template hipError_t launch_assign2d<float>(const double *, const double *, int64_t, int64_t, int64_t, double,
-                                           double, float *, float *, uint32_t *, int32_t *, unsigned long long *,
-                                           int *, hipStream_t);
-template hipError_t launch_assign2d<double>(const double *, const double *, int64_t, int64_t, int64_t, double,
-                                            double, double *, double *, uint32_t *, int32_t *,
+template hipError_t launch_assign2d<float>(const double *, const double *, const int32_t *, int64_t, int64_t,
+                                           int64_t, double, double, float *, float *, uint32_t *, int32_t *,
+                                           unsigned long long *, int *, hipStream_t);
+template hipError_t launch_assign2d<double>(const double *, const double *, const int32_t *, int64_t, int64_t,
+                                            int64_t, double, double, double *, double *, uint32_t *, int32_t *,
                                             unsigned long long *, int *, hipStream_t);
 
 }  // namespace nufft

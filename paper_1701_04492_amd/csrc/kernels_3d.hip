@@ -9,14 +9,14 @@
 //
 //   f_j = sum_r u^z_r(j) * [2-D type II of D_r[t^z_j] at (x_j, y_j)],
 //
-// and the samples of one z slice m share one 2-D type-II plan.  The slices'
-// results land in slice-sorted order and `k_3d_accum` adds u^z_r times them
-// into f in sample order.
+// and the samples of one z slice m form problem m of one stacked 2-D plan
+// (its keys carry the slice, so one pass-B launch serves every slice).
+// `k_3d_accum` adds u^z_r times the 2-D results into f.
 //
 // The 3-D type I (sign -1, the transpose) and adjoint (sign +1) run the same
 // factoring backwards: with w_r(j) = u^z_r(j) (type I) or its conjugate
-// (adjoint), `k_3d_weight` forms w_r(j) c_j in slice order, each slice m
-// gets a 2-D type I of those weights, E_r[m][k1][k2], and `k_3d_zfft_t`
+// (adjoint), `k_3d_weight` forms w_r(j) c_j, each slice m gets a 2-D type I
+// of those weights, E_r[m][k1][k2], and `k_3d_zfft_t`
 // finishes C[k1][k2][k3] += v^z_r(k3) sum_m E_r[m][k1][k2] exp(sign 2 pi i k3 m / Gz).
 #include "fused_common.h"
 #include "kernels_3d.h"
@@ -45,14 +45,6 @@ k_3d_assign(const double *__restrict__ z, int64_t M, int64_t n3, int64_t Gz, int
     t[j] = (int32_t)tt;
     X[j] = (R)d;
     atomicMax(gbits, (unsigned long long)__double_as_longlong(fabs(d)));
-}
-
-// out[i] = in[perm[i]] for doubles (the samples of the slices, slice by slice)
-__global__ void __launch_bounds__(256)
-k_3d_gather(const double *__restrict__ in, const int32_t *__restrict__ perm, int64_t M, double *__restrict__ out)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < M) out[i] = in[perm[i]];
 }
 
 // D_r[m][row] = FFT_m( v^z_r(k3) C[row][k3] ), rows = n1 * n2, RC rows per workgroup
@@ -100,43 +92,40 @@ k_3d_zfft(const cx_t<R> *__restrict__ Cin, int64_t rows, int64_t n3, int r, cons
     }
 }
 
-// f[perm[i]] (+)= u^z_r(X_i) fs[i] over the slice-sorted samples i (X in sorted order);
-// u_r = i^r exp(-i pi X) P_r(X / gamma).
+// f[j] (+)= u^z_r(X_j) fs[j]; u_r = i^r exp(-i pi X) P_r(X / gamma).
 template <typename R>
 __global__ void __launch_bounds__(256)
-k_3d_accum(const cx_t<R> *__restrict__ fs, const int32_t *__restrict__ perm, const R *__restrict__ Xs, int64_t M,
-           Factors<R> fac, int r, cx_t<R> *__restrict__ f)
+k_3d_accum(const cx_t<R> *__restrict__ fs, const R *__restrict__ Xz, int64_t M, Factors<R> fac, int r,
+           cx_t<R> *__restrict__ f)
 {
     using C = cx_t<R>;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    const R X = Xs[i];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    const R X = Xz[j];
     R sn, cs;
     sincospi_r(X, &sn, &cs);
     const RankPoly<R> up = rank_poly(fac, r);
     const C u = crot(cscale(cmake<C>(cs, -sn), rank_eval(up, X * fac.inv_gamma)), r);
-    const int32_t j = perm[i];
-    const C add = cmul(u, fs[i]);
+    const C add = cmul(u, fs[j]);
     f[j] = r == 0 ? add : cadd(f[j], add);
 }
 
-// cw[i] = w_r(i) c[perm[i]] over the slice-sorted samples i, w_r = u^z_r (DIR -1) or its
-// conjugate (DIR +1).
+// cw[j] = w_r(j) c[j], w_r = u^z_r (DIR -1) or its conjugate (DIR +1).
 template <typename R, int DIR>
 __global__ void __launch_bounds__(256)
-k_3d_weight(const cx_t<R> *__restrict__ c, const int32_t *__restrict__ perm, const R *__restrict__ Xs, int64_t M,
-            Factors<R> fac, int r, cx_t<R> *__restrict__ cw)
+k_3d_weight(const cx_t<R> *__restrict__ c, const R *__restrict__ Xz, int64_t M, Factors<R> fac, int r,
+            cx_t<R> *__restrict__ cw)
 {
     using C = cx_t<R>;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    const R X = Xs[i];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    const R X = Xz[j];
     R sn, cs;
     sincospi_r(X, &sn, &cs);
     const RankPoly<R> up = rank_poly(fac, r);
     C u = crot(cscale(cmake<C>(cs, -sn), rank_eval(up, X * fac.inv_gamma)), r);
     if (DIR > 0) u = cconj(u);
-    cw[i] = cmul(u, c[perm[i]]);
+    cw[j] = cmul(u, c[j]);
 }
 
 // C[row][k3] (r == 0 ? = : +=) v^z_r(k3) sum_m E[m][row] exp(DIR 2 pi i k3 m / GZ), k3 < n3:
@@ -200,12 +189,6 @@ hipError_t launch_3d_assign(const double *z, int64_t M, int64_t n3, int64_t Gz, 
     return hipGetLastError();
 }
 
-hipError_t launch_3d_gather(const double *in, const int32_t *perm, int64_t M, double *out, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_3d_gather, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, in, perm, M, out);
-    return hipGetLastError();
-}
-
 template <typename R>
 hipError_t launch_3d_zfft(const cx_t<R> *Cin, int64_t rows, int64_t n3, int64_t Gz, int r, const cx_t<R> *tw,
                           cx_t<R> *D, hipStream_t s)
@@ -226,23 +209,22 @@ hipError_t launch_3d_zfft(const cx_t<R> *Cin, int64_t rows, int64_t n3, int64_t 
 }
 
 template <typename R>
-hipError_t launch_3d_accum(const cx_t<R> *fs, const int32_t *perm, const R *Xs, int64_t M, const Factors<R> &fac,
-                           int r, cx_t<R> *f, hipStream_t s)
+hipError_t launch_3d_accum(const cx_t<R> *fs, const R *Xz, int64_t M, const Factors<R> &fac, int r, cx_t<R> *f,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_3d_accum<R>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, fs, perm, Xs, M, fac, r,
-                       f);
+    hipLaunchKernelGGL(k_3d_accum<R>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, fs, Xz, M, fac, r, f);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_3d_weight(const cx_t<R> *c, const int32_t *perm, const R *Xs, int64_t M, const Factors<R> &fac,
-                            int r, int sign, cx_t<R> *cw, hipStream_t s)
+hipError_t launch_3d_weight(const cx_t<R> *c, const R *Xz, int64_t M, const Factors<R> &fac, int r, int sign,
+                            cx_t<R> *cw, hipStream_t s)
 {
     const dim3 g((unsigned)((M + 255) / 256));
     if (sign < 0)
-        hipLaunchKernelGGL((k_3d_weight<R, -1>), g, dim3(256), 0, s, c, perm, Xs, M, fac, r, cw);
+        hipLaunchKernelGGL((k_3d_weight<R, -1>), g, dim3(256), 0, s, c, Xz, M, fac, r, cw);
     else
-        hipLaunchKernelGGL((k_3d_weight<R, 1>), g, dim3(256), 0, s, c, perm, Xs, M, fac, r, cw);
+        hipLaunchKernelGGL((k_3d_weight<R, 1>), g, dim3(256), 0, s, c, Xz, M, fac, r, cw);
     return hipGetLastError();
 }
 
@@ -276,15 +258,15 @@ template hipError_t launch_3d_zfft<float>(const float2 *, int64_t, int64_t, int6
                                           hipStream_t);
 template hipError_t launch_3d_zfft<double>(const double2 *, int64_t, int64_t, int64_t, int, const double2 *,
                                            double2 *, hipStream_t);
-template hipError_t launch_3d_accum<float>(const float2 *, const int32_t *, const float *, int64_t,
-                                           const Factors<float> &, int, float2 *, hipStream_t);
-template hipError_t launch_3d_accum<double>(const double2 *, const int32_t *, const double *, int64_t,
-                                            const Factors<double> &, int, double2 *, hipStream_t);
+template hipError_t launch_3d_accum<float>(const float2 *, const float *, int64_t, const Factors<float> &, int,
+                                           float2 *, hipStream_t);
+template hipError_t launch_3d_accum<double>(const double2 *, const double *, int64_t, const Factors<double> &, int,
+                                            double2 *, hipStream_t);
 
-template hipError_t launch_3d_weight<float>(const float2 *, const int32_t *, const float *, int64_t,
-                                            const Factors<float> &, int, int, float2 *, hipStream_t);
-template hipError_t launch_3d_weight<double>(const double2 *, const int32_t *, const double *, int64_t,
-                                             const Factors<double> &, int, int, double2 *, hipStream_t);
+template hipError_t launch_3d_weight<float>(const float2 *, const float *, int64_t, const Factors<float> &, int, int,
+                                            float2 *, hipStream_t);
+template hipError_t launch_3d_weight<double>(const double2 *, const double *, int64_t, const Factors<double> &, int,
+                                             int, double2 *, hipStream_t);
 template hipError_t launch_3d_zfft_t<float>(const float2 *, int64_t, int64_t, int64_t, int, int, const float2 *,
                                             float2 *, hipStream_t);
 template hipError_t launch_3d_zfft_t<double>(const double2 *, int64_t, int64_t, int64_t, int, int,

@@ -49,6 +49,11 @@ struct nufft_plan_s {
     // 2-D plans (Sec. 4): x pairs with k1 < N1 on Gx points, y with k2 < N2 on Gy points
     int64_t N1 = 0, N2 = 0;
     int Gx = 0, Gy = 0, Kx = 0, Ky = 0;
+    // S independent 2-D problems of the same shape stacked in one plan (the z
+    // slices of a 3-D transform): sample j belongs to problem slice[j] (read at
+    // build time only; null: S = 1); inputs and outputs are S arrays back to back
+    int S = 1;
+    const int32_t *slice = nullptr;
     double gammax = 0, gammay = 0;
     Factors<float> ffx, ffy;
     Factors<double> fdx, fdy;
