@@ -230,10 +230,12 @@ nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_d
  *   f_dev[j] ~ sum_{k1<n1,k2<n2,k3<n3} C_dev[(k1*n2+k2)*n3+k3] exp(-2 pi i (k1 x_j + k2 y_j + k3 z_j)).
  * x_dev, y_dev, z_dev: M doubles each, any finite reals; C_dev: n1*n2*n3 complex,
  * row-major; f_dev: M complex.  The z axis is factored with rank K(eps/2, gamma_z)
- * on a grid of Gz >= n3 points (Gz <= 1024), and each z slice of the samples
- * gets one 2-D type-II plan (n1, n2 up to 2048).  Error ~ eps * ||C||_1 per
- * output.  Plans (one 2-D plan per non-empty slice), allocates and
- * synchronises internally (not graph capturable); NONFINITE for a non-finite z. */
+ * on a grid of Gz >= n3 points (Gz <= 1024), and the samples of each z slice
+ * get a 2-D type II (n1, n2 up to 2048), all slices as the problems of one
+ * stacked 2-D plan.  UNSUPPORTED beyond Gz * Gx * Gy = 2^28 grid points (Gx, Gy:
+ * the powers of two >= n1, n2).  Error ~ eps * ||C||_1 per output.  Plans,
+ * allocates and synchronises internally (not graph capturable); NONFINITE for a
+ * non-finite z. */
 nufft_status nufft3d_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev,
                           int64_t n1, int64_t n2, int64_t n3, const void *C_dev, void *f_dev, double eps,
                           nufft_dtype dtype, void *stream);
@@ -243,7 +245,8 @@ nufft_status nufft3d_exec(int64_t n_pts, const double *x_dev, const double *y_de
  * k1 < n1, k2 < n2, k3 < n3.  x_dev, y_dev, z_dev: M doubles each, any finite reals;
  * c_dev: M complex; C_dev: n1*n2*n3 complex, row-major, overwritten.  The factoring of
  * nufft3d_exec run backwards: the samples weighted by u^z_r (or its conjugate), a
- * 2-D type I per z slice, and one length-Gz transform per (k1, k2) and rank.  Error
+ * 2-D type I per z slice (the stacked plan), and one length-Gz transform per
+ * (k1, k2) and rank; the same size limits.  Error
  * ~ eps * ||c||_1 per output.  Plans, allocates and synchronises internally (not
  * graph capturable); INVALID_ARG for sign not in {-1, +1}, NONFINITE for a
  * non-finite z. */
