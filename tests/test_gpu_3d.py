@@ -111,3 +111,29 @@ def test_3d_type1_rejects_bad_arguments():
         P.nufft3d_type1_exec(x, x, z, c, (2, 2, 2), 1e-6)
     with pytest.raises(P.NufftError):
         P.nufft3d_type1_exec(x, x, x, c, (2, 2, 2), 1e-6, sign=0)
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_3d_samples_in_few_slices(dtype):
+    """Samples crowded into two z slices (most slices of the stacked plan empty), with
+    uniform x, y: type II, type I and adjoint against the direct sums."""
+    rng = W.rng_for(96)
+    n1, n2, n3, M = 12, 20, 24, 3000
+    x, y = rng.random(M) * 2 - 0.5, rng.random(M)
+    z = np.where(rng.random(M) < 0.5, 0.25, 0.75) + (rng.random(M) - 0.5) * 1e-3   # slices near Gz/4, 3Gz/4
+    X, Y, Z = (_t(v, torch.float64) for v in (x, y, z))
+    C = W.complex_normal(rng, n1 * n2 * n3).reshape(n1, n2, n3)
+    c = W.complex_normal(rng, M)
+    Ct, ct = _t(C, dtype), _t(c, dtype)
+    f = P.nufft3d_exec(X, Y, Z, Ct, EPS[dtype]).cpu().numpy()
+    Cc = Ct.cpu().numpy().astype(np.complex128)
+    err = np.abs(f - D.nudft3d(x, y, z, Cc)).max() / np.abs(Cc).sum()
+    print("3-D few slices %s type II err/||C||_1 = %.3e" % (dtype, err), flush=True)
+    assert err <= 4 * EPS[dtype]
+    cc = ct.cpu().numpy().astype(np.complex128)
+    K1, K2, K3 = (k.ravel() for k in np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3), indexing="ij"))
+    for sign in (-1, 1):
+        got = P.nufft3d_type1_exec(X, Y, Z, ct, (n1, n2, n3), EPS[dtype], sign=sign).cpu().numpy().ravel()
+        err = np.abs(got - D.nudft3d_adj(x, y, z, cc, K1, K2, K3, sign=sign)).max() / np.abs(cc).sum()
+        print("   sign %+d err/||c||_1 = %.3e" % (sign, err), flush=True)
+        assert err <= 4 * EPS[dtype]
