@@ -254,6 +254,31 @@ nufft_status nufft3d_type1_exec(int64_t n_pts, const double *x_dev, const double
                                 int64_t n1, int64_t n2, int64_t n3, const void *c_dev, void *C_dev, int sign,
                                 double eps, nufft_dtype dtype, void *stream);
 
+/* A reusable 3-D plan: everything nufft3d_exec / nufft3d_type1_exec build on
+ * each call (the z factoring of the samples and the stacked 2-D plan of their z
+ * slices), built once for the samples x_dev, y_dev, z_dev (M = n_pts doubles
+ * each, read during this call only) and the n1 x n2 x n3 modes.  The same
+ * limits and errors as nufft3d_exec; synchronises once (gamma_z readback).
+ * nufft_plan_info reports K3 (the z rank), gamma_z and Gz * Gx * Gy.
+ * Release with nufft_destroy. */
+nufft_status nufft3d_plan(nufft_plan_t *out, int64_t n1, int64_t n2, int64_t n3, int64_t n_pts,
+                          const double *x_dev, const double *y_dev, const double *z_dev, double eps,
+                          nufft_dtype dtype, void *stream);
+
+/* 3-D type II on a 3-D plan: C_dev (n1*n2*n3 complex, row-major) -> f_dev (M
+ * complex), the result of nufft3d_exec for the plan's samples.  Allocates
+ * nothing and does not synchronise (graph capturable); calls on one plan must
+ * not overlap (they share its intermediate).  INVALID_ARG for a plan of another
+ * kind or a NULL pointer. */
+nufft_status nufft3d_plan_exec(nufft_plan_t plan, const void *C_dev, void *f_dev, void *stream);
+
+/* 3-D type I (sign = -1) or adjoint (sign = +1) on a 3-D plan: c_dev (M
+ * complex) -> C_dev (n1*n2*n3 complex, overwritten), the result of
+ * nufft3d_type1_exec.  Allocates nothing, does not synchronise; calls on one
+ * plan must not overlap.  INVALID_ARG for sign not in {-1, +1}, a plan of
+ * another kind or a NULL pointer. */
+nufft_status nufft3d_plan_type1(nufft_plan_t plan, const void *c_dev, void *C_dev, int sign, void *stream);
+
 /* ---- batches of independent 1-D type II transforms ---------------------- */
 
 /* Plan B independent type-II transforms of sizes N_b (modes, 1 <= N_b <= 2^20)

@@ -47,6 +47,9 @@ _sig = {
     "nufft2d3_exec": [_i64, _vp, _vp, _i64, _vp, _vp, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
     "nufft3d_exec": [_i64, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
     "nufft3d_type1_exec": [_i64, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _int, _dbl, _int, _vp],
+    "nufft3d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
+    "nufft3d_plan_exec": [_vp, _vp, _vp, _vp],
+    "nufft3d_plan_type1": [_vp, _vp, _vp, _int, _vp],
     "nufft2d_plan": [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _dbl, _int, _u32, _vp],
     "nufft2d_exec": [_vp, _vp, _vp, _int, _vp],
     "nufft2d_type1_exec": [_vp, _vp, _vp, _int, _vp],
@@ -264,6 +267,38 @@ def nufft3d_type1_exec(x, y, z, c, shape, eps, sign=-1, C=None):
                                   _dev_tensor(z, torch.float64, M, "z"), n1, n2, n3,
                                   _dev_tensor(c, c.dtype, M, "c"), _dev_tensor(C, c.dtype, n1 * n2 * n3, "C"),
                                   int(sign), float(eps), _cdtype(c.dtype), _stream(c.device)), "nufft3d_type1_exec")
+    return C
+
+
+def nufft3d_plan(x, y, z, shape, eps, dtype=torch.complex64):
+    """A reusable 3-D plan for the samples (x, y, z) and the n1 x n2 x n3 modes of ``shape``."""
+    M = x.numel()
+    n1, n2, n3 = (int(v) for v in shape)
+    h = _vp()
+    _check(lib.nufft3d_plan(ctypes.byref(h), n1, n2, n3, M, _dev_tensor(x, torch.float64, M, "x"),
+                            _dev_tensor(y, torch.float64, M, "y"), _dev_tensor(z, torch.float64, M, "z"),
+                            float(eps), _cdtype(dtype), _stream(x.device)), "nufft3d_plan")
+    return Plan(h, "3d", dtype, x.device, shape=(n1, n2, n3), M=M, eps=float(eps))
+
+
+def nufft3d_plan_exec(plan, C, f=None):
+    """3-D type II on a 3-D plan: C (n1, n2, n3) -> f (M)."""
+    n = plan.shape[0] * plan.shape[1] * plan.shape[2]
+    if f is None:
+        f = torch.empty(plan.M, dtype=plan.dtype, device=plan.device)
+    _check(lib.nufft3d_plan_exec(plan.handle, _dev_tensor(C, plan.dtype, n, "C"),
+                                 _dev_tensor(f, plan.dtype, plan.M, "f"), _stream(plan.device)), "nufft3d_plan_exec")
+    return f
+
+
+def nufft3d_plan_type1(plan, c, sign=-1, C=None):
+    """3-D type I (sign -1) or adjoint (sign +1) on a 3-D plan: c (M) -> C (n1, n2, n3)."""
+    if C is None:
+        C = torch.empty(plan.shape, dtype=plan.dtype, device=plan.device)
+    n = plan.shape[0] * plan.shape[1] * plan.shape[2]
+    _check(lib.nufft3d_plan_type1(plan.handle, _dev_tensor(c, plan.dtype, plan.M, "c"),
+                                  _dev_tensor(C, plan.dtype, n, "C"), int(sign), _stream(plan.device)),
+           "nufft3d_plan_type1")
     return C
 
 

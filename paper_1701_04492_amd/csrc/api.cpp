@@ -930,38 +930,29 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
 // goes to the z factorisation, half to the 2-D transforms, whose errors are
 // weighted by sum_r |u^z_r| w_r <= sum_{p,r} w_p w_r |b_pr| (the same bound
 // serves type I, whose inner inputs are u^z_r c or its conjugate).
+// p: a PLAN_3D plan with dtype, N1, N2, N3, M and eps set; it owns everything built.
 template <typename R>
-struct Slices3D {
-    int64_t Gz = 0, rows = 0;
-    int K3 = 0;
-    Factors<R> fz;
-    R *X = nullptr;               // z perturbation per sample
-    Plan *plan = nullptr;         // the stacked 2-D plan: Gz problems of n1 x n2
-    cx_t<R> *D = nullptr;         // Gz x rows, slice-major
-    void *tw = nullptr;           // length-Gz twiddles, -1 direction
-};
-
-template <typename R>
-static nufft_status setup_3d(Plan &tmp, int64_t M, const double *x, const double *y, const double *z, int64_t n1,
-                             int64_t n2, int64_t n3, double eps, nufft_dtype dt, hipStream_t s, Slices3D<R> &o)
+static nufft_status build_3d(Plan *p, const double *x, const double *y, const double *z, hipStream_t s)
 {
     using C = cx_t<R>;
+    const int64_t M = p->M, n1 = p->N1, n2 = p->N2, n3 = p->N3;
     int64_t Gz = 16;
     while (Gz < n3) Gz <<= 1;
     int gx = 16, gy = 16;
     while (gx < n1) gx <<= 1;
     while (gy < n2) gy <<= 1;
     if (Gz > 1024 || gx > 2048 || gy > 2048 || Gz * gx * gy > (int64_t(1) << 28)) return NUFFT_ERR_UNSUPPORTED;
-    o.Gz = Gz;
-    o.rows = n1 * n2;
-    int32_t *tz = (int32_t *)tmp.alloc(M * sizeof(int32_t));
-    o.X = (R *)tmp.alloc(M * sizeof(R));
-    unsigned long long *flags = (unsigned long long *)tmp.alloc(2 * sizeof(unsigned long long));
-    o.D = (C *)tmp.alloc(Gz * o.rows * sizeof(C));
-    if (!tz || !o.X || !flags || !o.D) return NUFFT_ERR_ALLOC;
+    p->Gz = Gz;
+    const int64_t rows = n1 * n2;
+    int32_t *tz = (int32_t *)p->alloc(M * sizeof(int32_t));
+    p->Xz = p->alloc(M * sizeof(R));
+    unsigned long long *flags = (unsigned long long *)p->alloc(2 * sizeof(unsigned long long));
+    p->Dz = p->alloc(Gz * rows * sizeof(C));
+    p->fsz = p->alloc(M * sizeof(C));
+    if (!tz || !p->Xz || !flags || !p->Dz || !p->fsz) return NUFFT_ERR_ALLOC;
     // z slice and perturbation per sample, and gamma_z
     NUFFT_HIP_CHECK(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), s));
-    NUFFT_HIP_CHECK(launch_3d_assign<R>(z, M, n3, Gz, tz, o.X, flags, (int *)(flags + 1), s));
+    NUFFT_HIP_CHECK(launch_3d_assign<R>(z, M, n3, Gz, tz, (R *)p->Xz, flags, (int *)(flags + 1), s));
     unsigned long long h[2];
     NUFFT_HIP_CHECK(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
     NUFFT_HIP_CHECK(hipStreamSynchronize(s));
@@ -969,25 +960,26 @@ static nufft_status setup_3d(Plan &tmp, int64_t M, const double *x, const double
     double gz;
     std::memcpy(&gz, &h[0], sizeof(double));
     gz = std::min(gz, 0.5);
-    o.K3 = choose_rank(eps / 2.0, gz);
-    if (o.K3 < 0 || (sizeof(R) == 4 && o.K3 > NUFFT_KMAX_F32)) return NUFFT_ERR_UNSUPPORTED;
-    fill_factors(o.fz, gz, o.K3);
+    p->K3 = choose_rank(p->eps / 2.0, gz);
+    if (p->K3 < 0 || (sizeof(R) == 4 && p->K3 > NUFFT_KMAX_F32)) return NUFFT_ERR_UNSUPPORTED;
+    if constexpr (sizeof(R) == 4) fill_factors(p->ffz, gz, p->K3);
+    else fill_factors(p->fdz, gz, p->K3);
     double b[NUFFT_KMAX * NUFFT_KMAX], S = 0.0;
-    bessel_b(gz, o.K3, b);
-    for (int p = 0; p < o.K3; ++p)
-        for (int r = 0; r < o.K3; ++r)
-            S += (p == 0 ? 0.5 : 1.0) * (r == 0 ? 0.5 : 1.0) * std::fabs(b[p * o.K3 + r]);
-    const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
-    const double eps2 = std::max(floor_eps, eps / (2.0 * std::max(S, 1.0)));
+    bessel_b(gz, p->K3, b);
+    for (int q = 0; q < p->K3; ++q)
+        for (int r = 0; r < p->K3; ++r)
+            S += (q == 0 ? 0.5 : 1.0) * (r == 0 ? 0.5 : 1.0) * std::fabs(b[q * p->K3 + r]);
+    const double floor_eps = p->dtype == NUFFT_C64 ? 1e-7 : 1e-15;
+    const double eps2 = std::max(floor_eps, p->eps / (2.0 * std::max(S, 1.0)));
     // one stacked 2-D plan: problem m holds the samples of z slice m
     Plan *q = new (std::nothrow) Plan();
     if (!q) return NUFFT_ERR_ALLOC;
-    tmp.children.push_back(q);
+    p->children.push_back(q);
     q->kind = PLAN_2D;
-    q->dtype = dt;
+    q->dtype = p->dtype;
     q->N1 = n1;
     q->N2 = n2;
-    q->N = o.rows;
+    q->N = rows;
     q->M = M;
     q->eps = eps2;
     q->Gx = gx;
@@ -996,63 +988,58 @@ static nufft_status setup_3d(Plan &tmp, int64_t M, const double *x, const double
     q->S = (int)Gz;
     q->slice = tz;
     const nufft_status st = build_2d<R>(q, x, y, s);
-    q->slice = nullptr;   // tz is not kept beyond the build
+    q->slice = nullptr;   // read at build time only
     if (st) return st;
-    o.plan = q;
+    p->stack = q;
+    p->K = p->K3;
+    p->gamma = gz;
+    p->L = Gz * gx * gy;
     std::vector<double> t(2 * (size_t)Gz);
     fft_twiddles(Gz, -1, t.data());
-    return upload_table<R>(&tmp, t, &o.tw, s);
+    return upload_table<R>(p, t, &p->twz, s);
 }
 
-struct StreamSyncGuard {   // declared after the Plan that owns the temporaries: no temporary is freed under a running kernel
-    hipStream_t s;
-    ~StreamSyncGuard() { (void)hipStreamSynchronize(s); }
-};
+template <typename R>
+static const Factors<R> &z_factors(const Plan *p)
+{
+    if constexpr (sizeof(R) == 4) return p->ffz;
+    else return p->fdz;
+}
 
 // 3-D type II: f = sum_r u^z_r * [2-D type II of slice t^z_j of D_r]
 template <typename R>
-static nufft_status type2_3d(int64_t M, const double *x, const double *y, const double *z, int64_t n1, int64_t n2,
-                             int64_t n3, const void *Cin, void *f, double eps, nufft_dtype dt, hipStream_t s)
+static hipError_t run_type2_3d(const Plan *p, const void *Cin, void *f, hipStream_t s)
 {
     using C = cx_t<R>;
-    Plan tmp;   // owns the temporaries and the stacked plan
-    StreamSyncGuard guard{s};
-    Slices3D<R> o;
-    nufft_status st = setup_3d<R>(tmp, M, x, y, z, n1, n2, n3, eps, dt, s, o);
-    if (st) return st;
-    C *fs = (C *)tmp.alloc(M * sizeof(C));
-    if (!fs) return NUFFT_ERR_ALLOC;
-    const Args2D<R> a = args_2d<R>(o.plan);
-    for (int r = 0; r < o.K3; ++r) {
-        NUFFT_HIP_CHECK(launch_3d_zfft<R>((const C *)Cin, o.rows, n3, o.Gz, r, (const C *)o.tw, o.D, s));
-        NUFFT_HIP_CHECK(fused_2d<R>(a, o.D, fs, s));
-        NUFFT_HIP_CHECK(launch_3d_accum<R>(fs, o.X, M, o.fz, r, (C *)f, s));
+    const Args2D<R> a = args_2d<R>(p->stack);
+    const int64_t rows = p->N1 * p->N2;
+    C *D = (C *)p->Dz, *fs = (C *)p->fsz;
+    for (int r = 0; r < p->K3; ++r) {
+        hipError_t e = launch_3d_zfft<R>((const C *)Cin, rows, p->N3, p->Gz, r, (const C *)p->twz, D, s);
+        if (e == hipSuccess) e = fused_2d<R>(a, D, fs, s);
+        if (e == hipSuccess) e = launch_3d_accum<R>(fs, (const R *)p->Xz, p->M, z_factors<R>(p), r, (C *)f, s);
+        if (e != hipSuccess) return e;
     }
-    return NUFFT_OK;
+    return hipSuccess;
 }
 
 // 3-D type I (sign -1) / adjoint (sign +1): C = sum_r v^z_r * z-DFT over the slices
 // of [2-D type I of slice m, weighted by w_r c]
 template <typename R>
-static nufft_status type1_3d(int64_t M, const double *x, const double *y, const double *z, int64_t n1, int64_t n2,
-                             int64_t n3, const void *c, void *Cout, int sign, double eps, nufft_dtype dt,
-                             hipStream_t s)
+static hipError_t run_type1_3d(const Plan *p, const void *c, void *Cout, int sign, hipStream_t s)
 {
     using C = cx_t<R>;
-    Plan tmp;
-    StreamSyncGuard guard{s};
-    Slices3D<R> o;
-    nufft_status st = setup_3d<R>(tmp, M, x, y, z, n1, n2, n3, eps, dt, s, o);
-    if (st) return st;
-    C *cw = (C *)tmp.alloc(M * sizeof(C));
-    if (!cw) return NUFFT_ERR_ALLOC;
-    const Args2D<R> a = args_2d<R>(o.plan);
-    for (int r = 0; r < o.K3; ++r) {
-        NUFFT_HIP_CHECK(launch_3d_weight<R>((const C *)c, o.X, M, o.fz, r, sign, cw, s));
-        NUFFT_HIP_CHECK(fused_2d_adj<R>(a, cw, o.D, sign, s));   // empty slices come out zero
-        NUFFT_HIP_CHECK(launch_3d_zfft_t<R>(o.D, o.rows, n3, o.Gz, r, sign, (const C *)o.tw, (C *)Cout, s));
+    const Args2D<R> a = args_2d<R>(p->stack);
+    const int64_t rows = p->N1 * p->N2;
+    C *D = (C *)p->Dz, *cw = (C *)p->fsz;
+    for (int r = 0; r < p->K3; ++r) {
+        hipError_t e = launch_3d_weight<R>((const C *)c, (const R *)p->Xz, p->M, z_factors<R>(p), r, sign, cw, s);
+        if (e == hipSuccess) e = fused_2d_adj<R>(a, cw, D, sign, s);   // empty slices come out zero
+        if (e == hipSuccess)
+            e = launch_3d_zfft_t<R>(D, rows, p->N3, p->Gz, r, sign, (const C *)p->twz, (C *)Cout, s);
+        if (e != hipSuccess) return e;
     }
-    return NUFFT_OK;
+    return hipSuccess;
 }
 
 // 2-D type III (Sec. 3.2 applied per axis; the composition is stated with the
@@ -1322,37 +1309,90 @@ nufft_status nufft3_exec(int64_t n_pts, const double *x, int64_t n_freq, const d
     return st;
 }
 
-nufft_status nufft3d_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev, int64_t n1,
-                          int64_t n2, int64_t n3, const void *C, void *f, double eps, nufft_dtype dtype, void *stream)
+// A 3-D plan on the stream, or an error with everything it built released.
+static nufft_status make_3d_plan(Plan **out, int64_t n1, int64_t n2, int64_t n3, int64_t n_pts, const double *x,
+                                 const double *y, const double *z, double eps, nufft_dtype dtype, hipStream_t s)
 {
-    if (n_pts < 1 || n1 < 1 || n2 < 1 || n3 < 1 || !x_dev || !y_dev || !z_dev || !C || !f)
-        return NUFFT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n_pts < 1 || n1 < 1 || n2 < 1 || n3 < 1 || !x || !y || !z) return NUFFT_ERR_INVALID_ARG;
     if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
     if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
     nufft_status st;
     if (!eps_ok(eps, dtype, &st)) return st;
-    hipStream_t s = (hipStream_t)stream;
-    st = dtype == NUFFT_C64 ? type2_3d<float>(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, C, f, eps, dtype, s)
-                            : type2_3d<double>(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, C, f, eps, dtype, s);
-    if (st != NUFFT_OK) (void)hipStreamSynchronize(s);
+    Plan *p = new (std::nothrow) Plan();
+    if (!p) return NUFFT_ERR_ALLOC;
+    p->kind = PLAN_3D;
+    p->dtype = dtype;
+    p->N1 = n1;
+    p->N2 = n2;
+    p->N3 = n3;
+    p->N = n1 * n2 * n3;
+    p->M = n_pts;
+    p->eps = eps;
+    st = dtype == NUFFT_C64 ? build_3d<float>(p, x, y, z, s) : build_3d<double>(p, x, y, z, s);
+    if (st != NUFFT_OK) {
+        (void)hipStreamSynchronize(s);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return NUFFT_OK;
+}
+
+static hipError_t exec_3d(const Plan *p, const void *in, void *out, int type1, int sign, hipStream_t s)
+{
+    if (type1)
+        return p->dtype == NUFFT_C64 ? run_type1_3d<float>(p, in, out, sign, s)
+                                     : run_type1_3d<double>(p, in, out, sign, s);
+    return p->dtype == NUFFT_C64 ? run_type2_3d<float>(p, in, out, s) : run_type2_3d<double>(p, in, out, s);
+}
+
+// The plan-free calls: a temporary plan, released once the stream has finished with it.
+static nufft_status oneshot_3d(int64_t n_pts, const double *x, const double *y, const double *z, int64_t n1,
+                               int64_t n2, int64_t n3, const void *in, void *out, int type1, int sign, double eps,
+                               nufft_dtype dtype, hipStream_t s)
+{
+    Plan *p = nullptr;
+    nufft_status st = make_3d_plan(&p, n1, n2, n3, n_pts, x, y, z, eps, dtype, s);
+    if (st) return st;
+    st = from_hip(exec_3d(p, in, out, type1, sign, s));
+    (void)hipStreamSynchronize(s);
+    delete p;
     return st;
+}
+
+nufft_status nufft3d_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev, int64_t n1,
+                          int64_t n2, int64_t n3, const void *C, void *f, double eps, nufft_dtype dtype, void *stream)
+{
+    if (!C || !f) return NUFFT_ERR_INVALID_ARG;
+    return oneshot_3d(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, C, f, 0, -1, eps, dtype, (hipStream_t)stream);
 }
 
 nufft_status nufft3d_type1_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev,
                                 int64_t n1, int64_t n2, int64_t n3, const void *c, void *C, int sign, double eps,
                                 nufft_dtype dtype, void *stream)
 {
-    if (n_pts < 1 || n1 < 1 || n2 < 1 || n3 < 1 || !x_dev || !y_dev || !z_dev || !c || !C)
-        return NUFFT_ERR_INVALID_ARG;
-    if ((sign != 1 && sign != -1) || (dtype != NUFFT_C64 && dtype != NUFFT_C128)) return NUFFT_ERR_INVALID_ARG;
-    if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
-    nufft_status st;
-    if (!eps_ok(eps, dtype, &st)) return st;
-    hipStream_t s = (hipStream_t)stream;
-    st = dtype == NUFFT_C64 ? type1_3d<float>(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, c, C, sign, eps, dtype, s)
-                            : type1_3d<double>(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, c, C, sign, eps, dtype, s);
-    if (st != NUFFT_OK) (void)hipStreamSynchronize(s);
-    return st;
+    if (!c || !C || (sign != 1 && sign != -1)) return NUFFT_ERR_INVALID_ARG;
+    return oneshot_3d(n_pts, x_dev, y_dev, z_dev, n1, n2, n3, c, C, 1, sign, eps, dtype, (hipStream_t)stream);
+}
+
+nufft_status nufft3d_plan(nufft_plan_t *out, int64_t n1, int64_t n2, int64_t n3, int64_t n_pts, const double *x_dev,
+                          const double *y_dev, const double *z_dev, double eps, nufft_dtype dtype, void *stream)
+{
+    if (!out) return NUFFT_ERR_INVALID_ARG;
+    return make_3d_plan(out, n1, n2, n3, n_pts, x_dev, y_dev, z_dev, eps, dtype, (hipStream_t)stream);
+}
+
+nufft_status nufft3d_plan_exec(nufft_plan_t plan, const void *C, void *f, void *stream)
+{
+    if (!plan || plan->kind != PLAN_3D || !C || !f) return NUFFT_ERR_INVALID_ARG;
+    return from_hip(exec_3d(plan, C, f, 0, -1, (hipStream_t)stream));
+}
+
+nufft_status nufft3d_plan_type1(nufft_plan_t plan, const void *c, void *C, int sign, void *stream)
+{
+    if (!plan || plan->kind != PLAN_3D || !c || !C || (sign != 1 && sign != -1)) return NUFFT_ERR_INVALID_ARG;
+    return from_hip(exec_3d(plan, c, C, 1, sign, (hipStream_t)stream));
 }
 
 nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_dev, int64_t n_freq,

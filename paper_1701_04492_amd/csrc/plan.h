@@ -5,7 +5,7 @@
 
 #include "kernels.h"
 
-enum PlanKind { PLAN_1D = 1, PLAN_2D = 2, PLAN_BATCH = 3 };
+enum PlanKind { PLAN_1D = 1, PLAN_2D = 2, PLAN_BATCH = 3, PLAN_3D = 4 };
 
 struct Profiler {
     struct Rec {
@@ -54,6 +54,15 @@ struct nufft_plan_s {
     // build time only; null: S = 1); inputs and outputs are S arrays back to back
     int S = 1;
     const int32_t *slice = nullptr;
+    // 3-D plans: the z axis (n3 modes on Gz points, rank K3, factors, perturbation
+    // per sample), the stacked 2-D plan of the z slices (a child), and the
+    // Gz x N1 x N2 intermediate, twiddle table and M-sample scratch
+    int64_t N3 = 0, Gz = 0;
+    int K3 = 0;
+    Factors<float> ffz;
+    Factors<double> fdz;
+    void *Xz = nullptr, *Dz = nullptr, *twz = nullptr, *fsz = nullptr;
+    nufft_plan_s *stack = nullptr;
     double gammax = 0, gammay = 0;
     Factors<float> ffx, ffy;
     Factors<double> fdx, fdy;

@@ -137,3 +137,60 @@ def test_3d_samples_in_few_slices(dtype):
         err = np.abs(got - D.nudft3d_adj(x, y, z, cc, K1, K2, K3, sign=sign)).max() / np.abs(cc).sum()
         print("   sign %+d err/||c||_1 = %.3e" % (sign, err), flush=True)
         assert err <= 4 * EPS[dtype]
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_3d_plan_reuse_matches_oneshot(dtype):
+    """A 3-D plan gives the one-shot results bit for bit (same kernels, same plan data),
+    call after call, in both directions; plans of other kinds are refused."""
+    rng = W.rng_for(97)
+    n1, n2, n3, M = 20, 12, 33, 5000
+    x, y, z = rng.random(M) * 2 - 0.5, rng.random(M), rng.random(M) * 3 - 1.0
+    X, Y, Z = (_t(v, torch.float64) for v in (x, y, z))
+    C = _t(W.complex_normal(rng, n1 * n2 * n3).reshape(n1, n2, n3), dtype)
+    c = _t(W.complex_normal(rng, M), dtype)
+    plan = P.nufft3d_plan(X, Y, Z, (n1, n2, n3), EPS[dtype], dtype)
+    f1 = P.nufft3d_exec(X, Y, Z, C, EPS[dtype])
+    for _ in range(2):
+        assert torch.equal(P.nufft3d_plan_exec(plan, C), f1)
+    for sign in (-1, 1):
+        ref = P.nufft3d_type1_exec(X, Y, Z, c, (n1, n2, n3), EPS[dtype], sign=sign)
+        for _ in range(2):
+            assert torch.equal(P.nufft3d_plan_type1(plan, c, sign=sign), ref)
+    plan2d = P.nufft2d_plan(X, Y, n1, n2, EPS[dtype], dtype)
+    with pytest.raises(P.NufftError):
+        P.binding._check(P.binding.lib.nufft3d_plan_exec(plan2d.handle, P.binding._vp(C.data_ptr()),
+                                                         P.binding._vp(c.data_ptr()), None), "kind")
+    with pytest.raises(P.NufftError):
+        P.binding._check(P.binding.lib.nufft2d_exec(plan.handle, P.binding._vp(C.data_ptr()),
+                                                    P.binding._vp(c.data_ptr()), 0, None), "kind")
+
+
+def test_3d_plan_graph_replay():
+    """The plan's type II and adjoint captured in a HIP graph: every replay, with eager
+    work between replays, equals the eager result."""
+    rng = W.rng_for(98)
+    n1, n2, n3, M = 16, 24, 20, 4000
+    x, y, z = rng.random(M), rng.random(M), rng.random(M)
+    X, Y, Z = (_t(v, torch.float64) for v in (x, y, z))
+    C = _t(W.complex_normal(rng, n1 * n2 * n3).reshape(n1, n2, n3), C64)
+    g = _t(W.complex_normal(rng, M), C64)
+    plan = P.nufft3d_plan(X, Y, Z, (n1, n2, n3), 1e-6, C64)
+    f = torch.empty(M, dtype=C64, device=DEV)
+    A = torch.empty((n1, n2, n3), dtype=C64, device=DEV)
+    P.nufft3d_plan_exec(plan, C, f)
+    P.nufft3d_plan_type1(plan, g, sign=1, C=A)
+    f_ref, A_ref = f.clone(), A.clone()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        P.nufft3d_plan_exec(plan, C, f)
+        P.nufft3d_plan_type1(plan, g, sign=1, C=A)
+    for rep in range(3):
+        f.zero_()
+        A.zero_()
+        _ = (C.abs() + 1).sum().item()   # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(f, f_ref), rep
+        assert torch.equal(A, A_ref), rep
