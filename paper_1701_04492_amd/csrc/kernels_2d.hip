@@ -208,7 +208,7 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     __shared__ C buf[RC * P];
     __shared__ C tw_s[TWG ? 1 : GX];
     __shared__ C sval[SCAP];
-    __shared__ R szx[SCAP], szy[SCAP], spy[SCAP];
+    __shared__ R szx[SCAP], szy[SCAP];
     __shared__ unsigned short spos[SCAP];
     __shared__ C hv[RC * NT], tv[RC * NT];
     __shared__ int hix[NT], tix[NT], nxa[NT], nxb[NT];
@@ -259,12 +259,8 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     }
     const ZMap zm = zmap(N1);
     for (int r2 = 0; r2 < fy.K; ++r2) {
-        __syncthreads();   // staging done / previous readers of spy done
-        {
-            const RankPoly<R> uy = rank_poly(fy, r2);
-            for (int i = tid; i < cnt; i += NT) spy[i] = rank_eval(uy, szy[i]);
-        }
-        __syncthreads();
+        __syncthreads();   // staging done
+        const RankPoly<R> uy = rank_poly(fy, r2);   // P^y_r2 is evaluated per sample in the spread
         C za[ZA];
 #pragma unroll
         for (int m = 0; m < ZA; ++m) za[m] = cmake<C>(0, 0);
@@ -281,7 +277,9 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
                 C w;   // exp(DIR i pi (Xx + Xy)) g_j P^y_r2(zy_j)
                 R zx;
             };
-            auto load = [&](int i) -> Sample { return Sample{(int)spos[i], cscale(sval[i], spy[i]), szx[i]}; };
+            auto load = [&](int i) -> Sample {
+                return Sample{(int)spos[i], cscale(sval[i], rank_eval(uy, szy[i])), szx[i]};
+            };
             auto contrib = [&](const Sample &sm, int gg) -> C {
                 // i^(r1 + r2) for the type I, i^-(r1 + r2) for the adjoint
                 return crot(cscale(sm.w, rank_eval(ux[gg], sm.zx)), -DIR * (r0 + gg + r2));
@@ -493,7 +491,7 @@ static hipError_t fused_2d_t1_dir(const Args2D<R> &a, const cx_t<R> *gin, cx_t<R
         BA2(128, 16, 512, 8, 512, false)
         BA2(256, 16, 512, 8, 512, false)
         BA2(512, 8, 1024, 4, 768, false)
-        BA2(1024, 4, 1024, 4, 768, true)
+        BA2(1024, 4, 1280, 4, 768, true)
         BA2(2048, 2, 2304, 2, 1280, true)
 #undef BA2
     default: return hipErrorInvalidValue;
@@ -543,7 +541,7 @@ int pass_b2d_adj_cap(int GX, bool fp32)
     case 16: case 32: case 64: return 256;
     case 128: case 256: return 512;
     case 512: return fp32 ? 1024 : 768;
-    case 1024: return fp32 ? 1024 : 768;
+    case 1024: return fp32 ? 1280 : 768;
     case 2048: return fp32 ? 2304 : 1280;
     default: return 0;
     }
