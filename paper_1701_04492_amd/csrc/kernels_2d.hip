@@ -205,10 +205,13 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     constexpr int NT = RC * TPF;
     constexpr int ZA = GX / NT;           // output positions per thread
     constexpr int P = fft_pitch(GX);
-    __shared__ C buf[RC * P];
+    __shared__ __align__(16) C buf[RC * P];   // 16-byte aligned: cleared with 16-byte stores
     __shared__ C tw_s[TWG ? 1 : GX];
-    __shared__ C sval[SCAP];
-    __shared__ R szx[SCAP], szy[SCAP];
+    // one 16-byte (FP32) record per staged sample: exp(DIR i pi (Xx + Xy)) g_j, zx, zy
+    struct alignas(4 * sizeof(R)) Staged {
+        R re, im, zx, zy;
+    };
+    __shared__ Staged sst[SCAP];
     __shared__ unsigned short spos[SCAP];
     __shared__ C hv[RC * NT], tv[RC * NT];
     __shared__ int hix[NT], tix[NT], nxa[NT], nxb[NT];
@@ -249,9 +252,8 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
                 if (i < cnt) {
                     R sn, cs;
                     sincospi_r(ax[u] + ay[u], &sn, &cs);
-                    sval[i] = cmul(cmake<C>(cs, DIR * sn), gv[u]);   // exp(DIR i pi (Xx + Xy))
-                    szx[i] = ax[u] * fx.inv_gamma;
-                    szy[i] = ay[u] * fy.inv_gamma;
+                    const C v = cmul(cmake<C>(cs, DIR * sn), gv[u]);   // exp(DIR i pi (Xx + Xy))
+                    sst[i] = Staged{v.x, v.y, ax[u] * fx.inv_gamma, ay[u] * fy.inv_gamma};
                     spos[i] = (unsigned short)(kv[u] & (uint32_t)(GX - 1));
                 }
             }
@@ -266,7 +268,13 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
         for (int m = 0; m < ZA; ++m) za[m] = cmake<C>(0, 0);
         for (int r0 = 0; r0 < fx.K; r0 += RC) {
             const int nr = min(RC, fx.K - r0);
-            for (int m = tid; m < RC * P; m += NT) buf[m] = cmake<C>(0, 0);
+            if constexpr (sizeof(R) == 4) {   // 16-byte stores: two grid values each
+                float4 *b4 = reinterpret_cast<float4 *>(buf);
+                for (int m = tid; m < (RC * P) / 2; m += NT) b4[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if ((RC * P) % 2 && tid == 0) buf[RC * P - 1] = cmake<C>(0, 0);
+            } else {
+                for (int m = tid; m < RC * P; m += NT) buf[m] = cmake<C>(0, 0);
+            }
             __syncthreads();
             auto pos = [&](int i) -> int { return (int)spos[i]; };
             RankPoly<R> ux[RC];
@@ -278,7 +286,8 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
                 R zx;
             };
             auto load = [&](int i) -> Sample {
-                return Sample{(int)spos[i], cscale(sval[i], rank_eval(uy, szy[i])), szx[i]};
+                const Staged t = sst[i];
+                return Sample{(int)spos[i], cscale(cmake<C>(t.re, t.im), rank_eval(uy, t.zy)), t.zx};
             };
             auto contrib = [&](const Sample &sm, int gg) -> C {
                 // i^(r1 + r2) for the type I, i^-(r1 + r2) for the adjoint

@@ -1,4 +1,4 @@
-// 3-D type II (Sec. 4's construction with a third axis): device launchers.
+// 3-D type II, type I and adjoint (Sec. 4's construction with a third axis): device launchers.
 #pragma once
 
 #include "kernels.h"

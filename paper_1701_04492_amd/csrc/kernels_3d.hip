@@ -1,4 +1,4 @@
-// 3-D type II by the construction of Sec. 4 with a third axis:
+// 3-D transforms by the construction of Sec. 4 with a third axis; the type II:
 //
 //   f_j = sum_{k1,k2,k3} C[k1][k2][k3] exp(-2 pi i (k1 x_j + k2 y_j + k3 z_j)).
 //
