@@ -219,12 +219,13 @@ def bench_batch(P, W, torch, dev):
     fs = [torch.empty(n, dtype=torch.complex64, device=dev) for n in Ns]
     pts = sum(Ns)
     t0 = time.perf_counter()
-    plan = P.nufft_batch_plan(Ns, xs, 1e-6, torch.complex64, P.NUFFT_FLAG_AUTOTUNE)
+    plan = P.nufft_batch_plan(Ns, xs, 1e-6, torch.complex64)   # autotuned (the default)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     t_batch = time_best(lambda: P.nufft_batch_exec(plan, cs, fs), 20, 3, torch)
     modes = {}
-    for label, fl in (("phased", 0), ("persistent", P.NUFFT_FLAG_BATCH_PERSISTENT)):
+    for label, fl in (("phased", P.NUFFT_FLAG_NO_AUTOTUNE),
+                      ("persistent", P.NUFFT_FLAG_BATCH_PERSISTENT | P.NUFFT_FLAG_NO_AUTOTUNE)):
         pm = P.nufft_batch_plan(Ns, xs, 1e-6, torch.complex64, fl)
         modes[label + "_us"] = round(time_best(lambda: P.nufft_batch_exec(pm, cs, fs), 20, 3, torch) * 1e3, 1)
         del pm
@@ -234,14 +235,14 @@ def bench_batch(P, W, torch, dev):
         with torch.cuda.graph(g, stream=st):
             P.nufft_batch_exec(plan, cs, fs)
     t_graph = time_best(lambda: g.replay(), 20, 3, torch)
-    singles = [P.nufft2_plan(x, n, 1e-6, torch.complex64) for x, n in zip(xs, Ns)]
+    singles = [P.nufft2_plan(x, n, 1e-6, torch.complex64, P.NUFFT_FLAG_NO_AUTOTUNE) for x, n in zip(xs, Ns)]
 
     def run_singles():
         for pl, c, f in zip(singles, cs, fs):
             P.nufft2_exec(pl, c, f)
     t_sep = time_loop(run_singles, 5, 1, torch)
     del singles
-    plains = [P.nufft2_plan(x, n, 1e-6, torch.complex64, P.NUFFT_FLAG_PLAIN) for x, n in zip(xs, Ns)]
+    plains = [P.nufft2_plan(x, n, 1e-6, torch.complex64, P.NUFFT_FLAG_PLAIN_UNFUSED) for x, n in zip(xs, Ns)]
 
     def run_plains():
         for pl, c, f in zip(plains, cs, fs):
@@ -296,7 +297,7 @@ def bench_oversampling(P, W, torch, dev):
     x = torch.from_numpy(W.iid_samples(rng, M)).to(dev)
     f = torch.empty(M, dtype=torch.complex64, device=dev)
     out = {"N": N, "M": M}
-    for label, fl in (("default", 0), ("autotuned", P.NUFFT_FLAG_AUTOTUNE)):
+    for label, fl in (("default", P.NUFFT_FLAG_NO_AUTOTUNE), ("autotuned", 0)):
         pl = P.nufft2_plan(x, N, 1e-6, torch.complex64, fl)
         t = time_best(lambda: P.nufft2_exec(pl, c, f), 20, 3, torch)
         ta = time_best(lambda: P.nufft1_exec(pl, f, +1, c), 10, 2, torch)
@@ -413,12 +414,94 @@ def bench_2d(P, W, torch, dev):
     n, M = 1024, x.shape[0]
     flop = 5 * n * n * 10 * (K2 + K1 * K2) + 8 * M * K1 * K2
     peak = 157.3e12
+    peak_np = 78.6e12   # without packed FP32 instructions (this build disables them)
     return {"Kx": plan.K, "forward_us": round(t_f * 1e3, 1), "adjoint_us": round(t_a * 1e3, 1),
             "type1_us": round(t_1 * 1e3, 1), "forward_pts_per_s": x.shape[0] / (t_f * 1e-3),
             "alu_roofline": {"alg_gflop": round(flop / 1e9, 2), "peak_tflops_fp32": 157.3,
                              "forward_frac": round(flop / (t_f * 1e-3) / peak, 4),
-                             "adjoint_frac": round(flop / (t_a * 1e-3) / peak, 4)},
+                             "adjoint_frac": round(flop / (t_a * 1e-3) / peak, 4),
+                             "peak_tflops_fp32_non_packed": 78.6,
+                             "forward_frac_non_packed": round(flop / (t_f * 1e-3) / peak_np, 4),
+                             "adjoint_frac_non_packed": round(flop / (t_a * 1e-3) / peak_np, 4)},
             "kernels_avg_us": kern}
+
+
+def autograd_step(P, torch, plan, x, c, y):
+    """One forward + backward pass through torch.autograd on the plan: f = F2(x) c,
+    loss = ||f - y||^2, dL/dc and dL/dx."""
+    xg = x.clone().requires_grad_(True)
+    cg = c.clone().requires_grad_(True)
+
+    def step():
+        xg.grad = None
+        cg.grad = None
+        f = P.nufft2(xg, cg, plan)
+        loss = torch.view_as_real(f - y).pow(2).sum()
+        loss.backward()
+    return step, xg, cg
+
+
+def bench_plain_step(P, torch, x, c, y, N, M, eps, steps, warmup):
+    """The spec denominator: the same forward+backward step (N = M = 2^22, eps 1e-6)
+    on the plain unfused FP64 path (scale, stand-alone FFT passes, stored U, separate
+    gather; spread, FFT passes, weighted sum for the adjoint)."""
+    plan = P.nufft2_plan(x, N, eps, torch.complex128, P.NUFFT_FLAG_PLAIN_UNFUSED)
+    step, _, _ = autograd_step(P, torch, plan, x, c.to(torch.complex128), y.to(torch.complex128))
+    ms = time_loop(step, max(3, steps // 4), 2, torch)
+    P.nufft_plan_profile(plan, 1, reserve=32 * (steps + 1))
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    kern = {k: round(t / n * 1e3, 1) for k, (n, t) in P.nufft_plan_profile_read(plan).items()}
+    P.nufft_plan_profile(plan, 0)
+    out = {"K": plan.K, "ms_per_step": round(ms, 4), "pts_per_s": M / (ms * 1e-3), "kernels_avg_us": kern}
+    del plan, step
+    return out
+
+
+def bench_config_rows(P, W, torch, dev):
+    """Rows of the remaining workload configurations:
+    * N = M = 1024, FP64 plain unfused, eps 1e-12 (a launch-latency case);
+    * N = M = 2^20 type II on jittered samples x_j = (j + U(-1/2, 1/2))/N, FP32 eps 1e-6 and FP64 1e-12;
+    * N = M = 2^20 type I and adjoint, iid and jittered, FP32 eps 1e-6 and FP64 eps 1e-12."""
+    out = {}
+    x1, c1 = W.type2_case(1, 1024)
+    pl = P.nufft2_plan(torch.from_numpy(x1).to(dev), 1024, 1e-12, torch.complex128, P.NUFFT_FLAG_PLAIN_UNFUSED)
+    ct = torch.from_numpy(c1).to(dev)
+    ft = torch.empty(1024, dtype=torch.complex128, device=dev)
+    t = time_best(lambda: P.nufft2_exec(pl, ct, ft), 50, 10, torch)
+    out["n1024_fp64_plain_eps1e-12"] = {"K": pl.K, "us": round(t * 1e3, 2), "pts_per_s": 1024 / (t * 1e-3)}
+    del pl
+    N = 1 << 20
+    for dist in ("iid", "jitter"):
+        x, c = W.type2_case(2, N, N, dist)
+        xt = torch.from_numpy(x).to(dev)
+        for label, dt, e in (("fp32_eps1e-6", torch.complex64, 1e-6), ("fp64_eps1e-12", torch.complex128, 1e-12)):
+            pl = P.nufft2_plan(xt, N, e, dt)
+            ct = torch.from_numpy(c).to(dt).to(dev)
+            ft = torch.empty(N, dtype=dt, device=dev)
+            row = {"K": pl.K, "grid": pl.grid}
+            if dist == "jitter":
+                t = time_best(lambda: P.nufft2_exec(pl, ct, ft), 20, 3, torch)
+                row["type2_us"] = round(t * 1e3, 2)
+                row["type2_pts_per_s"] = N / (t * 1e-3)
+            for sign, nm in ((-1, "type1"), (1, "adjoint")):
+                t = time_best(lambda: P.nufft1_exec(pl, ft, sign, ct), 20, 3, torch)
+                row[nm + "_us"] = round(t * 1e3, 2)
+                row[nm + "_pts_per_s"] = N / (t * 1e-3)
+            out["2p20_%s_%s" % (dist, label)] = row
+            del pl
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -469,16 +552,7 @@ def main():
     plan = P.nufft2_plan(x, N, eps, torch.complex64)
     torch.cuda.synchronize()
     plan_ms = 1e3 * (time.perf_counter() - t0)
-    xg = x.clone().requires_grad_(True)
-    cg = c.clone().requires_grad_(True)
-
-    def step():
-        xg.grad = None
-        cg.grad = None
-        f = P.nufft2(xg, cg, plan)
-        loss = torch.view_as_real(f - y).pow(2).sum()
-        loss.backward()
-
+    step, xg, cg = autograd_step(P, torch, plan, x, c, y)
     ms = time_loop(step, args.steps, args.warmup, torch)
     assert xg.grad is not None and cg.grad is not None
     value = M / (ms * 1e-3)
@@ -503,12 +577,16 @@ def main():
     dk = kernels[dom]
     lib_us = sum(v["avg_us"] * v["calls"] for v in kernels.values()) / args.steps
     lib_bytes = sum(v["alg_bytes"] * v["calls"] for v in kernels.values() if v["alg_bytes"]) / args.steps
+    step_bytes = sum(v["alg_bytes"] * v["calls"] for v in kernels.values() if v["alg_bytes"]) / args.steps
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dk["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic_record(dom),
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_us": dk["avg_us"],
                 "all_library_kernels": {"us_per_step": round(lib_us, 2),
                                         "GBs": round(lib_bytes / (lib_us * 1e-6) / 1e9, 1),
                                         "frac": round(lib_bytes / (lib_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+                "step": {"alg_bytes": int(step_bytes), "ms": round(ms, 4),
+                         "GBs": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+                         "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                 "kernels": kernels}
 
     out = {
@@ -540,9 +618,9 @@ def main():
         x2 = torch.from_numpy(W.iid_samples(r2, N2)).to(dev)
         sec = {}
         for label, dt, e, fl in (("fused_fp32_eps1e-6", torch.complex64, 1e-6, 0),
-                                 ("plain_fp64_eps1e-6", torch.complex128, 1e-6, P.NUFFT_FLAG_PLAIN),
+                                 ("plain_fp64_eps1e-6", torch.complex128, 1e-6, P.NUFFT_FLAG_PLAIN_UNFUSED),
                                  ("fused_fp64_eps1e-12", torch.complex128, 1e-12, 0),
-                                 ("plain_fp64_eps1e-12", torch.complex128, 1e-12, P.NUFFT_FLAG_PLAIN)):
+                                 ("plain_fp64_eps1e-12", torch.complex128, 1e-12, P.NUFFT_FLAG_PLAIN_UNFUSED)):
             pl = P.nufft2_plan(x2, N2, e, dt, fl)
             ct = torch.from_numpy(c2).to(dt).to(dev)
             ft = torch.empty(N2, dtype=dt, device=dev)
@@ -566,6 +644,10 @@ def main():
         out["forward_2p20"] = sec
 
     if not args.no_secondary:
+        ps = bench_plain_step(P, torch, x, c, y, N, M, eps, args.steps, args.warmup)
+        ps["speedup_fused_fp32_vs_plain_fp64"] = round(ps["ms_per_step"] / ms, 2)
+        out["fwd_bwd_2p22_plain_fp64"] = ps
+        out["config_rows"] = bench_config_rows(P, W, torch, dev)
         out["fwd_bwd_2p22_half"] = bench_half(P, torch, xg.detach(), c, y, N, M, args.steps, args.warmup)
         out["batch_512"] = bench_batch(P, W, torch, dev)
         out["polar_2d"] = bench_2d(P, W, torch, dev)
@@ -580,6 +662,12 @@ def main():
         c_in = c.cpu().numpy().astype(np.complex128)   # the complex64 input the GPU transformed
         out["cpu_baseline"], out["accuracy_2p22_forward"] = cpu_baseline(x_np, c_in, N, args.cpu_seconds,
                                                                          f_gpu, eps)
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+    # release every plan and the device tensors before returning
+    del plan, step, xg, cg
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

@@ -63,18 +63,31 @@ enum {
      * max|N(x_j - s_j/L)|: K then depends only on N, L and eps (Sec. 2.2),
      * e.g. for plans rebuilt as samples move during optimisation. */
     NUFFT_FLAG_FIX_GAMMA_HALF = 1u,
-    /* Run the plain unfused online stage: scale kernel, stand-alone FFT
-     * passes over a K x L buffer, a stored U table (Sec. 2.3, "Planning the
-     * transform") and a separate gather/row-sum kernel.  Default is fused. */
-    NUFFT_FLAG_PLAIN = 2u,
-    /* Autotuning at plan time (reported as `grid` by nufft_plan_info).
-     * 1-D plans: oversampling (Sec. 2.3) -- the plan is built on the grid
-     * L0 (smallest power of two >= max(16, N)) and on 2 L0, where
-     * gamma <= N / (4 L0) lowers K; one type-II transform of each is timed
-     * on a scratch input and the faster plan is kept (up to L = 2^23).
-     * Batches: the persistent launch is timed at a few grid sizes and the
-     * fastest kept.  Results do not depend on the choice beyond eps. */
-    NUFFT_FLAG_AUTOTUNE = 4u,
+    /* Run the plain unfused online stage (Sec. 2.3, the two-step form as
+     * written): every intermediate goes through HBM.
+     *   type II: scale kernel (K x L buffer), stand-alone FFT passes, a
+     *     stored U table (M x K) and a separate gather/row-sum kernel;
+     *   type I / adjoint (Sec. 3.1): a spread kernel (one thread per grid
+     *     point sums its samples times u_r or conj(u_r) into a K x L buffer),
+     *     the stand-alone FFT passes of the other sign, and a kernel that
+     *     weights by v_r and sums over r;
+     *   derivative pass: the type II on -2 pi i k c.
+     * The grid is never autotuned.  Default is the fused kernels. */
+    NUFFT_FLAG_PLAIN_UNFUSED = 2u,
+    /* Plans are autotuned by default (the choice is reported as `grid` by
+     * nufft_plan_info); this flag turns it off.
+     * 1-D plans: oversampling (Sec. 2.3) -- besides the grid L0 (smallest
+     * power of two >= max(16, N)) the plan is built on 2 L0, where
+     * gamma <= N / (4 L0) lowers K; one type-II transform of each is timed on
+     * a scratch input and the faster plan is kept (up to L = 2^23).
+     * Batches: the three phased launches and the persistent launch at a few
+     * grid sizes are timed and the fastest kept.
+     * A choice is remembered per problem class (plan kind, sizes, dtype, eps,
+     * flags and the rank at L0) for the life of the process, so later plans of
+     * the class are not timed again and get the same grid.  Results do not
+     * depend on the choice beyond eps.  PLAIN_UNFUSED plans and 2-D / 3-D
+     * plans have nothing to tune. */
+    NUFFT_FLAG_NO_AUTOTUNE = 4u,
     /* 1-D complex64 plans only, eps >= 2^-10 (Table 1's "half" precision):
      * the K x L intermediate that the two passes exchange through HBM
      * (N > 4096) is stored as fp16 pairs, 4 bytes per value instead of 8,
@@ -82,12 +95,13 @@ enum {
      * adjoint) so that no value overflows.  Arithmetic stays FP32.  The
      * storage rounding adds at most about 2^-11 * sum_r |u_r| * ||c||_1 to
      * each output, inside the 4 eps ||c||_1 bound for eps >= 2^-10.
-     * Combined with NUFFT_FLAG_PLAIN: NUFFT_ERR_INVALID_ARG; with complex128
-     * or a smaller eps: NUFFT_ERR_UNSUPPORTED. */
+     * Combined with NUFFT_FLAG_PLAIN_UNFUSED: NUFFT_ERR_INVALID_ARG; with
+     * complex128 or a smaller eps: NUFFT_ERR_UNSUPPORTED. */
     NUFFT_FLAG_HALF_EXCHANGE = 8u,
     /* Batches only: run each exec as one persistent launch over a task queue
      * (workgroups claim tasks; a pass-B task waits on its transform's pass-A
-     * tasks) instead of three plain launches, one per task type. */
+     * tasks) instead of three plain launches, one per task type.  The
+     * autotuner then times only persistent grid sizes. */
     NUFFT_FLAG_BATCH_PERSISTENT = 16u
 };
 
@@ -101,8 +115,9 @@ enum {
  *   n_pts    M >= 1, number of samples.
  *   x_dev    M doubles, any finite reals (periodic in 1); read during the call.
  *   eps      working accuracy, 0 < eps < 1, above the precision floor.
- * The FFT grid L is the smallest power of two >= 16 and >= N (oversampling
- * with N <= L < 2N, Sec. 2.3); N up to 2^23 (NUFFT_ERR_UNSUPPORTED beyond),
+ * The FFT grid L is the smallest power of two L0 >= 16 and >= N (oversampling
+ * with N <= L < 2N, Sec. 2.3), or 2 L0 when the autotuner (on unless
+ * NUFFT_FLAG_NO_AUTOTUNE) finds it faster; N up to 2^23 (NUFFT_ERR_UNSUPPORTED beyond),
  * M up to 2^30.  Synchronises `stream` once, to read gamma and the
  * non-finite flag back (NUFFT_ERR_NONFINITE). */
 nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts,
@@ -117,7 +132,8 @@ nufft_status nufft2_exec(nufft_plan_t plan, const void *c_dev, void *f_dev, void
 /* Transpose and adjoint of type II (Sec. 3.1):
  *   sign = -1: f_dev[k] ~ sum_{j<M} c_dev[j] exp(-2 pi i x_j k)   (type I, F2^T c)
  *   sign = +1: f_dev[k] ~ sum_{j<M} c_dev[j] exp(+2 pi i x_j k)   (adjoint, F2^H c)
- * c_dev: M complex, f_dev: N complex. */
+ * c_dev: M complex, f_dev: N complex.  On a NUFFT_FLAG_PLAIN_UNFUSED plan the
+ * plain kernels run (spread, FFT passes, weighted sum). */
 nufft_status nufft1_exec(nufft_plan_t plan, const void *c_dev, void *f_dev, int sign,
                          void *stream);
 
@@ -178,7 +194,13 @@ nufft_status nufft1_solve(nufft_plan_t plan, const void *f_dev, void *c_dev, dou
 /* Type III (Sec. 3.2): f_dev[j] ~ sum_{k<N} c_dev[k] exp(-2 pi i x_j w_k), j < M,
  * composed as F3 = A o B o F1(t,:) from up to 2K type-I transforms on the
  * samples w/N.  x_dev: M doubles in [0, 1); w_dev: N doubles in [0, N).
- * Plans, allocates and synchronises internally (not graph capturable). */
+ * Error bound: half of eps goes to the factorisation, and the inner
+ * transforms run at eps_i = max(eps / (2 s), floor) with s = sum_{p,r} w_p |b_pr|
+ * (about 4 at gamma = 1/2) and the precision floor of the dtype, so
+ * |f~_j - f_j| <= (eps/2 + s eps_i) ||c||_1 plus rounding; when that exceeds
+ * 4 eps ||c||_1 the call returns NUFFT_ERR_UNSUPPORTED (complex64 with
+ * gamma near 1/2: eps below about 1.2e-7).  Plans, allocates and
+ * synchronises internally (not graph capturable). */
 nufft_status nufft3_exec(int64_t n_pts, const double *x_dev, int64_t n_freq,
                          const double *w_dev, const void *c_dev, void *f_dev,
                          double eps, nufft_dtype dtype, void *stream);
@@ -217,7 +239,10 @@ nufft_status nufft2d_type1_exec(nufft_plan_t plan, const void *c_dev, void *F_de
  * the Kx * Ky inner transforms are 2-D type I on the samples
  * (w1/n1, w2/n2) with n1 + 1 by n2 + 1 modes, read at
  * (round(n1 x_j), round(n2 y_j)).  c_dev: Q complex, f_dev: M complex.
- * Error ~ eps * ||c||_1 per output.  Plans, allocates and synchronises
+ * Error per output at most (eps/2 + s eps_i) ||c||_1 with s = s_x s_y (about
+ * 16 at gamma = 1/2, s_axis as for nufft3_exec) and eps_i = max(eps / (2 s),
+ * floor); NUFFT_ERR_UNSUPPORTED when that exceeds 4 eps ||c||_1 (complex64
+ * with gamma near 1/2: eps below about 5e-7).  Plans, allocates and synchronises
  * internally (not graph capturable); INVALID_ARG for samples or
  * frequencies out of range or not finite. */
 nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_dev, int64_t n_freq,
@@ -233,7 +258,10 @@ nufft_status nufft2d3_exec(int64_t n_pts, const double *x_dev, const double *y_d
  * on a grid of Gz >= n3 points (Gz <= 1024), and the samples of each z slice
  * get a 2-D type II (n1, n2 up to 2048), all slices as the problems of one
  * stacked 2-D plan.  UNSUPPORTED beyond Gz * Gx * Gy = 2^28 grid points (Gx, Gy:
- * the powers of two >= n1, n2).  Error ~ eps * ||C||_1 per output.  Plans,
+ * the powers of two >= n1, n2).  Error per output at most (eps/2 + S eps2)
+ * ||C||_1, S = sum_{p,r} w_p w_r |b_pr| of the z factors (about 3 at
+ * gamma = 1/2) and eps2 = max(eps / (2 S), floor) for the 2-D transforms;
+ * NUFFT_ERR_UNSUPPORTED when that exceeds 4 eps ||C||_1.  Plans,
  * allocates and synchronises internally (not graph capturable); NONFINITE for a
  * non-finite z. */
 nufft_status nufft3d_exec(int64_t n_pts, const double *x_dev, const double *y_dev, const double *z_dev,
@@ -290,9 +318,9 @@ nufft_status nufft3d_plan_type1(nufft_plan_t plan, const void *c_dev, void *C_de
  * launches (whole small transforms, pass-A column groups, pass-B tiles; one
  * workgroup per task, tasks in decreasing order of size), or one persistent
  * launch with NUFFT_FLAG_BATCH_PERSISTENT.
- * Flags: NUFFT_FLAG_FIX_GAMMA_HALF, NUFFT_FLAG_AUTOTUNE (times the
- * persistent launch at 1..4 workgroups per CU and, unless
- * NUFFT_FLAG_BATCH_PERSISTENT, the phased launches; keeps the fastest),
+ * Flags: NUFFT_FLAG_FIX_GAMMA_HALF, NUFFT_FLAG_NO_AUTOTUNE (by default the
+ * persistent launch is timed at 1..4 workgroups per CU and, unless
+ * NUFFT_FLAG_BATCH_PERSISTENT, the phased launches too; the fastest is kept),
  * NUFFT_FLAG_BATCH_PERSISTENT. */
 nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_modes_host,
                               const int64_t *n_pts_host, const double *const *x_dev_host,
@@ -306,6 +334,16 @@ nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_mod
 nufft_status nufft_batch_exec(nufft_plan_t plan, const void *const *c_dev_host,
                               void *const *f_dev_host, void *stream);
 
+/* Health of a batch plan's persistent launches.  A pass-B task of the
+ * persistent launch waits for its transform's pass-A tasks with a bounded
+ * spin (by construction every such wait ends; the bound only guarantees that
+ * no kernel can hang).  A wait that reaches its bound gives up, its task then
+ * reads an unfinished intermediate, and the launch still returns normally.
+ * Waits for `stream`, then reports in *timeouts_host the number of waits that
+ * gave up since the previous call (0 for a healthy plan) and clears the
+ * count.  Synchronises the stream (not graph capturable). */
+nufft_status nufft_batch_status(nufft_plan_t plan, int64_t *timeouts_host, void *stream);
+
 /* ---- plan queries and lifetime ----------------------------------------- */
 
 /* Any output pointer may be NULL.  For 2-D plans K and gamma describe the
@@ -318,7 +356,11 @@ nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *
  * sample index at sorted position i (M int32).  1-D plans only. */
 nufft_status nufft_plan_perm(nufft_plan_t plan, int32_t *perm_host);
 
-/* Waits for the plan's work, then frees it.  NULL is accepted. */
+/* Frees the plan.  When the stream the plan last ran on (or was built on) is
+ * not being captured into a graph, its queued work is waited for first; no
+ * other stream or device-wide wait is made, so another stream may be
+ * capturing meanwhile.  A plan whose work was captured into a graph must
+ * outlive every replay of that graph.  NULL is accepted. */
 nufft_status nufft_destroy(nufft_plan_t plan);
 
 const char *nufft_status_string(nufft_status status);
@@ -348,6 +390,14 @@ nufft_status nufft_plan_profile_read(nufft_plan_t plan, int index, char *name, i
  * built; the injection then disarms itself.  n < 0 disarms it.  Process-wide
  * state, not meant for concurrent use.  Always returns NUFFT_OK. */
 nufft_status nufft_debug_fail_alloc(int64_t n);
+
+/* For tests of the persistent batch launch's bounded wait: from the next exec
+ * on, each pass-B wait spins at most spin_limit times (default 2^28), and with
+ * unreachable != 0 its target count is one that is never reached, so that
+ * every wait gives up after its bound and is reported by nufft_batch_status;
+ * every kernel still ends normally.  INVALID_ARG for a non-batch plan or a
+ * negative limit. */
+nufft_status nufft_debug_batch_wait(nufft_plan_t plan, int64_t spin_limit, int unreachable);
 
 /* ---- host-side factor generator (no GPU work) --------------------------- */
 

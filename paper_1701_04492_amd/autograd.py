@@ -15,9 +15,17 @@ from . import binding as B
 class NufftTypeII(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, c, plan):
+        # the plan must belong to x: the same number of samples, and when x is the very
+        # tensor the plan was built from, no in-place write since then (a copy of the
+        # planned samples, e.g. x.clone().requires_grad_(), is accepted as it is)
+        key = getattr(plan, "x_key", None)
+        if key is not None:
+            ptr, version, m = key
+            if x.numel() != m or (x.data_ptr() == ptr and x._version != version):
+                raise ValueError("the plan was built from other samples (or x changed in place since): re-plan")
         ctx.plan = plan
         ctx.save_for_backward(c)
-        return B.nufft2_exec(plan, c.contiguous())
+        return B.nufft2_exec(plan, c.resolve_conj().resolve_neg().contiguous())
 
     @staticmethod
     def backward(ctx, g):
@@ -26,7 +34,9 @@ class NufftTypeII(torch.autograd.Function):
         if not (need_x or need_c):
             return None, None, None
         # one call: g is put in the plan's sample order once for both passes
-        gc, gx = B.nufft2_backward(ctx.plan, c.contiguous(), g.contiguous(), need_c=need_c, need_x=need_x)
+        # a conjugated view of g (e.g. from a loss over f.conj()) shares the unconjugated storage
+        g = g.resolve_conj().resolve_neg().contiguous()
+        gc, gx = B.nufft2_backward(ctx.plan, c.contiguous(), g, need_c=need_c, need_x=need_x)
         return gx, gc, None
 
 

@@ -18,8 +18,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "nufft_mi355x.h")
 
 NUFFT_C64, NUFFT_C128 = 0, 1
 NUFFT_FLAG_FIX_GAMMA_HALF = 1
-NUFFT_FLAG_PLAIN = 2
-NUFFT_FLAG_AUTOTUNE = 4
+NUFFT_FLAG_PLAIN_UNFUSED = 2
+NUFFT_FLAG_NO_AUTOTUNE = 4
 NUFFT_FLAG_HALF_EXCHANGE = 8
 NUFFT_FLAG_BATCH_PERSISTENT = 16
 STATUS = {0: "NUFFT_OK", 1: "NUFFT_ERR_INVALID_ARG", 2: "NUFFT_ERR_UNSUPPORTED", 3: "NUFFT_ERR_ALLOC",
@@ -62,6 +62,8 @@ _sig = {
     "nufft_plan_profile": [_vp, _int, _int],
     "nufft_plan_profile_read": [_vp, _int, ctypes.c_char_p, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl)],
     "nufft_debug_fail_alloc": [_i64],
+    "nufft_batch_status": [_vp, ctypes.POINTER(_i64), _vp],
+    "nufft_debug_batch_wait": [_vp, _i64, _int],
     "nufft_choose_rank": [_dbl, _dbl, ctypes.POINTER(_int)],
     "nufft_bessel_coefficients": [_dbl, _int, _vp],
 }
@@ -94,9 +96,19 @@ def _stream(dev):
     return _vp(torch.cuda.current_stream(dev).cuda_stream)
 
 
+def _res(t):
+    """An input with its lazy conjugate / negative bits materialised: such a view shares
+    the unconjugated storage, so its raw pointer would carry the wrong values."""
+    if isinstance(t, torch.Tensor) and (t.is_conj() or t.is_neg()):
+        return t.resolve_conj().resolve_neg()
+    return t
+
+
 def _dev_tensor(t, dtype, n, name):
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.is_conj() or t.is_neg():
+        raise ValueError("%s is a lazily conjugated or negated view; resolve it first" % name)
     if t.dtype != dtype:
         raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
     if n is not None and t.numel() != n:
@@ -145,12 +157,14 @@ def nufft2_plan(x, n_modes, eps, dtype=torch.complex64, flags=0):
     h = _vp()
     _check(lib.nufft2_plan(ctypes.byref(h), int(n_modes), M, px, float(eps), _cdtype(dtype), int(flags),
                            _stream(x.device)), "nufft2_plan")
-    return Plan(h, "1d", dtype, x.device, N=int(n_modes), M=M, eps=float(eps), flags=int(flags))
+    return Plan(h, "1d", dtype, x.device, N=int(n_modes), M=M, eps=float(eps), flags=int(flags),
+                x_key=(x.data_ptr(), x._version, M))
 
 
 def nufft2_exec(plan, c, f=None):
     if f is None:
         f = torch.empty(plan.M, dtype=plan.dtype, device=plan.device)
+    c = _res(c)
     _check(lib.nufft2_exec(plan.handle, _dev_tensor(c, plan.dtype, plan.N, "c"),
                            _dev_tensor(f, plan.dtype, plan.M, "f"), _stream(plan.device)), "nufft2_exec")
     return f
@@ -159,6 +173,7 @@ def nufft2_exec(plan, c, f=None):
 def nufft1_exec(plan, c, sign=-1, f=None):
     if f is None:
         f = torch.empty(plan.N, dtype=plan.dtype, device=plan.device)
+    c = _res(c)
     _check(lib.nufft1_exec(plan.handle, _dev_tensor(c, plan.dtype, plan.M, "c"),
                            _dev_tensor(f, plan.dtype, plan.N, "f"), int(sign), _stream(plan.device)),
            "nufft1_exec")
@@ -168,6 +183,7 @@ def nufft1_exec(plan, c, sign=-1, f=None):
 def nufft2_grad_x(plan, c, g, gx=None):
     if gx is None:
         gx = torch.empty(plan.M, dtype=torch.float64, device=plan.device)
+    c, g = _res(c), _res(g)
     _check(lib.nufft2_grad_x(plan.handle, _dev_tensor(c, plan.dtype, plan.N, "c"),
                              _dev_tensor(g, plan.dtype, plan.M, "g"),
                              _dev_tensor(gx, torch.float64, plan.M, "gx"), _stream(plan.device)),
@@ -184,6 +200,7 @@ def nufft2_backward(plan, c, g, gc=None, gx=None, need_c=True, need_x=True):
         gc = torch.empty(plan.N, dtype=plan.dtype, device=plan.device)
     if need_x and gx is None:
         gx = torch.empty(plan.M, dtype=torch.float64, device=plan.device)
+    c, g = _res(c), _res(g)
     _check(lib.nufft2_backward(plan.handle, _dev_tensor(c, plan.dtype, plan.N, "c") if need_x else None,
                                _dev_tensor(g, plan.dtype, plan.M, "g"),
                                _dev_tensor(gc, plan.dtype, plan.N, "gc") if need_c else None,
@@ -199,6 +216,7 @@ def nufft2_solve(plan, f, c=None, tol=1e-6, max_iter=200):
         c = torch.empty(plan.N, dtype=plan.dtype, device=plan.device)
     it = _int()
     res = _dbl()
+    f = _res(f)
     _check(lib.nufft2_solve(plan.handle, _dev_tensor(f, plan.dtype, plan.M, "f"),
                             _dev_tensor(c, plan.dtype, plan.N, "c"), float(tol), int(max_iter),
                             ctypes.byref(it), ctypes.byref(res), _stream(plan.device)), "nufft2_solve")
@@ -212,6 +230,7 @@ def nufft1_solve(plan, f, c=None, tol=1e-6, max_iter=200):
         c = torch.empty(plan.M, dtype=plan.dtype, device=plan.device)
     it = _int()
     res = _dbl()
+    f = _res(f)
     _check(lib.nufft1_solve(plan.handle, _dev_tensor(f, plan.dtype, plan.N, "f"),
                             _dev_tensor(c, plan.dtype, plan.M, "c"), float(tol), int(max_iter),
                             ctypes.byref(it), ctypes.byref(res), _stream(plan.device)), "nufft1_solve")
@@ -220,6 +239,7 @@ def nufft1_solve(plan, f, c=None, tol=1e-6, max_iter=200):
 
 def nufft3_exec(x, w, c, eps, f=None):
     M, N = x.numel(), w.numel()
+    c = _res(c)
     if f is None:
         f = torch.empty(M, dtype=c.dtype, device=c.device)
     _check(lib.nufft3_exec(M, _dev_tensor(x, torch.float64, M, "x"), N, _dev_tensor(w, torch.float64, N, "w"),
@@ -232,6 +252,7 @@ def nufft2d3_exec(x, y, w1, w2, n1, n2, c, eps, f=None):
     """2-D type III: f_j = sum_k c_k exp(-2 pi i (x_j w1_k + y_j w2_k)); x, y in [0, 1),
     w1 in [0, n1), w2 in [0, n2)."""
     M, Q = x.numel(), w1.numel()
+    c = _res(c)
     if f is None:
         f = torch.empty(M, dtype=c.dtype, device=c.device)
     _check(lib.nufft2d3_exec(M, _dev_tensor(x, torch.float64, M, "x"), _dev_tensor(y, torch.float64, M, "y"), Q,
@@ -246,7 +267,7 @@ def nufft3d_exec(x, y, z, C, eps, f=None):
     an (n1, n2, n3) complex tensor (row-major)."""
     M = x.numel()
     n1, n2, n3 = C.shape
-    Cf = C.reshape(-1)   # held here for the duration of the call
+    Cf = _res(C).reshape(-1)   # held here for the duration of the call
     if f is None:
         f = torch.empty(M, dtype=C.dtype, device=C.device)
     _check(lib.nufft3d_exec(M, _dev_tensor(x, torch.float64, M, "x"), _dev_tensor(y, torch.float64, M, "y"),
@@ -261,6 +282,7 @@ def nufft3d_type1_exec(x, y, z, c, shape, eps, sign=-1, C=None):
     C[k1,k2,k3] = sum_j c_j exp(sign 2 pi i (k1 x_j + k2 y_j + k3 z_j)), shape = (n1, n2, n3)."""
     M = x.numel()
     n1, n2, n3 = (int(v) for v in shape)
+    c = _res(c)
     if C is None:
         C = torch.empty((n1, n2, n3), dtype=c.dtype, device=c.device)
     _check(lib.nufft3d_type1_exec(M, _dev_tensor(x, torch.float64, M, "x"), _dev_tensor(y, torch.float64, M, "y"),
@@ -284,6 +306,7 @@ def nufft3d_plan(x, y, z, shape, eps, dtype=torch.complex64):
 def nufft3d_plan_exec(plan, C, f=None):
     """3-D type II on a 3-D plan: C (n1, n2, n3) -> f (M)."""
     n = plan.shape[0] * plan.shape[1] * plan.shape[2]
+    C = _res(C)
     if f is None:
         f = torch.empty(plan.M, dtype=plan.dtype, device=plan.device)
     _check(lib.nufft3d_plan_exec(plan.handle, _dev_tensor(C, plan.dtype, n, "C"),
@@ -296,6 +319,7 @@ def nufft3d_plan_type1(plan, c, sign=-1, C=None):
     if C is None:
         C = torch.empty(plan.shape, dtype=plan.dtype, device=plan.device)
     n = plan.shape[0] * plan.shape[1] * plan.shape[2]
+    c = _res(c)
     _check(lib.nufft3d_plan_type1(plan.handle, _dev_tensor(c, plan.dtype, plan.M, "c"),
                                   _dev_tensor(C, plan.dtype, n, "C"), int(sign), _stream(plan.device)),
            "nufft3d_plan_type1")
@@ -312,6 +336,11 @@ def nufft2d_plan(x, y, n1, n2, eps, dtype=torch.complex64, flags=0):
 
 
 def nufft2d_exec(plan, C, f, adjoint=0):
+    """adjoint=0: f <- F C (C read); adjoint=1: C <- F^H f (f read).  The output is overwritten."""
+    if adjoint:
+        f = _res(f)
+    else:
+        C = _res(C)
     _check(lib.nufft2d_exec(plan.handle, _dev_tensor(C, plan.dtype, plan.n1 * plan.n2, "C"),
                             _dev_tensor(f, plan.dtype, plan.M, "f"), int(adjoint), _stream(plan.device)),
            "nufft2d_exec")
@@ -321,6 +350,7 @@ def nufft2d_type1_exec(plan, c, F=None, sign=-1):
     """2-D type I (sign -1) or adjoint (sign +1) on the plan's samples: c (M) -> F (n1*n2)."""
     if F is None:
         F = torch.empty(plan.n1 * plan.n2, dtype=plan.dtype, device=plan.device)
+    c = _res(c)
     _check(lib.nufft2d_type1_exec(plan.handle, _dev_tensor(c, plan.dtype, plan.M, "c"),
                                   _dev_tensor(F, plan.dtype, plan.n1 * plan.n2, "F"), int(sign),
                                   _stream(plan.device)), "nufft2d_type1_exec")
@@ -342,10 +372,25 @@ def nufft_batch_plan(n_modes, xs, eps, dtype=torch.complex64, flags=0):
 
 def nufft_batch_exec(plan, cs, fs):
     B = len(cs)
+    cs = [_res(c) for c in cs]
     cp = (ctypes.c_void_p * B)(*[_dev_tensor(c, plan.dtype, n, "c").value for c, n in zip(cs, plan.Ns)])
     fp = (ctypes.c_void_p * B)(*[_dev_tensor(f, plan.dtype, m, "f").value for f, m in zip(fs, plan.Ms)])
     _check(lib.nufft_batch_exec(plan.handle, ctypes.cast(cp, _vp), ctypes.cast(fp, _vp),
                                 _stream(plan.device)), "nufft_batch_exec")
+
+
+def nufft_batch_status(plan):
+    """Waits for the current stream and returns the number of persistent-launch waits that
+    gave up since the previous call (0 for a healthy plan), clearing the count."""
+    n = _i64()
+    _check(lib.nufft_batch_status(plan.handle, ctypes.byref(n), _stream(plan.device)), "nufft_batch_status")
+    return n.value
+
+
+def nufft_debug_batch_wait(plan, spin_limit, unreachable=False):
+    """Bound of the persistent launch's pass-B waits, and (tests) an unreachable wait target."""
+    _check(lib.nufft_debug_batch_wait(plan.handle, int(spin_limit), int(bool(unreachable))),
+           "nufft_debug_batch_wait")
 
 
 def nufft_plan_info(plan):

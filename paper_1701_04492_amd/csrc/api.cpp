@@ -1,7 +1,12 @@
 // C ABI of the MI355X low-rank NUFFT: plans, dispatch, error handling.
 #include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <new>
 #include <algorithm>
 #include <vector>
@@ -68,6 +73,83 @@ void prof_end(Profiler *p, hipStream_t s)
     if (!p || !p->on || p->used == p->pool.size()) return;
     (void)hipEventRecord(p->pool[p->used].b, s);
     ++p->used;
+}
+
+// ---- autotuning decisions -------------------------------------------------------
+// A choice made by timing is remembered per problem class for the life of the
+// process (and, when the environment variable NUFFT_MI355X_WISDOM names a file,
+// read from and appended to that JSON object), so that later plans of the
+// class are not timed again and get the same configuration.
+static std::mutex tune_mu;
+static std::map<std::string, long long> tune_table;
+static bool tune_loaded = false;
+
+static const char *wisdom_path()
+{
+    const char *p = std::getenv("NUFFT_MI355X_WISDOM");
+    return (p && *p) ? p : nullptr;
+}
+
+// The file is one JSON object of "key": integer members, as written below.
+static void tune_load_locked()
+{
+    tune_loaded = true;
+    const char *path = wisdom_path();
+    if (!path) return;
+    FILE *fp = std::fopen(path, "r");
+    if (!fp) return;
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof(buf), fp)) > 0) txt.append(buf, n);
+    std::fclose(fp);
+    size_t i = 0;
+    while ((i = txt.find('"', i)) != std::string::npos) {
+        const size_t j = txt.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = txt.substr(i + 1, j - i - 1);
+        size_t k = txt.find(':', j);
+        if (k == std::string::npos) break;
+        char *end = nullptr;
+        const long long v = std::strtoll(txt.c_str() + k + 1, &end, 10);
+        if (end == txt.c_str() + k + 1) break;
+        tune_table[key] = v;
+        i = (size_t)(end - txt.c_str());
+    }
+}
+
+static void tune_save_locked()
+{
+    const char *path = wisdom_path();
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return;
+    std::fprintf(fp, "{\n");
+    size_t i = 0;
+    for (const auto &kv : tune_table)
+        std::fprintf(fp, "  \"%s\": %lld%s\n", kv.first.c_str(), kv.second, ++i < tune_table.size() ? "," : "");
+    std::fprintf(fp, "}\n");
+    std::fclose(fp);
+    std::rename(tmp.c_str(), path);
+}
+
+static bool tune_lookup(const std::string &key, long long *v)
+{
+    std::lock_guard<std::mutex> g(tune_mu);
+    if (!tune_loaded) tune_load_locked();
+    auto it = tune_table.find(key);
+    if (it == tune_table.end()) return false;
+    *v = it->second;
+    return true;
+}
+
+static void tune_store(const std::string &key, long long v)
+{
+    std::lock_guard<std::mutex> g(tune_mu);
+    if (!tune_loaded) tune_load_locked();
+    tune_table[key] = v;
+    tune_save_locked();
 }
 
 namespace nufft {
@@ -207,7 +289,7 @@ nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
     nufft_status st = upload_twiddles<R>(p, s);
     if (st) return st;
     const size_t cs = 2 * sizeof(R);
-    if (p->flags & NUFFT_FLAG_PLAIN) {
+    if (p->flags & NUFFT_FLAG_PLAIN_UNFUSED) {
         p->U = p->alloc((size_t)M * p->K * cs);
         p->W = p->alloc((size_t)p->K * L * cs);
         if (p->L2 > 1) p->W2 = p->alloc((size_t)p->K * L * cs);
@@ -290,7 +372,7 @@ static hipError_t exec_type2(const Plan *p, const void *c, void *f, int mode, co
                              hipStream_t s)
 {
     using C = cx_t<R>;
-    if (p->flags & NUFFT_FLAG_PLAIN) {
+    if (p->flags & NUFFT_FLAG_PLAIN_UNFUSED) {
         PlainArgs<R> a;
         a.c = (const C *)c;
         a.N = p->N;
@@ -317,17 +399,51 @@ static hipError_t exec_type2(const Plan *p, const void *c, void *f, int mode, co
     return fused_type2<R>(fused_args<R>(p), (const C *)c, (C *)f, mode, (const C *)g, gx, s);
 }
 
+// Type I (sign -1) / adjoint (sign +1) on a 1-D plan: the plain unfused kernels
+// on a NUFFT_FLAG_PLAIN_UNFUSED plan, the fused ones otherwise.
+template <typename R>
+static hipError_t exec_type1(const Plan *p, const void *c, void *f, int sign, hipStream_t s)
+{
+    using C = cx_t<R>;
+    if (p->flags & NUFFT_FLAG_PLAIN_UNFUSED) {
+        PlainT1Args<R> a;
+        a.c = (const C *)c;
+        a.N = p->N;
+        a.L = p->L;
+        a.M = p->M;
+        a.L1 = p->L1;
+        a.L2 = p->L2;
+        a.K = p->K;
+        a.perm = p->perm;
+        a.off = p->off;
+        a.U = (const C *)p->U;
+        a.W = (C *)p->W;
+        a.W2 = (C *)p->W2;
+        a.tw1 = (const C *)p->tw1;
+        a.tw2 = (const C *)p->tw2;
+        a.hi = (const C *)p->hi;
+        a.lo = (const C *)p->lo;
+        a.f = (C *)f;
+        a.prof = const_cast<Profiler *>(&p->prof);
+        return plain_type1<R>(a, sign, s);
+    }
+    return fused_type1<R>(fused_args<R>(p), (const C *)c, (C *)f, sign, s);
+}
+
 template <typename R>
 static nufft_status exec_backward(const Plan *p, const void *c, const void *g, void *gc, double *gx, hipStream_t s)
 {
     using C = cx_t<R>;
     FusedArgs<R> a = fused_args<R>(p);
-    const bool share = !(p->flags & NUFFT_FLAG_PLAIN) && p->L2 > 1 && gc && gx;
+    const bool share = !(p->flags & NUFFT_FLAG_PLAIN_UNFUSED) && p->L2 > 1 && gc && gx;
     if (share) {
         NUFFT_HIP_CHECK(fused_sort_input<R>(a, (const C *)g, "bwd_sort", s));
         a.presorted = 1;
     }
-    if (gc) NUFFT_HIP_CHECK(fused_type1<R>(a, (const C *)g, (C *)gc, +1, s));
+    if (gc) {
+        if (share) NUFFT_HIP_CHECK(fused_type1<R>(a, (const C *)g, (C *)gc, +1, s));
+        else NUFFT_HIP_CHECK(exec_type1<R>(p, g, gc, +1, s));
+    }
     if (gx) {
         if (share) NUFFT_HIP_CHECK(fused_type2<R>(a, (const C *)c, nullptr, 1, (const C *)g, gx, s));
         else NUFFT_HIP_CHECK(exec_type2<R>(p, c, nullptr, 1, g, gx, s));
@@ -419,9 +535,13 @@ static nufft_status type3(int64_t M, const double *x, int64_t N, const double *w
     Factors<double> fac;
     double su;
     t3_factors(gamma, K, fac, &su);
+    // the inner transforms work at eps_i >= the precision floor; the composed
+    // bound eps/2 + su eps_i must stay within 4 eps
     const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
-    double eps_i = eps / (2.0 * (su > 1.0 ? su : 1.0));
+    const double sw = su > 1.0 ? su : 1.0;
+    double eps_i = eps / (2.0 * sw);
     if (eps_i < floor_eps) eps_i = floor_eps;
+    if (eps / 2.0 + sw * eps_i > 4.0 * eps) return NUFFT_ERR_UNSUPPORTED;
     // inner type-I plan on the samples w/N with N modes
     Plan *inner = new (std::nothrow) Plan();
     if (!inner) return NUFFT_ERR_ALLOC;
@@ -490,7 +610,6 @@ static nufft_status solve_impl(Plan *p, const void *f, void *c, double tol, int 
     double2 *dd = (double2 *)tmp.alloc(sizeof(double2));
     if (!ones || !tau || !b || !r || !pv || !ap || !lam1 || !lam2 || !q1 || !q2 || !part || !dd)
         return NUFFT_ERR_ALLOC;
-    const FusedArgs<R> a = fused_args<R>(p);
     const C *tw1 = (const C *)circ->tw1, *tw2 = (const C *)circ->tw2;
     const C *hi = (const C *)circ->hi, *lo = (const C *)circ->lo;
     auto dot = [&](const C *u, const C *v, double *re) -> nufft_status {
@@ -503,7 +622,7 @@ static nufft_status solve_impl(Plan *p, const void *f, void *c, double tol, int 
     };
     // eigenvalues of the circulant embedding
     NUFFT_HIP_CHECK(solve_fill<R>(ones, M, 1.0, 0.0, s));
-    NUFFT_HIP_CHECK(fused_type1<R>(a, ones, tau, +1, s));
+    NUFFT_HIP_CHECK(exec_type1<R>(p, ones, tau, +1, s));
     if (T1) {   // first column of conj(F2^* F2)
         NUFFT_HIP_CHECK(solve_take_conj<R>(tau, N, ap, s));
         NUFFT_HIP_CHECK(solve_circulant_column<R>(ap, N, Lc, lam1, s));
@@ -516,7 +635,7 @@ static nufft_status solve_impl(Plan *p, const void *f, void *c, double tol, int 
     // iteration from zero; x is c itself for the type II, y (in b) for the type I
     const C *rhs = (const C *)f;
     if (!T1) {
-        NUFFT_HIP_CHECK(fused_type1<R>(a, (const C *)f, b, +1, s));
+        NUFFT_HIP_CHECK(exec_type1<R>(p, f, b, +1, s));
         rhs = b;
     }
     C *x = T1 ? b : (C *)c;
@@ -764,7 +883,8 @@ static hipError_t batch_run(const Plan *p, int mode, int grid, hipStream_t s)
         return batch_launch_phased<R>((const BatchDesc<R> *)p->bdesc, (const int4 *)p->btasks3, p->bcnt,
                                       (const cx_t<R> *const *)p->bcs, (cx_t<R> *const *)p->bfs, p->blds, s);
     return batch_launch<R>((const BatchDesc<R> *)p->bdesc, (const int4 *)p->btasks, p->bntasks, (BatchCtl *)p->bctl,
-                           (const cx_t<R> *const *)p->bcs, (cx_t<R> *const *)p->bfs, grid, p->blds, s);
+                           (const cx_t<R> *const *)p->bcs, (cx_t<R> *const *)p->bfs, grid, p->blds, p->spin_limit,
+                           p->wait_unreachable, s);
 }
 
 template <typename R>
@@ -872,7 +992,27 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
     const bool persistent = (p->flags & NUFFT_FLAG_BATCH_PERSISTENT) != 0;
     p->bmode = persistent ? 0 : 1;
     p->bgrid = persistent ? 2 * cus : p->bntasks;
-    if (p->flags & NUFFT_FLAG_AUTOTUNE) {
+    // the problem class: member sizes (hashed), dtype, eps, flags
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&](unsigned long long v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int b = 0; b < B; ++b) {
+        mix((unsigned long long)Ns[b]);
+        mix((unsigned long long)Ms[b]);
+    }
+    char kb[192];
+    std::snprintf(kb, sizeof(kb), "batch B=%d dt=%d eps=%.17g flags=%u cus=%d sizes=%016llx", B, (int)p->dtype,
+                  p->eps, (unsigned)p->flags, cus, h);
+    const std::string key(kb);
+    long long known = 0;
+    if (!(p->flags & NUFFT_FLAG_NO_AUTOTUNE) && tune_lookup(key, &known)) {
+        p->bmode = (int)(known >> 32);
+        p->bgrid = (int)(known & 0xffffffff);
+    } else if (!(p->flags & NUFFT_FLAG_NO_AUTOTUNE)) {
         // time the launch at 1..4 workgroups per CU on scratch inputs, keep the fastest
         int64_t nc = 0, nf = 0;
         for (int b = 0; b < B; ++b) {
@@ -919,6 +1059,7 @@ static nufft_status build_batch(Plan *p, int B, const int64_t *Ns, const int64_t
         (void)hipEventDestroy(e1);
         p->hcs.clear();   // scratch pointers: force the next exec to upload its own
         p->hfs.clear();
+        tune_store(key, ((long long)p->bmode << 32) | (long long)p->bgrid);
     }
     return NUFFT_OK;
 }
@@ -971,6 +1112,8 @@ static nufft_status build_3d(Plan *p, const double *x, const double *y, const do
             S += (q == 0 ? 0.5 : 1.0) * (r == 0 ? 0.5 : 1.0) * std::fabs(b[q * p->K3 + r]);
     const double floor_eps = p->dtype == NUFFT_C64 ? 1e-7 : 1e-15;
     const double eps2 = std::max(floor_eps, p->eps / (2.0 * std::max(S, 1.0)));
+    // the composed bound eps/2 + S eps2 stays within 4 eps, or the precision floor cannot serve eps
+    if (p->eps / 2.0 + std::max(S, 1.0) * eps2 > 4.0 * p->eps) return NUFFT_ERR_UNSUPPORTED;
     // one stacked 2-D plan: problem m holds the samples of z slice m
     Plan *q = new (std::nothrow) Plan();
     if (!q) return NUFFT_ERR_ALLOC;
@@ -1088,8 +1231,10 @@ static nufft_status type3_2d(int64_t M, const double *x, const double *y, int64_
     t3_factors(gx, Kx, fx, &sux);
     t3_factors(gy, Ky, fy, &suy);
     const double floor_eps = dt == NUFFT_C64 ? 1e-7 : 1e-15;
-    double eps_i = eps / (2.0 * std::max(sux, 1.0) * std::max(suy, 1.0));
+    const double sw = std::max(sux, 1.0) * std::max(suy, 1.0);
+    double eps_i = eps / (2.0 * sw);
     if (eps_i < floor_eps) eps_i = floor_eps;
+    if (eps / 2.0 + sw * eps_i > 4.0 * eps) return NUFFT_ERR_UNSUPPORTED;   // as in the 1-D type III
     // inner 2-D type-I plan on the samples (w1/n1, w2/n2) with n1+1 by n2+1 modes
     Plan *inner = new (std::nothrow) Plan();
     if (!inner) return NUFFT_ERR_ALLOC;
@@ -1130,11 +1275,11 @@ static nufft_status from_hip(hipError_t e) { return e == hipSuccess ? NUFFT_OK :
 
 // Oversampling choice.  Sec. 2.3 leaves the grid free as long as it has at least
 // N points; a larger grid lowers gamma_eff = max|X| <= N / (2L) and with it K,
-// at the price of longer FFTs.  With NUFFT_FLAG_AUTOTUNE the plan is built on
-// the smallest power-of-two grid L0 >= N and on 2 L0 (gamma_eff <= 1/4), one
-// type-II transform of each is timed on a scratch input, and the faster plan
-// is kept.  The larger grid wins when the per-sample work K M outweighs the
-// FFT work K L log L, e.g. for many more samples than modes.
+// at the price of longer FFTs.  Unless NUFFT_FLAG_NO_AUTOTUNE is given, the plan
+// is built on the smallest power-of-two grid L0 >= N and on 2 L0 (gamma_eff <=
+// 1/4), one type-II transform of each is timed on a scratch input, and the
+// faster plan is kept.  The larger grid wins when the per-sample work K M
+// outweighs the FFT work K L log L, e.g. for many more samples than modes.
 template <typename R>
 static nufft_status time_type2(Plan *p, hipStream_t s, float *ms_out)
 {
@@ -1166,6 +1311,13 @@ static nufft_status autotune_grid(Plan **pp, const double *x, hipStream_t s)
 {
     Plan *p = *pp;
     if (2 * p->L > (int64_t(1) << 23)) return NUFFT_OK;   // the larger grid is not supported
+    char kb[192];
+    std::snprintf(kb, sizeof(kb), "1d N=%lld M=%lld dt=%d eps=%.17g flags=%u K0=%d", (long long)p->N,
+                  (long long)p->M, (int)p->dtype, p->eps, (unsigned)p->flags, p->K);
+    const std::string key(kb);
+    long long factor = 0;
+    const bool known = tune_lookup(key, &factor);
+    if (known && factor == 1) return NUFFT_OK;
     Plan *q = new (std::nothrow) Plan();
     if (!q) return NUFFT_ERR_ALLOC;
     q->kind = PLAN_1D;
@@ -1177,10 +1329,17 @@ static nufft_status autotune_grid(Plan **pp, const double *x, hipStream_t s)
     nufft_status st = NUFFT_OK;
     if (!choose_grid(2 * p->L, &q->L, &q->L1, &q->L2)) st = NUFFT_ERR_UNSUPPORTED;
     if (!st) st = build_1d<R>(q, x, s);
-    float t0 = 0, t1 = 0;
-    if (!st) st = time_type2<R>(p, s, &t0);
-    if (!st) st = time_type2<R>(q, s, &t1);
-    if (st || !(t1 < t0)) {
+    bool larger = known;
+    if (!st && !known) {
+        float t0 = 0, t1 = 0;
+        st = time_type2<R>(p, s, &t0);
+        if (!st) st = time_type2<R>(q, s, &t1);
+        if (!st) {
+            larger = t1 < t0;
+            tune_store(key, larger ? 2 : 1);
+        }
+    }
+    if (st || !larger) {
         (void)hipStreamSynchronize(s);
         delete q;
         return st;
@@ -1207,10 +1366,10 @@ nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, cons
     *out = nullptr;
     if (n_modes < 1 || n_pts < 1 || !x_dev) return NUFFT_ERR_INVALID_ARG;
     if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_PLAIN | NUFFT_FLAG_HALF_EXCHANGE |
-                            NUFFT_FLAG_AUTOTUNE))
+    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_PLAIN_UNFUSED | NUFFT_FLAG_HALF_EXCHANGE |
+                            NUFFT_FLAG_NO_AUTOTUNE))
         return NUFFT_ERR_INVALID_ARG;
-    if ((flags & NUFFT_FLAG_HALF_EXCHANGE) && (flags & NUFFT_FLAG_PLAIN)) return NUFFT_ERR_INVALID_ARG;
+    if ((flags & NUFFT_FLAG_HALF_EXCHANGE) && (flags & NUFFT_FLAG_PLAIN_UNFUSED)) return NUFFT_ERR_INVALID_ARG;
     if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
     nufft_status st;
     if (!eps_ok(eps, dtype, &st)) return st;
@@ -1230,13 +1389,14 @@ nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, cons
     }
     hipStream_t s = (hipStream_t)stream;
     st = dtype == NUFFT_C64 ? build_1d<float>(p, x_dev, s) : build_1d<double>(p, x_dev, s);
-    if (st == NUFFT_OK && (flags & NUFFT_FLAG_AUTOTUNE))
+    if (st == NUFFT_OK && !(flags & (NUFFT_FLAG_NO_AUTOTUNE | NUFFT_FLAG_PLAIN_UNFUSED)))
         st = dtype == NUFFT_C64 ? autotune_grid<float>(&p, x_dev, s) : autotune_grid<double>(&p, x_dev, s);
     if (st != NUFFT_OK) {
         (void)hipStreamSynchronize(s);
         delete p;
         return st;
     }
+    p->last = s;
     *out = p;
     return NUFFT_OK;
 }
@@ -1245,6 +1405,7 @@ nufft_status nufft2_exec(nufft_plan_t plan, const void *c, void *f, void *stream
 {
     if (!plan || plan->kind != PLAN_1D || !c || !f) return NUFFT_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    plan->last = s;
     return from_hip(plan->dtype == NUFFT_C64 ? exec_type2<float>(plan, c, f, 0, nullptr, nullptr, s)
                                              : exec_type2<double>(plan, c, f, 0, nullptr, nullptr, s));
 }
@@ -1253,6 +1414,7 @@ nufft_status nufft2_grad_x(nufft_plan_t plan, const void *c, const void *g, doub
 {
     if (!plan || plan->kind != PLAN_1D || !c || !g || !gx) return NUFFT_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    plan->last = s;
     return from_hip(plan->dtype == NUFFT_C64 ? exec_type2<float>(plan, c, nullptr, 1, g, gx, s)
                                              : exec_type2<double>(plan, c, nullptr, 1, g, gx, s));
 }
@@ -1263,6 +1425,7 @@ nufft_status nufft2_solve(nufft_plan_t plan, const void *f, void *c, double tol,
     if (!plan || plan->kind != PLAN_1D || !f || !c || !(tol > 0.0) || max_iter < 0) return NUFFT_ERR_INVALID_ARG;
     if (plan->N > (int64_t(1) << 22)) return NUFFT_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
+    plan->last = s;
     return plan->dtype == NUFFT_C64 ? solve_impl<float, false>(plan, f, c, tol, max_iter, iters, resid, s)
                                     : solve_impl<double, false>(plan, f, c, tol, max_iter, iters, resid, s);
 }
@@ -1273,6 +1436,7 @@ nufft_status nufft1_solve(nufft_plan_t plan, const void *f, void *c, double tol,
     if (!plan || plan->kind != PLAN_1D || !f || !c || !(tol > 0.0) || max_iter < 0) return NUFFT_ERR_INVALID_ARG;
     if (plan->N > (int64_t(1) << 22)) return NUFFT_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
+    plan->last = s;
     return plan->dtype == NUFFT_C64 ? solve_impl<float, true>(plan, f, c, tol, max_iter, iters, resid, s)
                                     : solve_impl<double, true>(plan, f, c, tol, max_iter, iters, resid, s);
 }
@@ -1281,6 +1445,7 @@ nufft_status nufft2_backward(nufft_plan_t plan, const void *c, const void *g, vo
 {
     if (!plan || plan->kind != PLAN_1D || !g || (!gc && !gx) || (gx && !c)) return NUFFT_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    plan->last = s;
     return plan->dtype == NUFFT_C64 ? exec_backward<float>(plan, c, g, gc, gx, s)
                                     : exec_backward<double>(plan, c, g, gc, gx, s);
 }
@@ -1289,9 +1454,9 @@ nufft_status nufft1_exec(nufft_plan_t plan, const void *c, void *f, int sign, vo
 {
     if (!plan || plan->kind != PLAN_1D || !c || !f || (sign != 1 && sign != -1)) return NUFFT_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    if (plan->dtype == NUFFT_C64)
-        return from_hip(fused_type1<float>(fused_args<float>(plan), (const float2 *)c, (float2 *)f, sign, s));
-    return from_hip(fused_type1<double>(fused_args<double>(plan), (const double2 *)c, (double2 *)f, sign, s));
+    plan->last = s;
+    return from_hip(plan->dtype == NUFFT_C64 ? exec_type1<float>(plan, c, f, sign, s)
+                                             : exec_type1<double>(plan, c, f, sign, s));
 }
 
 nufft_status nufft3_exec(int64_t n_pts, const double *x, int64_t n_freq, const double *w, const void *c, void *f,
@@ -1335,6 +1500,7 @@ static nufft_status make_3d_plan(Plan **out, int64_t n1, int64_t n2, int64_t n3,
         delete p;
         return st;
     }
+    p->last = s;
     *out = p;
     return NUFFT_OK;
 }
@@ -1386,12 +1552,14 @@ nufft_status nufft3d_plan(nufft_plan_t *out, int64_t n1, int64_t n2, int64_t n3,
 nufft_status nufft3d_plan_exec(nufft_plan_t plan, const void *C, void *f, void *stream)
 {
     if (!plan || plan->kind != PLAN_3D || !C || !f) return NUFFT_ERR_INVALID_ARG;
+    plan->last = (hipStream_t)stream;
     return from_hip(exec_3d(plan, C, f, 0, -1, (hipStream_t)stream));
 }
 
 nufft_status nufft3d_plan_type1(nufft_plan_t plan, const void *c, void *C, int sign, void *stream)
 {
     if (!plan || plan->kind != PLAN_3D || !c || !C || (sign != 1 && sign != -1)) return NUFFT_ERR_INVALID_ARG;
+    plan->last = (hipStream_t)stream;
     return from_hip(exec_3d(plan, c, C, 1, sign, (hipStream_t)stream));
 }
 
@@ -1420,7 +1588,7 @@ nufft_status nufft2d_plan(nufft_plan_t *out, int64_t n1, int64_t n2, int64_t n_p
     *out = nullptr;
     if (n1 < 1 || n2 < 1 || n_pts < 1 || !x_dev || !y_dev) return NUFFT_ERR_INVALID_ARG;
     if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)NUFFT_FLAG_FIX_GAMMA_HALF) return NUFFT_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_NO_AUTOTUNE)) return NUFFT_ERR_INVALID_ARG;
     if (n_pts > (int64_t(1) << 30)) return NUFFT_ERR_UNSUPPORTED;
     nufft_status st;
     if (!eps_ok(eps, dtype, &st)) return st;
@@ -1448,6 +1616,7 @@ nufft_status nufft2d_plan(nufft_plan_t *out, int64_t n1, int64_t n2, int64_t n_p
         delete p;
         return st;
     }
+    p->last = s;
     *out = p;
     return NUFFT_OK;
 }
@@ -1456,6 +1625,7 @@ nufft_status nufft2d_exec(nufft_plan_t plan, void *C, void *f, int adjoint, void
 {
     if (!plan || plan->kind != PLAN_2D || !C || !f || (adjoint != 0 && adjoint != 1)) return NUFFT_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    plan->last = s;
     hipError_t e;
     if (plan->dtype == NUFFT_C64) {
         const Args2D<float> a = args_2d<float>(plan);
@@ -1473,6 +1643,7 @@ nufft_status nufft2d_type1_exec(nufft_plan_t plan, const void *c, void *F, int s
 {
     if (!plan || plan->kind != PLAN_2D || !c || !F || (sign != 1 && sign != -1)) return NUFFT_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    plan->last = s;
     if (plan->dtype == NUFFT_C64)
         return from_hip(fused_2d_adj<float>(args_2d<float>(plan), (const float2 *)c, (float2 *)F, sign, s));
     return from_hip(fused_2d_adj<double>(args_2d<double>(plan), (const double2 *)c, (double2 *)F, sign, s));
@@ -1486,7 +1657,7 @@ nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_mod
     *out = nullptr;
     if (batch < 1 || !n_modes || !n_pts || !x_dev) return NUFFT_ERR_INVALID_ARG;
     if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_AUTOTUNE | NUFFT_FLAG_BATCH_PERSISTENT))
+    if (flags & ~(uint32_t)(NUFFT_FLAG_FIX_GAMMA_HALF | NUFFT_FLAG_NO_AUTOTUNE | NUFFT_FLAG_BATCH_PERSISTENT))
         return NUFFT_ERR_INVALID_ARG;
     for (int b = 0; b < batch; ++b) {
         if (n_modes[b] < 1 || n_pts[b] < 1 || !x_dev[b]) return NUFFT_ERR_INVALID_ARG;
@@ -1509,6 +1680,7 @@ nufft_status nufft_batch_plan(nufft_plan_t *out, int batch, const int64_t *n_mod
         return st;
     }
     p->L = p->bgrid;
+    p->last = s;
     *out = p;
     return NUFFT_OK;
 }
@@ -1519,6 +1691,7 @@ nufft_status nufft_batch_exec(nufft_plan_t plan, const void *const *c, void *con
     for (size_t b = 0; b < plan->children.size(); ++b)
         if (!c[b] || !f[b]) return NUFFT_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    plan->last = s;
     nufft_status st = plan->dtype == NUFFT_C64 ? batch_upload_ptrs<float>(plan, c, f, s)
                                                : batch_upload_ptrs<double>(plan, c, f, s);
     if (st) return st;
@@ -1543,11 +1716,43 @@ nufft_status nufft_plan_perm(nufft_plan_t plan, int32_t *perm_host)
     return NUFFT_OK;
 }
 
+nufft_status nufft_batch_status(nufft_plan_t plan, int64_t *timeouts, void *stream)
+{
+    if (!plan || plan->kind != PLAN_BATCH || !timeouts) return NUFFT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    BatchCtl *ctl = (BatchCtl *)plan->bctl;
+    int h = 0;
+    NUFFT_HIP_CHECK(hipMemcpyAsync(&h, &ctl->timeouts, sizeof(int), hipMemcpyDeviceToHost, s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    if (h != 0) NUFFT_HIP_CHECK(hipMemsetAsync(&ctl->timeouts, 0, sizeof(int), s));
+    NUFFT_HIP_CHECK(hipStreamSynchronize(s));
+    *timeouts = h;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_debug_batch_wait(nufft_plan_t plan, int64_t spin_limit, int unreachable)
+{
+    if (!plan || plan->kind != PLAN_BATCH || spin_limit < 0) return NUFFT_ERR_INVALID_ARG;
+    plan->spin_limit = spin_limit;
+    plan->wait_unreachable = unreachable != 0;
+    return NUFFT_OK;
+}
+
+// Waits for the plan's own stream only (unless it is capturing), then frees.
+// The calls run in relaxed capture mode: another stream of this thread or
+// process may be capturing a graph meanwhile, and waiting for or freeing
+// memory that the capture does not use must not disturb it.
 nufft_status nufft_destroy(nufft_plan_t plan)
 {
     if (!plan) return NUFFT_OK;
-    (void)hipDeviceSynchronize();
+    hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+    const bool swapped = hipThreadExchangeStreamCaptureMode(&mode) == hipSuccess;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(plan->last, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+        (void)hipStreamSynchronize(plan->last);
+    (void)hipGetLastError();
     delete plan;
+    if (swapped) (void)hipThreadExchangeStreamCaptureMode(&mode);
     return NUFFT_OK;
 }
 

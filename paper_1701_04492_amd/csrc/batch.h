@@ -27,7 +27,7 @@ struct BatchDesc {
 struct BatchCtl {
     int next;        // next task to claim
     int exited;      // workgroups that have left
-    int error;       // set if a wait ever exceeded its bound
+    int timeouts;    // waits that reached their bound (read and cleared by nufft_batch_status)
     int ntransforms;
     int done_a[1];   // per transform: finished pass-A tasks (ntransforms entries)
 };
@@ -37,9 +37,13 @@ int batch_threads();
 int batch_small_chunk();
 int batch_pass_a_cols(int L2);
 int batch_pass_b_points();     // grid points per PASS_B task (runs of whole tiles)
+// spin_limit: iterations of a pass-B wait before it gives up (counted in
+// ctl->timeouts); unreachable != 0 (tests only) makes every wait's target count
+// one that is never reached.
 template <typename R>
 hipError_t batch_launch(const BatchDesc<R> *descs, const int4 *tasks, int ntasks, BatchCtl *ctl,
-                        const cx_t<R> *const *cs, cx_t<R> *const *fs, int grid, size_t lds, hipStream_t s);
+                        const cx_t<R> *const *cs, cx_t<R> *const *fs, int grid, size_t lds, int64_t spin_limit,
+                        int unreachable, hipStream_t s);
 // The same work as three plain launches (SMALL, PASS_A, PASS_B tasks; counts[3]),
 // tasks laid out in that order, one workgroup per task.
 template <typename R>

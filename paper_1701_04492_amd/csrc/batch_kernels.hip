@@ -253,7 +253,8 @@ __device__ __noinline__ void b_passB(const BatchDesc<R> &d, cx_t<R> *__restrict_
 template <typename R>
 __global__ void __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(NUFFT_BATCH_WAVES)))
 k_batch(const BatchDesc<R> *__restrict__ descs, const int4 *__restrict__ tasks, int ntasks, BatchCtl *ctl,
-        const cx_t<R> *const *__restrict__ cs, cx_t<R> *const *__restrict__ fs, int64_t spin_limit)
+        const cx_t<R> *const *__restrict__ cs, cx_t<R> *const *__restrict__ fs, int64_t spin_limit,
+        int unreachable)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ int s_task;
@@ -274,13 +275,14 @@ k_batch(const BatchDesc<R> *__restrict__ descs, const int4 *__restrict__ tasks, 
         const BatchDesc<R> &d = descs[b];
         if (type == BATCH_PASS_B) {
             if (tid == 0) {
+                const int target = unreachable ? 0x7fffffff : d.n_pass_a;
                 int64_t it = 0;
-                while (__hip_atomic_load(&ctl->done_a[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < d.n_pass_a) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++it > spin_limit) {   // cannot happen by construction; never hang
-                        atomicOr(&ctl->error, 1);
+                while (__hip_atomic_load(&ctl->done_a[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    if (it++ >= spin_limit) {   // cannot happen by construction; never hang
+                        atomicAdd(&ctl->timeouts, 1);
                         break;
                     }
+                    __builtin_amdgcn_s_sleep(2);
                 }
             }
             __syncthreads();
@@ -390,10 +392,11 @@ int batch_pass_b_points() { return 2048; }
 
 template <typename R>
 hipError_t batch_launch(const BatchDesc<R> *descs, const int4 *tasks, int ntasks, BatchCtl *ctl,
-                        const cx_t<R> *const *cs, cx_t<R> *const *fs, int grid, size_t lds, hipStream_t s)
+                        const cx_t<R> *const *cs, cx_t<R> *const *fs, int grid, size_t lds, int64_t spin_limit,
+                        int unreachable, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch<R>, dim3(grid), dim3(BNT), lds, s, descs, tasks, ntasks, ctl, cs, fs,
-                       (int64_t)1 << 28);
+    hipLaunchKernelGGL(k_batch<R>, dim3(grid), dim3(BNT), lds, s, descs, tasks, ntasks, ctl, cs, fs, spin_limit,
+                       unreachable);
     return hipGetLastError();
 }
 
@@ -429,9 +432,11 @@ hipError_t batch_set_lds_limit(size_t lds)
 }
 
 template hipError_t batch_launch<float>(const BatchDesc<float> *, const int4 *, int, BatchCtl *,
-                                        const float2 *const *, float2 *const *, int, size_t, hipStream_t);
+                                        const float2 *const *, float2 *const *, int, size_t, int64_t, int,
+                                        hipStream_t);
 template hipError_t batch_launch<double>(const BatchDesc<double> *, const int4 *, int, BatchCtl *,
-                                         const double2 *const *, double2 *const *, int, size_t, hipStream_t);
+                                         const double2 *const *, double2 *const *, int, size_t, int64_t, int,
+                                         hipStream_t);
 template hipError_t batch_launch_phased<float>(const BatchDesc<float> *, const int4 *, const int *,
                                                const float2 *const *, float2 *const *, size_t, hipStream_t);
 template hipError_t batch_launch_phased<double>(const BatchDesc<double> *, const int4 *, const int *,

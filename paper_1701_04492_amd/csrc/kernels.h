@@ -113,6 +113,23 @@ struct PlainArgs {
     Profiler *prof;
 };
 
+// Plain type I / adjoint (Sec. 3.1): spread into W (K x L), stand-alone FFT
+// passes (W2: second four-step buffer), weighted sum over r into f (N).
+template <typename R>
+struct PlainT1Args {
+    const cx_t<R> *c;      // M inputs
+    int64_t N, L, M;
+    int L1, L2, K;
+    const int32_t *perm, *off;   // the plan's sorted order and its CSR offsets per key
+    const cx_t<R> *U;      // M x K stored factors
+    cx_t<R> *W, *W2;
+    const cx_t<R> *tw1, *tw2, *hi, *lo;   // forward-sign tables
+    cx_t<R> *f;            // N outputs
+    Profiler *prof;
+};
+template <typename R>
+hipError_t plain_type1(const PlainT1Args<R> &a, int sign, hipStream_t s);
+
 template <typename R>
 hipError_t plain_build_U(const R *X, int64_t M, const Factors<R> &fac, cx_t<R> *U, hipStream_t s);
 template <typename R>

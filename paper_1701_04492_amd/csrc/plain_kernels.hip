@@ -1,4 +1,5 @@
-// Plain (unfused) online stage of the type-II NUFFT, Sec. 2.3 two-step form:
+// Plain (unfused) online stage of the type-II NUFFT, Sec. 2.3 two-step form
+// (and of its transpose and adjoint, Sec. 3.1, further down):
 //   W_r = D_{v_r} c (K x L buffer in HBM)      -> k_scale
 //   X_r = F_L W_r (stand-alone FFT passes)      -> k_fft_rows / k_fft_cols
 //   f_j = sum_r U[j][r] X_r[t_j]                -> k_gather (U stored by the plan)
@@ -167,6 +168,64 @@ k_gather(const cx_t<R> *__restrict__ U, const cx_t<R> *__restrict__ Xr, const in
     }
 }
 
+// ---- type I / adjoint (Sec. 3.1, the transpose of the two-step form) ---------
+//   W_r[n] = sum_{j: t_j = n} u_r(j) c_j       (DIR = -1, type I)
+//   W_r[n] = sum_{j: t_j = n} conj(u_r(j)) c_j (DIR = +1, adjoint)   -> k_spread
+//   X_r = F_L W_r (DIR -1) or F_L^H W_r (DIR +1)  -> k_fft_cols / k_fft_rows
+//   f_k = sum_r v_r(k) X_r[k], k < N             -> k_vsum
+// One thread per grid point n sums the samples of its segment of the plan's
+// sorted order (key (n mod L2) L1 + n / L2, CSR offsets off[]) in that order:
+// a deterministic sum with no atomics; every W_r[n], n < L, is written.
+template <typename R, int DIR>
+__global__ void __launch_bounds__(256)
+k_spread(const cx_t<R> *__restrict__ c, const int32_t *__restrict__ perm, const int32_t *__restrict__ off,
+         const cx_t<R> *__restrict__ U, int K, int64_t L, int L1, int L2, cx_t<R> *__restrict__ W)
+{
+    using C = cx_t<R>;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= L) return;
+    const int64_t key = (n % L2) * L1 + n / L2;
+    const int i0 = off[key], i1 = off[key + 1];
+    C acc[NUFFT_KMAX];
+#pragma unroll
+    for (int r = 0; r < NUFFT_KMAX; ++r) acc[r] = cmake<C>(0, 0);
+    for (int i = i0; i < i1; ++i) {
+        const int64_t j = perm[i];
+        const C cj = c[j];
+#pragma unroll
+        for (int r = 0; r < NUFFT_KMAX; ++r) {
+            if (r < K) {
+                const C u = U[j * K + r];
+                acc[r] = cadd(acc[r], cmul(DIR < 0 ? u : cconj(u), cj));
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NUFFT_KMAX; ++r)
+        if (r < K) W[(int64_t)r * L + n] = acc[r];
+}
+
+// f_k = sum_r v_r(k) X[r][k], v_r(k) = T_r(2k/N - 1) (v_0 halved), k < N.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_vsum(const cx_t<R> *__restrict__ X, int64_t N, int64_t L, int K, cx_t<R> *__restrict__ f)
+{
+    using C = cx_t<R>;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const R z = (R)(2.0 * (double)k / (double)N - 1.0);
+    C acc = cmake<C>(0, 0);
+    R tm2 = 1, tm1 = z;
+    for (int r = 0; r < K; ++r) {
+        R v;
+        if (r == 0) v = (R)0.5;
+        else if (r == 1) v = z;
+        else { v = 2 * z * tm1 - tm2; tm2 = tm1; tm1 = v; }
+        acc = cadd(acc, cscale(X[(int64_t)r * L + k], v));
+    }
+    f[k] = acc;
+}
+
 // ---- launchers --------------------------------------------------------------
 
 template <typename R>
@@ -274,6 +333,45 @@ hipError_t plain_exec(const PlainArgs<R> &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename R, int DIR>
+static hipError_t plain_type1_dir(const PlainT1Args<R> &a, hipStream_t s)
+{
+    using C = cx_t<R>;
+    const int64_t L = a.L;
+    prof_begin(a.prof, DIR > 0 ? "plain_adj_spread" : "plain_type1_spread", s);
+    hipLaunchKernelGGL((k_spread<R, DIR>), dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, a.c, a.perm, a.off,
+                       a.U, a.K, L, a.L1, a.L2, a.W);
+    prof_end(a.prof, s);
+    bool ok;
+    const C *spec;
+    // tables of the forward sign; the kernels conjugate them for DIR = +1
+    if (a.L2 == 1) {
+        prof_begin(a.prof, DIR > 0 ? "plain_adj_fft" : "plain_type1_fft", s);
+        ok = dispatch_rows<R, DIR, 0>((int)L, a.W, a.W, 1, a.K, a.tw1, s);
+        prof_end(a.prof, s);
+        spec = a.W;
+    } else {
+        prof_begin(a.prof, DIR > 0 ? "plain_adj_fft_cols" : "plain_type1_fft_cols", s);
+        ok = dispatch_cols<R, DIR>(a.L2, a.W, a.L1, a.K, a.tw2, a.hi, a.lo, s);
+        prof_end(a.prof, s);
+        prof_begin(a.prof, DIR > 0 ? "plain_adj_fft_rows" : "plain_type1_fft_rows", s);
+        ok = ok && dispatch_rows<R, DIR, 1>(a.L1, a.W, a.W2, a.L2, a.K, a.tw1, s);
+        prof_end(a.prof, s);
+        spec = a.W2;
+    }
+    if (!ok) return hipErrorInvalidValue;
+    prof_begin(a.prof, DIR > 0 ? "plain_adj_vsum" : "plain_type1_vsum", s);
+    hipLaunchKernelGGL(k_vsum<R>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, spec, a.N, L, a.K, a.f);
+    prof_end(a.prof, s);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t plain_type1(const PlainT1Args<R> &a, int sign, hipStream_t s)
+{
+    return sign < 0 ? plain_type1_dir<R, -1>(a, s) : plain_type1_dir<R, 1>(a, s);
+}
+
 template <typename R>
 hipError_t plain_fft(int64_t L, int L1, int L2, cx_t<R> *data, cx_t<R> *out, const cx_t<R> *tw1,
                      const cx_t<R> *tw2, const cx_t<R> *hi, const cx_t<R> *lo, cx_t<R> **result, hipStream_t s)
@@ -299,6 +397,8 @@ template hipError_t plain_build_U<float>(const float *, int64_t, const Factors<f
 template hipError_t plain_build_U<double>(const double *, int64_t, const Factors<double> &, double2 *,
                                           hipStream_t);
 template hipError_t plain_exec<float>(const PlainArgs<float> &, hipStream_t);
+template hipError_t plain_type1<float>(const PlainT1Args<float> &, int, hipStream_t);
+template hipError_t plain_type1<double>(const PlainT1Args<double> &, int, hipStream_t);
 template hipError_t plain_exec<double>(const PlainArgs<double> &, hipStream_t);
 
 }  // namespace nufft

@@ -86,6 +86,10 @@ struct nufft_plan_s {
     size_t blds = 0;
 
     Profiler prof;
+    hipStream_t last = nullptr;     // stream of the latest call on the plan (waited for by nufft_destroy)
+    // persistent batch launch: bound of a pass-B wait, and (tests) an unreachable wait target
+    int64_t spin_limit = int64_t(1) << 28;
+    int wait_unreachable = 0;
 
     std::vector<void *> blocks;
     std::vector<nufft_plan_s *> children;   // sub-plans (2-D axes, batch members)

@@ -62,3 +62,25 @@ def test_host_argument_errors():
     assert B.lib.nufft2_exec(None, None, None, None) == 1
     assert B.lib.nufft1_exec(None, None, None, -1, None) == 1
     assert B.lib.nufft_destroy(None) == 0
+
+
+def test_enum_values_are_pinned():
+    """Status codes, dtypes and flag bits as the header declares them (and the binding mirrors)."""
+    import re
+    txt = open(B.HEADER).read()
+    vals = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"(NUFFT_\w+)\s*=\s*(\d+)u?", txt))
+    want = {"NUFFT_OK": 0, "NUFFT_ERR_INVALID_ARG": 1, "NUFFT_ERR_UNSUPPORTED": 2, "NUFFT_ERR_ALLOC": 3,
+            "NUFFT_ERR_NONFINITE": 4, "NUFFT_ERR_HIP": 5, "NUFFT_C64": 0, "NUFFT_C128": 1,
+            "NUFFT_FLAG_FIX_GAMMA_HALF": 1, "NUFFT_FLAG_PLAIN_UNFUSED": 2, "NUFFT_FLAG_NO_AUTOTUNE": 4,
+            "NUFFT_FLAG_HALF_EXCHANGE": 8, "NUFFT_FLAG_BATCH_PERSISTENT": 16}
+    for k, v in want.items():
+        assert vals.get(k) == v, k
+        if k.startswith("NUFFT_FLAG") or k.startswith("NUFFT_C"):
+            assert getattr(B, k) == v, k
+    assert "NUFFT_FLAG_AUTOTUNE" not in vals and "NUFFT_FLAG_PLAIN" not in vals
+
+
+def test_batch_and_debug_entry_points_reject_bad_handles():
+    n = ctypes.c_int64()
+    assert B.lib.nufft_batch_status(None, ctypes.byref(n), None) == 1
+    assert B.lib.nufft_debug_batch_wait(None, 10, 1) == 1

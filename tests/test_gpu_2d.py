@@ -95,10 +95,13 @@ def test_2d_polar_full_size_sampled():
     rng = np.random.default_rng(52)
     M = x.shape[0]
     r = np.hypot(x - 0.5, y - 0.5)
-    rows = np.unique(np.concatenate([rng.choice(M, 40, replace=False), np.argsort(r)[:12], [0, M - 1]]))
+    # 448 seeded rows, the 64 samples nearest the centre (the densest cells), the ends
+    rows = np.unique(np.concatenate([rng.choice(M, 448, replace=False), np.argsort(r)[:64], [0, M - 1]]))
+    assert rows.size >= 512
     g = W.complex_normal(W.rng_for(53), M)
-    kq = (np.concatenate([[0, 1023, 512], rng.integers(0, 1024, 21)]),
-          np.concatenate([[0, 1023, 511], rng.integers(0, 1024, 21)]))
+    k1 = np.concatenate([[0, 1023, 512, 0, 1023], rng.integers(0, 1024, 256)])
+    k2 = np.concatenate([[0, 1023, 511, 1023, 0], rng.integers(0, 1024, 256)])
+    kq = (k1, k2)
     plan = run_2d(x, y, C, C64, rows=rows, kq=kq, g=g, label="polar 1024^2")
     assert plan.K == 10
 
@@ -163,8 +166,8 @@ def test_2d_type1_polar_full_size_sampled():
     M = x.shape[0]
     rng = np.random.default_rng(56)
     g = W.complex_normal(W.rng_for(57), M)
-    kq = (np.concatenate([[0, 1023, 512], rng.integers(0, 1024, 13)]),
-          np.concatenate([[0, 1023, 511], rng.integers(0, 1024, 13)]))
+    kq = (np.concatenate([[0, 1023, 512, 0, 1023], rng.integers(0, 1024, 256)]),
+          np.concatenate([[0, 1023, 511, 1023, 0], rng.integers(0, 1024, 256)]))
     run_2d_type1(x, y, 1024, 1024, g, C64, kq=kq, label="polar 1024^2")
 
 

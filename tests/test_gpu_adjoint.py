@@ -91,13 +91,16 @@ def test_adjoint_deterministic():
 
 
 @pytest.mark.parametrize("dtype", [C64, C128])
-def test_n2p20_sampled(dtype):
+@pytest.mark.parametrize("dist", ["iid", "jitter"])
+def test_n2p20_sampled(dtype, dist):
+    """Type I and adjoint at N = M = 2^20 on both sample distributions of the workload
+    (iid uniform, and jittered x_j = (j + U(-1/2, 1/2))/N where every t_j is j or j +- 1)."""
     N = 1 << 20
-    x, g = W.type2_case(2, N)
-    kq = np.sort(np.random.default_rng(5).choice(N, 192, replace=False))
-    kq = np.concatenate([[0, 1, N - 1], kq])
-    check_type1(x, g, N, dtype, +1, kq=kq, label="2^20 adjoint")
-    check_type1(x, g, N, dtype, -1, kq=kq, label="2^20 type I")
+    x, g = W.type2_case(2, N, N, dist)
+    kq = np.sort(np.random.default_rng(5).choice(N, 256, replace=False))
+    kq = np.unique(np.concatenate([[0, 1, N // 2, N - 2, N - 1], kq]))
+    check_type1(x, g, N, dtype, +1, kq=kq, label="2^20 adjoint " + dist)
+    check_type1(x, g, N, dtype, -1, kq=kq, label="2^20 type I " + dist)
 
 
 def test_n2p23_max_size_sampled():

@@ -19,7 +19,7 @@ def _t(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(DEV)
 
 
-def _check_members(Ns, xs, cs, fs, dtype, max_terms=4e7, seed=0):
+def _check_members(Ns, xs, cs, fs, dtype, max_terms=4e7, seed=0, nrows=48):
     rng = np.random.default_rng(seed)
     worst = 0.0
     for b, (n, x, c, f) in enumerate(zip(Ns, xs, cs, fs)):
@@ -29,7 +29,7 @@ def _check_members(Ns, xs, cs, fs, dtype, max_terms=4e7, seed=0):
         if n * xx.shape[0] <= max_terms:
             rows = np.arange(xx.shape[0])
         else:
-            rows = np.unique(np.concatenate([rng.choice(xx.shape[0], 48, replace=False), [0, xx.shape[0] - 1]]))
+            rows = np.unique(np.concatenate([rng.choice(xx.shape[0], nrows, replace=False), [0, xx.shape[0] - 1]]))
         err = np.abs(f[rows] - D.nudft2(xx[rows], cc)).max() / np.abs(cc).sum()
         worst = max(worst, err)
         assert np.all(np.isfinite(f)), b
@@ -95,7 +95,7 @@ def test_batch_matches_single_plans():
 def test_batch_graph_replay(flags):
     Ns = [500, 3000, 12000, 50000]
     xs, cs, fs = _make(Ns, Ns, 62, C64)
-    plan = P.nufft_batch_plan(Ns, xs, 1e-6, C64, P.NUFFT_FLAG_AUTOTUNE | flags)
+    plan = P.nufft_batch_plan(Ns, xs, 1e-6, C64, flags)
     assert plan.grid >= 1
     P.nufft_batch_exec(plan, cs, fs)          # uploads the pointers; the capture holds the kernel only
     torch.cuda.synchronize()
@@ -123,7 +123,6 @@ def test_batch_workload_512_sampled():
     plan = P.nufft_batch_plan([int(n) for n in Ns], xs, 1e-6, C64)
     P.nufft_batch_exec(plan, cs, fs)
     torch.cuda.synchronize()
-    pick = list(np.random.default_rng(63).choice(len(Ns), 12, replace=False)) + [int(np.argmax(Ns))]
-    worst = _check_members([Ns[i] for i in pick], [xs[i] for i in pick], [cs[i] for i in pick],
-                           [fs[i] for i in pick], C64, max_terms=2e7)
-    print("512-batch worst sampled err/||c||_1 %.3e" % worst, flush=True)
+    # every member: all rows when N_b * M_b <= 2^21, else 40 seeded rows plus the first and last
+    worst = _check_members([int(n) for n in Ns], xs, cs, fs, C64, max_terms=float(1 << 21), seed=63, nrows=40)
+    print("512-batch (every member) worst err/||c||_1 %.3e" % worst, flush=True)

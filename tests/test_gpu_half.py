@@ -101,8 +101,8 @@ def test_half_is_inert_for_one_pass_sizes():
     """N <= 4096 runs in one workgroup with no HBM exchange: the flag changes nothing."""
     x, c = W.type2_case(74, 3000, 5000)
     xt, ct = _t(x, torch.float64), _t(c, C64)
-    a = P.nufft2_exec(P.nufft2_plan(xt, 3000, EPS, C64, HALF), ct)
-    b = P.nufft2_exec(P.nufft2_plan(xt, 3000, EPS, C64, 0), ct)
+    a = P.nufft2_exec(P.nufft2_plan(xt, 3000, EPS, C64, HALF | P.NUFFT_FLAG_NO_AUTOTUNE), ct)
+    b = P.nufft2_exec(P.nufft2_plan(xt, 3000, EPS, C64, P.NUFFT_FLAG_NO_AUTOTUNE), ct)
     assert torch.equal(a, b)
 
 
@@ -129,7 +129,7 @@ def test_half_full_size_sampled():
     """N = M = 2^22 (the forward+backward workload's shape) at eps = 2^-10, sampled rows."""
     N = 1 << 22
     x, c = W.type2_case(3, N)
-    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS, C64, HALF)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, EPS, C64, HALF | P.NUFFT_FLAG_NO_AUTOTUNE)
     assert plan.K == 7
     ct = _t(c, C64)
     cc = ct.cpu().numpy().astype(np.complex128)
@@ -150,5 +150,5 @@ def test_half_flag_validation():
         P.nufft2_plan(x, 10000, 1e-4, C64, HALF)
     assert e.value.status == 2
     with pytest.raises(P.NufftError) as e:
-        P.nufft2_plan(x, 10000, EPS, C64, HALF | P.NUFFT_FLAG_PLAIN)
+        P.nufft2_plan(x, 10000, EPS, C64, HALF | P.NUFFT_FLAG_PLAIN_UNFUSED)
     assert e.value.status == 1

@@ -1,5 +1,6 @@
-"""Autotuned oversampling (NUFFT_FLAG_AUTOTUNE on 1-D plans, Sec. 2.3): the plan is
-built on the grids L0 and 2 L0, the faster type-II transform is kept.  Whatever it
+"""Autotuned oversampling (the default of 1-D plans, Sec. 2.3; NUFFT_FLAG_NO_AUTOTUNE
+turns it off): the plan is built on the grids L0 and 2 L0, the faster type-II
+transform is kept.  Whatever it
 picks, the result must meet the 4 eps ||c||_1 bar against the FP64 direct sums, and
 K and gamma must be those of the grid it picked."""
 import numpy as np
@@ -39,7 +40,7 @@ def test_autotune_grid_parity(dtype, N, M):
     x, c = W.type2_case(80, N, M)
     g = W.complex_normal(W.rng_for(81), M)
     eps = EPS[dtype]
-    plan = P.nufft2_plan(_t(x, torch.float64), N, eps, dtype, P.NUFFT_FLAG_AUTOTUNE)
+    plan = P.nufft2_plan(_t(x, torch.float64), N, eps, dtype)
     L0 = _next_pow2(N)
     _say("autotune N=%d M=%d %s: grid %d (L0 %d), K=%d gamma=%.4f" % (N, M, dtype, plan.grid, L0, plan.K, plan.gamma))
     assert plan.grid in (L0, 2 * L0)
@@ -68,11 +69,25 @@ def test_autotune_matches_fixed_grid_choice():
     N, M = 1 << 12, 1 << 21
     x, c = W.type2_case(83, N, M)
     xt, ct = _t(x, torch.float64), _t(c, C64)
-    pa = P.nufft2_plan(xt, N, 1e-6, C64, P.NUFFT_FLAG_AUTOTUNE)
-    pd = P.nufft2_plan(xt, N, 1e-6, C64)
+    pa = P.nufft2_plan(xt, N, 1e-6, C64)
+    pd = P.nufft2_plan(xt, N, 1e-6, C64, P.NUFFT_FLAG_NO_AUTOTUNE)
     fa = P.nufft2_exec(pa, ct)
     fd = P.nufft2_exec(pd, ct)
     diff = (fa - fd).abs().max().item() / ct.abs().sum().item()
     _say("N=2^12 M=2^21: autotuned grid %d (K=%d), default grid %d (K=%d), diff %.3e"
          % (pa.grid, pa.K, pd.grid, pd.K, diff))
     assert diff <= 8e-6
+
+
+def test_autotune_choice_is_remembered():
+    """A second plan of the same problem class reuses the first one's timed choice (same
+    grid, K and bit-identical results), and NUFFT_FLAG_NO_AUTOTUNE keeps the grid L0."""
+    N, M = 1 << 12, 1 << 20
+    x, c = W.type2_case(84, N, M)
+    xt, ct = _t(x, torch.float64), _t(c, C64)
+    p1 = P.nufft2_plan(xt, N, 1e-6, C64)
+    p2 = P.nufft2_plan(xt, N, 1e-6, C64)
+    p0 = P.nufft2_plan(xt, N, 1e-6, C64, P.NUFFT_FLAG_NO_AUTOTUNE)
+    _say("remembered choice: grid %d / %d, no-autotune grid %d" % (p1.grid, p2.grid, p0.grid))
+    assert p1.grid == p2.grid and p1.K == p2.K and p0.grid == _next_pow2(N)
+    assert torch.equal(P.nufft2_exec(p1, ct), P.nufft2_exec(p2, ct))

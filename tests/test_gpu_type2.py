@@ -67,14 +67,14 @@ def check_type2(x, c, N, dtype, eps=None, flags=0, rows=None, label=""):
 
 def test_n1024_fp64_plain():
     x, c = W.type2_case(1, 1024)
-    _, _, err = check_type2(x, c, 1024, C128, 1e-12, P.NUFFT_FLAG_PLAIN, label="plain")
+    _, _, err = check_type2(x, c, 1024, C128, 1e-12, P.NUFFT_FLAG_PLAIN_UNFUSED, label="plain")
     assert err < 1e-13      # regression gate: observed ~3e-14 in FP64 at K = 15
 
 
 def test_n1024_fp64_fused_equals_plain():
     x, c = W.type2_case(1, 1024)
     _, f1, _ = check_type2(x, c, 1024, C128, 1e-12, 0)
-    _, f2, _ = check_type2(x, c, 1024, C128, 1e-12, P.NUFFT_FLAG_PLAIN)
+    _, f2, _ = check_type2(x, c, 1024, C128, 1e-12, P.NUFFT_FLAG_PLAIN_UNFUSED)
     assert np.abs(f1 - f2).max() <= 1e-13 * np.abs(c).sum()
 
 
@@ -102,7 +102,7 @@ def test_two_pass_full(dtype, N, dist):
 def test_plain_two_pass(dtype):
     N = 1 << 14
     x, c = W.type2_case(22, N, N + 123)
-    check_type2(x, c, N, dtype, flags=P.NUFFT_FLAG_PLAIN, label="plain two-pass")
+    check_type2(x, c, N, dtype, flags=P.NUFFT_FLAG_PLAIN_UNFUSED, label="plain two-pass")
 
 
 def test_uniform_grid_is_one_fft():
@@ -153,7 +153,7 @@ def test_nonfinite_samples_rejected():
 
 def test_fixed_gamma_half():
     x, c = W.type2_case(25, 5000)
-    plan, _, _ = check_type2(x, c, 5000, C64, flags=P.NUFFT_FLAG_FIX_GAMMA_HALF)
+    plan, _, _ = check_type2(x, c, 5000, C64, flags=P.NUFFT_FLAG_FIX_GAMMA_HALF | P.NUFFT_FLAG_NO_AUTOTUNE)
     assert plan.gamma == pytest.approx(5000 / (2 * 8192))
 
 
@@ -165,7 +165,7 @@ def test_n2p20_sampled(dtype, dist):
     N = 1 << 20
     x, c = W.type2_case(2, N, N, dist)
     rows = _rows_subset(x, N, N, 256, 7)
-    plan, _, err = check_type2(x, c, N, dtype, rows=rows, label="2^20 " + dist)
+    plan, _, err = check_type2(x, c, N, dtype, flags=P.NUFFT_FLAG_NO_AUTOTUNE, rows=rows, label="2^20 " + dist)
     assert plan.K == (10 if dtype == C64 else 15)
     if dtype == C64:
         assert err < 2e-7
@@ -175,7 +175,7 @@ def test_n2p20_fp64_plain_sampled():
     N = 1 << 20
     x, c = W.type2_case(2, N)
     rows = _rows_subset(x, N, N, 128, 8)
-    check_type2(x, c, N, C128, flags=P.NUFFT_FLAG_PLAIN, rows=rows, label="2^20 plain")
+    check_type2(x, c, N, C128, flags=P.NUFFT_FLAG_PLAIN_UNFUSED, rows=rows, label="2^20 plain")
 
 
 def test_n2p22_fp32_sampled():
