@@ -205,6 +205,23 @@ nufft_status nufft3_exec(int64_t n_pts, const double *x_dev, int64_t n_freq,
                          const double *w_dev, const void *c_dev, void *f_dev,
                          double eps, nufft_dtype dtype, void *stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation): the
+ * transform of nufft3_exec, same arguments, same kernels and same result, with
+ * every temporary (the assignment of x, the scaled inputs, the inner type-I
+ * plan and its exchange buffer) carved from a fixed device array of 48 MiB
+ * that the library holds on each device it runs on until the process ends.
+ * No hipMalloc, hipFree or other allocating call is made.  Limits:
+ * n_pts <= 2^20 and n_freq <= 2^15 (NUFFT_ERR_UNSUPPORTED beyond, before any
+ * device work).  The array keeps the last call's contents; everything the
+ * transform needs zeroed is cleared by the call itself.  Calls in one process
+ * are serialised by a lock and each returns with `stream` synchronised; calls
+ * from different processes use different copies of the array.  Not graph
+ * capturable (it synchronises, as nufft3_exec does). */
+nufft_status nufft3_exec_noalloc(int64_t n_pts, const double *x_dev, int64_t n_freq,
+                                 const double *w_dev, const void *c_dev, void *f_dev,
+                                 double eps, nufft_dtype dtype, void *stream);
+
 /* ---- 2-D type II and its adjoint --------------------------------------- */
 
 /* Planning stage of the 2-D type II (Sec. 4): x pairs with k1 < n1 and

@@ -9,7 +9,7 @@ from .binding import (  # noqa: F401
     NUFFT_FLAG_BATCH_PERSISTENT, NUFFT_FLAG_FIX_GAMMA_HALF, NUFFT_FLAG_HALF_EXCHANGE, NUFFT_FLAG_NO_AUTOTUNE,
     NUFFT_FLAG_PLAIN_UNFUSED, NufftError, Plan,
     nufft1_exec, nufft1_solve, nufft2_backward, nufft2_exec, nufft2_grad_x, nufft2_plan, nufft2_solve,
-    nufft2d3_exec, nufft2d_exec, nufft2d_plan, nufft2d_type1_exec, nufft3_exec, nufft3d_exec, nufft3d_plan, nufft3d_plan_exec, nufft3d_plan_type1,
+    nufft2d3_exec, nufft2d_exec, nufft2d_plan, nufft2d_type1_exec, nufft3_exec, nufft3_exec_noalloc, nufft3d_exec, nufft3d_plan, nufft3d_plan_exec, nufft3d_plan_type1,
     nufft3d_type1_exec,
     nufft_batch_exec, nufft_batch_plan, nufft_batch_status, nufft_bessel_coefficients, nufft_choose_rank,
     nufft_debug_batch_wait, nufft_debug_fail_alloc,

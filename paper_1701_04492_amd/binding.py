@@ -44,6 +44,7 @@ _sig = {
     "nufft2_solve": [_vp, _vp, _vp, _dbl, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _vp],
     "nufft1_solve": [_vp, _vp, _vp, _dbl, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _vp],
     "nufft3_exec": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
+    "nufft3_exec_noalloc": [_i64, _vp, _i64, _vp, _vp, _vp, _dbl, _int, _vp],
     "nufft2d3_exec": [_i64, _vp, _vp, _i64, _vp, _vp, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
     "nufft3d_exec": [_i64, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _dbl, _int, _vp],
     "nufft3d_type1_exec": [_i64, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _int, _dbl, _int, _vp],
@@ -245,6 +246,20 @@ def nufft3_exec(x, w, c, eps, f=None):
     _check(lib.nufft3_exec(M, _dev_tensor(x, torch.float64, M, "x"), N, _dev_tensor(w, torch.float64, N, "w"),
                            _dev_tensor(c, c.dtype, N, "c"), _dev_tensor(f, c.dtype, M, "f"), float(eps),
                            _cdtype(c.dtype), _stream(c.device)), "nufft3_exec")
+    return f
+
+
+def nufft3_exec_noalloc(x, w, c, eps, f=None):
+    """nufft3_exec with every temporary in the library's fixed device scratch (no device
+    allocation inside the call; M <= 2^20, N <= 2^15)."""
+    M, N = x.numel(), w.numel()
+    c = _res(c)
+    if f is None:
+        f = torch.empty(M, dtype=c.dtype, device=c.device)
+    _check(lib.nufft3_exec_noalloc(M, _dev_tensor(x, torch.float64, M, "x"), N,
+                                   _dev_tensor(w, torch.float64, N, "w"), _dev_tensor(c, c.dtype, N, "c"),
+                                   _dev_tensor(f, c.dtype, M, "f"), float(eps), _cdtype(c.dtype),
+                                   _stream(c.device)), "nufft3_exec_noalloc")
     return f
 
 

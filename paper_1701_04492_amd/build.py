@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnufft_mi355x.so")
-SOURCES = ["api.cpp", "factors.cpp", "plan_kernels.hip", "plain_kernels.hip", "fused_kernels.hip", "type3_kernels.hip", "kernels_2d.hip", "kernels_3d.hip", "batch_kernels.hip", "solve_kernels.hip"]
+SOURCES = ["api.cpp", "factors.cpp", "plan_kernels.hip", "plain_kernels.hip", "fused_kernels.hip", "type3_kernels.hip", "kernels_2d.hip", "kernels_3d.hip", "batch_kernels.hip", "solve_kernels.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -18,6 +18,7 @@
 #include "kernels_3d.h"
 #include "solve.h"
 #include "batch.h"
+#include "noalloc.h"
 
 using namespace nufft;
 
@@ -32,6 +33,12 @@ void *nufft_plan_s::alloc(size_t bytes)
     }
     if (v == 0) return nullptr;   // the injected failure
     if (bytes == 0) bytes = 16;
+    if (arena) {
+        const size_t at = (arena->used + 255) & ~(size_t)255;
+        if (at + bytes > arena->cap) return nullptr;
+        arena->used = at + bytes;
+        return arena->base + at;
+    }
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -496,12 +503,16 @@ static void t3_factors(double gamma, int K, Factors<double> &fac, double *su_out
     *su_out = su;
 }
 
+// arena non-null: every temporary (and the inner plan's buffers) comes from it.
 template <typename R>
 static nufft_status type3(int64_t M, const double *x, int64_t N, const double *w, const void *c, void *f,
-                          double eps, nufft_dtype dt, hipStream_t s)
+                          double eps, nufft_dtype dt, hipStream_t s, Arena *arena = nullptr)
 {
     using C = cx_t<R>;
     Plan tmp;   // owns the temporaries
+    tmp.arena = arena;
+    Plan inner_plan;   // the inner type-I plan (its buffers are released with it)
+    inner_plan.arena = arena;
     struct SyncGuard {   // destroyed before tmp: no temporary is freed under a running kernel
         hipStream_t s;
         ~SyncGuard() { (void)hipStreamSynchronize(s); }
@@ -543,9 +554,7 @@ static nufft_status type3(int64_t M, const double *x, int64_t N, const double *w
     if (eps_i < floor_eps) eps_i = floor_eps;
     if (eps / 2.0 + sw * eps_i > 4.0 * eps) return NUFFT_ERR_UNSUPPORTED;
     // inner type-I plan on the samples w/N with N modes
-    Plan *inner = new (std::nothrow) Plan();
-    if (!inner) return NUFFT_ERR_ALLOC;
-    tmp.children.push_back(inner);
+    Plan *inner = &inner_plan;
     inner->kind = PLAN_1D;
     inner->dtype = dt;
     inner->N = N;
@@ -1471,6 +1480,34 @@ nufft_status nufft3_exec(int64_t n_pts, const double *x, int64_t n_freq, const d
     st = dtype == NUFFT_C64 ? type3<float>(n_pts, x, n_freq, w, c, f, eps, dtype, s)
                             : type3<double>(n_pts, x, n_freq, w, c, f, eps, dtype, s);
     if (st != NUFFT_OK) (void)hipStreamSynchronize(s);
+    return st;
+}
+
+// The same transform with every temporary in the device's fixed scratch array
+// (no device allocation).  Calls of one process are serialised: each one ends
+// with its stream synchronised, so the next finds the array free.
+static std::mutex noalloc_mu;
+
+nufft_status nufft3_exec_noalloc(int64_t n_pts, const double *x, int64_t n_freq, const double *w, const void *c,
+                                 void *f, double eps, nufft_dtype dtype, void *stream)
+{
+    if (n_pts < 1 || n_freq < 1 || !x || !w || !c || !f) return NUFFT_ERR_INVALID_ARG;
+    if (dtype != NUFFT_C64 && dtype != NUFFT_C128) return NUFFT_ERR_INVALID_ARG;
+    if (n_pts > NUFFT_NOALLOC_MAX_M || n_freq > NUFFT_NOALLOC_MAX_N) return NUFFT_ERR_UNSUPPORTED;
+    nufft_status st;
+    if (!eps_ok(eps, dtype, &st)) return st;
+    std::lock_guard<std::mutex> g(noalloc_mu);
+    void *base = nullptr;
+    size_t cap = 0;
+    NUFFT_HIP_CHECK(noalloc_scratch(&base, &cap));
+    Arena arena;
+    arena.base = (char *)base;
+    arena.cap = cap;
+    hipStream_t s = (hipStream_t)stream;
+    st = dtype == NUFFT_C64 ? type3<float>(n_pts, x, n_freq, w, c, f, eps, dtype, s, &arena)
+                            : type3<double>(n_pts, x, n_freq, w, c, f, eps, dtype, s, &arena);
+    (void)hipStreamSynchronize(s);   // the array is free again when the call returns
+    if (st == NUFFT_ERR_ALLOC) st = NUFFT_ERR_UNSUPPORTED;   // beyond the array (not expected within the limits)
     return st;
 }
 

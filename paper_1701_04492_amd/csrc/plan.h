@@ -18,8 +18,17 @@ struct Profiler {
     ~Profiler();
 };
 
+// Bump allocation from a caller-provided device block (the fixed scratch of the
+// allocation-free entry point): blocks are 256-byte aligned and never freed one
+// by one; the block is reused from the start by the next call.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+};
+
 struct nufft_plan_s {
     int kind = 0;
+    Arena *arena = nullptr;         // non-null: alloc() carves from it instead of hipMalloc
     nufft_dtype dtype = NUFFT_C64;
     uint32_t flags = 0;
     int64_t N = 0, M = 0, L = 0;    // modes, samples, FFT grid

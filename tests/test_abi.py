@@ -84,3 +84,11 @@ def test_batch_and_debug_entry_points_reject_bad_handles():
     n = ctypes.c_int64()
     assert B.lib.nufft_batch_status(None, ctypes.byref(n), None) == 1
     assert B.lib.nufft_debug_batch_wait(None, 10, 1) == 1
+
+
+def test_noalloc_entry_point_refuses_sizes_beyond_its_scratch():
+    """Refused on the host before any device work (no GPU needed): M > 2^20 or N > 2^15."""
+    p = ctypes.c_void_p(8)
+    assert B.lib.nufft3_exec_noalloc((1 << 20) + 1, p, 16, p, p, p, 1e-6, 0, None) == 2
+    assert B.lib.nufft3_exec_noalloc(16, p, (1 << 15) + 1, p, p, p, 1e-6, 0, None) == 2
+    assert B.lib.nufft3_exec_noalloc(0, p, 16, p, p, p, 1e-6, 0, None) == 1
