@@ -369,6 +369,20 @@ nufft_status nufft_batch_status(nufft_plan_t plan, int64_t *timeouts_host, void 
  * or of the three phased launches together (one per task). */
 nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *grid);
 
+/* The tuning schedule of a 1-D plan's two-pass kernels: *schedule is the one
+ * in use and *n_schedules how many the plan offers (either may be NULL).
+ * complex64 plans whose split has L1, L2 in {1024, 2048} offer three:
+ *   0  default tile shapes, FFT stages radix 16 first (16 x 16 x 8 for 2048 points);
+ *   1  default tile shapes, radix 8 first (8 x 16 x 16), with twiddle tables of that order;
+ *   2  alternative tile shapes (half the columns per pass-A workgroup, half
+ *      the ranks and twice the sample slots per pass-B workgroup, half the
+ *      ranks in pass B', twice the columns per pass-A' workgroup).
+ * Other plans offer one.  Unless NUFFT_FLAG_NO_AUTOTUNE is given, nufft2_plan
+ * times a type-II transform and an adjoint under each and keeps the fastest
+ * (remembered per problem class, see NUFFT_FLAG_NO_AUTOTUNE).  Results of the
+ * schedules differ only by rounding. */
+nufft_status nufft_plan_tuning(nufft_plan_t plan, int *schedule, int *n_schedules);
+
 /* Copies the plan's sorted sample order to host memory: perm_host[i] is the
  * sample index at sorted position i (M int32).  1-D plans only. */
 nufft_status nufft_plan_perm(nufft_plan_t plan, int32_t *perm_host);
@@ -415,6 +429,10 @@ nufft_status nufft_debug_fail_alloc(int64_t n);
  * every kernel still ends normally.  INVALID_ARG for a non-batch plan or a
  * negative limit. */
 nufft_status nufft_debug_batch_wait(nufft_plan_t plan, int64_t spin_limit, int unreachable);
+
+/* For tests of the tuning schedules: makes the plan run `schedule` (below the
+ * count nufft_plan_tuning reports, else INVALID_ARG) from the next exec on. */
+nufft_status nufft_debug_set_schedule(nufft_plan_t plan, int schedule);
 
 /* ---- host-side factor generator (no GPU work) --------------------------- */
 

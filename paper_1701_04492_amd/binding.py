@@ -64,6 +64,8 @@ _sig = {
     "nufft_plan_profile_read": [_vp, _int, ctypes.c_char_p, _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl)],
     "nufft_debug_fail_alloc": [_i64],
     "nufft_batch_status": [_vp, ctypes.POINTER(_i64), _vp],
+    "nufft_plan_tuning": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)],
+    "nufft_debug_set_schedule": [_vp, _int],
     "nufft_debug_batch_wait": [_vp, _i64, _int],
     "nufft_choose_rank": [_dbl, _dbl, ctypes.POINTER(_int)],
     "nufft_bessel_coefficients": [_dbl, _int, _vp],
@@ -406,6 +408,17 @@ def nufft_debug_batch_wait(plan, spin_limit, unreachable=False):
     """Bound of the persistent launch's pass-B waits, and (tests) an unreachable wait target."""
     _check(lib.nufft_debug_batch_wait(plan.handle, int(spin_limit), int(bool(unreachable))),
            "nufft_debug_batch_wait")
+
+
+def nufft_plan_tuning(plan):
+    """(schedule in use, number of schedules the plan offers)."""
+    sc, n = _int(), _int()
+    _check(lib.nufft_plan_tuning(plan.handle, ctypes.byref(sc), ctypes.byref(n)), "nufft_plan_tuning")
+    return sc.value, n.value
+
+
+def nufft_debug_set_schedule(plan, schedule):
+    _check(lib.nufft_debug_set_schedule(plan.handle, int(schedule)), "nufft_debug_set_schedule")
 
 
 def nufft_plan_info(plan):

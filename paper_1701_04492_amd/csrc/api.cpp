@@ -234,6 +234,17 @@ nufft_status upload_twiddles(Plan *p, hipStream_t s)
         if ((st = upload_table<R>(p, t2, &p->tw2, s))) return st;
         if ((st = upload_table<R>(p, lo, &p->lo, s))) return st;
         if ((st = upload_table<R>(p, hi, &p->hi, s))) return st;
+        if (sizeof(R) == 4 && (p->L1 == 1024 || p->L1 == 2048) && (p->L2 == 1024 || p->L2 == 2048)) {
+            // the radix-8-first stage order of the tuning schedule 1
+            fft_twiddles(p->L1, -1, t1.data(), 8);
+            fft_twiddles(p->L1, 1, t1i.data(), 8);
+            fft_twiddles(p->L2, -1, t2.data(), 8);
+            fft_twiddles(p->L2, 1, t2i.data(), 8);
+            if ((st = upload_table<R>(p, t1, &p->tw1r8, s))) return st;
+            if ((st = upload_table<R>(p, t1i, &p->tw1ir8, s))) return st;
+            if ((st = upload_table<R>(p, t2, &p->tw2r8, s))) return st;
+            if ((st = upload_table<R>(p, t2i, &p->tw2ir8, s))) return st;
+        }
     }
     return NUFFT_OK;
 }
@@ -367,6 +378,11 @@ FusedArgs<R> fused_args(const Plan *p)
     a.lo = (const cx_t<R> *)p->lo;
     a.part = (cx_t<R> *)p->part;
     a.part_cap = p->part_cap;
+    a.sched = p->tw1r8 ? p->sched : 0;
+    a.tw1r8 = (const cx_t<R> *)p->tw1r8;
+    a.tw1ir8 = (const cx_t<R> *)p->tw1ir8;
+    a.tw2r8 = (const cx_t<R> *)p->tw2r8;
+    a.tw2ir8 = (const cx_t<R> *)p->tw2ir8;
     a.prof = const_cast<Profiler *>(&p->prof);
     return a;
 }
@@ -1358,6 +1374,76 @@ static nufft_status autotune_grid(Plan **pp, const double *x, hipStream_t s)
     return NUFFT_OK;
 }
 
+// Tuning schedule of the two-pass kernels (first FFT radix, tile shapes; the
+// kernels list the schedules).  Unless NUFFT_FLAG_NO_AUTOTUNE is given, an
+// FP32 plan offering them times one type-II transform and one adjoint under
+// each schedule on scratch inputs and keeps the fastest; the choice is
+// remembered per (L1, L2, K, tile population class, flags).
+template <typename R>
+static nufft_status autotune_schedule(Plan *p, hipStream_t s)
+{
+    if (!p->tw1r8) return NUFFT_OK;   // the plan offers only the default
+    int mc = 0;   // tile population class: log2 of samples per grid point, rounded down, in [-8, 8]
+    for (int64_t v = p->M; v >= 2 * p->L && mc < 8; v >>= 1) ++mc;
+    for (int64_t v = p->M; 2 * v <= p->L && mc > -8; v <<= 1) --mc;
+    char kb[192];
+    std::snprintf(kb, sizeof(kb), "sched L1=%d L2=%d dt=%d K=%d mc=%d flags=%u", p->L1, p->L2, (int)p->dtype, p->K,
+                  mc, (unsigned)p->flags);
+    const std::string key(kb);
+    long long known = 0;
+    if (tune_lookup(key, &known)) {
+        p->sched = (int)known;
+        return NUFFT_OK;
+    }
+    Plan scratch;
+    void *c = scratch.alloc((size_t)p->N * 2 * sizeof(R));
+    void *g = scratch.alloc((size_t)p->M * 2 * sizeof(R));
+    void *f = scratch.alloc((size_t)std::max(p->N, p->M) * 2 * sizeof(R));
+    if (!c || !g || !f) return NUFFT_ERR_ALLOC;
+    NUFFT_HIP_CHECK(hipMemsetAsync(c, 0, (size_t)p->N * 2 * sizeof(R), s));
+    NUFFT_HIP_CHECK(hipMemsetAsync(g, 0, (size_t)p->M * 2 * sizeof(R), s));
+    hipEvent_t e0, e1;
+    NUFFT_HIP_CHECK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return NUFFT_ERR_HIP;
+    }
+    // the schedules are timed in interleaved rounds and each keeps its best round,
+    // so that a slow moment of the device does not decide the choice
+    constexpr int NS = 3, ROUNDS = 3, REPS = 3;
+    float best_of[NS];
+    for (int sc = 0; sc < NS; ++sc) best_of[sc] = 1e30f;
+    hipError_t e = hipSuccess;
+    for (int round = 0; round < ROUNDS && e == hipSuccess; ++round)
+        for (int sc = 0; sc < NS && e == hipSuccess; ++sc) {
+            p->sched = sc;
+            const FusedArgs<R> a = fused_args<R>(p);
+            auto once = [&]() {
+                hipError_t r = fused_type2<R>(a, (const cx_t<R> *)c, (cx_t<R> *)f, 0, nullptr, nullptr, s);
+                if (r == hipSuccess) r = fused_type1<R>(a, (const cx_t<R> *)g, (cx_t<R> *)f, +1, s);
+                return r;
+            };
+            e = once();   // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int rep = 0; rep < REPS && e == hipSuccess; ++rep) e = once();
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) best_of[sc] = std::min(best_of[sc], ms);
+        }
+    int pick = 0;
+    for (int sc = 1; sc < NS; ++sc)
+        if (best_of[sc] < best_of[pick]) pick = sc;
+    (void)hipStreamSynchronize(s);   // nothing may still use the scratch buffers freed on return
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->sched = pick;
+    if (e != hipSuccess) return NUFFT_ERR_HIP;
+    tune_store(key, pick);
+    return NUFFT_OK;
+}
+
 static bool eps_ok(double eps, nufft_dtype dt, nufft_status *st)
 {
     if (!(eps > 0.0 && eps < 1.0)) { *st = NUFFT_ERR_INVALID_ARG; return false; }
@@ -1400,6 +1486,8 @@ nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, cons
     st = dtype == NUFFT_C64 ? build_1d<float>(p, x_dev, s) : build_1d<double>(p, x_dev, s);
     if (st == NUFFT_OK && !(flags & (NUFFT_FLAG_NO_AUTOTUNE | NUFFT_FLAG_PLAIN_UNFUSED)))
         st = dtype == NUFFT_C64 ? autotune_grid<float>(&p, x_dev, s) : autotune_grid<double>(&p, x_dev, s);
+    if (st == NUFFT_OK && !(flags & (NUFFT_FLAG_NO_AUTOTUNE | NUFFT_FLAG_PLAIN_UNFUSED)))
+        st = dtype == NUFFT_C64 ? autotune_schedule<float>(p, s) : autotune_schedule<double>(p, s);
     if (st != NUFFT_OK) {
         (void)hipStreamSynchronize(s);
         delete p;
@@ -1742,6 +1830,23 @@ nufft_status nufft_plan_info(nufft_plan_t plan, int *K, double *gamma, int64_t *
     if (K) *K = plan->K;
     if (gamma) *gamma = plan->gamma;
     if (grid) *grid = plan->L;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_plan_tuning(nufft_plan_t plan, int *schedule, int *n_schedules)
+{
+    if (!plan) return NUFFT_ERR_INVALID_ARG;
+    if (schedule) *schedule = plan->sched;
+    if (n_schedules) *n_schedules = (plan->kind == PLAN_1D && plan->tw1r8) ? 3 : 1;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_debug_set_schedule(nufft_plan_t plan, int schedule)
+{
+    int n = 0;
+    if (!plan || nufft_plan_tuning(plan, nullptr, &n) != NUFFT_OK || schedule < 0 || schedule >= n)
+        return NUFFT_ERR_INVALID_ARG;
+    plan->sched = schedule;
     return NUFFT_OK;
 }
 

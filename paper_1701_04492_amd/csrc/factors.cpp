@@ -107,7 +107,7 @@ void cis_2pi_frac(int64_t m, int64_t L, double *c, double *s)
     }
 }
 
-void fft_twiddles(int64_t L, int dir, double *out)
+void fft_twiddles(int64_t L, int dir, double *out, int r0)
 {
     // Stage-major layout read by the LDS FFT: the stage that combines NS-point
     // transforms with radix R keeps exp(dir 2 pi i q k / (NS R)), 0 <= k < NS,
@@ -117,7 +117,8 @@ void fft_twiddles(int64_t L, int dir, double *out)
     out[2 * (L - 1)] = 1.0;   // entry L - 1 is unused
     out[2 * (L - 1) + 1] = 0.0;
     for (int64_t NS = 1; NS < L;) {
-        const int64_t R = (L / NS >= 16) ? 16 : L / NS;
+        // the stage radices of the LDS FFT: r0 first, then 16 while possible, then the remainder
+        const int64_t R = NS == 1 ? (r0 < L ? r0 : L) : (L / NS >= 16) ? 16 : L / NS;
         for (int64_t k = 0; k < NS; ++k)
             for (int64_t q = 1; q < R; ++q) {
                 double c, s;

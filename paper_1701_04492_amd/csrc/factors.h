@@ -26,7 +26,7 @@ void cis_2pi_frac(int64_t m, int64_t L, double *c, double *s);
 // out[2i], out[2i+1] = exp(dir 2 pi i (i*step) / L) for i < count.
 void twiddles(int64_t L, int64_t count, int64_t step, int dir, double *out);
 // FFT stage twiddles of a length-L transform (L a power of two, 16..4096), in
-// the stage-major order the LDS FFT reads; L entries.
-void fft_twiddles(int64_t L, int dir, double *out);
+// the stage-major order the LDS FFT reads for first radix r0 (16 or 8); L entries.
+void fft_twiddles(int64_t L, int dir, double *out, int r0 = 16);
 
 }  // namespace nufft

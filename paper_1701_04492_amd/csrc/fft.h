@@ -2,10 +2,14 @@
 //
 // A length-L transform (L a power of two, 16 <= L <= 4096) is held in LDS and
 // computed by L/16 threads with 16 complex values per thread per stage
-// (Stockham auto-sort: radix-16 stages, then one radix-2/4/8 stage if L is
-// not a power of 16).  Several transforms share a workgroup; every thread of
-// the workgroup runs the same stage sequence, so __syncthreads() separates
-// the read and write phases of each stage.
+// (Stockham auto-sort).  The stage radices are R0, then 16 while at least 16
+// points per sub-transform remain, then the remainder: R0 = 16 gives radix-16
+// stages and one radix-2/4/8 stage last; R0 = 8 starts with a radix-8 stage
+// (two butterflies per thread), e.g. 8 x 16 x 16 instead of 16 x 16 x 8 for
+// L = 2048.  The order is a tuning choice (the arithmetic per point is the
+// same).  Several transforms share a workgroup; every thread of the workgroup
+// runs the same stage sequence, so __syncthreads() separates the read and
+// write phases of each stage.
 //
 // LDS layout: element i of a transform lives at lds_pad(i) = i + i/16 (one
 // spare slot per 16 breaks the power-of-two strides of the radix-16 write
@@ -39,6 +43,13 @@ __host__ __device__ constexpr int fft_pitch_g(int L, int G)
 }
 
 namespace fftk {
+
+// Radix of the stage that combines NS-point sub-transforms (first radix R0).
+template <int L, int NS, int R0>
+__host__ __device__ constexpr int stage_radix()
+{
+    return NS == 1 ? (R0 < L ? R0 : L) : (L / NS >= 16 ? 16 : L / NS);
+}
 
 // Ordering between the read and write phases of a stage.  WS (wave sync): the
 // transform's threads all belong to one wavefront and no other wave touches
@@ -188,11 +199,11 @@ __device__ __forceinline__ void stage_compute_store(C *buf, const C *tw, int lt,
     stage_sync<WS>();
 }
 
-template <typename C, int L, int DIR, int NS, bool WS>
+template <typename C, int L, int DIR, int NS, bool WS, int R0 = 16>
 __device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt, bool active)
 {
     if constexpr (NS < L) {
-        constexpr int R = (L / NS >= 16) ? 16 : (L / NS);
+        constexpr int R = stage_radix<L, NS, R0>();
         constexpr int BPT = 16 / R;
         C v[16];
         if (active) {
@@ -204,7 +215,7 @@ __device__ __forceinline__ void stages_from(C *buf, const C *tw, int lt, bool ac
             }
         }
         stage_compute_store<C, L, DIR, NS, R, WS>(buf, tw, lt, v, active);
-        stages_from<C, L, DIR, NS * R, WS>(buf, tw, lt, active);
+        stages_from<C, L, DIR, NS * R, WS, R0>(buf, tw, lt, active);
     }
 }
 
@@ -227,12 +238,13 @@ __device__ __forceinline__ void fft_publish()
 // Full transform whose input is already in LDS (natural order, padded).
 // Result: natural order in the same buffer.  Called by all threads of the
 // workgroup; lt in [0, L/16) is this thread's lane within the transform.
-template <typename C, int L, int DIR, bool WS = false>
+template <typename C, int L, int DIR, bool WS = false, int R0 = 16>
 __device__ __forceinline__ void block_fft_lds(C *buf, const C *tw, int lt, bool active = true)
 {
     static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "unsupported FFT length");
     static_assert(!WS || L <= 1024, "a wave-synchronous transform must fit one wavefront");
-    fftk::stages_from<C, L, DIR, 1, WS>(buf, tw, lt, active);
+    static_assert(R0 == 16 || R0 == 8, "first radix 16 or 8");
+    fftk::stages_from<C, L, DIR, 1, WS, R0>(buf, tw, lt, active);
 }
 
 // Full transform whose input is in registers: v[q] = x[lt + q*L/16], q < 16
@@ -241,18 +253,31 @@ __device__ __forceinline__ void block_fft_lds(C *buf, const C *tw, int lt, bool 
 // (a __syncthreads() since the last use).  Result: natural order in buf.
 // `active` false (uniform over whole waves): the transform is skipped, the
 // barriers are still taken, and its part of buf is left as it was.
-template <typename C, int L, int DIR, bool WS = false>
+template <typename C, int L, int DIR, bool WS = false, int R0 = 16>
 __device__ __forceinline__ void block_fft_regs(C *buf, const C *tw, int lt, C *v, bool active = true)
 {
     static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "unsupported FFT length");
     static_assert(!WS || L <= 1024, "a wave-synchronous transform must fit one wavefront");
-    // first stage: NS = 1, R = 16, one butterfly per thread, no twiddles
-    if (active) {
-        fftk::dft<16, C, DIR>(v);
-        const int base = lt * 16;
+    static_assert(R0 == 16 || R0 == 8, "first radix 16 or 8");
+    if constexpr (R0 == 16) {
+        // first stage: NS = 1, R = 16, one butterfly per thread, no twiddles
+        if (active) {
+            fftk::dft<16, C, DIR>(v);
+            const int base = lt * 16;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) buf[lds_pad(base + q)] = v[q];
+            for (int q = 0; q < 16; ++q) buf[lds_pad(base + q)] = v[q];
+        }
+        fftk::stage_sync<WS>();
+        fftk::stages_from<C, L, DIR, 16, WS>(buf, tw, lt, active);
+    } else {
+        // first stage: NS = 1, R = 8, two butterflies per thread: butterfly i
+        // (b = lt + i L/16) takes x[b + q L/8] = v[i + 2q]
+        C w[16];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) w[i * 8 + q] = v[i + 2 * q];
+        fftk::stage_compute_store<C, L, DIR, 1, 8, WS>(buf, tw, lt, w, active);
+        fftk::stages_from<C, L, DIR, 8, WS, 8>(buf, tw, lt, active);
     }
-    fftk::stage_sync<WS>();
-    fftk::stages_from<C, L, DIR, 16, WS>(buf, tw, lt, active);
 }

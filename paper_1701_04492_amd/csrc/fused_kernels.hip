@@ -235,7 +235,7 @@ hipError_t fused_sort_input(const FusedArgs<R> &a, const cx_t<R> *in, const char
 // Y_r[n2][k1] (G-element runs).
 // H (FP32 only): Y in fp16 pairs with one scale exponent per (rank, column),
 // E[r * L1 + k1] (the half-precision exchange).
-template <typename R, int L2, int G, bool TWG, bool H>
+template <typename R, int L2, int G, bool TWG, bool H, int FR = 16>
 __global__ void __launch_bounds__(G * L2 / 16)
 k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, int mode,
         const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
@@ -299,7 +299,7 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
             for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], wq[q]);
         }
         __syncthreads();   // earlier readers of buf are done
-        block_fft_regs<C, L2, -1, fft_wave_sync<L2>>(buf + g * P, tw, lt, v);
+        block_fft_regs<C, L2, -1, fft_wave_sync<L2>, FR>(buf + g * P, tw, lt, v);
         fft_publish<L2>();
         if constexpr (H) {
             // this thread's 16 outputs all lie in column gg = tid % G (NT is a multiple of G)
@@ -350,7 +350,7 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
 // With many more samples than grid points, `splits` tasks share a tile, each
 // transforming its rows and taking an equal slice of the tile's samples.
 // H: Y holds fp16 pairs scaled per (rank, column) by 2^E[r * L1 + k1].
-template <typename R, int L1, int RC, int S, bool TWG, bool H>
+template <typename R, int L1, int RC, int S, bool TWG, bool H, int FR = 16>
 __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
         const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
@@ -450,7 +450,7 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
                 if (r0 + RC < fac.K) fetch(r0 + RC + g, vn, en);
                 __syncthreads();
                 // a rank slot beyond K (the last chunk of ranks) skips its transform
-                block_fft_regs<C, L1, -1, fft_wave_sync<L1>>(buf + g * P, tw, lt, v, r0 + g < fac.K);
+                block_fft_regs<C, L1, -1, fft_wave_sync<L1>, FR>(buf + g * P, tw, lt, v, r0 + g < fac.K);
                 fft_publish<L1>();
             }
             gather(r0, min(RC, fac.K - r0), c0, kv, xs, acc);
@@ -491,7 +491,7 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
 // of an LDS copy, for the sizes where LDS would otherwise cap occupancy.
 // H (FP32 only): Z in fp16 pairs with one scale exponent per (rank, row),
 // E[r * L2 + n2] (the half-precision exchange).
-template <typename R, int L1, int RC, int SCAP, int dir, bool TWG, bool H>
+template <typename R, int L1, int RC, int SCAP, int dir, bool TWG, bool H, int FR = 16>
 __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__ Xs,
             const uint32_t *__restrict__ keys, const int32_t *__restrict__ off,
@@ -639,7 +639,7 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
                 if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -dir * (r0 + gg));
         }
         __syncthreads();
-        block_fft_lds<C, L1, dir, fft_wave_sync<L1>>(buf + g * P, tw, lt);   // each thread then reads only its own transform
+        block_fft_lds<C, L1, dir, fft_wave_sync<L1>, FR>(buf + g * P, tw, lt);   // each thread then reads only its own transform
         const int r = r0 + g;
         if constexpr (H) {
             // row g's block maximum over its TPF threads (whole waves when TPF >= 64)
@@ -819,7 +819,7 @@ k_sum_split_rows(const cx_t<R> *__restrict__ Zp, int splits, int K, int L1, int6
 // this one is transformed) are transformed along n2 -> k2 and accumulated
 // with weight v_r(k1 + L1 k2) in registers; the sum over r is written once.
 // H: Z holds fp16 pairs scaled per (rank, row) by 2^E[r * L2 + n2].
-template <typename R, int L2, int G, int DIR, bool TWG, bool H>
+template <typename R, int L2, int G, int DIR, bool TWG, bool H, int FR = 16>
 __global__ void __launch_bounds__(G * L2 / 16)
 k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const cx_t<R> *__restrict__ tw_g,
             cx_t<R> *__restrict__ out, const int8_t *__restrict__ E)
@@ -882,7 +882,7 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
         }
         if (r + 1 < K) fetch(r + 1);   // its exponents go to the other parity, last read at rank r - 1
         __syncthreads();
-        block_fft_lds<C, L2, DIR, fft_wave_sync<L2>>(buf + g * P, tw, lt);
+        block_fft_lds<C, L2, DIR, fft_wave_sync<L2>, FR>(buf + g * P, tw, lt);
         fft_publish<L2>();
 #pragma unroll
         for (int h = 0; h < 16; h += 8) {   // two halves of 8: bounded transient registers
@@ -1076,6 +1076,91 @@ static inline int pass_a_ranks(int K, int ncg)
     return (K + nrc - 1) / nrc;
 }
 
+// ---- launches of the two-pass kernels, and the tuning schedules ----------------
+// A plan's schedule (FusedArgs::sched, chosen by timing at plan time) selects,
+// for FP32 two-pass plans with L1, L2 in {1024, 2048}:
+//   0  the default shapes, FFT stages 16 x 16 x ... (first radix 16);
+//   1  the default shapes with first radix 8 (8 x 16 x 16 for 2048 points,
+//      8 x 16 x 8 for 1024), which reads the plan's radix-8 twiddle tables;
+//   2  the alternative tile shapes: half the columns per pass-A workgroup,
+//      pass B with half the ranks side by side and twice the sample slots,
+//      pass B' with half the ranks, twice the columns per pass-A' workgroup.
+// Other plans always run schedule 0.
+static inline bool sched_sizes(int L1, int64_t L2)
+{
+    return (L1 == 1024 || L1 == 2048) && (L2 == 1024 || L2 == 2048);
+}
+
+template <typename R, int LL, int G, bool HX, int FR>
+static void launch_pass_a(const FusedArgs<R> &a, const cx_t<R> *c, int mode, hipStream_t s)
+{
+    const int ncg = a.L1 / G, rca = pass_a_ranks(a.fac.K, ncg);
+    const int T = ncg * ((a.fac.K + rca - 1) / rca);
+    hipLaunchKernelGGL((k_passA<R, LL, G, false, HX, FR>), dim3(xcd_grid(T)), dim3(G * LL / 16), 0, s, c, a.N,
+                       (int64_t)a.L1, a.fac.K, rca, mode, FR == 8 ? a.tw2r8 : a.tw2, a.hi, a.lo, a.Y, a.E);
+}
+
+template <typename R, int LL, int RR, int SS, bool HX, int FR>
+static void launch_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_t<R> *g, double *gx, hipStream_t s)
+{
+    const int sp = pass_b_splits(a.M, a.L2, LL, RR * (LL / 16) * SS);
+    hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false, HX, FR>), dim3(xcd_grid(a.L2 * sp)), dim3(RR * LL / 16), 0, s,
+                       (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,
+                       FR == 8 ? a.tw1r8 : a.tw1, f, mode, g, gx, a.E, sp);
+}
+
+template <typename R, int LL, int RR, int SC, int DIR, bool TG, bool HX, int FR>
+static void launch_pass_b_adj(const FusedArgs<R> &a, hipStream_t s)
+{
+    const cx_t<R> *tw = FR == 8 ? (DIR < 0 ? a.tw1r8 : a.tw1ir8) : (DIR < 0 ? a.tw1 : a.tw1i);
+    hipLaunchKernelGGL((k_passB_adj<R, LL, RR, SC, DIR, TG, HX, FR>), dim3(xcd_grid(a.L2)), dim3(RR * LL / 16), 0, s,
+                       a.gsort, (int64_t)a.L2, a.Xs, a.keys, a.off, a.fac, tw, a.hi, a.lo, a.Y, a.E);
+}
+
+template <typename R, int LL, int G, int DIR, bool HX, int FR>
+static void launch_pass_a_adj(const FusedArgs<R> &a, cx_t<R> *f, hipStream_t s)
+{
+    const cx_t<R> *tw = FR == 8 ? (DIR < 0 ? a.tw2r8 : a.tw2ir8) : (DIR < 0 ? a.tw2 : a.tw2i);
+    hipLaunchKernelGGL((k_passA_adj<R, LL, G, DIR, false, HX, FR>), dim3(xcd_grid(a.L1 / G)), dim3(G * LL / 16), 0, s,
+                       (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, tw, f, a.E);
+}
+
+// Schedules 1 and 2 of an FP32 plan (false: not this plan's sizes, run the default).
+// GD: columns per workgroup relative to the default (1, or 2 for half as many);
+// FR: first radix.
+template <typename R, int GD, int FR>
+static bool tuned_pass_a(const FusedArgs<R> &a, const cx_t<R> *c, int mode, hipStream_t s)
+{
+    if (a.half || !sched_sizes(a.L1, a.L2)) return false;
+    if (a.L2 == 1024) launch_pass_a<R, 1024, Cfg<R>::G1024 / GD, false, FR>(a, c, mode, s);
+    else launch_pass_a<R, 2048, Cfg<R>::G2048 / GD, false, FR>(a, c, mode, s);
+    return true;
+}
+template <typename R, int RD, int FR>
+static bool tuned_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_t<R> *g, double *gx, hipStream_t s)
+{
+    if (a.half || !sched_sizes(a.L1, a.L2)) return false;
+    if (a.L1 == 1024) launch_pass_b<R, 1024, NUFFT_F32_PB1024_RC / RD, NUFFT_F32_PB1024_S * RD, false, FR>(a, f, mode, g, gx, s);
+    else launch_pass_b<R, 2048, NUFFT_F32_PB2048_RC / RD, NUFFT_F32_PB2048_S * RD, false, FR>(a, f, mode, g, gx, s);
+    return true;
+}
+template <typename R, int DIR, int RD, int FR>
+static bool tuned_pass_b_adj(const FusedArgs<R> &a, hipStream_t s)
+{
+    if (a.half || !sched_sizes(a.L1, a.L2)) return false;
+    if (a.L1 == 1024) launch_pass_b_adj<R, 1024, 4 / RD, pba_cap(1024, true), DIR, false, false, FR>(a, s);
+    else launch_pass_b_adj<R, 2048, NUFFT_F32_PBA2048_RC / RD, pba_cap(2048, true), DIR, true, false, FR>(a, s);
+    return true;
+}
+template <typename R, int DIR, int GM, int FR>
+static bool tuned_pass_a_adj(const FusedArgs<R> &a, cx_t<R> *f, hipStream_t s)
+{
+    if (a.half || !sched_sizes(a.L1, a.L2)) return false;
+    if (a.L2 == 1024) launch_pass_a_adj<R, 1024, Cfg<R>::GA1024 * GM, DIR, false, FR>(a, f, s);
+    else launch_pass_a_adj<R, 2048, Cfg<R>::GA2048 * GM, DIR, false, FR>(a, f, s);
+    return true;
+}
+
 template <typename R>
 hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int mode, const cx_t<R> *g,
                        double *gx, hipStream_t s)
@@ -1095,49 +1180,56 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     }
     // pass A
     prof_begin(a.prof, mode ? "gradx_passA" : "fwd_passA", s);
-    switch (a.L2) {
+    bool ok = false;
+    if constexpr (sizeof(R) == 4) {
+        if (a.sched == 1) ok = tuned_pass_a<R, 1, 8>(a, c, mode, s);          // 8 x 16 x ... column FFTs
+        else if (a.sched == 2) ok = tuned_pass_a<R, 2, 16>(a, c, mode, s);    // half the columns per workgroup
+    }
+    if (!ok) {
+        switch (a.L2) {
 #define PA(LL, GG)                                                                                         \
     case LL: {                                                                                             \
         constexpr int G = GG;                                                                              \
-        const int ncg = a.L1 / G, rca = pass_a_ranks(a.fac.K, ncg);                                        \
-        const int T = ncg * ((a.fac.K + rca - 1) / rca);                                                   \
-        HX_DISPATCH(hipLaunchKernelGGL((k_passA<R, LL, G, false, HX>), dim3(xcd_grid(T)), dim3(G * LL / 16), \
-                                       0, s, c, a.N, (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo,   \
-                                       a.Y, a.E));                                                          \
+        HX_DISPATCH((launch_pass_a<R, LL, G, HX, 16>(a, c, mode, s)));                                      \
         break;                                                                                             \
     }
-        PA(64, 8)
-        PA(128, 8)
-        PA(256, 8)
-        PA(512, 8)
-        PA(1024, Cfg<R>::G1024)
-        PA(2048, Cfg<R>::G2048)
+            PA(64, 8)
+            PA(128, 8)
+            PA(256, 8)
+            PA(512, 8)
+            PA(1024, Cfg<R>::G1024)
+            PA(2048, Cfg<R>::G2048)
 #undef PA
-    default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
     }
     prof_end(a.prof, s);
     // pass B: RC ranks side by side, S sample slots per thread (about 1.25 x the
     // mean tile population L1 when M = N)
     prof_begin(a.prof, mode ? "gradx_passB" : "fwd_passB", s);
-    switch (a.L1) {
+    ok = false;
+    if constexpr (sizeof(R) == 4) {
+        if (a.sched == 1) ok = tuned_pass_b<R, 1, 8>(a, f, mode, g, gx, s);
+        else if (a.sched == 2) ok = tuned_pass_b<R, 2, 16>(a, f, mode, g, gx, s);
+    }
+    if (!ok) {
+        switch (a.L1) {
 #define PB(LL, RF, SF, RD, SD)                                                                             \
     case LL: {                                                                                             \
         constexpr bool F = sizeof(R) == 4;                                                                 \
         constexpr int RR = F ? RF : RD, SS = F ? SF : SD;                                                  \
-        const int sp = pass_b_splits(a.M, a.L2, LL, RR * (LL / 16) * SS);                                   \
-        HX_DISPATCH(hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false, HX>), dim3(xcd_grid(a.L2 * sp)),       \
-                                       dim3(RR * LL / 16), 0, s, (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M,   \
-                                       a.keys, a.perm, a.Xs, a.off, a.fac, a.tw1, f, mode, g, gx, a.E, sp)); \
+        HX_DISPATCH((launch_pass_b<R, LL, RR, SS, HX, 16>(a, f, mode, g, gx, s)));                          \
         break;                                                                                             \
     }
-        PB(128, 16, 1, 8, 2)
-        PB(256, 16, 2, 8, 3)
-        PB(512, 8, 3, 4, 5)
-        PB(1024, NUFFT_F32_PB1024_RC, NUFFT_F32_PB1024_S, 4, 5)
-        PB(2048, NUFFT_F32_PB2048_RC, NUFFT_F32_PB2048_S, 2, 5)
-        PB(4096, 2, 10, 1, 5)
+            PB(128, 16, 1, 8, 2)
+            PB(256, 16, 2, 8, 3)
+            PB(512, 8, 3, 4, 5)
+            PB(1024, NUFFT_F32_PB1024_RC, NUFFT_F32_PB1024_S, 4, 5)
+            PB(2048, NUFFT_F32_PB2048_RC, NUFFT_F32_PB2048_S, 2, 5)
+            PB(4096, 2, 10, 1, 5)
 #undef PB
-    default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
     }
     prof_end(a.prof, s);
     return hipGetLastError();
@@ -1158,7 +1250,13 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
     const int sp = pass_b_adj_splits(a.M, a.L2, a.L1, sizeof(R) == 4);
     if (sp > 0 && !a.Zp) return hipErrorInvalidValue;   // the plan sizes Zp by the same rule
     prof_begin(a.prof, DIR > 0 ? "adj_passB" : "type1_passB", s);
-    switch (a.L1) {
+    bool ok = false;
+    if constexpr (sizeof(R) == 4) {
+        if (sp == 0 && a.sched == 1) ok = tuned_pass_b_adj<R, DIR, 1, 8>(a, s);
+        else if (sp == 0 && a.sched == 2) ok = tuned_pass_b_adj<R, DIR, 2, 16>(a, s);
+    }
+    if (!ok) {
+        switch (a.L1) {
 #define PBA(LL, RF, RD, TG)                                                                                \
     case LL: {                                                                                             \
         constexpr bool F = sizeof(R) == 4;                                                                 \
@@ -1168,20 +1266,19 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
                                dim3(xcd_grid(a.L2 * sp)), dim3(RR * LL / 16), 0, s, a.gsort, (int64_t)a.L2,  \
                                a.Xs, a.keys, a.off, a.fac, DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, sp, a.Zp);  \
         } else {                                                                                           \
-            HX_DISPATCH(hipLaunchKernelGGL((k_passB_adj<R, LL, RR, SC, DIR, TG, HX>), dim3(xcd_grid(a.L2)),  \
-                                           dim3(RR * LL / 16), 0, s, a.gsort, (int64_t)a.L2, a.Xs, a.keys,   \
-                                           a.off, a.fac, DIR < 0 ? a.tw1 : a.tw1i, a.hi, a.lo, a.Y, a.E));  \
+            HX_DISPATCH((launch_pass_b_adj<R, LL, RR, SC, DIR, TG, HX, 16>(a, s)));                         \
         }                                                                                                  \
         break;                                                                                             \
     }
-        PBA(128, 16, 8, false)
-        PBA(256, 16, 8, false)
-        PBA(512, 8, 4, false)
-        PBA(1024, 4, 4, false)
-        PBA(2048, NUFFT_F32_PBA2048_RC, 2, true)
-        PBA(4096, 1, 1, true)
+            PBA(128, 16, 8, false)
+            PBA(256, 16, 8, false)
+            PBA(512, 8, 4, false)
+            PBA(1024, 4, 4, false)
+            PBA(2048, NUFFT_F32_PBA2048_RC, 2, true)
+            PBA(4096, 1, 1, true)
 #undef PBA
-    default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
     }
     prof_end(a.prof, s);
     if (sp > 0) {
@@ -1191,23 +1288,28 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         prof_end(a.prof, s);
     }
     prof_begin(a.prof, DIR > 0 ? "adj_passA" : "type1_passA", s);
-    switch (a.L2) {
+    ok = false;
+    if constexpr (sizeof(R) == 4) {
+        if (a.sched == 1) ok = tuned_pass_a_adj<R, DIR, 1, 8>(a, f, s);
+        else if (a.sched == 2) ok = tuned_pass_a_adj<R, DIR, 2, 16>(a, f, s);
+    }
+    if (!ok) {
+        switch (a.L2) {
 #define PAA(LL, GG)                                                                                        \
     case LL: {                                                                                             \
         constexpr int G = GG;                                                                              \
-        HX_DISPATCH(hipLaunchKernelGGL((k_passA_adj<R, LL, G, DIR, false, HX>), dim3(xcd_grid(a.L1 / G)),    \
-                                       dim3(G * LL / 16), 0, s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1,    \
-                                       a.fac.K, DIR < 0 ? a.tw2 : a.tw2i, f, a.E));                          \
+        HX_DISPATCH((launch_pass_a_adj<R, LL, G, DIR, HX, 16>(a, f, s)));                                   \
         break;                                                                                             \
     }
-        PAA(64, 8)
-        PAA(128, 8)
-        PAA(256, 8)
-        PAA(512, 8)
-        PAA(1024, Cfg<R>::GA1024)
-        PAA(2048, Cfg<R>::GA2048)
+            PAA(64, 8)
+            PAA(128, 8)
+            PAA(256, 8)
+            PAA(512, 8)
+            PAA(1024, Cfg<R>::GA1024)
+            PAA(2048, Cfg<R>::GA2048)
 #undef PAA
-    default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
     }
     prof_end(a.prof, s);
     return hipGetLastError();

@@ -162,6 +162,10 @@ struct FusedArgs {
     int8_t *E;               // K x max(L1, L2) block exponents of the half-precision exchange
     const cx_t<R> *tw1, *tw2, *hi, *lo;
     const cx_t<R> *tw1i, *tw2i;   // inverse-sign twiddles of lengths L1, L2
+    // tuning schedule of the two-pass kernels (0: default; 1: first FFT radix 8,
+    // with these stage-major tables of that radix order; 2: alternative tile shapes)
+    int sched;
+    const cx_t<R> *tw1r8, *tw1ir8, *tw2r8, *tw2ir8;
     cx_t<R> *part;           // scratch for partial sums of the one-workgroup adjoint
     int64_t part_cap;        // complex elements available in part
     Profiler *prof;

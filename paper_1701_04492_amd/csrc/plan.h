@@ -52,6 +52,10 @@ struct nufft_plan_s {
     int8_t *E = nullptr;            // K x max(L1, L2) block exponents of the half-precision exchange
     void *tw1 = nullptr, *tw2 = nullptr, *hi = nullptr, *lo = nullptr;
     void *tw1i = nullptr, *tw2i = nullptr;   // inverse-sign tables
+    // tuning schedule of the two-pass kernels and the twiddle tables of its
+    // radix-8-first FFT stage order (FP32 plans with L1, L2 in {1024, 2048})
+    int sched = 0;
+    void *tw1r8 = nullptr, *tw1ir8 = nullptr, *tw2r8 = nullptr, *tw2ir8 = nullptr;
     void *part = nullptr;           // partial sums of the one-workgroup adjoint
     int64_t part_cap = 0;
 
