@@ -47,6 +47,10 @@ def kernel_bytes(name, K, N, M, L, cs, ys=None):
         "adj_sort": M * cs + M * 4 + M * cs,                    # g, sorted position -> g sorted
         "gradx_sort": M * cs + M * 4 + M * cs,
         "bwd_sort": M * cs + M * 4 + M * cs,
+        # large plans: pass B leaves its outputs in the destination-bucketed layout,
+        # and this pass moves them to sample order (values, 2-byte in-block index, values)
+        "fwd_unsort": M * cs + M * 2 + M * cs,
+        "gradx_unsort": M * 8 + M * 2 + M * 8,
         "type1_sort": M * cs + M * 4 + M * cs,
         "adj_passB": M * cs + M * (4 + 4) + (L + 1) * 4 + inter,  # sorted g, X, key, offsets -> Z
         "adj_passA": inter + N * cs,

@@ -434,6 +434,14 @@ nufft_status nufft_debug_batch_wait(nufft_plan_t plan, int64_t spin_limit, int u
  * count nufft_plan_tuning reports, else INVALID_ARG) from the next exec on. */
 nufft_status nufft_debug_set_schedule(nufft_plan_t plan, int schedule);
 
+/* For tests of the destination-bucketed permutations: large 1-D plans write
+ * their outputs through a layout ordered by destination block, and sort their
+ * inputs through it.  enable = 0 makes the plan scatter and gather directly
+ * (the same values, bit for bit) from the next exec on; enable = 1 restores the
+ * layout.  *has (may be NULL) is set to 1 if the plan has the layout, else 0.
+ * INVALID_ARG for a plan that is not 1-D. */
+nufft_status nufft_debug_set_buckets(nufft_plan_t plan, int enable, int *has);
+
 /* ---- host-side factor generator (no GPU work) --------------------------- */
 
 /* K(eps, gamma): the smallest K whose Chebyshev truncation tail

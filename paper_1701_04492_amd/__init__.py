@@ -12,7 +12,7 @@ from .binding import (  # noqa: F401
     nufft2d3_exec, nufft2d_exec, nufft2d_plan, nufft2d_type1_exec, nufft3_exec, nufft3_exec_noalloc, nufft3d_exec, nufft3d_plan, nufft3d_plan_exec, nufft3d_plan_type1,
     nufft3d_type1_exec,
     nufft_batch_exec, nufft_batch_plan, nufft_batch_status, nufft_bessel_coefficients, nufft_choose_rank,
-    nufft_debug_batch_wait, nufft_debug_fail_alloc, nufft_debug_set_schedule, nufft_plan_tuning,
+    nufft_debug_batch_wait, nufft_debug_fail_alloc, nufft_debug_set_schedule, nufft_debug_set_buckets, nufft_plan_tuning,
     nufft_destroy,
     nufft_plan_info, nufft_plan_perm, nufft_plan_profile, nufft_plan_profile_read, nufft_status_string,
 )

@@ -66,6 +66,7 @@ _sig = {
     "nufft_batch_status": [_vp, ctypes.POINTER(_i64), _vp],
     "nufft_plan_tuning": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)],
     "nufft_debug_set_schedule": [_vp, _int],
+    "nufft_debug_set_buckets": [_vp, _int, ctypes.POINTER(_int)],
     "nufft_debug_batch_wait": [_vp, _i64, _int],
     "nufft_choose_rank": [_dbl, _dbl, ctypes.POINTER(_int)],
     "nufft_bessel_coefficients": [_dbl, _int, _vp],
@@ -419,6 +420,14 @@ def nufft_plan_tuning(plan):
 
 def nufft_debug_set_schedule(plan, schedule):
     _check(lib.nufft_debug_set_schedule(plan.handle, int(schedule)), "nufft_debug_set_schedule")
+
+
+def nufft_debug_set_buckets(plan, enable):
+    """Switches the plan's destination-bucketed permutations on or off; returns
+    whether the plan has them."""
+    has = _int(0)
+    _check(lib.nufft_debug_set_buckets(plan.handle, int(bool(enable)), ctypes.byref(has)), "nufft_debug_set_buckets")
+    return bool(has.value)
 
 
 def nufft_plan_info(plan):

@@ -331,6 +331,21 @@ nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
         p->gsort = p->alloc((size_t)M * cs);
         if (!p->Y || !p->sinv || !p->gsort) return NUFFT_ERR_ALLOC;
         NUFFT_HIP_CHECK(launch_invert_perm(p->perm, M, p->sinv, s));
+        // Destination buckets for the permutations between sample order and sorted
+        // order (large plans): blocks of 2^14 samples (2^13 in FP64), 16 to 1024 of them.
+        const int bshift = sizeof(R) == 4 ? 14 : 13;
+        const int64_t nbk = (M + (int64_t(1) << bshift) - 1) >> bshift;
+        if (nbk >= 16 && nbk <= 1024) {
+            p->bshift = bshift;
+            p->bdst = (int32_t *)p->alloc((size_t)M * sizeof(int32_t));
+            p->lidx = (uint16_t *)p->alloc((size_t)M * sizeof(uint16_t));
+            p->bbuf = p->alloc((size_t)M * std::max<size_t>(cs, sizeof(double)));
+            if (!p->bdst || !p->lidx || !p->bbuf) return NUFFT_ERR_ALLOC;
+            // scratch: keys_u and iota, with the bucket buffer as the alternate pair
+            uint32_t *kalt = (uint32_t *)p->bbuf;
+            int32_t *valt = (int32_t *)p->bbuf + M;
+            NUFFT_HIP_CHECK(launch_bucket_maps(p->perm, M, bshift, keys_u, iota, kalt, valt, tmp, p->bdst, p->lidx, s));
+        }
     } else {
         int64_t nparts = (M + 65535) / 65536;
         if (nparts > 64) nparts = 64;
@@ -378,6 +393,10 @@ FusedArgs<R> fused_args(const Plan *p)
     a.lo = (const cx_t<R> *)p->lo;
     a.part = (cx_t<R> *)p->part;
     a.part_cap = p->part_cap;
+    a.bshift = p->bshift;
+    a.bdst = p->buckets_off ? nullptr : p->bdst;
+    a.lidx = p->lidx;
+    a.bbuf = p->bbuf;
     a.sched = p->tw1r8 ? p->sched : 0;
     a.tw1r8 = (const cx_t<R> *)p->tw1r8;
     a.tw1ir8 = (const cx_t<R> *)p->tw1ir8;
@@ -1847,6 +1866,14 @@ nufft_status nufft_debug_set_schedule(nufft_plan_t plan, int schedule)
     if (!plan || nufft_plan_tuning(plan, nullptr, &n) != NUFFT_OK || schedule < 0 || schedule >= n)
         return NUFFT_ERR_INVALID_ARG;
     plan->sched = schedule;
+    return NUFFT_OK;
+}
+
+nufft_status nufft_debug_set_buckets(nufft_plan_t plan, int enable, int *has)
+{
+    if (!plan || plan->kind != PLAN_1D) return NUFFT_ERR_INVALID_ARG;
+    plan->buckets_off = enable ? 0 : 1;
+    if (has) *has = plan->bdst ? 1 : 0;
     return NUFFT_OK;
 }
 

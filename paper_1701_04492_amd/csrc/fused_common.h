@@ -165,6 +165,80 @@ __device__ __forceinline__ int xcd_task(int T)
 static inline unsigned xcd_grid(int T) { return (unsigned)(8 * ((T + 7) / 8)); }
 
 
+// ---- destination-bucketed permutation writes ---------------------------------
+// Scattering values to random positions costs one DRAM transaction per value;
+// grouping them so that the lanes of one store instruction write neighbouring
+// places makes the stores coalesce.  The plan orders the places of a large
+// permutation by destination bucket (blocks of 2^shift samples): the values of
+// one workgroup that fall into the same bucket have consecutive places.
+
+// Exclusive prefix sum of cnt[0..n) in LDS, in place, by the NT threads of the
+// workgroup (n <= 2 NT); returns the total.  Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int *cnt, int n, int *wsum)
+{
+    const int tid = threadIdx.x;
+    const int a = 2 * tid < n ? cnt[2 * tid] : 0, b = 2 * tid + 1 < n ? cnt[2 * tid + 1] : 0;
+    int v = a + b;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            const int t = wsum[w];
+            wsum[w] = run;
+            run += t;
+        }
+        wsum[NT / 64] = run;
+    }
+    __syncthreads();
+    const int excl = v - (a + b) + wsum[wave];
+    if (2 * tid < n) cnt[2 * tid] = excl;
+    if (2 * tid + 1 < n) cnt[2 * tid + 1] = excl + a;
+    __syncthreads();
+    return wsum[NT / 64];
+}
+
+// The S values per thread of a workgroup (slot s of thread t valid when
+// valid[s]) written to out[dst[s]], dst being places of the bucketed layout:
+// the values are ordered by bucket (dst >> shift) in LDS, then thread t writes
+// the t-th, so that the values of one bucket, which have consecutive places,
+// go out in coalesced runs.  nbk <= 2 NT buckets.  LDS scratch (may alias
+// other buffers no longer read): hist (nbk + 1 ints), wsum (NT/64 + 1 ints),
+// vals (NT*S values), dsts (NT*S ints).  Begins and ends with a barrier.
+template <typename T, int NT, int S>
+__device__ __forceinline__ void bucketed_store(const T (&val)[S], const int (&dst)[S], const bool (&valid)[S],
+                                               int shift, int nbk, T *__restrict__ out, int *hist, int *wsum,
+                                               T *vals, int *dsts)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();   // the caller's readers of the scratch are done
+    for (int b = tid; b < nbk; b += NT) hist[b] = 0;
+    __syncthreads();
+    int rank[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) rank[s] = valid[s] ? atomicAdd(&hist[dst[s] >> shift], 1) : 0;
+    __syncthreads();
+    const int n = block_exclusive_scan<NT>(hist, nbk, wsum);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (valid[s]) {
+            const int slot = hist[dst[s] >> shift] + rank[s];
+            vals[slot] = val[s];
+            dsts[slot] = dst[s];
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < n; t += NT) out[dsts[t]] = vals[t];
+    __syncthreads();
+}
+
 // Deterministic segmented sum of per-sample contributions into RC grids in LDS.
 // The cnt samples of a tile are sorted by grid point; thread t takes a
 // balanced slice of them (empty slices, when cnt < NT, only at the end), sums

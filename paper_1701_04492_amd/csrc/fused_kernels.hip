@@ -212,12 +212,167 @@ k_scatter_sorted(const cx_t<R> *__restrict__ in, const int32_t *__restrict__ sin
     if (j < M) out[sinv[j]] = in[j];
 }
 
+// ---- the permutation through the destination-bucketed layout ------------------
+// (large plans; see bucketed_store).  Bucket q holds the samples
+// j in [q BS, (q+1) BS) (BS = 2^bshift); place p of its range holds sample
+// q BS + lidx[p], the places ordered by sorted position.  One workgroup per
+// bucket moves it through LDS in both directions with coalesced reads and
+// writes.
+
+// out[q BS + lidx[p]] = in[p] for p in bucket q: the bucketed layout to sample order.
+template <typename T, int BS>
+__global__ void __launch_bounds__(1024)
+k_bucket_to_samples(const T *__restrict__ in, const uint16_t *__restrict__ lidx, int64_t M, T *__restrict__ out)
+{
+    __shared__ T v[BS];
+    const int64_t base = (int64_t)blockIdx.x * BS;
+    const int n = (int)min((int64_t)BS, M - base);
+    constexpr int E = BS / 1024;
+    T w[E];
+    int li[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = min((int)threadIdx.x + e * 1024, n - 1);
+        w[e] = in[base + p];
+        li[e] = lidx[base + p];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if ((int)threadIdx.x + e * 1024 < n) v[li[e]] = w[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + e * 1024;
+        if (t < n) out[base + t] = v[t];
+    }
+}
+
+// out[p] = in[q BS + lidx[p]] for p in bucket q: sample order to the bucketed layout.
+template <typename T, int BS>
+__global__ void __launch_bounds__(1024)
+k_samples_to_bucket(const T *__restrict__ in, const uint16_t *__restrict__ lidx, int64_t M, T *__restrict__ out)
+{
+    __shared__ T v[BS];
+    const int64_t base = (int64_t)blockIdx.x * BS;
+    const int n = (int)min((int64_t)BS, M - base);
+    constexpr int E = BS / 1024;
+    T w[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) w[e] = in[base + min((int)threadIdx.x + e * 1024, n - 1)];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + e * 1024;
+        if (t < n) v[t] = w[e];
+    }
+    __syncthreads();
+    int li[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) li[e] = lidx[base + min((int)threadIdx.x + e * 1024, n - 1)];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = threadIdx.x + e * 1024;
+        if (p < n) out[base + p] = v[li[e]];
+    }
+}
+
+// out[i] = in[bdst[i]] for a range of RNG sorted positions per workgroup: the
+// range's places are ordered by bucket in LDS, so that the reads of one bucket
+// (consecutive places) coalesce, and the values are written back in sorted order.
+template <typename T, int RNG, int NT>
+__global__ void __launch_bounds__(NT)
+k_bucket_to_sorted(const T *__restrict__ in, const int32_t *__restrict__ bdst, int64_t M, int shift, int nbk,
+                   T *__restrict__ out)
+{
+    constexpr int E = RNG / NT;
+    __shared__ int hist[1026], wsum[NT / 64 + 1];
+    __shared__ int dsts[RNG];
+    __shared__ unsigned short locs[RNG];
+    __shared__ T v[RNG];
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * RNG;
+    const int n = (int)min((int64_t)RNG, M - i0);
+    int d[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) d[e] = bdst[i0 + min(tid + e * NT, n - 1)];
+    for (int b = tid; b < nbk; b += NT) hist[b] = 0;
+    __syncthreads();
+    int rank[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) rank[e] = tid + e * NT < n ? atomicAdd(&hist[d[e] >> shift], 1) : 0;
+    __syncthreads();
+    block_exclusive_scan<NT>(hist, nbk, wsum);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (tid + e * NT < n) {
+            const int slot = hist[d[e] >> shift] + rank[e];
+            dsts[slot] = d[e];
+            locs[slot] = (unsigned short)(tid + e * NT);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = tid + e * NT;
+        if (t < n) v[locs[t]] = in[dsts[t]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = tid + e * NT;
+        if (t < n) out[i0 + t] = v[t];
+    }
+}
+
+// Bucketed outputs (values of type T at the places of the plan's layout) to sample order.
+template <typename T, typename R>
+static hipError_t bucket_to_samples_bs(const FusedArgs<R> &a, const T *in, T *out, hipStream_t s)
+{
+    const unsigned nbk = (unsigned)((a.M + (int64_t(1) << a.bshift) - 1) >> a.bshift);
+    if (a.bshift == 14)
+        hipLaunchKernelGGL((k_bucket_to_samples<T, 16384>), dim3(nbk), dim3(1024), 0, s, in, a.lidx, a.M, out);
+    else if (a.bshift == 13)
+        hipLaunchKernelGGL((k_bucket_to_samples<T, 8192>), dim3(nbk), dim3(1024), 0, s, in, a.lidx, a.M, out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+template <typename T, typename R>
+static hipError_t bucket_to_samples(const FusedArgs<R> &a, const T *in, T *out, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 16) {   // complex128: buckets of 2^13 (128 KB of LDS)
+        if (a.bshift != 13) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_bucket_to_samples<T, 8192>), dim3((unsigned)((a.M + 8191) >> 13)), dim3(1024), 0, s, in,
+                           a.lidx, a.M, out);
+        return hipGetLastError();
+    } else {
+        return bucket_to_samples_bs<T, R>(a, in, out, s);
+    }
+}
+
 template <typename R>
 hipError_t fused_sort_input(const FusedArgs<R> &a, const cx_t<R> *in, const char *name, hipStream_t s)
 {
+    using C = cx_t<R>;
     prof_begin(a.prof, name, s);
-    hipLaunchKernelGGL(k_scatter_sorted<R>, dim3((unsigned)((a.M + 255) / 256)), dim3(256), 0, s, in, a.sinv, a.M,
-                       a.gsort);
+    if (a.bdst) {
+        // sample order -> bucketed layout (coalesced through LDS) -> sorted order (coalesced runs)
+        const int nbk = (int)((a.M + (int64_t(1) << a.bshift) - 1) >> a.bshift);
+        if constexpr (sizeof(R) == 4) {
+            if (a.bshift != 14) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_samples_to_bucket<C, 16384>), dim3((unsigned)nbk), dim3(1024), 0, s, in, a.lidx, a.M,
+                               (C *)a.bbuf);
+        } else {
+            if (a.bshift != 13) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_samples_to_bucket<C, 8192>), dim3((unsigned)nbk), dim3(1024), 0, s, in, a.lidx, a.M,
+                               (C *)a.bbuf);
+        }
+        constexpr int RNG = sizeof(R) == 4 ? 4096 : 2048;
+        hipLaunchKernelGGL((k_bucket_to_sorted<C, RNG, 512>), dim3((unsigned)((a.M + RNG - 1) / RNG)), dim3(512), 0, s,
+                           (const C *)a.bbuf, a.bdst, a.M, a.bshift, nbk, a.gsort);
+    } else {
+        hipLaunchKernelGGL(k_scatter_sorted<R>, dim3((unsigned)((a.M + 255) / 256)), dim3(256), 0, s, in, a.sinv, a.M,
+                           a.gsort);
+    }
     prof_end(a.prof, s);
     return hipGetLastError();
 }
@@ -339,6 +494,19 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     }
 }
 
+// LDS bytes of the bucketed store of pass B's outputs (bucketed_store): bin
+// counts of up to 1024 buckets, wave sums, then NT*S values and their places.
+__host__ __device__ constexpr int bucket_scratch_bytes(int NT, int S, int vbytes)
+{
+    return 4352 + NT * S * (vbytes + 4);
+}
+// Whether pass B with these shapes can order its outputs by bucket inside its
+// FFT buffer (values of complex size, or double for the derivative pass).
+__host__ __device__ constexpr bool pass_b_buckets(int L1, int RC, int S, int cbytes)
+{
+    return bucket_scratch_bytes(RC * L1 / 16, S, cbytes > 8 ? cbytes : 8) <= cbytes * RC * fft_pitch(L1);
+}
+
 // Pass B of type II.  Task = one output tile n2.  RC ranks are transformed
 // side by side (L1/16 threads each); the next chunk's rows are loaded into
 // registers while the current chunk is transformed and gathered.  Every
@@ -355,13 +523,16 @@ __global__ void __launch_bounds__(RC * L1 / 16)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
         const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
         Factors<R> fac, const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ f, int mode,
-        const cx_t<R> *__restrict__ gup, double *__restrict__ gx, const int8_t *__restrict__ E, int splits)
+        const cx_t<R> *__restrict__ gup, double *__restrict__ gx, const int8_t *__restrict__ E, int splits,
+        const int32_t *__restrict__ bdst, int bshift, int nbk, void *__restrict__ bout)
 {
     using C = cx_t<R>;
     constexpr int TPF = L1 / 16;
     constexpr int NT = RC * TPF;
     constexpr int P = fft_pitch(L1);
     constexpr int CAP = NT * S;
+    static_assert(bucket_scratch_bytes(NT, S, sizeof(C)) <= (int)sizeof(C) * RC * P || !pass_b_buckets(L1, RC, S, sizeof(C)),
+                  "bucketed store scratch exceeds the FFT buffer");
     __shared__ C buf[RC * P];
     __shared__ C tw_s[TWG ? 1 : L1];
     const C *tw = TWG ? tw_g : tw_s;
@@ -455,22 +626,54 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             }
             gather(r0, min(RC, fac.K - r0), c0, kv, xs, acc);
         }
-        int32_t jv[S];   // output positions: loaded together once the sums are done
+        // output places: the samples' indices, or (bdst) their places in the
+        // destination-bucketed layout; loaded together once the sums are done
+        int32_t jv[S];
         C gj[S];         // derivative pass: g in sorted order (contiguous)
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int64_t i = min(c0 + s * NT + tid, tile_hi - 1);
-            jv[s] = perm[i];
+            jv[s] = bdst ? bdst[i] : perm[i];
             if (mode != 0) gj[s] = gup[i];
         }
+        C out[S];
+        bool valid[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            if (c0 + s * NT + tid < tile_hi) {
-                R sn, cs;
-                sincospi_r(xs[s], &sn, &cs);
-                const C out = cmul(cmake<C>(cs, -sn), acc[s]);
-                if (mode == 0) f[jv[s]] = out;
-                else gx[jv[s]] = (double)(gj[s].x * out.x + gj[s].y * out.y);
+            valid[s] = c0 + s * NT + tid < tile_hi;
+            R sn, cs;
+            sincospi_r(xs[s], &sn, &cs);
+            out[s] = cmul(cmake<C>(cs, -sn), acc[s]);
+        }
+        bool bucketed = false;
+        if constexpr (pass_b_buckets(L1, RC, S, sizeof(C))) {
+            if (bdst) {
+                // the spectra in buf are not read again (K > RC): its space holds the
+                // bucketed ordering of this round's outputs
+                int *hist = reinterpret_cast<int *>(buf);
+                int *wsum = hist + 1026;
+                char *vbase = reinterpret_cast<char *>(buf) + 4352;
+                if (mode == 0) {
+                    bucketed_store<C, NT, S>(out, jv, valid, bshift, nbk, reinterpret_cast<C *>(bout), hist, wsum,
+                                             reinterpret_cast<C *>(vbase), reinterpret_cast<int *>(vbase + CAP * sizeof(C)));
+                } else {
+                    double d[S];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) d[s] = (double)(gj[s].x * out[s].x + gj[s].y * out[s].y);
+                    bucketed_store<double, NT, S>(d, jv, valid, bshift, nbk, reinterpret_cast<double *>(bout), hist,
+                                                  wsum, reinterpret_cast<double *>(vbase),
+                                                  reinterpret_cast<int *>(vbase + CAP * sizeof(double)));
+                }
+                bucketed = true;
+            }
+        }
+        if (!bucketed) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (valid[s]) {
+                    if (mode == 0) f[jv[s]] = out[s];
+                    else gx[jv[s]] = (double)(gj[s].x * out[s].x + gj[s].y * out[s].y);
+                }
             }
         }
         if (!once) __syncthreads();   // the next round's transforms overwrite buf
@@ -1100,13 +1303,21 @@ static void launch_pass_a(const FusedArgs<R> &a, const cx_t<R> *c, int mode, hip
                        (int64_t)a.L1, a.fac.K, rca, mode, FR == 8 ? a.tw2r8 : a.tw2, a.hi, a.lo, a.Y, a.E);
 }
 
+// Pass B writes its outputs through the destination-bucketed layout (a.bbuf,
+// then bucket_to_samples) when the plan has one and the shapes allow it; returns whether it did.
 template <typename R, int LL, int RR, int SS, bool HX, int FR>
-static void launch_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_t<R> *g, double *gx, hipStream_t s)
+static bool launch_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_t<R> *g, double *gx, hipStream_t s)
 {
     const int sp = pass_b_splits(a.M, a.L2, LL, RR * (LL / 16) * SS);
+    const int nbk = (int)((a.M + (int64_t(1) << a.bshift) - 1) >> a.bshift);
+    // the bucket counts are scanned by the workgroup's threads, two each
+    const bool buck = a.bdst && a.fac.K > RR && nbk <= 2 * RR * (LL / 16) &&
+                      pass_b_buckets(LL, RR, SS, (int)sizeof(cx_t<R>));
     hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false, HX, FR>), dim3(xcd_grid(a.L2 * sp)), dim3(RR * LL / 16), 0, s,
                        (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,
-                       FR == 8 ? a.tw1r8 : a.tw1, f, mode, g, gx, a.E, sp);
+                       FR == 8 ? a.tw1r8 : a.tw1, f, mode, g, gx, a.E, sp, buck ? a.bdst : nullptr, a.bshift, nbk,
+                       a.bbuf);
+    return buck;
 }
 
 template <typename R, int LL, int RR, int SC, int DIR, bool TG, bool HX, int FR>
@@ -1137,11 +1348,14 @@ static bool tuned_pass_a(const FusedArgs<R> &a, const cx_t<R> *c, int mode, hipS
     return true;
 }
 template <typename R, int RD, int FR>
-static bool tuned_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_t<R> *g, double *gx, hipStream_t s)
+static bool tuned_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_t<R> *g, double *gx, hipStream_t s,
+                         bool *buck)
 {
     if (a.half || !sched_sizes(a.L1, a.L2)) return false;
-    if (a.L1 == 1024) launch_pass_b<R, 1024, NUFFT_F32_PB1024_RC / RD, NUFFT_F32_PB1024_S * RD, false, FR>(a, f, mode, g, gx, s);
-    else launch_pass_b<R, 2048, NUFFT_F32_PB2048_RC / RD, NUFFT_F32_PB2048_S * RD, false, FR>(a, f, mode, g, gx, s);
+    if (a.L1 == 1024)
+        *buck = launch_pass_b<R, 1024, NUFFT_F32_PB1024_RC / RD, NUFFT_F32_PB1024_S * RD, false, FR>(a, f, mode, g, gx, s);
+    else
+        *buck = launch_pass_b<R, 2048, NUFFT_F32_PB2048_RC / RD, NUFFT_F32_PB2048_S * RD, false, FR>(a, f, mode, g, gx, s);
     return true;
 }
 template <typename R, int DIR, int RD, int FR>
@@ -1208,9 +1422,10 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     // mean tile population L1 when M = N)
     prof_begin(a.prof, mode ? "gradx_passB" : "fwd_passB", s);
     ok = false;
+    bool buck = false;   // pass B wrote the outputs in the destination-bucketed layout
     if constexpr (sizeof(R) == 4) {
-        if (a.sched == 1) ok = tuned_pass_b<R, 1, 8>(a, f, mode, g, gx, s);
-        else if (a.sched == 2) ok = tuned_pass_b<R, 2, 16>(a, f, mode, g, gx, s);
+        if (a.sched == 1) ok = tuned_pass_b<R, 1, 8>(a, f, mode, g, gx, s, &buck);
+        else if (a.sched == 2) ok = tuned_pass_b<R, 2, 16>(a, f, mode, g, gx, s, &buck);
     }
     if (!ok) {
         switch (a.L1) {
@@ -1218,7 +1433,7 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     case LL: {                                                                                             \
         constexpr bool F = sizeof(R) == 4;                                                                 \
         constexpr int RR = F ? RF : RD, SS = F ? SF : SD;                                                  \
-        HX_DISPATCH((launch_pass_b<R, LL, RR, SS, HX, 16>(a, f, mode, g, gx, s)));                          \
+        HX_DISPATCH((buck = launch_pass_b<R, LL, RR, SS, HX, 16>(a, f, mode, g, gx, s)));                   \
         break;                                                                                             \
     }
             PB(128, 16, 1, 8, 2)
@@ -1232,6 +1447,13 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
         }
     }
     prof_end(a.prof, s);
+    if (buck) {   // the bucketed outputs to sample order
+        prof_begin(a.prof, mode ? "gradx_unsort" : "fwd_unsort", s);
+        const hipError_t e = mode ? bucket_to_samples<double>(a, (const double *)a.bbuf, gx, s)
+                                  : bucket_to_samples<cx_t<R>>(a, (const cx_t<R> *)a.bbuf, f, s);
+        prof_end(a.prof, s);
+        if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
 }
 

@@ -89,6 +89,13 @@ hipError_t launch_iota(int32_t *v, int64_t n, hipStream_t s);
 // out[i] = in[i * stride], i < n
 hipError_t launch_strided_i32(const int32_t *in, int64_t stride, int64_t n, int32_t *out, hipStream_t s);
 hipError_t launch_invert_perm(const int32_t *perm, int64_t n, int32_t *sinv, hipStream_t s);
+// The destination-bucketed layout of the sample permutation (blocks of 2^shift
+// samples): bdst[i] is sorted position i's place in the layout ordered by
+// (bucket perm[i] >> shift, i), lidx[p] = perm[i] mod 2^shift of the sample at
+// place p.  keys, vals, keys_alt, vals_alt (n each) and tmp (radix_tmp_elems(n)) are scratch.
+hipError_t launch_bucket_maps(const int32_t *perm, int64_t n, int shift, uint32_t *keys, int32_t *vals,
+                              uint32_t *keys_alt, int32_t *vals_alt, int32_t *tmp, int32_t *bdst, uint16_t *lidx,
+                              hipStream_t s);
 hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
 int64_t radix_tmp_elems(int64_t n);
@@ -166,6 +173,12 @@ struct FusedArgs {
     // with these stage-major tables of that radix order; 2: alternative tile shapes)
     int sched;
     const cx_t<R> *tw1r8, *tw1ir8, *tw2r8, *tw2ir8;
+    // destination-bucketed permutation (null bdst: sample-order outputs are
+    // written at perm[i] directly, and inputs are put in sorted order by sinv)
+    int bshift;
+    const int32_t *bdst;     // M: place of sorted position i in the bucketed layout
+    const uint16_t *lidx;    // M: sample index within its bucket, per place
+    void *bbuf;              // M values (complex or double): the bucketed layout
     cx_t<R> *part;           // scratch for partial sums of the one-workgroup adjoint
     int64_t part_cap;        // complex elements available in part
     Profiler *prof;

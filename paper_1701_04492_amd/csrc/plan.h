@@ -46,6 +46,14 @@ struct nufft_plan_s {
     int32_t *perm = nullptr;        // M sample index per sorted position
     int32_t *off = nullptr;         // L + 1 CSR offsets per key
     int32_t *sinv = nullptr;        // M sorted position per sample (two-pass)
+    // destination-bucketed layout of the permutation (large two-pass plans, else null):
+    // buckets of 2^bshift samples; bdst[i] place of sorted position i, lidx[p] its
+    // sample index within the bucket; bbuf: M values of max(complex, double) size
+    int bshift = 0;
+    int buckets_off = 0;   // tests: scatter and gather directly
+    int32_t *bdst = nullptr;
+    uint16_t *lidx = nullptr;
+    void *bbuf = nullptr;
     void *gsort = nullptr;          // M complex: sample-ordered input in sorted order (two-pass)
     void *U = nullptr, *W = nullptr, *W2 = nullptr;   // plain path
     void *Y = nullptr;              // K x L two-pass intermediate (fp16 pairs with NUFFT_FLAG_HALF_EXCHANGE)

@@ -244,6 +244,47 @@ __global__ void k_invert_perm(const int32_t *__restrict__ perm, int64_t n, int32
     if (i < n) sinv[perm[i]] = (int32_t)i;
 }
 
+// Destination buckets of the sample permutation (blocks of 2^shift sample
+// indices): key[i] = perm[i] >> shift for every sorted position i.
+__global__ void k_bucket_keys(const int32_t *__restrict__ perm, int64_t n, int shift, uint32_t *__restrict__ key)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) key[i] = (uint32_t)perm[i] >> shift;
+}
+
+// order[p]: the sorted position at bucketed position p (stable by bucket);
+// bdst[i] = p, lidx[p] = perm[i] mod 2^shift.
+__global__ void k_bucket_maps(const int32_t *__restrict__ order, const int32_t *__restrict__ perm, int64_t n,
+                              int shift, int32_t *__restrict__ bdst, uint16_t *__restrict__ lidx)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) {
+        const int32_t i = order[p];
+        bdst[i] = (int32_t)p;
+        lidx[p] = (uint16_t)(perm[i] & ((1 << shift) - 1));
+    }
+}
+
+hipError_t launch_bucket_maps(const int32_t *perm, int64_t n, int shift, uint32_t *keys, int32_t *vals,
+                              uint32_t *keys_alt, int32_t *vals_alt, int32_t *tmp, int32_t *bdst, uint16_t *lidx,
+                              hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_bucket_keys, dim3(nb), dim3(256), 0, s, perm, n, shift, keys);
+    hipLaunchKernelGGL(k_iota, dim3(nb), dim3(256), 0, s, vals, n);
+    int bits = 0;
+    while ((int64_t(1) << bits) < ((n + (int64_t(1) << shift) - 1) >> shift)) ++bits;
+    uint32_t *ks = keys;
+    int32_t *order = vals;
+    if (bits > 0) {
+        const hipError_t e = radix_sort_pairs(keys, vals, keys_alt, vals_alt, n, bits, tmp, s, &ks, &order);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_bucket_maps, dim3(nb), dim3(256), 0, s, (const int32_t *)order, perm, n, shift, bdst, lidx);
+    return hipGetLastError();
+}
+
 int64_t radix_tmp_elems(int64_t n)
 {
     const int64_t nb = (n + RS_BLOCK - 1) / RS_BLOCK;
