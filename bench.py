@@ -33,6 +33,11 @@ def _fail_multi(n):
     sys.exit(2)
 
 
+def _progress(msg):
+    """One progress line per finished section, on stderr (the JSON line stays alone on stdout)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
 def kernel_bytes(name, K, N, M, L, cs, ys=None):
     """Algorithmic bytes moved by one launch of a fused kernel: compulsory I/O plus the
     K-wide intermediate written by the first pass and read by the second (ys bytes per
@@ -104,10 +109,17 @@ def traffic_record(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
-# Counter runs (rocprofv3 --pmc): the six kernels of one fwd+bwd step at N = M = 2^22
-# in the order the autograd step launches them, then a plain copy of known size whose
-# counters calibrate FETCH_SIZE / WRITE_SIZE.
-COUNTER_ORDER = ["fwd_passA", "fwd_passB", "adj_passB", "adj_passA", "gradx_passA", "gradx_passB"]
+# Passes that move values between sample order and the destination-bucketed layout:
+# not part of the method's compulsory traffic, so the step's algorithmic bytes leave them out.
+LAYOUT_PHASES = {"fwd_unsort", "gradx_unsort"}
+
+# Counter runs (rocprofv3 --pmc): the ten kernels of one fwd+bwd step at N = M = 2^22
+# in the order the step launches them (the backward sort is two kernels through the
+# bucketed layout), then a plain copy of known size whose counters calibrate
+# FETCH_SIZE / WRITE_SIZE.
+COUNTER_ORDER = ["fwd_passA", "fwd_passB", "fwd_unsort", "bwd_sort.1", "bwd_sort.2", "adj_passB", "adj_passA",
+                 "gradx_passA", "gradx_passB", "gradx_unsort"]
+COUNTER_KERNELS = ("nufft::k_pass", "nufft::k_bucket_to", "nufft::k_samples_to_bucket")
 CALIB_BYTES = 256 << 20
 
 
@@ -125,10 +137,10 @@ def counter_run(steps):
     f = torch.empty_like(c)
     gc = torch.empty_like(c)
     gx = torch.empty(N, dtype=torch.float64, device=dev)
+    assert P.nufft_debug_set_buckets(plan, True), "the 2^22 plan should have the bucketed layout"
     for _ in range(steps):
-        P.nufft2_exec(plan, c, f)              # fwd_passA, fwd_passB
-        P.nufft1_exec(plan, g, +1, gc)         # adj_passB, adj_passA
-        P.nufft2_grad_x(plan, c, g, gx)        # gradx_passA, gradx_passB
+        P.nufft2_exec(plan, c, f)              # fwd_passA, fwd_passB, fwd_unsort
+        P.nufft2_backward(plan, c, g, gc, gx)  # bwd_sort (2 kernels), adj_passB, adj_passA, gradx_passA, _passB, _unsort
     src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     torch.mul(src, 1.0, out=dst)               # calibration: reads and writes CALIB_BYTES
@@ -148,7 +160,7 @@ def traffic_summary(fetch_dir, write_dir, out_path, command):
                 if r["Counter_Name"] == counter:
                     rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
         rows.sort()
-        lib = [(n, v) for _, n, v in rows if "nufft::k_pass" in n]
+        lib = [(n, v) for _, n, v in rows if any(k in n for k in COUNTER_KERNELS)]
         cal = [v for _, n, v in rows if "MulFunctor" in n]
         if not cal or not lib or len(lib) % len(COUNTER_ORDER):
             raise SystemExit("unexpected dispatches in %s (%d library, %d calibration)" % (d, len(lib), len(cal)))
@@ -171,6 +183,11 @@ def traffic_summary(fetch_dir, write_dir, out_path, command):
         b = fetch[k] * 1024.0 * fs + write[k] * 1024.0 * ws
         rec["kernels"][k] = {"kernel": names[k], "fetch_kib": round(fetch[k], 1), "write_kib": round(write[k], 1),
                              "bytes_per_launch": int(b)}
+    sub = [rec["kernels"][k] for k in ("bwd_sort.1", "bwd_sort.2")]
+    rec["kernels"]["bwd_sort"] = {"kernel": " + ".join(r["kernel"] for r in sub),
+                                  "fetch_kib": round(sum(r["fetch_kib"] for r in sub), 1),
+                                  "write_kib": round(sum(r["write_kib"] for r in sub), 1),
+                                  "bytes_per_launch": sum(r["bytes_per_launch"] for r in sub)}
     json.dump(rec, open(out_path, "w"), indent=1)
     print(json.dumps(rec, indent=1))
 
@@ -560,6 +577,7 @@ def main():
     ms = time_loop(step, args.steps, args.warmup, torch)
     assert xg.grad is not None and cg.grad is not None
     value = M / (ms * 1e-3)
+    _progress("2^22 step: %.4f ms" % ms)
 
     # per-kernel durations: same step, events around every library kernel
     P.nufft_plan_profile(plan, 1, reserve=8 * (args.steps + 1))
@@ -580,8 +598,9 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["calls"])
     dk = kernels[dom]
     lib_us = sum(v["avg_us"] * v["calls"] for v in kernels.values()) / args.steps
-    lib_bytes = sum(v["alg_bytes"] * v["calls"] for v in kernels.values() if v["alg_bytes"]) / args.steps
-    step_bytes = sum(v["alg_bytes"] * v["calls"] for v in kernels.values() if v["alg_bytes"]) / args.steps
+    step_bytes = sum(v["alg_bytes"] * v["calls"] for k, v in kernels.items()
+                     if v["alg_bytes"] and k not in LAYOUT_PHASES) / args.steps
+    lib_bytes = step_bytes
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dk["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic_record(dom),
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_us": dk["avg_us"],
@@ -646,19 +665,29 @@ def main():
         sec["speedup_fused_fp32_vs_plain_fp64_same_eps"] = round(
             sec["plain_fp64_eps1e-6"]["us"] / sec["fused_fp32_eps1e-6"]["us"], 2)
         out["forward_2p20"] = sec
+        _progress("2^20 forward rows")
 
     if not args.no_secondary:
         ps = bench_plain_step(P, torch, x, c, y, N, M, eps, args.steps, args.warmup)
         ps["speedup_fused_fp32_vs_plain_fp64"] = round(ps["ms_per_step"] / ms, 2)
         out["fwd_bwd_2p22_plain_fp64"] = ps
+        _progress("fwd_bwd_2p22_plain_fp64")
         out["config_rows"] = bench_config_rows(P, W, torch, dev)
+        _progress("config_rows")
         out["fwd_bwd_2p22_half"] = bench_half(P, torch, xg.detach(), c, y, N, M, args.steps, args.warmup)
+        _progress("fwd_bwd_2p22_half")
         out["batch_512"] = bench_batch(P, W, torch, dev)
+        _progress("batch_512")
         out["polar_2d"] = bench_2d(P, W, torch, dev)
+        _progress("polar_2d")
         out["inverse_2p20"] = bench_solve(P, W, torch, dev)
+        _progress("inverse_2p20")
         out["oversampling_2p14_modes_2p22_samples"] = bench_oversampling(P, W, torch, dev)
+        _progress("oversampling_2p14_modes_2p22_samples")
         out["type3"] = bench_type3(P, W, torch, dev)
+        _progress("type3")
         out["type2_3d"] = bench_3d(P, W, torch, dev)
+        _progress("type2_3d")
 
     if not args.no_cpu_baseline:
         import numpy as np
@@ -667,6 +696,7 @@ def main():
         out["cpu_baseline"], out["accuracy_2p22_forward"] = cpu_baseline(x_np, c_in, N, args.cpu_seconds,
                                                                          f_gpu, eps)
         out["cpu_baseline"]["cpu_model"] = cpu_model()
+        _progress("cpu baseline")
     # release every plan and the device tensors before returning
     del plan, step, xg, cg
     import gc

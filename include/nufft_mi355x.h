@@ -115,14 +115,33 @@ enum {
  *   n_pts    M >= 1, number of samples.
  *   x_dev    M doubles, any finite reals (periodic in 1); read during the call.
  *   eps      working accuracy, 0 < eps < 1, above the precision floor.
- * The FFT grid L is the smallest power of two L0 >= 16 and >= N (oversampling
- * with N <= L < 2N, Sec. 2.3), or 2 L0 when the autotuner (on unless
- * NUFFT_FLAG_NO_AUTOTUNE) finds it faster; N up to 2^23 (NUFFT_ERR_UNSUPPORTED beyond),
- * M up to 2^30.  Synchronises `stream` once, to read gamma and the
- * non-finite flag back (NUFFT_ERR_NONFINITE). */
+ * The FFT grid L (oversampling, Sec. 2.3) starts as the smallest power of
+ * two L0 >= 16 and >= N.  Unless NUFFT_FLAG_NO_AUTOTUNE (or
+ * NUFFT_FLAG_PLAIN_UNFUSED) is given, every supported grid with
+ * N <= L <= 2 L0 is planned and timed and the fastest kept (remembered per
+ * problem): powers of two, and 3 * 2^k and 5 * 2^k in the two-pass range
+ * (see nufft2_plan_grid) unless NUFFT_FLAG_HALF_EXCHANGE is given.  A larger
+ * grid lowers gamma and K.  N up to 2^23 (NUFFT_ERR_UNSUPPORTED beyond),
+ * M up to 2^30.  Synchronises `stream` (once without autotuning), to read
+ * gamma and the non-finite flag back (NUFFT_ERR_NONFINITE). */
 nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts,
                          const double *x_dev, double eps, nufft_dtype dtype,
                          uint32_t flags, void *stream);
+
+/* nufft2_plan on a grid the caller chooses (the oversampled grid of Sec. 2.3;
+ * the grid is not autotuned, the tuning schedule is unless
+ * NUFFT_FLAG_NO_AUTOTUNE).  grid >= N is
+ *   a power of two up to 2^23, or
+ *   P * 2^k with P = 3 or 5: the column transforms of the two-pass form take
+ *   one radix-P stage, so grid = L1 * P * Q with L1 a power of two in
+ *   [128, 4096] and Q one in [64, 512] (P = 3) or [64, 256] (P = 5); e.g.
+ *   24576 = 128 * 3 * 64 up to 6291456 = 4096 * 3 * 512, 40960 up to
+ *   5242880 = 4096 * 5 * 256.  Not with NUFFT_FLAG_PLAIN_UNFUSED or
+ *   NUFFT_FLAG_HALF_EXCHANGE.
+ * Other grids: NUFFT_ERR_UNSUPPORTED; grid < 1: NUFFT_ERR_INVALID_ARG. */
+nufft_status nufft2_plan_grid(nufft_plan_t *out, int64_t n_modes, int64_t n_pts,
+                              const double *x_dev, double eps, nufft_dtype dtype,
+                              uint32_t flags, int64_t grid, void *stream);
 
 /* Online stage of type II (Sec. 2.3, two-step form):
  *   f_dev[j] ~ sum_{k<N} c_dev[k] exp(-2 pi i x_j k),  j < M.

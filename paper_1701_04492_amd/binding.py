@@ -37,6 +37,7 @@ _dbl = ctypes.c_double
 lib = ctypes.CDLL(LIB_PATH)
 _sig = {
     "nufft2_plan": [ctypes.POINTER(_vp), _i64, _i64, _vp, _dbl, _int, _u32, _vp],
+    "nufft2_plan_grid": [ctypes.POINTER(_vp), _i64, _i64, _vp, _dbl, _int, _u32, _i64, _vp],
     "nufft2_exec": [_vp, _vp, _vp, _vp],
     "nufft1_exec": [_vp, _vp, _vp, _int, _vp],
     "nufft2_grad_x": [_vp, _vp, _vp, _vp, _vp],
@@ -154,15 +155,24 @@ class Plan:
             self.handle = None
 
 
-def nufft2_plan(x, n_modes, eps, dtype=torch.complex64, flags=0):
-    """Plan a 1-D type II / type I transform on samples x (float64 CUDA tensor)."""
+def nufft2_plan(x, n_modes, eps, dtype=torch.complex64, flags=0, grid=None):
+    """Plan a 1-D type II / type I transform on samples x (float64 CUDA tensor);
+    grid: an explicit FFT grid (nufft2_plan_grid), else chosen and autotuned."""
     M = x.numel()
     px = _dev_tensor(x, torch.float64, None, "x")
     h = _vp()
-    _check(lib.nufft2_plan(ctypes.byref(h), int(n_modes), M, px, float(eps), _cdtype(dtype), int(flags),
-                           _stream(x.device)), "nufft2_plan")
+    if grid is None:
+        _check(lib.nufft2_plan(ctypes.byref(h), int(n_modes), M, px, float(eps), _cdtype(dtype), int(flags),
+                               _stream(x.device)), "nufft2_plan")
+    else:
+        _check(lib.nufft2_plan_grid(ctypes.byref(h), int(n_modes), M, px, float(eps), _cdtype(dtype), int(flags),
+                                    int(grid), _stream(x.device)), "nufft2_plan_grid")
     return Plan(h, "1d", dtype, x.device, N=int(n_modes), M=M, eps=float(eps), flags=int(flags),
                 x_key=(x.data_ptr(), x._version, M))
+
+
+def nufft2_plan_grid(x, n_modes, eps, dtype, flags, grid):
+    return nufft2_plan(x, n_modes, eps, dtype, flags, grid)
 
 
 def nufft2_exec(plan, c, f=None):

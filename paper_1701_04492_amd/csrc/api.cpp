@@ -161,27 +161,58 @@ static void tune_store(const std::string &key, long long v)
 
 namespace nufft {
 
-// Grid size and two-pass split: L = smallest power of two >= N (Sec. 2.3,
-// oversampling with N <= L < 2N); L <= 4096 runs in one pass; otherwise
-// L = L1 * L2 with L2 = 2^floor(log2(L)/2) (at most 2048) and L1 = L / L2.
+// Split of an FFT grid of L points into L1 x L2 (pass B transforms rows of
+// L1 points, pass A columns of L2; L = L1 when L2 = 1, the one-pass path).
+// A power of two up to 4096 is one pass; a larger one splits near the square
+// root (L2 <= 2048, L1 <= 4096).  L = P 2^k (P = 3 or 5, the oversampled grids
+// between powers of two) puts P into the columns: L2 = P Q with Q a power of
+// two in [64, 512] (P = 3) or [64, 256] (P = 5), L1 a power of two in
+// [128, 4096], the most balanced such split.  False: L is not supported.
+bool grid_split(int64_t L, int *L1, int *L2)
+{
+    if (L < 16 || L > (int64_t(1) << 23)) return false;
+    const int P = L % 3 == 0 ? 3 : (L % 5 == 0 ? 5 : 1);
+    const int64_t r = L / P;
+    if (r & (r - 1)) return false;
+    if (P == 1) {
+        if (L <= 4096) {
+            *L1 = (int)L;
+            *L2 = 1;
+            return true;
+        }
+        int lg = 0;
+        while ((int64_t(1) << lg) < L) ++lg;
+        int l2 = 1 << (lg / 2);
+        if (l2 > 2048) l2 = 2048;
+        *L2 = l2;
+        *L1 = (int)(L / l2);
+        return *L1 <= 4096;
+    }
+    int best_q = 0;
+    double best = 0.0;
+    for (int64_t q = 64; q <= (P == 3 ? 512 : 256); q <<= 1) {
+        const int64_t l1 = r / q;
+        if (l1 < 128 || l1 > 4096) continue;
+        const double imbalance = std::fabs(std::log2((double)l1 / (double)(P * q)));
+        if (!best_q || imbalance < best) {
+            best_q = (int)q;
+            best = imbalance;
+        }
+    }
+    if (!best_q) return false;
+    *L2 = P * best_q;
+    *L1 = (int)(r / best_q);
+    return true;
+}
+
+// The default grid (Sec. 2.3, oversampling with N <= L < 2N): the smallest
+// power of two >= N and >= 16, and its split.
 bool choose_grid(int64_t N, int64_t *L, int *L1, int *L2)
 {
     int64_t l = 16;
     while (l < N) l <<= 1;
-    if (l > (int64_t(1) << 23)) return false;
     *L = l;
-    if (l <= 4096) {
-        *L1 = (int)l;
-        *L2 = 1;
-        return true;
-    }
-    int lg = 0;
-    while ((int64_t(1) << lg) < l) ++lg;
-    int l2 = 1 << (lg / 2);
-    if (l2 > 2048) l2 = 2048;
-    *L2 = l2;
-    *L1 = (int)(l / l2);
-    return *L1 <= 4096;
+    return grid_split(l, L1, L2);
 }
 
 template <typename R>
@@ -224,13 +255,13 @@ nufft_status upload_twiddles(Plan *p, hipStream_t s)
     if (st) return st;
     if ((st = upload_table<R>(p, t1i, &p->tw1i, s))) return st;
     if (p->L2 > 1) {
-        std::vector<double> t2(2 * (size_t)p->L2), lo(2 * 4096), hi(2 * (size_t)(p->L / 4096));
+        std::vector<double> t2(2 * (size_t)p->L2), lo(2 * 4096), hi(2 * (size_t)((p->L + 4095) / 4096));
         std::vector<double> t2i(2 * (size_t)p->L2);
         fft_twiddles(p->L2, -1, t2.data());
         fft_twiddles(p->L2, 1, t2i.data());
         if ((st = upload_table<R>(p, t2i, &p->tw2i, s))) return st;
         twiddles(p->L, 4096, 1, -1, lo.data());
-        twiddles(p->L, p->L / 4096, 4096, -1, hi.data());
+        twiddles(p->L, (p->L + 4095) / 4096, 4096, -1, hi.data());
         if ((st = upload_table<R>(p, t2, &p->tw2, s))) return st;
         if ((st = upload_table<R>(p, lo, &p->lo, s))) return st;
         if ((st = upload_table<R>(p, hi, &p->hi, s))) return st;
@@ -258,8 +289,6 @@ template <typename R>
 nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
 {
     const int64_t M = p->M, L = p->L;
-    int log2_L2 = 0;
-    while ((1 << log2_L2) < p->L2) ++log2_L2;
     p->t = (int32_t *)p->alloc(M * sizeof(int32_t));
     p->X = p->alloc(M * sizeof(R));
     p->Xs = p->alloc(M * sizeof(R));
@@ -277,7 +306,7 @@ nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
         return NUFFT_ERR_ALLOC;
     NUFFT_HIP_CHECK(hipMemsetAsync(hist, 0, (L + 1) * sizeof(int32_t), s));
     NUFFT_HIP_CHECK(hipMemsetAsync(dflags, 0, 2 * sizeof(unsigned long long), s));
-    NUFFT_HIP_CHECK(launch_assign<R>(x, M, L, (double)p->N / (double)L, p->L1, log2_L2, p->t, (R *)p->X,
+    NUFFT_HIP_CHECK(launch_assign<R>(x, M, L, (double)p->N / (double)L, p->L1, p->L2, p->t, (R *)p->X,
                                      keys_u, hist, dflags, (int *)(dflags + 1), s));
     NUFFT_HIP_CHECK(exclusive_scan(hist, p->off, L + 1, tmp, s));
     NUFFT_HIP_CHECK(launch_iota(iota, M, s));
@@ -1350,44 +1379,94 @@ static nufft_status time_type2(Plan *p, hipStream_t s, float *ms_out)
     return from_hip(e);
 }
 
+// Oversampling (Sec. 2.3): every grid L with N <= L <= 2 L0 (L0 the power of
+// two the plan starts from) that the kernels support is a candidate: powers
+// of two and, unless the plan uses the half-precision exchange, 3 * 2^k and
+// 5 * 2^k.  A larger L lowers gamma and with it K (less work per sample) at
+// the cost of a larger FFT.  Each candidate is planned on the same samples and
+// its type-II transform timed (two interleaved rounds, the best of each); the
+// fastest plan replaces *pp and its grid is remembered per (N, M, dtype, eps,
+// flags).
 template <typename R>
 static nufft_status autotune_grid(Plan **pp, const double *x, hipStream_t s)
 {
     Plan *p = *pp;
-    if (2 * p->L > (int64_t(1) << 23)) return NUFFT_OK;   // the larger grid is not supported
-    char kb[192];
-    std::snprintf(kb, sizeof(kb), "1d N=%lld M=%lld dt=%d eps=%.17g flags=%u K0=%d", (long long)p->N,
-                  (long long)p->M, (int)p->dtype, p->eps, (unsigned)p->flags, p->K);
-    const std::string key(kb);
-    long long factor = 0;
-    const bool known = tune_lookup(key, &factor);
-    if (known && factor == 1) return NUFFT_OK;
-    Plan *q = new (std::nothrow) Plan();
-    if (!q) return NUFFT_ERR_ALLOC;
-    q->kind = PLAN_1D;
-    q->dtype = p->dtype;
-    q->flags = p->flags;
-    q->N = p->N;
-    q->M = p->M;
-    q->eps = p->eps;
-    nufft_status st = NUFFT_OK;
-    if (!choose_grid(2 * p->L, &q->L, &q->L1, &q->L2)) st = NUFFT_ERR_UNSUPPORTED;
-    if (!st) st = build_1d<R>(q, x, s);
-    bool larger = known;
-    if (!st && !known) {
-        float t0 = 0, t1 = 0;
-        st = time_type2<R>(p, s, &t0);
-        if (!st) st = time_type2<R>(q, s, &t1);
-        if (!st) {
-            larger = t1 < t0;
-            tune_store(key, larger ? 2 : 1);
+    const int64_t L0 = p->L;
+    const bool mixed_ok = !(p->flags & NUFFT_FLAG_HALF_EXCHANGE);
+    std::vector<int64_t> cand;   // besides L0, ascending
+    for (int64_t b = 16; b <= 2 * L0; b <<= 1)
+        for (int P : {1, 3, 5}) {
+            const int64_t L = P * b;
+            int l1, l2;
+            if (L == L0 || L < p->N || L > 2 * L0 || (P > 1 && !mixed_ok) || !grid_split(L, &l1, &l2)) continue;
+            cand.push_back(L);
         }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    if (cand.empty()) return NUFFT_OK;
+    char kb[192];
+    std::snprintf(kb, sizeof(kb), "1d-grid N=%lld M=%lld dt=%d eps=%.17g flags=%u", (long long)p->N,
+                  (long long)p->M, (int)p->dtype, p->eps, (unsigned)p->flags);
+    const std::string key(kb);
+    long long known = 0;
+    if (tune_lookup(key, &known)) {
+        if (known == L0 || std::find(cand.begin(), cand.end(), (int64_t)known) == cand.end()) return NUFFT_OK;
+        cand.assign(1, (int64_t)known);
     }
-    if (st || !larger) {
-        (void)hipStreamSynchronize(s);
-        delete q;
-        return st;
+    // the candidate plans (owned by `keep` until one of them replaces *pp)
+    std::vector<Plan *> plans;
+    struct Owner {
+        std::vector<Plan *> *v;
+        hipStream_t s;
+        ~Owner()
+        {
+            if (!v->empty()) (void)hipStreamSynchronize(s);
+            for (Plan *q : *v) delete q;
+        }
+    } keep{&plans, s};
+    for (int64_t L : cand) {
+        Plan *q = new (std::nothrow) Plan();
+        if (!q) return NUFFT_ERR_ALLOC;
+        q->kind = PLAN_1D;
+        q->dtype = p->dtype;
+        q->flags = p->flags;
+        q->N = p->N;
+        q->M = p->M;
+        q->eps = p->eps;
+        q->L = L;
+        grid_split(L, &q->L1, &q->L2);
+        const nufft_status st = build_1d<R>(q, x, s);
+        if (st == NUFFT_ERR_UNSUPPORTED) {   // e.g. K beyond the FP32 rank limit on a smaller grid
+            (void)hipStreamSynchronize(s);
+            delete q;
+            continue;
+        }
+        plans.push_back(q);
+        if (st) return st;
     }
+    if (plans.empty()) return NUFFT_OK;
+    int pick = -1;   // -1: the plan on L0
+    if (known) {
+        pick = 0;
+    } else {
+        std::vector<float> best(plans.size() + 1, 1e30f);
+        for (int round = 0; round < 2; ++round)
+            for (size_t i = 0; i <= plans.size(); ++i) {
+                float t = 0;
+                const nufft_status st = time_type2<R>(i == 0 ? p : plans[i - 1], s, &t);
+                if (st) return st;
+                best[i] = std::min(best[i], t);
+            }
+        size_t bi = 0;
+        for (size_t i = 1; i < best.size(); ++i)
+            if (best[i] < best[bi]) bi = i;
+        pick = (int)bi - 1;
+        tune_store(key, pick < 0 ? (long long)L0 : (long long)plans[pick]->L);
+    }
+    if (pick < 0) return NUFFT_OK;
+    (void)hipStreamSynchronize(s);
+    Plan *q = plans[pick];
+    plans.erase(plans.begin() + pick);
     delete p;
     *pp = q;
     return NUFFT_OK;
@@ -1473,8 +1552,9 @@ static bool eps_ok(double eps, nufft_dtype dt, nufft_status *st)
 
 extern "C" {
 
-nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, const double *x_dev, double eps,
-                         nufft_dtype dtype, uint32_t flags, void *stream)
+// grid 0: the grid is chosen (and autotuned); else the plan uses that grid.
+static nufft_status plan_1d(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, const double *x_dev, double eps,
+                            nufft_dtype dtype, uint32_t flags, int64_t grid, void *stream)
 {
     if (!out) return NUFFT_ERR_INVALID_ARG;
     *out = nullptr;
@@ -1497,13 +1577,23 @@ nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, cons
     p->N = n_modes;
     p->M = n_pts;
     p->eps = eps;
-    if (!choose_grid(n_modes, &p->L, &p->L1, &p->L2)) {
-        delete p;
-        return NUFFT_ERR_UNSUPPORTED;
+    if (grid == 0) {
+        if (!choose_grid(n_modes, &p->L, &p->L1, &p->L2)) {
+            delete p;
+            return NUFFT_ERR_UNSUPPORTED;
+        }
+    } else {
+        p->L = grid;
+        const bool pow2 = (grid & (grid - 1)) == 0;
+        if (grid < n_modes || !grid_split(grid, &p->L1, &p->L2) ||
+            (!pow2 && (flags & (NUFFT_FLAG_PLAIN_UNFUSED | NUFFT_FLAG_HALF_EXCHANGE)))) {
+            delete p;
+            return NUFFT_ERR_UNSUPPORTED;
+        }
     }
     hipStream_t s = (hipStream_t)stream;
     st = dtype == NUFFT_C64 ? build_1d<float>(p, x_dev, s) : build_1d<double>(p, x_dev, s);
-    if (st == NUFFT_OK && !(flags & (NUFFT_FLAG_NO_AUTOTUNE | NUFFT_FLAG_PLAIN_UNFUSED)))
+    if (st == NUFFT_OK && grid == 0 && !(flags & (NUFFT_FLAG_NO_AUTOTUNE | NUFFT_FLAG_PLAIN_UNFUSED)))
         st = dtype == NUFFT_C64 ? autotune_grid<float>(&p, x_dev, s) : autotune_grid<double>(&p, x_dev, s);
     if (st == NUFFT_OK && !(flags & (NUFFT_FLAG_NO_AUTOTUNE | NUFFT_FLAG_PLAIN_UNFUSED)))
         st = dtype == NUFFT_C64 ? autotune_schedule<float>(p, s) : autotune_schedule<double>(p, s);
@@ -1515,6 +1605,20 @@ nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, cons
     p->last = s;
     *out = p;
     return NUFFT_OK;
+}
+
+nufft_status nufft2_plan(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, const double *x_dev, double eps,
+                         nufft_dtype dtype, uint32_t flags, void *stream)
+{
+    return plan_1d(out, n_modes, n_pts, x_dev, eps, dtype, flags, 0, stream);
+}
+
+nufft_status nufft2_plan_grid(nufft_plan_t *out, int64_t n_modes, int64_t n_pts, const double *x_dev, double eps,
+                              nufft_dtype dtype, uint32_t flags, int64_t grid, void *stream)
+{
+    if (out) *out = nullptr;
+    if (grid < 1) return NUFFT_ERR_INVALID_ARG;
+    return plan_1d(out, n_modes, n_pts, x_dev, eps, dtype, flags, grid, stream);
 }
 
 nufft_status nufft2_exec(nufft_plan_t plan, const void *c, void *f, void *stream)

@@ -109,6 +109,21 @@ void cis_2pi_frac(int64_t m, int64_t L, double *c, double *s)
 
 void fft_twiddles(int64_t L, int dir, double *out, int r0)
 {
+    const int64_t P = L % 3 == 0 ? 3 : (L % 5 == 0 ? 5 : 1);
+    if (P > 1) {
+        // mixed length P Q: the Q-point table, then the radix-P stage's
+        // exp(dir 2 pi i s m / L) at Q + (s - 1) Q + m, 1 <= s < P, m < Q
+        const int64_t Q = L / P;
+        fft_twiddles(Q, dir, out, r0);
+        for (int64_t sj = 1; sj < P; ++sj)
+            for (int64_t m = 0; m < Q; ++m) {
+                double c, s;
+                cis_2pi_frac(sj * m, L, &c, &s);
+                out[2 * (Q + (sj - 1) * Q + m)] = c;
+                out[2 * (Q + (sj - 1) * Q + m) + 1] = dir * s;
+            }
+        return;
+    }
     // Stage-major layout read by the LDS FFT: the stage that combines NS-point
     // transforms with radix R keeps exp(dir 2 pi i q k / (NS R)), 0 <= k < NS,
     // 1 <= q < R, at NS - 1 + k (R - 1) + q - 1 (the stages tile [0, L - 1)).

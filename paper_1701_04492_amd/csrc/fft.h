@@ -247,6 +247,100 @@ __device__ __forceinline__ void block_fft_lds(C *buf, const C *tw, int lt, bool 
     fftk::stages_from<C, L, DIR, 1, WS, R0>(buf, tw, lt, active);
 }
 
+// ---- mixed radix: L = P Q points, P = 3 or 5, Q a power of two --------------
+// One radix-P decimation-in-frequency stage splits the transform into P
+// transforms of Q points on interleaved outputs.  With W_n = exp(DIR 2 pi i / n):
+//   X[P k + s] = sum_{m<Q} W_Q^{m k} y_s[m],
+//   y_s[m]     = W_L^{s m} sum_{p<P} x[m + p Q] W_P^{s p}.
+// The padded natural layout puts x[m + p Q] at lds_pad(m) + p (Q + Q/16), so
+// y_s overwrites the inputs of its butterflies in place and sub-transform s
+// runs on the padded buffer at s (Q + Q/16); X[n] ends at fft_out_pos<L>(n).
+// Twiddle table of a mixed length L (L entries, sign DIR): the stage-major
+// table of the Q-point transform in entries [0, Q), then W_L^{s m} at
+// Q + (s - 1) Q + m for 1 <= s < P, m < Q.
+
+__host__ __device__ constexpr int fft_radix_p(int L) { return L % 3 == 0 ? 3 : (L % 5 == 0 ? 5 : 1); }
+
+// Padded LDS position of output n of a length-L transform (natural order for
+// powers of two; the sub-transform layout above for mixed lengths).
+template <int L>
+__host__ __device__ constexpr int fft_out_pos(int n)
+{
+    constexpr int P = fft_radix_p(L), Q = L / P;
+    if constexpr (P == 1) return lds_pad(n);
+    else return (n % P) * (Q + Q / 16) + lds_pad(n / P);
+}
+
+namespace fftk {
+
+// In-place P-point DFT (P = 3 or 5): x[s] <- sum_p x[p] exp(DIR 2 pi i s p / P).
+template <typename C, int P, int DIR>
+__device__ __forceinline__ void dftp(C *x)
+{
+    using R = decltype(C{}.x);
+    if constexpr (P == 3) {
+        const R c1 = (R)-0.5, s1 = (R)0.86602540378443864676;   // cos, sin of 2 pi / 3
+        const C t = cadd(x[1], x[2]);
+        const C u = cmake<C>(x[0].x + c1 * t.x, x[0].y + c1 * t.y);
+        const C d = csub(x[1], x[2]);
+        const C v = mul_w4<C, DIR>(cmake<C>(s1 * d.x, s1 * d.y));   // DIR i s1 (x1 - x2)
+        x[0] = cadd(x[0], t);
+        x[1] = cadd(u, v);
+        x[2] = csub(u, v);
+    } else {
+        static_assert(P == 5, "radix 3 or 5");
+        // cos and sin of 2 pi / 5 and 4 pi / 5
+        const R c1 = (R)0.30901699437494742410, s1 = (R)0.95105651629515357212;
+        const R c2 = (R)-0.80901699437494742410, s2 = (R)0.58778525229247312917;
+        const C a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+        const C a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+        const C u1 = cmake<C>(x[0].x + c1 * a1.x + c2 * a2.x, x[0].y + c1 * a1.y + c2 * a2.y);
+        const C u2 = cmake<C>(x[0].x + c2 * a1.x + c1 * a2.x, x[0].y + c2 * a1.y + c1 * a2.y);
+        const C v1 = mul_w4<C, DIR>(cmake<C>(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+        const C v2 = mul_w4<C, DIR>(cmake<C>(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+        x[0] = cadd(x[0], cadd(a1, a2));
+        x[1] = cadd(u1, v1);
+        x[4] = csub(u1, v1);
+        x[2] = cadd(u2, v2);
+        x[3] = csub(u2, v2);
+    }
+}
+
+}  // namespace fftk
+
+// Full transform of any supported length L (a power of two up to 4096, or P Q
+// with P = 3, 5 and Q a power of two, 64 <= Q <= 1024) whose input is in LDS
+// (natural padded order), by the L/16 threads of the transform (lane lt).
+// Called by all threads of the workgroup; the caller has made the input
+// visible (a barrier).  Ends with the results readable by every thread of
+// the workgroup at fft_out_pos<L>(n).
+template <typename C, int L, int DIR, int R0 = 16>
+__device__ __forceinline__ void block_fft_any_lds(C *buf, const C *tw, int lt)
+{
+    constexpr int P = fft_radix_p(L);
+    if constexpr (P == 1) {
+        block_fft_lds<C, L, DIR, fft_wave_sync<L>, R0>(buf, tw, lt);
+        fft_publish<L>();
+    } else {
+        constexpr int Q = L / P, QP = Q + Q / 16, TPF = L / 16;
+        static_assert(Q * P == L && (Q & (Q - 1)) == 0 && Q >= 64 && Q <= 1024, "unsupported mixed length");
+        const C *twp = tw + Q;
+        for (int m = lt; m < Q; m += TPF) {   // the Q radix-P butterflies
+            C x[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) x[p] = buf[lds_pad(m) + p * QP];
+            fftk::dftp<C, P, DIR>(x);
+            buf[lds_pad(m)] = x[0];
+#pragma unroll
+            for (int q = 1; q < P; ++q) buf[lds_pad(m) + q * QP] = cmul(x[q], twp[(q - 1) * Q + m]);
+        }
+        __syncthreads();
+        // sub-transform s: threads s Q/16 .. (s + 1) Q/16 - 1 of the transform (one wavefront)
+        block_fft_lds<C, Q, DIR, fft_wave_sync<Q>, R0>(buf + (lt / (Q / 16)) * QP, tw, lt % (Q / 16));
+        __syncthreads();
+    }
+}
+
 // Full transform whose input is in registers: v[q] = x[lt + q*L/16], q < 16
 // (exactly the operands of the first radix-16 stage, so that stage skips the
 // LDS round trip).  The caller must have finished every earlier read of buf

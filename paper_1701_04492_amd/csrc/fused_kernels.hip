@@ -454,8 +454,15 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
             for (int q = 0; q < 16; ++q) v[q] = cscale(cv[q], wq[q]);
         }
         __syncthreads();   // earlier readers of buf are done
-        block_fft_regs<C, L2, -1, fft_wave_sync<L2>, FR>(buf + g * P, tw, lt, v);
-        fft_publish<L2>();
+        if constexpr (fft_radix_p(L2) == 1) {
+            block_fft_regs<C, L2, -1, fft_wave_sync<L2>, FR>(buf + g * P, tw, lt, v);
+            fft_publish<L2>();
+        } else {   // mixed length: its radix-3/5 stage reads across the transform's waves
+#pragma unroll
+            for (int q = 0; q < 16; ++q) buf[g * P + lds_pad(lt + q * TPF)] = v[q];
+            __syncthreads();
+            block_fft_any_lds<C, L2, -1, FR>(buf + g * P, tw, lt);
+        }
         if constexpr (H) {
             // this thread's 16 outputs all lie in column gg = tid % G (NT is a multiple of G)
             C o[16];
@@ -463,7 +470,7 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int i = tid + e * NT;
-                o[e] = cmul(buf[(i % G) * P + lds_pad(i / G)], wt[e]);
+                o[e] = cmul(buf[(i % G) * P + fft_out_pos<L2>(i / G)], wt[e]);
                 m = fmaxf(m, cmaxabs(o[e]));
             }
             m = wave_max_mod(m, G);
@@ -488,7 +495,7 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
             for (int e = 0; e < 16; ++e) {
                 const int i = tid + e * NT;
                 const int gg = i % G, n2 = i / G;
-                Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + lds_pad(n2)], wt[e]);
+                Yr[(int64_t)n2 * L1 + gg] = cmul(buf[gg * P + fft_out_pos<L2>(n2)], wt[e]);
             }
         }
     }
@@ -1085,8 +1092,7 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
         }
         if (r + 1 < K) fetch(r + 1);   // its exponents go to the other parity, last read at rank r - 1
         __syncthreads();
-        block_fft_lds<C, L2, DIR, fft_wave_sync<L2>, FR>(buf + g * P, tw, lt);
-        fft_publish<L2>();
+        block_fft_any_lds<C, L2, DIR, FR>(buf + g * P, tw, lt);
 #pragma unroll
         for (int h = 0; h < 16; h += 8) {   // two halves of 8: bounded transient registers
             R zq[8], wq[8];
@@ -1099,7 +1105,7 @@ k_passA_adj(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const c
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int i = tid + (h + e) * NT;
-                acc[h + e] = cadd(acc[h + e], cscale(buf[(i % G) * P + lds_pad(i / G)], wq[e]));
+                acc[h + e] = cadd(acc[h + e], cscale(buf[(i % G) * P + fft_out_pos<L2>(i / G)], wq[e]));
             }
         }
     }
@@ -1210,6 +1216,18 @@ static hipError_t run_small_adj(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R>
     }
     return hipGetLastError();
 }
+
+// Column lengths L2 = 3 * 2^k and 5 * 2^k of the oversampled grids between
+// powers of two (radix-3/5 stage, then power-of-two transforms of 64 to 512
+// points), with the columns per pass-A / pass-A' workgroup.
+#define MIXED_L2_SWITCH(MACRO) \
+    MACRO(192, 16)             \
+    MACRO(384, 16)             \
+    MACRO(768, 8)              \
+    MACRO(1536, 4)             \
+    MACRO(320, 16)             \
+    MACRO(640, 8)              \
+    MACRO(1280, 4)
 
 #define SMALL_SWITCH(MACRO) \
     switch (a.L) {          \
@@ -1414,6 +1432,13 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
             PA(1024, Cfg<R>::G1024)
             PA(2048, Cfg<R>::G2048)
 #undef PA
+#define PAM(LL, GG)                                                                                        \
+    case LL:                                                                                               \
+        if (a.half) return hipErrorInvalidValue;                                                           \
+        launch_pass_a<R, LL, GG, false, 16>(a, c, mode, s);                                                \
+        break;
+            MIXED_L2_SWITCH(PAM)
+#undef PAM
         default: return hipErrorInvalidValue;
         }
     }
@@ -1530,6 +1555,13 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
             PAA(1024, Cfg<R>::GA1024)
             PAA(2048, Cfg<R>::GA2048)
 #undef PAA
+#define PAAM(LL, GG)                                                                                       \
+    case LL:                                                                                               \
+        if (a.half) return hipErrorInvalidValue;                                                           \
+        launch_pass_a_adj<R, LL, GG, DIR, false, 16>(a, f, s);                                             \
+        break;
+            MIXED_L2_SWITCH(PAAM)
+#undef PAAM
         default: return hipErrorInvalidValue;
         }
     }

@@ -80,7 +80,7 @@ __device__ __forceinline__ void stage_factors(const Factors<R> &fac, R *ucoef_s,
 
 // ---- plan kernels ----------------------------------------------------------
 template <typename R>
-hipError_t launch_assign(const double *x, int64_t M, int64_t L, double n_over_L, int L1, int log2_L2,
+hipError_t launch_assign(const double *x, int64_t M, int64_t L, double n_over_L, int L1, int L2,
                          int32_t *t, R *X, uint32_t *key, int32_t *hist, unsigned long long *gbits,
                          int *bad, hipStream_t s);
 template <typename R>

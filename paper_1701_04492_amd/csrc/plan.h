@@ -123,6 +123,7 @@ struct nufft_plan_s {
 namespace nufft {
 using Plan = nufft_plan_s;
 bool choose_grid(int64_t N, int64_t *L, int *L1, int *L2);
+bool grid_split(int64_t L, int *L1, int *L2);
 template <typename R> nufft_status build_1d(Plan *p, const double *x, hipStream_t s);
 template <typename R> FusedArgs<R> fused_args(const Plan *p);
 template <typename R> nufft_status upload_twiddles(Plan *p, hipStream_t s);

@@ -20,7 +20,7 @@ __device__ __forceinline__ double wave_max(double v)
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_assign(const double *__restrict__ x, int64_t M, int64_t L, double n_over_L, int L1,
-         int log2_L2, int32_t *__restrict__ t_out, R *__restrict__ X_out,
+         int L2, int32_t *__restrict__ t_out, R *__restrict__ X_out,
          uint32_t *__restrict__ key_out, int32_t *__restrict__ hist,
          unsigned long long *gamma_bits, int *bad)
 {
@@ -42,8 +42,7 @@ k_assign(const double *__restrict__ x, int64_t M, int64_t L, double n_over_L, in
             X = d * n_over_L;
             amax = fabs(X);
         }
-        const uint32_t L2mask = (1u << log2_L2) - 1u;
-        const uint32_t key = ((uint32_t)t & L2mask) * (uint32_t)L1 + ((uint32_t)t >> log2_L2);
+        const uint32_t key = ((uint32_t)t % (uint32_t)L2) * (uint32_t)L1 + (uint32_t)t / (uint32_t)L2;
         t_out[j] = t;
         X_out[j] = (R)X;
         key_out[j] = key;
@@ -323,13 +322,13 @@ __global__ void k_gather_sorted(const int32_t *__restrict__ perm, const R *__res
 }
 
 template <typename R>
-hipError_t launch_assign(const double *x, int64_t M, int64_t L, double n_over_L, int L1, int log2_L2,
+hipError_t launch_assign(const double *x, int64_t M, int64_t L, double n_over_L, int L1, int L2,
                          int32_t *t, R *X, uint32_t *key, int32_t *hist, unsigned long long *gbits,
                          int *bad, hipStream_t s)
 {
     if (M == 0) return hipSuccess;
     const unsigned nb = (unsigned)((M + 255) / 256);
-    hipLaunchKernelGGL(k_assign<R>, dim3(nb), dim3(256), 0, s, x, M, L, n_over_L, L1, log2_L2, t, X,
+    hipLaunchKernelGGL(k_assign<R>, dim3(nb), dim3(256), 0, s, x, M, L, n_over_L, L1, L2, t, X,
                        key, hist, gbits, bad);
     return hipGetLastError();
 }

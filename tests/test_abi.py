@@ -64,6 +64,21 @@ def test_host_argument_errors():
     assert B.lib.nufft_destroy(None) == 0
 
 
+def test_plan_grid_argument_errors():
+    """Explicit grids the kernels cannot run are refused before any device work."""
+    h, p = ctypes.c_void_p(), ctypes.c_void_p(8)
+    f = B.lib.nufft2_plan_grid
+    assert f(ctypes.byref(h), 1000, 16, p, 1e-6, 0, 0, 0, None) == 1            # no grid
+    assert f(ctypes.byref(h), 1000, 16, p, 1e-6, 0, 0, 512, None) == 2          # grid < N
+    assert f(ctypes.byref(h), 1000, 16, p, 1e-6, 0, 0, 7 * 4096, None) == 2     # no radix-7 stage
+    assert f(ctypes.byref(h), 1000, 16, p, 1e-6, 0, 0, 3072, None) == 2         # mixed only in the two-pass range
+    assert f(ctypes.byref(h), 1000, 16, p, 1e-6, 0, 0, 5 * 4096, None) == 2     # 5 x 64 columns need L1 >= 128
+    assert f(ctypes.byref(h), 1000, 16, p, 1e-6, 0, 0, 3 << 22, None) == 2      # beyond 2^23
+    assert f(ctypes.byref(h), 1000, 16, p, 1e-6, 0, 2, 24576, None) == 2        # plain path: powers of two
+    assert f(ctypes.byref(h), 1000, 16, p, 1e-6, 0, 8, 24576, None) == 2        # half exchange: powers of two
+    assert f(None, 1000, 16, p, 1e-6, 0, 0, 24576, None) == 1
+
+
 def test_enum_values_are_pinned():
     """Status codes, dtypes and flag bits as the header declares them (and the binding mirrors)."""
     import re

@@ -38,7 +38,7 @@ def test_algorithmic_bytes_of_the_step_kernels():
 
 
 def _write_counters(d, counter, values, calib):
-    """One fake rocprofv3 counter CSV: the six step kernels in launch order, three steps,
+    """One fake rocprofv3 counter CSV: the step kernels in launch order, three steps,
     then the calibration copy."""
     os.makedirs(d, exist_ok=True)
     rows, i = [], 0
@@ -68,6 +68,9 @@ def test_counter_reduction(tmp_path):
     assert rec["calibration"]["write_scale"] == pytest.approx(1.0)
     for k in bench.COUNTER_ORDER:
         assert rec["kernels"][k]["bytes_per_launch"] == int(fetch[k] * 1024 * 2 + write[k] * 1024)
+    # the backward sort's two kernels are also reported together
+    assert rec["kernels"]["bwd_sort"]["bytes_per_launch"] == (rec["kernels"]["bwd_sort.1"]["bytes_per_launch"]
+                                                             + rec["kernels"]["bwd_sort.2"]["bytes_per_launch"])
     assert rec["source_sha256_16"] == bench.kernel_source_hash()
 
 
@@ -75,7 +78,7 @@ def test_counter_reduction_rejects_a_mismatched_run(tmp_path):
     fetch = {k: 1.0 for k in bench.COUNTER_ORDER}
     _write_counters(str(tmp_path / "F"), "FETCH_SIZE", fetch, 1.0)
     with open(os.path.join(str(tmp_path / "F"), "1_counter_collection.csv"), "a") as fh:
-        fh.write('99,"void nufft::k_passA<float>(...)",FETCH_SIZE,1.0\n')       # a seventh step kernel
+        fh.write('99,"void nufft::k_passA<float>(...)",FETCH_SIZE,1.0\n')       # one kernel too many
     _write_counters(str(tmp_path / "W"), "WRITE_SIZE", fetch, 1.0)
     with pytest.raises(SystemExit):
         bench.traffic_summary(str(tmp_path / "F"), str(tmp_path / "W"), str(tmp_path / "t.json"), ["test"])

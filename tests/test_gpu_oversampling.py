@@ -1,8 +1,8 @@
 """Autotuned oversampling (the default of 1-D plans, Sec. 2.3; NUFFT_FLAG_NO_AUTOTUNE
-turns it off): the plan is built on the grids L0 and 2 L0, the faster type-II
-transform is kept.  Whatever it
-picks, the result must meet the 4 eps ||c||_1 bar against the FP64 direct sums, and
-K and gamma must be those of the grid it picked."""
+turns it off): the plan is built on every supported grid N <= L <= 2 L0 (powers of
+two, 3 * 2^k and 5 * 2^k in the two-pass range), the fastest type-II transform is
+kept.  Whatever it picks, the result must meet the 4 eps ||c||_1 bar against the
+FP64 direct sums, and K and gamma must be those of the grid it picked."""
 import numpy as np
 import pytest
 import torch
@@ -34,6 +34,26 @@ def _next_pow2(n):
     return l
 
 
+def _supported(L):
+    """The grids nufft2_plan_grid documents: powers of two up to 2^23, and P * 2^k
+    (P = 3, 5) = L1 * P * Q with L1 in [128, 4096], Q in [64, 512 or 256], powers of two."""
+    if L < 16 or L > 1 << 23:
+        return False
+    P = 3 if L % 3 == 0 else (5 if L % 5 == 0 else 1)
+    r = L // P
+    if r & (r - 1):
+        return False
+    if P == 1:
+        return True
+    return any(128 <= r // q <= 4096 for q in (64, 128, 256, 512) if q <= (512 if P == 3 else 256))
+
+
+def _candidates(N):
+    L0 = _next_pow2(N)
+    return sorted({p * b for b in (1 << k for k in range(4, 25)) for p in (1, 3, 5)
+                   if N <= p * b <= 2 * L0 and _supported(p * b)})
+
+
 @pytest.mark.parametrize("dtype", [C64, C128])
 @pytest.mark.parametrize("N,M", [(1 << 14, 1 << 22), (3000, 1 << 20), (1 << 16, 1 << 16), (20000, 30000)])
 def test_autotune_grid_parity(dtype, N, M):
@@ -43,7 +63,7 @@ def test_autotune_grid_parity(dtype, N, M):
     plan = P.nufft2_plan(_t(x, torch.float64), N, eps, dtype)
     L0 = _next_pow2(N)
     _say("autotune N=%d M=%d %s: grid %d (L0 %d), K=%d gamma=%.4f" % (N, M, dtype, plan.grid, L0, plan.K, plan.gamma))
-    assert plan.grid in (L0, 2 * L0)
+    assert plan.grid in _candidates(N), _candidates(N)
     # gamma and K belong to the chosen grid: X_j = (L x_j - s_j) N / L
     _, _, d = D.grid_assign(x, plan.grid)
     gam = np.abs(d).max() * N / plan.grid
