@@ -309,24 +309,57 @@ def bench_half(P, torch, x, c, y, N, M, steps, warmup):
             "kernels": kern}
 
 
+def oversampling_grids(N):
+    """The grids the autotuner tries for N modes: powers of two, 3 * 2^k and 5 * 2^k with
+    N <= L <= 2 L0 that have a two-pass split (or are one-pass powers of two)."""
+    L0 = 16
+    while L0 < N:
+        L0 *= 2
+    out = []
+    for k in range(4, 24):
+        for p in (1, 3, 5):
+            L = p << k
+            if not N <= L <= 2 * L0 or L > 1 << 23:
+                continue
+            if p > 1 and not any(128 <= (L // p) // q <= 4096 for q in (64, 128, 256, 512)
+                                 if q <= (512 if p == 3 else 256)):
+                continue
+            out.append(L)
+    return sorted(set(out))
+
+
 def bench_oversampling(P, W, torch, dev):
-    """Autotuned oversampling (Sec. 2.3): N = 2^14 modes, M = 2^22 iid samples, complex64,
-    eps 1e-6; the default grid L0 = N against the plan's timed choice of L0 or 2 L0."""
-    N, M = 1 << 14, 1 << 22
+    """Autotuned oversampling (Sec. 2.3): M = 2^22 iid samples, complex64, eps 1e-6, for
+    N = 2^14 and N = 20000 modes: the default grid L0 (the power of two >= N), the plan's
+    timed choice, and every candidate grid planned explicitly (type II and adjoint)."""
+    M = 1 << 22
     rng = W.rng_for(7)
-    c = torch.from_numpy(W.complex_normal(rng, N)).to(torch.complex64).to(dev)
     x = torch.from_numpy(W.iid_samples(rng, M)).to(dev)
     f = torch.empty(M, dtype=torch.complex64, device=dev)
-    out = {"N": N, "M": M}
-    for label, fl in (("default", P.NUFFT_FLAG_NO_AUTOTUNE), ("autotuned", 0)):
-        pl = P.nufft2_plan(x, N, 1e-6, torch.complex64, fl)
-        t = time_best(lambda: P.nufft2_exec(pl, c, f), 20, 3, torch)
-        ta = time_best(lambda: P.nufft1_exec(pl, f, +1, c), 10, 2, torch)
-        out[label] = {"grid": pl.grid, "K": pl.K, "gamma": round(pl.gamma, 4), "us": round(t * 1e3, 2),
-                      "pts_per_s": M / (t * 1e-3), "adjoint_us": round(ta * 1e3, 2)}
-        del pl
-    out["speedup"] = round(out["default"]["us"] / out["autotuned"]["us"], 3)
-    return out
+    res = {}
+    for N in (1 << 14, 20000):
+        c = torch.from_numpy(W.complex_normal(rng, N)).to(torch.complex64).to(dev)
+        out = {"N": N, "M": M}
+
+        def timed(pl):
+            t = time_best(lambda: P.nufft2_exec(pl, c, f), 20, 3, torch)
+            ta = time_best(lambda: P.nufft1_exec(pl, f, +1, c), 10, 2, torch)
+            return {"grid": pl.grid, "K": pl.K, "gamma": round(pl.gamma, 4), "us": round(t * 1e3, 2),
+                    "pts_per_s": M / (t * 1e-3), "adjoint_us": round(ta * 1e3, 2)}
+        for label, fl in (("default", P.NUFFT_FLAG_NO_AUTOTUNE), ("autotuned", 0)):
+            pl = P.nufft2_plan(x, N, 1e-6, torch.complex64, fl)
+            out[label] = timed(pl)
+            del pl
+        grids = {}
+        for L in oversampling_grids(N):
+            pl = P.nufft2_plan(x, N, 1e-6, torch.complex64, P.NUFFT_FLAG_NO_AUTOTUNE, grid=L)
+            r = timed(pl)
+            grids[str(L)] = {k: r[k] for k in ("K", "us", "adjoint_us")}
+            del pl
+        out["grids"] = grids
+        out["speedup"] = round(out["default"]["us"] / out["autotuned"]["us"], 3)
+        res["N%d" % N] = out
+    return res
 
 
 def bench_type3(P, W, torch, dev):
@@ -682,8 +715,8 @@ def main():
         _progress("polar_2d")
         out["inverse_2p20"] = bench_solve(P, W, torch, dev)
         _progress("inverse_2p20")
-        out["oversampling_2p14_modes_2p22_samples"] = bench_oversampling(P, W, torch, dev)
-        _progress("oversampling_2p14_modes_2p22_samples")
+        out["oversampling_2p22_samples"] = bench_oversampling(P, W, torch, dev)
+        _progress("oversampling_2p22_samples")
         out["type3"] = bench_type3(P, W, torch, dev)
         _progress("type3")
         out["type2_3d"] = bench_3d(P, W, torch, dev)

@@ -82,3 +82,11 @@ def test_counter_reduction_rejects_a_mismatched_run(tmp_path):
     _write_counters(str(tmp_path / "W"), "WRITE_SIZE", fetch, 1.0)
     with pytest.raises(SystemExit):
         bench.traffic_summary(str(tmp_path / "F"), str(tmp_path / "W"), str(tmp_path / "t.json"), ["test"])
+
+
+def test_oversampling_grid_list():
+    """The grids the bench plans explicitly: every supported length N <= L <= 2 L0."""
+    assert bench.oversampling_grids(1 << 14) == [16384, 24576, 32768]
+    assert bench.oversampling_grids(20000) == [24576, 32768, 40960, 49152, 65536]
+    assert bench.oversampling_grids(1 << 22) == [4194304, 5242880, 6291456, 8388608]
+    assert bench.oversampling_grids(3000) == [4096, 8192]
