@@ -193,6 +193,13 @@ k_2d_passB(const cx_t<R> *__restrict__ H, int64_t N1, int64_t GY, const int4 *__
 // weighted by v^x_r1(k1) and summed over r1 in registers; the row for
 // r2 is written once: to Z_r2[n2][:] when the task holds the whole column
 // (slot < 0), else to partial row `slot` of Zp, which k_2d_sum_parts adds up.
+// Sparse tasks (no thread's grid points hold more than about twice the
+// average) take a second route: thread (g, lt) owns the 16 grid points
+// lt + q GX/16 of rank slot g, which are exactly the operands of its first
+// FFT stage.  Per r2 the samples' w_j = exp(DIR i pi (Xx + Xy)) g_j P^y_r2(zy_j)
+// are formed once; per rank the thread sums each owned point's run of
+// samples in registers and starts the transform from registers: no grid
+// clearing, no cross-thread stitching, no grid stores.
 template <typename R, int GX, int RC, int SCAP, bool TWG, int DIR>
 __global__ void __launch_bounds__(RC * GX / 16)
 k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const int4 *__restrict__ tasks, int ntasks,
@@ -213,8 +220,17 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
     };
     __shared__ Staged sst[SCAP];
     __shared__ unsigned short spos[SCAP];
-    __shared__ C hv[RC * NT], tv[RC * NT];
-    __shared__ int hix[NT], tix[NT], nxa[NT], nxb[NT];
+    // the segmented spread's scratch; the owner route's per-r2 sample records reuse it
+    struct alignas(4 * sizeof(R)) Weighted {
+        R re, im, zx, pad;
+    };
+    constexpr int SEGS = 2 * RC * NT * (int)sizeof(C) + 4 * NT * (int)sizeof(int);
+    constexpr int SEGW = SCAP * (int)sizeof(Weighted);
+    constexpr int SEGB = SEGS > SEGW ? SEGS : SEGW;
+    __shared__ __align__(16) char segs[SEGB];
+    C *hv = reinterpret_cast<C *>(segs), *tv = hv + RC * NT;
+    int *hix = reinterpret_cast<int *>(tv + RC * NT), *tix = hix + NT, *nxa = tix + NT, *nxb = nxa + NT;
+    Weighted *sw = reinterpret_cast<Weighted *>(segs);
     const C *tw = TWG ? twd_g : tw_s;
     const int task = xcd_task(ntasks);
     if (task < 0) return;
@@ -260,6 +276,86 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
         }
     }
     const ZMap zm = zmap(N1);
+    // runs of the owned grid points: start | count << 16 (counts <= SCAP < 2^16),
+    // from the first sample at or after each point (binary search in spos),
+    // built in buf before its first transform
+    __syncthreads();   // staging done
+    int *soff = reinterpret_cast<int *>(buf);   // GX + 1 ints
+    static_assert((GX + 1) * (int)sizeof(int) <= RC * P * (int)sizeof(C), "offsets exceed the grid buffer");
+    for (int p = tid; p <= GX; p += NT) {
+        int lo = 0, hi = cnt;   // first i with spos[i] >= p
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((int)spos[mid] < p) lo = mid + 1;
+            else hi = mid;
+        }
+        soff[p] = lo;
+    }
+    __syncthreads();
+    int pk[16];
+    int work = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int p = lt + q * TPF;
+        const int a = soff[p], n = soff[p + 1] - a;
+        pk[q] = a | (n << 16);
+        work += n;
+    }
+    // the owner route when no thread's points hold more than twice the average plus 16
+    const bool own = !__syncthreads_or(work > 2 * (cnt * 16 / GX) + 16);
+    if (own) {
+        for (int r2 = 0; r2 < fy.K; ++r2) {
+            __syncthreads();   // the previous r2's readers of sw and buf are done
+            const RankPoly<R> uy = rank_poly(fy, r2);
+            for (int i = tid; i < cnt; i += NT) {
+                const Staged t = sst[i];
+                const R wy = rank_eval(uy, t.zy);
+                sw[i] = Weighted{t.re * wy, t.im * wy, t.zx, (R)0};
+            }
+            C za[ZA];
+#pragma unroll
+            for (int m = 0; m < ZA; ++m) za[m] = cmake<C>(0, 0);
+            for (int r0 = 0; r0 < fx.K; r0 += RC) {
+                const int nr = min(RC, fx.K - r0);
+                const int r1 = r0 + g;
+                const RankPoly<R> ux = rank_poly(fx, min(r1, fx.K - 1));
+                __syncthreads();   // sw complete; the previous chunk's readers of buf are done
+                C v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    C acc = cmake<C>(0, 0);
+                    const int a = pk[q] & 0xffff, e = a + (pk[q] >> 16);
+                    for (int i = a; i < e; ++i) {
+                        const Weighted w = sw[i];
+                        acc = cadd(acc, cscale(cmake<C>(w.re, w.im), rank_eval(ux, w.zx)));
+                    }
+                    // i^(r1 + r2) for the type I, i^-(r1 + r2) for the adjoint
+                    v[q] = crot(acc, -DIR * (r1 + r2));
+                }
+                block_fft_regs<C, GX, DIR, fft_wave_sync<GX>>(buf + g * P, tw, lt, v, r1 < fx.K);
+                fft_publish<GX>();
+                R zq[ZA], t0[ZA], t1[ZA];
+#pragma unroll
+                for (int m = 0; m < ZA; ++m) zq[m] = zcoord<R>(tid + m * NT, zm);
+                cheb_pair_many<R, ZA>(r0, zq, t0, t1);
+                for (int gg = 0; gg < nr; ++gg) {
+#pragma unroll
+                    for (int m = 0; m < ZA; ++m) {
+                        const int k1 = tid + m * NT;
+                        const R w = (r0 + gg == 0) ? (R)0.5 : t0[m];
+                        za[m] = cadd(za[m], cscale(buf[gg * P + lds_pad(k1)], w));
+                        const R c = 2 * zq[m] * t1[m] - t0[m];
+                        t0[m] = t1[m];
+                        t1[m] = c;
+                    }
+                }
+            }
+            C *Zrow = tk.w < 0 ? Z + ((int64_t)r2 * GY + n2) * GX : Zp + ((int64_t)tk.w * fy.K + r2) * GX;
+#pragma unroll
+            for (int m = 0; m < ZA; ++m) Zrow[tid + m * NT] = za[m];
+        }
+        return;
+    }
     for (int r2 = 0; r2 < fy.K; ++r2) {
         __syncthreads();   // staging done
         const RankPoly<R> uy = rank_poly(fy, r2);   // P^y_r2 is evaluated per sample in the spread
