@@ -238,13 +238,16 @@ def test_allocation_failure_is_reported():
     ref = P.nufft2_exec(P.nufft2_plan(xt, N, 1e-6, C64), ct)
     yt = _t(W.iid_samples(rng, M), torch.float64)
     zt = _t(np.zeros(M), torch.float64)            # one z slice: a bounded number of allocations
-    calls = [("1-D plan", lambda: P.nufft2_plan(xt, N, 1e-6, C64)),
+    Mb = (1 << 18) + 3                             # 17 destination blocks: the bucketed layout's buffers too
+    xb = _t(W.iid_samples(rng, Mb), torch.float64)
+    calls = [("1-D plan", lambda: P.nufft2_plan(xt, N, 1e-6, C64)),     # autotuned: every candidate grid's plan
+             ("1-D plan, bucketed", lambda: P.nufft2_plan(xb, 1 << 13, 1e-6, C64, P.NUFFT_FLAG_NO_AUTOTUNE)),
              ("2-D plan", lambda: P.nufft2d_plan(xt, yt, 256, 256, 1e-6, C64)),
              ("3-D exec", lambda: P.nufft3d_exec(xt, yt, zt, _t(np.ones((8, 8, 16)), C64), 1e-6))]
     try:
         for label, call in calls:
             refused = 0
-            for n in range(64):
+            for n in range(200):
                 _say(label, "refusing allocation", n)
                 P.nufft_debug_fail_alloc(n)
                 try:
@@ -257,8 +260,9 @@ def test_allocation_failure_is_reported():
             P.nufft_debug_fail_alloc(-1)
             torch.cuda.synchronize()
             _say("   %s: %d allocation sites refused" % (label, refused))
-            assert 5 <= refused < 64
+            assert 5 <= refused < 200
     finally:
         P.nufft_debug_fail_alloc(-1)
     f = P.nufft2_exec(P.nufft2_plan(xt, N, 1e-6, C64), ct)
     assert torch.equal(f, ref)
+    assert P.nufft_debug_set_buckets(P.nufft2_plan(xb, 1 << 13, 1e-6, C64, P.NUFFT_FLAG_NO_AUTOTUNE), True)
