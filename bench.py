@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def _fail_multi(n):
-    print("bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus %d)" % n,
+    print("bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus %d)" % n,
           file=sys.stderr)
     sys.exit(2)
 
@@ -470,7 +470,7 @@ def bench_2d(P, W, torch, dev):
     n, M = 1024, x.shape[0]
     flop = 5 * n * n * 10 * (K2 + K1 * K2) + 8 * M * K1 * K2
     peak = 157.3e12
-    peak_np = 78.6e12   # without packed FP32 instructions (this build disables them)
+    peak_np = 78.6e12   # without packed FP32 instructions (the kernels are compiled with them disabled)
     return {"Kx": plan.K, "forward_us": round(t_f * 1e3, 1), "adjoint_us": round(t_a * 1e3, 1),
             "type1_us": round(t_1 * 1e3, 1), "forward_pts_per_s": x.shape[0] / (t_f * 1e-3),
             "alu_roofline": {"alg_gflop": round(flop / 1e9, 2), "peak_tflops_fp32": 157.3,

@@ -47,7 +47,7 @@ typedef struct nufft_plan_s *nufft_plan_t;
 typedef enum {
     NUFFT_OK = 0,
     NUFFT_ERR_INVALID_ARG = 1,   /* bad size, pointer, eps or flag combination   */
-    NUFFT_ERR_UNSUPPORTED = 2,   /* valid request this build cannot serve (size, eps floor) */
+    NUFFT_ERR_UNSUPPORTED = 2,   /* valid request the library cannot serve (size, eps floor) */
     NUFFT_ERR_ALLOC = 3,         /* device or host allocation failed              */
     NUFFT_ERR_NONFINITE = 4,     /* a sample coordinate is NaN or infinite        */
     NUFFT_ERR_HIP = 5            /* a HIP runtime call failed                     */
