@@ -1219,15 +1219,16 @@ static hipError_t run_small_adj(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R>
 
 // Column lengths L2 = 3 * 2^k and 5 * 2^k of the oversampled grids between
 // powers of two (radix-3/5 stage, then power-of-two transforms of 64 to 512
-// points), with the columns per pass-A / pass-A' workgroup.
+// points), with the columns per pass-A / pass-A' workgroup in FP32 and FP64
+// (half as many in FP64, whose transforms hold twice the registers).
 #define MIXED_L2_SWITCH(MACRO) \
-    MACRO(192, 16)             \
-    MACRO(384, 16)             \
-    MACRO(768, 8)              \
-    MACRO(1536, 4)             \
-    MACRO(320, 16)             \
-    MACRO(640, 8)              \
-    MACRO(1280, 4)
+    MACRO(192, 16, 8)          \
+    MACRO(384, 16, 8)          \
+    MACRO(768, 8, 4)           \
+    MACRO(1536, 4, 2)          \
+    MACRO(320, 16, 8)          \
+    MACRO(640, 8, 4)           \
+    MACRO(1280, 4, 2)
 
 #define SMALL_SWITCH(MACRO) \
     switch (a.L) {          \
@@ -1432,10 +1433,10 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
             PA(1024, Cfg<R>::G1024)
             PA(2048, Cfg<R>::G2048)
 #undef PA
-#define PAM(LL, GG)                                                                                        \
+#define PAM(LL, GF, GD)                                                                                    \
     case LL:                                                                                               \
         if (a.half) return hipErrorInvalidValue;                                                           \
-        launch_pass_a<R, LL, GG, false, 16>(a, c, mode, s);                                                \
+        launch_pass_a<R, LL, sizeof(R) == 4 ? GF : GD, false, 16>(a, c, mode, s);                          \
         break;
             MIXED_L2_SWITCH(PAM)
 #undef PAM
@@ -1555,10 +1556,10 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
             PAA(1024, Cfg<R>::GA1024)
             PAA(2048, Cfg<R>::GA2048)
 #undef PAA
-#define PAAM(LL, GG)                                                                                       \
+#define PAAM(LL, GF, GD)                                                                                   \
     case LL:                                                                                               \
         if (a.half) return hipErrorInvalidValue;                                                           \
-        launch_pass_a_adj<R, LL, GG, DIR, false, 16>(a, f, s);                                             \
+        launch_pass_a_adj<R, LL, sizeof(R) == 4 ? GF : GD, DIR, false, 16>(a, f, s);                       \
         break;
             MIXED_L2_SWITCH(PAAM)
 #undef PAAM
