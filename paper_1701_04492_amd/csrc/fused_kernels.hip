@@ -501,6 +501,103 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     }
 }
 
+// Pass A with wide column blocks (FP32, full-precision exchange, L2 = 1024 or
+// 2048): G columns per workgroup with each thread transforming two of them
+// (columns g and g + G/2), so that the exchange is written in G*8-byte runs
+// (64 bytes at G = 8) at the register budget of G/2 columns.  Narrow runs
+// waste most of each DRAM burst: measured on this store pattern alone, 32-byte
+// runs reach 3.3 TB/s and 64-byte runs 5.7 TB/s.  The inter-pass twiddle of
+// output (k1, n2) is Bv[jb] * Av[ja] with n2 = n2_0 + (NT/G)(8 jb + ja): twelve
+// table values per thread instead of 32.
+template <typename R, int L2, int G, int FR = 16>
+__global__ void __launch_bounds__(G / 2 * L2 / 16)
+k_passA_wide(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, int mode,
+             const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
+             cx_t<R> *__restrict__ Y)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L2 / 16;
+    constexpr int GH = G / 2;            // columns per half
+    constexpr int NT = GH * TPF;
+    constexpr int P = fft_pitch_g(L2, G);
+    constexpr int ST = NT / G;           // rows between a thread's consecutive outputs
+    static_assert(fft_radix_p(L2) == 1 && NT % G == 0 && G * L2 == 32 * NT, "two halves of 16 elements");
+    __shared__ C buf[G * P];
+    __shared__ C tw_s[L2];
+    const int nrc = (K + RCA - 1) / RCA;
+    const int task = xcd_task((int)(L1 / G) * nrc);
+    if (task < 0) return;
+    const int cg = task / nrc, rc = task % nrc;
+    const int r_lo = rc * RCA, r_hi = min(K, r_lo + RCA);
+    load_tw_s<C, L2, -1, NT>(tw_s, tw_g);
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t k1_0 = (int64_t)cg * G;
+    const int64_t L = L1 * L2;
+    // the G x L2 block of c: G-wide rows, two rounds of 16 loads in flight
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        C cl[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + (h * 16 + e) * NT;
+            cl[e] = load_coef<R>(c, k1_0 + i % G + L1 * (int64_t)(i / G), N, mode);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + (h * 16 + e) * NT;
+            buf[(i % G) * P + lds_pad(i / G)] = cl[e];
+        }
+    }
+    __syncthreads();
+    C cv[2][16];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) cv[h][q] = buf[(g + h * GH) * P + lds_pad(lt + q * TPF)];
+    // twiddle factors of this thread's outputs: column gg = tid % G, rows n2_0 + ST e
+    const int gg = tid % G, n2_0 = tid / G;
+    const int64_t k1 = k1_0 + gg;
+    C Av[8], Bv[4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Av[j] = tw_big<C, -1>(hi, lo, (k1 * ST * j) % L);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bv[j] = tw_big<C, -1>(hi, lo, k1 * (n2_0 + 8 * ST * j));
+    const ZMap zm = zmap(N);
+    for (int r = r_lo; r < r_hi; ++r) {
+        __syncthreads();   // earlier readers of buf are done
+        // the sample coordinates are recomputed per rank: an empty asm makes the row
+        // index opaque, so the compiler keeps them out of registers across ranks
+        int lr = lt;
+        asm volatile("" : "+v"(lr));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            C v[16];
+            R wq[16], zk[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) zk[q] = zcoord<R>((k1_0 + g + h * GH) + L1 * (int64_t)(lr + q * TPF), zm);
+            cheb_v_many<R, 16>(r, zk, wq);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = cscale(cv[h][q], wq[q]);
+            block_fft_regs<C, L2, -1, fft_wave_sync<L2>, FR>(buf + (g + h * GH) * P, tw_s, lt, v);
+        }
+        __syncthreads();   // both halves' transforms are visible
+        // (opaque copies again: the 32 output addresses are formed here, not kept across ranks)
+        int n2o = n2_0, go = gg;
+        asm volatile("" : "+v"(n2o), "+v"(go));
+        C *Yr = Y + (int64_t)r * L + k1_0 + go;
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            C o[8];
+#pragma unroll
+            for (int ja = 0; ja < 8; ++ja) o[ja] = buf[go * P + lds_pad(n2o + ST * (8 * jb + ja))];
+#pragma unroll
+            for (int ja = 0; ja < 8; ++ja)
+                Yr[(int64_t)(n2o + ST * (8 * jb + ja)) * L1] = cmul(cmul(o[ja], Bv[jb]), Av[ja]);
+        }
+    }
+}
+
 // LDS bytes of the bucketed store of pass B's outputs (bucketed_store): bin
 // counts of up to 1024 buckets, wave sums, then NT*S values and their places.
 __host__ __device__ constexpr int bucket_scratch_bytes(int NT, int S, int vbytes)
@@ -1417,6 +1514,20 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     if constexpr (sizeof(R) == 4) {
         if (a.sched == 1) ok = tuned_pass_a<R, 1, 8>(a, c, mode, s);          // 8 x 16 x ... column FFTs
         else if (a.sched == 2) ok = tuned_pass_a<R, 2, 16>(a, c, mode, s);    // half the columns per workgroup
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (!ok && !a.half && (a.L2 == 1024 || a.L2 == 2048)) {
+            const int G = a.L2 == 2048 ? 8 : 16;
+            const int ncg = a.L1 / G, rca = pass_a_ranks(a.fac.K, ncg);
+            const int T = ncg * ((a.fac.K + rca - 1) / rca);
+            if (a.L2 == 2048)
+                hipLaunchKernelGGL((k_passA_wide<R, 2048, 8>), dim3(xcd_grid(T)), dim3(4 * 128), 0, s, c, a.N,
+                                   (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);
+            else
+                hipLaunchKernelGGL((k_passA_wide<R, 1024, 16>), dim3(xcd_grid(T)), dim3(8 * 64), 0, s, c, a.N,
+                                   (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);
+            ok = true;
+        }
     }
     if (!ok) {
         switch (a.L2) {
