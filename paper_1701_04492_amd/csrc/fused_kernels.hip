@@ -1121,6 +1121,77 @@ k_sum_split_rows(const cx_t<R> *__restrict__ Zp, int splits, int K, int L1, int6
     }
 }
 
+// Pass A' with wide column blocks (FP32, full-precision exchange, L2 = 1024 or
+// 2048): G columns per workgroup, each thread transforming two of them, so
+// that the intermediate is read in G*8-byte runs (64 bytes at G = 8; a
+// 16-byte-run read of the same block measured 2.3 TB/s against 4.1 TB/s at
+// 64 bytes).  The rank's block goes to LDS in two rounds of sixteen loads per
+// thread (no register prefetch: the accumulators of 32 outputs hold the
+// registers); outputs (k1, n2) with k1 = tid mod G accumulate in registers.
+template <typename R, int L2, int G, int DIR, int FR = 16>
+__global__ void __launch_bounds__(G / 2 * L2 / 16)
+k_passA_adj_wide(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const cx_t<R> *__restrict__ tw_g,
+                 cx_t<R> *__restrict__ out)
+{
+    using C = cx_t<R>;
+    constexpr int TPF = L2 / 16;
+    constexpr int GH = G / 2;
+    constexpr int NT = GH * TPF;
+    constexpr int P = fft_pitch_g(L2, G);
+    constexpr int ST = NT / G;
+    static_assert(fft_radix_p(L2) == 1 && NT % G == 0 && G * L2 == 32 * NT, "two halves of 16 elements");
+    __shared__ C buf[G * P];
+    __shared__ C tw_s[L2];
+    const int task = xcd_task((int)(L1 / G));
+    if (task < 0) return;
+    load_tw_s<C, L2, -1, NT>(tw_s, tw_g);   // tw_g already has the sign DIR
+    const int tid = threadIdx.x;
+    const int g = tid / TPF, lt = tid % TPF;
+    const int64_t k1_0 = (int64_t)task * G;
+    const int64_t L = L1 * L2;
+    const ZMap zm = zmap(N);
+    const int gg = tid % G, n2_0 = tid / G;
+    C acc[32];
+#pragma unroll
+    for (int e = 0; e < 32; ++e) acc[e] = cmake<C>(0, 0);
+    for (int r = 0; r < K; ++r) {
+        __syncthreads();   // the previous rank's readers of buf are done
+        // (an opaque copy of the thread index: the 32 load and LDS addresses are
+        // formed per rank instead of being kept in registers across ranks)
+        int ti = tid;
+        asm volatile("" : "+v"(ti));
+        const C *Zr = Z + (int64_t)r * L + k1_0 + ti % G + (int64_t)(ti / G) * L1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            C cl[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) cl[e] = Zr[(int64_t)((h * 16 + e) * ST) * L1];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) buf[(ti % G) * P + lds_pad(ti / G + (h * 16 + e) * ST)] = cl[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) block_fft_lds<C, L2, DIR, fft_wave_sync<L2>, FR>(buf + (g + h * GH) * P, tw_s, lt);
+        __syncthreads();   // every transform is visible
+        const int n2o = ti / G, go = ti % G;
+#pragma unroll
+        for (int h = 0; h < 32; h += 8) {
+            R zq[8], wq[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) zq[e] = zcoord<R>(k1_0 + go + L1 * (int64_t)(n2o + ST * (h + e)), zm);
+            cheb_v_many<R, 8>(r, zq, wq);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                acc[h + e] = cadd(acc[h + e], cscale(buf[go * P + lds_pad(n2o + ST * (h + e))], wq[e]));
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) {
+        const int64_t k = k1_0 + gg + L1 * (int64_t)(n2_0 + ST * e);
+        if (k < N) out[k] = acc[e];
+    }
+}
+
 // Pass A' of type I / adjoint.  Task = G adjacent columns k1.  For each r the
 // columns Z_r[:][k1] (the next rank's block is loaded into registers while
 // this one is transformed) are transformed along n2 -> k2 and accumulated
@@ -1651,6 +1722,18 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
     if constexpr (sizeof(R) == 4) {
         if (a.sched == 1) ok = tuned_pass_a_adj<R, DIR, 1, 8>(a, f, s);
         else if (a.sched == 2) ok = tuned_pass_a_adj<R, DIR, 2, 16>(a, f, s);
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (!ok && !a.half && (a.L2 == 1024 || a.L2 == 2048)) {
+            const cx_t<R> *tw = DIR < 0 ? a.tw2 : a.tw2i;
+            if (a.L2 == 2048)
+                hipLaunchKernelGGL((k_passA_adj_wide<R, 2048, 8, DIR>), dim3(xcd_grid(a.L1 / 8)), dim3(4 * 128), 0, s,
+                                   (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, tw, f);
+            else
+                hipLaunchKernelGGL((k_passA_adj_wide<R, 1024, 16, DIR>), dim3(xcd_grid(a.L1 / 16)), dim3(8 * 64), 0,
+                                   s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, tw, f);
+            ok = true;
+        }
     }
     if (!ok) {
         switch (a.L2) {
