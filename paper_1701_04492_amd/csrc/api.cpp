@@ -361,8 +361,10 @@ nufft_status build_1d(Plan *p, const double *x, hipStream_t s)
         if (!p->Y || !p->sinv || !p->gsort) return NUFFT_ERR_ALLOC;
         NUFFT_HIP_CHECK(launch_invert_perm(p->perm, M, p->sinv, s));
         // Destination buckets for the permutations between sample order and sorted
-        // order (large plans): blocks of 2^14 samples (2^13 in FP64), 16 to 1024 of them.
-        const int bshift = sizeof(R) == 4 ? 14 : 13;
+        // order (large plans): about 256 blocks (one per CU for the layout passes)
+        // of 2^12 to 2^14 samples (at most 2^13 in FP64), 16 to 1024 of them.
+        int bshift = 12;
+        while (bshift < (sizeof(R) == 4 ? 14 : 13) && (M >> bshift) > 256) ++bshift;
         const int64_t nbk = (M + (int64_t(1) << bshift) - 1) >> bshift;
         if (nbk >= 16 && nbk <= 1024) {
             p->bshift = bshift;

@@ -323,30 +323,31 @@ k_bucket_to_sorted(const T *__restrict__ in, const int32_t *__restrict__ bdst, i
     }
 }
 
+// Launches KERNEL<T, BS> over the plan's blocks for its block size BS = 2^bshift
+// (2^12 to 2^14 samples; 2^12 and 2^13 for 16-byte values, whose LDS copy of
+// a block would not fit at 2^14).
+#define BUCKET_LAUNCH(KERNEL, T, a, s, ...)                                                              \
+    do {                                                                                                 \
+        const unsigned nbk_ = (unsigned)(((a).M + (int64_t(1) << (a).bshift) - 1) >> (a).bshift);      \
+        if ((a).bshift == 12)                                                                            \
+            hipLaunchKernelGGL((KERNEL<T, 4096>), dim3(nbk_), dim3(1024), 0, s, __VA_ARGS__);           \
+        else if ((a).bshift == 13)                                                                       \
+            hipLaunchKernelGGL((KERNEL<T, 8192>), dim3(nbk_), dim3(1024), 0, s, __VA_ARGS__);           \
+        else if constexpr (sizeof(T) <= 8) {                                                             \
+            if ((a).bshift == 14)                                                                        \
+                hipLaunchKernelGGL((KERNEL<T, 16384>), dim3(nbk_), dim3(1024), 0, s, __VA_ARGS__);      \
+            else                                                                                         \
+                return hipErrorInvalidValue;                                                             \
+        } else                                                                                           \
+            return hipErrorInvalidValue;                                                                 \
+    } while (0)
+
 // Bucketed outputs (values of type T at the places of the plan's layout) to sample order.
-template <typename T, typename R>
-static hipError_t bucket_to_samples_bs(const FusedArgs<R> &a, const T *in, T *out, hipStream_t s)
-{
-    const unsigned nbk = (unsigned)((a.M + (int64_t(1) << a.bshift) - 1) >> a.bshift);
-    if (a.bshift == 14)
-        hipLaunchKernelGGL((k_bucket_to_samples<T, 16384>), dim3(nbk), dim3(1024), 0, s, in, a.lidx, a.M, out);
-    else if (a.bshift == 13)
-        hipLaunchKernelGGL((k_bucket_to_samples<T, 8192>), dim3(nbk), dim3(1024), 0, s, in, a.lidx, a.M, out);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
-}
 template <typename T, typename R>
 static hipError_t bucket_to_samples(const FusedArgs<R> &a, const T *in, T *out, hipStream_t s)
 {
-    if constexpr (sizeof(T) == 16) {   // complex128: buckets of 2^13 (128 KB of LDS)
-        if (a.bshift != 13) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_bucket_to_samples<T, 8192>), dim3((unsigned)((a.M + 8191) >> 13)), dim3(1024), 0, s, in,
-                           a.lidx, a.M, out);
-        return hipGetLastError();
-    } else {
-        return bucket_to_samples_bs<T, R>(a, in, out, s);
-    }
+    BUCKET_LAUNCH(k_bucket_to_samples, T, a, s, in, a.lidx, a.M, out);
+    return hipGetLastError();
 }
 
 template <typename R>
@@ -357,15 +358,7 @@ hipError_t fused_sort_input(const FusedArgs<R> &a, const cx_t<R> *in, const char
     if (a.bdst) {
         // sample order -> bucketed layout (coalesced through LDS) -> sorted order (coalesced runs)
         const int nbk = (int)((a.M + (int64_t(1) << a.bshift) - 1) >> a.bshift);
-        if constexpr (sizeof(R) == 4) {
-            if (a.bshift != 14) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_samples_to_bucket<C, 16384>), dim3((unsigned)nbk), dim3(1024), 0, s, in, a.lidx, a.M,
-                               (C *)a.bbuf);
-        } else {
-            if (a.bshift != 13) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_samples_to_bucket<C, 8192>), dim3((unsigned)nbk), dim3(1024), 0, s, in, a.lidx, a.M,
-                               (C *)a.bbuf);
-        }
+        BUCKET_LAUNCH(k_samples_to_bucket, C, a, s, in, a.lidx, a.M, (C *)a.bbuf);
         constexpr int RNG = sizeof(R) == 4 ? 4096 : 2048;
         hipLaunchKernelGGL((k_bucket_to_sorted<C, RNG, 512>), dim3((unsigned)((a.M + RNG - 1) / RNG)), dim3(512), 0, s,
                            (const C *)a.bbuf, a.bdst, a.M, a.bshift, nbk, a.gsort);
@@ -501,8 +494,8 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     }
 }
 
-// Pass A with wide column blocks (FP32, full-precision exchange, L2 = 1024 or
-// 2048): G columns per workgroup with each thread transforming two of them
+// Pass A with wide column blocks (FP32, full-precision exchange; launched at
+// L2 = 2048, see WIDE_A): G columns per workgroup with each thread transforming two of them
 // (columns g and g + G/2), so that the exchange is written in G*8-byte runs
 // (64 bytes at G = 8) at the register budget of G/2 columns.  Narrow runs
 // waste most of each DRAM burst: measured on this store pattern alone, 32-byte
@@ -1121,8 +1114,15 @@ k_sum_split_rows(const cx_t<R> *__restrict__ Zp, int splits, int K, int L1, int6
     }
 }
 
-// Pass A' with wide column blocks (FP32, full-precision exchange, L2 = 1024 or
-// 2048): G columns per workgroup, each thread transforming two of them, so
+// Where the wide column blocks run (FP32 plans with the full-precision exchange
+// and the default schedule): columns of 2048 points (at 1024 points the narrow
+// pass A measured faster, 35 against 40 us at 2^20); pass A' also needs
+// L1/G >= 256 column groups, since it cannot split its ranks over workgroups
+// (at 2^20, 64 wide workgroups took 101 us against 47 us for the narrow kernel).
+#define WIDE_A(L1, L2) ((L2) == 2048)
+#define WIDE_A_ADJ(L1, L2) ((L2) == 2048 && (L1) / 8 >= 256)
+// Pass A' with wide column blocks (FP32, full-precision exchange; launched at
+// L2 = 2048 with at least 256 column groups, see WIDE_A_ADJ): G columns per workgroup, each thread transforming two of them, so
 // that the intermediate is read in G*8-byte runs (64 bytes at G = 8; a
 // 16-byte-run read of the same block measured 2.3 TB/s against 4.1 TB/s at
 // 64 bytes).  The rank's block goes to LDS in two rounds of sixteen loads per
@@ -1587,16 +1587,11 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
         else if (a.sched == 2) ok = tuned_pass_a<R, 2, 16>(a, c, mode, s);    // half the columns per workgroup
     }
     if constexpr (sizeof(R) == 4) {
-        if (!ok && !a.half && (a.L2 == 1024 || a.L2 == 2048)) {
-            const int G = a.L2 == 2048 ? 8 : 16;
-            const int ncg = a.L1 / G, rca = pass_a_ranks(a.fac.K, ncg);
+        if (!ok && !a.half && WIDE_A(a.L1, a.L2)) {   // L2 = 2048: eight columns per workgroup
+            const int ncg = a.L1 / 8, rca = pass_a_ranks(a.fac.K, ncg);
             const int T = ncg * ((a.fac.K + rca - 1) / rca);
-            if (a.L2 == 2048)
-                hipLaunchKernelGGL((k_passA_wide<R, 2048, 8>), dim3(xcd_grid(T)), dim3(4 * 128), 0, s, c, a.N,
-                                   (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);
-            else
-                hipLaunchKernelGGL((k_passA_wide<R, 1024, 16>), dim3(xcd_grid(T)), dim3(8 * 64), 0, s, c, a.N,
-                                   (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);
+            hipLaunchKernelGGL((k_passA_wide<R, 2048, 8>), dim3(xcd_grid(T)), dim3(4 * 128), 0, s, c, a.N,
+                               (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);
             ok = true;
         }
     }
@@ -1724,14 +1719,10 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         else if (a.sched == 2) ok = tuned_pass_a_adj<R, DIR, 2, 16>(a, f, s);
     }
     if constexpr (sizeof(R) == 4) {
-        if (!ok && !a.half && (a.L2 == 1024 || a.L2 == 2048)) {
+        if (!ok && !a.half && WIDE_A_ADJ(a.L1, a.L2)) {   // L2 = 2048: eight columns per workgroup
             const cx_t<R> *tw = DIR < 0 ? a.tw2 : a.tw2i;
-            if (a.L2 == 2048)
-                hipLaunchKernelGGL((k_passA_adj_wide<R, 2048, 8, DIR>), dim3(xcd_grid(a.L1 / 8)), dim3(4 * 128), 0, s,
-                                   (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, tw, f);
-            else
-                hipLaunchKernelGGL((k_passA_adj_wide<R, 1024, 16, DIR>), dim3(xcd_grid(a.L1 / 16)), dim3(8 * 64), 0,
-                                   s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, tw, f);
+            hipLaunchKernelGGL((k_passA_adj_wide<R, 2048, 8, DIR>), dim3(xcd_grid(a.L1 / 8)), dim3(4 * 128), 0, s,
+                               (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, tw, f);
             ok = true;
         }
     }

@@ -20,7 +20,16 @@ P = pytest.importorskip("paper_1701_04492_amd")
 DEV = torch.device("cuda:0")
 C64, C128 = torch.complex64, torch.complex128
 EPS = {C64: 1e-6, C128: 1e-12}
-BLOCK = {C64: 1 << 14, C128: 1 << 13}   # samples per destination block
+
+
+def _has_layout(M, dtype):
+    """The plan's rule: blocks of 2^12 to 2^14 samples (2^13 in FP64), about 256 of them,
+    and the layout only for 16 to 1024 blocks."""
+    top = 14 if dtype == C64 else 13
+    b = 12
+    while b < top and (M >> b) > 256:
+        b += 1
+    return 16 <= (M + (1 << b) - 1) >> b <= 1024
 
 
 def _t(a, dtype):
@@ -35,14 +44,17 @@ def _run(plan, ct, gt):
     return f, gc, gx, t1
 
 
-# (dtype, N, M): below the 16-block threshold (no layout), a ragged last block,
-# many samples per output tile, and the full 2^22 size
+# (dtype, N, M): below the 16-block threshold (no layout), 16 blocks with a ragged
+# last one, blocks of 2^12, 2^13 and 2^14 samples, many samples per output tile, and
+# the full 2^22 size
 CASES = [
-    (C64, 20000, 15 * (1 << 14)),
+    (C64, 20000, 15 * (1 << 12)),
+    (C64, 1 << 16, 15 * (1 << 12) + 1),
     (C64, 1 << 18, 16 * (1 << 14) + 777),
     (C64, 1 << 12, 1 << 20),
+    (C64, 1 << 20, 1 << 21),
     (C64, 1 << 22, 1 << 22),
-    (C128, 3000, 15 * (1 << 13)),
+    (C128, 3000, 15 * (1 << 12)),
     (C128, 1 << 17, 16 * (1 << 13) + 5),
     (C128, 1 << 21, 1 << 21),
 ]
@@ -57,7 +69,8 @@ def test_bucketed_equals_direct(dtype, N, M):
     ct, gt = _t(c, dtype), _t(g, dtype)
     plan = P.nufft2_plan(_t(x, torch.float64), N, EPS[dtype], dtype)
     has = P.nufft_debug_set_buckets(plan, True)
-    assert has == (M > 15 * BLOCK[dtype])
+    # (only two-pass plans, grids above 4096 points, permute their outputs)
+    assert has == (plan.grid > 4096 and _has_layout(M, dtype)), (plan.grid, has)
     _, nsched = P.nufft_plan_tuning(plan)
     for sched in range(nsched):
         P.nufft_debug_set_schedule(plan, sched)
