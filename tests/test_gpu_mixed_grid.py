@@ -123,3 +123,30 @@ def test_mixed_grid_bucketed_graph_replay():
         graph.replay()
         torch.cuda.synchronize()
         assert all(torch.equal(a, b) for a, b in zip((f, gc, gx), ref)), rep
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+@pytest.mark.parametrize("M", [1, 7, 1000])
+def test_mixed_grid_edge_cases(dtype, M):
+    """N = L on a 3 * 2^k grid (gamma up to 1/2), tiny sample counts, and samples on the
+    edges of the period (0, just below 1, negative and beyond 1, the wrap sample s = L):
+    every row and mode against the direct sums."""
+    N = grid = 24576
+    rng = W.rng_for(98)
+    x = rng.random(M) * 1.5 - 0.25
+    edges = np.array([0.0, 1.0 - 1e-12, -0.25, 1.25, (grid - 0.5) / grid, 0.5 / grid, 1.0 / 3.0])
+    x[:min(M, edges.size)] = edges[:min(M, edges.size)]
+    c, g = W.complex_normal(rng, N), W.complex_normal(rng, M)
+    eps = EPS[dtype]
+    plan = P.nufft2_plan(_t(x, torch.float64), N, eps, dtype, grid=grid)
+    assert plan.grid == grid
+    ct, gt = _t(c, dtype), _t(g, dtype)
+    cc, gg = ct.cpu().numpy().astype(np.complex128), gt.cpu().numpy().astype(np.complex128)
+    f = P.nufft2_exec(plan, ct).cpu().numpy()
+    a = P.nufft1_exec(plan, gt, sign=+1).cpu().numpy()
+    t1 = P.nufft1_exec(plan, gt, sign=-1).cpu().numpy()
+    err_f = np.abs(f - D.nudft2(x, cc)).max() / np.abs(cc).sum()
+    err_a = np.abs(a - D.nudft1(x, gg, N, sign=+1)).max() / np.abs(gg).sum()
+    err_1 = np.abs(t1 - D.nudft1(x, gg, N, sign=-1)).max() / np.abs(gg).sum()
+    print("   M=%d K=%d type II %.2e adjoint %.2e type I %.2e" % (M, plan.K, err_f, err_a, err_1), flush=True)
+    assert err_f <= 4 * eps and err_a <= 4 * eps and err_1 <= 4 * eps
