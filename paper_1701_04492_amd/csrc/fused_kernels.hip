@@ -780,13 +780,19 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
 // Pass B' of type I / adjoint.  Task = tile n2.  The tile's samples are
 // staged once in LDS as exp(DIR i pi X_j) c_j, z_j = X_j / gamma and their
 // grid point n1 (up to SCAP of them; any further ones are read from global
-// memory).  For each chunk of RC ranks, thread t owns the contiguous grid
-// points [t*GPT, (t+1)*GPT), GPT = L1/NT: their samples are one contiguous
-// run of the sorted order, which the thread walks once, summing
-// P_r(z_j) exp(DIR i pi X_j) c_j for every rank of the chunk in fixed order
-// and storing each grid value (times i^r for type I, i^-r for the adjoint)
-// when the grid point changes.  The RC grids are then transformed along n1
-// and multiplied by exp(DIR 2 pi i n2 k1 / L): Z_r[n2][k1].
+// memory).  Thread t walks one contiguous run of the sorted order: the
+// samples from t*cnt/NT to (t+1)*cnt/NT, both ends moved forward to the next
+// grid-point boundary, so that every grid point's samples belong to one run
+// and the runs are about equally long whatever the points' occupancy.  For
+// each chunk of RC ranks the walk sums P_r(z_j) exp(DIR i pi X_j) c_j for
+// every rank of the chunk in sample order and stores each grid value when
+// the grid point changes; the factor i^r (type I) or i^-r (adjoint) is
+// taken into the sum, as a sign on the polynomial and, for odd powers, a
+// swap of the components (exact, so the stored value is the rotated sum).
+// Grid points without samples stay zero: the grids are cleared once, and
+// each output read clears the value it has read.  The RC grids are then
+// transformed along n1 and multiplied by exp(DIR 2 pi i n2 k1 / L):
+// Z_r[n2][k1].
 // TWG: read the FFT twiddles (already of sign DIR) from global memory instead
 // of an LDS copy, for the sizes where LDS would otherwise cap occupancy.
 // H (FP32 only): Z in fp16 pairs with one scale exponent per (rank, row),
@@ -801,17 +807,41 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
     using C = cx_t<R>;
     constexpr int TPF = L1 / 16;
     constexpr int NT = RC * TPF;
-    constexpr int GPT = L1 / NT;          // grid points per thread in the spread phase
     constexpr int P = fft_pitch(L1);
     __shared__ C buf[RC * P];
     __shared__ C tw_s[TWG ? 1 : L1];
     const C *tw = TWG ? tw_g : tw_s;
-    __shared__ C sval[SCAP];
-    __shared__ R sz[SCAP];
-    __shared__ unsigned short spos[SCAP];
+    // staged samples: in FP32 one 16-byte record (value, z, grid point) each,
+    // which the walk reads in one access; in FP64 three arrays
+    constexpr bool REC = sizeof(R) == 4;
+    __shared__ float4 srec[REC ? SCAP : 1];
+    __shared__ C sval[REC ? 1 : SCAP];
+    __shared__ R sz[REC ? 1 : SCAP];
+    __shared__ unsigned short spos[REC ? 1 : SCAP];
     __shared__ int soff[L1 + 1];
     __shared__ unsigned smax[H ? 2 * RC : 1];   // per-row block maxima (float bits), two parities
     static_assert(!H || sizeof(R) == 4, "the half-precision exchange is an FP32 path");
+    auto put_s = [&](int i, const C &v, R z, int n1) __attribute__((always_inline)) {
+        if constexpr (REC) {
+            srec[i] = make_float4(v.x, v.y, z, __int_as_float(n1));
+        } else {
+            sval[i] = v;
+            sz[i] = z;
+            spos[i] = (unsigned short)n1;
+        }
+    };
+    auto get_s = [&](int i, C &v, R &z, int &n1) __attribute__((always_inline)) {
+        if constexpr (REC) {
+            const float4 t = srec[i];
+            v = cmake<C>(t.x, t.y);
+            z = t.z;
+            n1 = __float_as_int(t.w);
+        } else {
+            v = sval[i];
+            z = sz[i];
+            n1 = spos[i];
+        }
+    };
     const int task = xcd_task((int)L2);
     if (task < 0) return;
     const int tid = threadIdx.x;
@@ -855,13 +885,13 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
                 if (i < nst) {
                     R sn, cs;
                     sincospi_r(xv[u], &sn, &cs);
-                    sval[i] = cmul(cmake<C>(cs, dir * sn), cj[u]);
-                    sz[i] = xv[u] * fac.inv_gamma;
-                    spos[i] = (unsigned short)(kv[u] & (uint32_t)(L1 - 1));
+                    put_s(i, cmul(cmake<C>(cs, dir * sn), cj[u]), xv[u] * fac.inv_gamma,
+                          (int)(kv[u] & (uint32_t)(L1 - 1)));
                 }
             }
         }
     }
+    for (int i = tid; i < RC * P; i += NT) buf[i] = cmake<C>(0, 0);
     // inter-pass twiddles of this thread's 16 grid points k1 (the same for every rank)
     C wt[16];
 #pragma unroll
@@ -870,21 +900,41 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
         wt[q] = dir > 0 ? cconj(w) : w;
     }
     __syncthreads();
-    const int n_lo = tid * GPT;
+    // this thread's run [i0, i1): the balanced split points moved to the next
+    // grid-point boundary (soff[n + 1] is the first sample after point n)
+    auto snap = [&](int b) __attribute__((always_inline)) {
+        if (b <= 0 || b >= cnt) return b;
+        int n1;
+        if (b - 1 < SCAP) {
+            C v;
+            R z;
+            get_s(b - 1, v, z, n1);
+        } else {
+            n1 = (int)(keys[tile_lo + b - 1] & (uint32_t)(L1 - 1));
+        }
+        return soff[n1 + 1];
+    };
+    const int i0 = snap((int)((int64_t)tid * cnt / NT)), i1 = snap((int)((int64_t)(tid + 1) * cnt / NT));
     for (int r0 = 0; r0 < fac.K; r0 += RC) {
         const int nr = min(RC, fac.K - r0);
-        // spread: zero this thread's grid points, then one walk over their samples
-#pragma unroll
-        for (int gg = 0; gg < RC; ++gg)
-#pragma unroll
-            for (int q = 0; q < GPT; ++q) buf[gg * P + lds_pad(n_lo + q)] = cmake<C>(0, 0);
-        const int i0 = soff[n_lo], i1 = soff[n_lo + GPT];
         C a[RC];
 #pragma unroll
         for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
+        // rank r0 + gg with the factor i^q, q = -dir (r0 + gg), split as
+        // (-1)^(q >> 1) on the coefficients and i^(q & 1), q & 1 = the rank's parity
+        // (known at compile time when RC is even: r0 is then even)
         RankPoly<R> up[RC];
+        bool odd[RC];
 #pragma unroll
-        for (int gg = 0; gg < RC; ++gg) up[gg] = rank_poly(fac, min(r0 + gg, fac.K - 1));
+        for (int gg = 0; gg < RC; ++gg) {
+            const int r = min(r0 + gg, fac.K - 1);
+            up[gg] = rank_poly(fac, r);
+            odd[gg] = RC % 2 == 0 ? (gg & 1) != 0 : (r & 1) != 0;
+            if (((-dir * r) >> 1) & 1) {
+#pragma unroll
+                for (int m = 0; m < rank_terms<R>; ++m) up[gg].c[m] = -up[gg].c[m];
+            }
+        }
         int ncur = -1;
         // one sample of the walk: store the finished grid value when the grid
         // point changes, then add this sample's terms
@@ -893,15 +943,27 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
                 if (ncur >= 0) {
 #pragma unroll
                     for (int gg = 0; gg < RC; ++gg)
-                        if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -dir * (r0 + gg));
+                        if (gg < nr) buf[gg * P + lds_pad(ncur)] = a[gg];
                 }
 #pragma unroll
                 for (int gg = 0; gg < RC; ++gg) a[gg] = cmake<C>(0, 0);
                 ncur = n1;
             }
+            const R w = z * z;
 #pragma unroll
-            for (int gg = 0; gg < RC; ++gg)
-                if (gg < nr) a[gg] = cadd(a[gg], cscale(val, rank_eval(up[gg], z)));
+            for (int gg = 0; gg < RC; ++gg) {
+                if (gg < nr) {
+                    R p = up[gg].c[rank_terms<R> - 1];
+#pragma unroll
+                    for (int m = rank_terms<R> - 2; m >= 0; --m) p = p * w + up[gg].c[m];
+                    if (odd[gg]) {
+                        p = p * z;
+                        a[gg] = cmake<C>(a[gg].x - val.y * p, a[gg].y + val.x * p);
+                    } else {
+                        a[gg] = cmake<C>(a[gg].x + val.x * p, a[gg].y + val.y * p);
+                    }
+                }
+            }
         };
         if (i1 <= SCAP) {
             // the whole slice is staged: its LDS reads go out four samples at a time
@@ -910,12 +972,7 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
                 R zz[4];
                 int nn[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = min(i + u, i1 - 1);
-                    vv[u] = sval[j];
-                    zz[u] = sz[j];
-                    nn[u] = spos[j];
-                }
+                for (int u = 0; u < 4; ++u) get_s(min(i + u, i1 - 1), vv[u], zz[u], nn[u]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     if (i + u < i1) step(vv[u], zz[u], nn[u]);
@@ -923,7 +980,11 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
         } else {
             for (int i = i0; i < i1; ++i) {
                 if (i < SCAP) {
-                    step(sval[i], sz[i], spos[i]);
+                    C v;
+                    R z;
+                    int n1;
+                    get_s(i, v, z, n1);
+                    step(v, z, n1);
                 } else {
                     const R Xi = Xs[tile_lo + i];
                     R sn, cs;
@@ -936,18 +997,21 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
         if (ncur >= 0) {
 #pragma unroll
             for (int gg = 0; gg < RC; ++gg)
-                if (gg < nr) buf[gg * P + lds_pad(ncur)] = crot(a[gg], -dir * (r0 + gg));
+                if (gg < nr) buf[gg * P + lds_pad(ncur)] = a[gg];
         }
         __syncthreads();
         block_fft_lds<C, L1, dir, fft_wave_sync<L1>, FR>(buf + g * P, tw, lt);   // each thread then reads only its own transform
         const int r = r0 + g;
+        const bool more = r0 + RC < fac.K;   // a later chunk spreads into buf: clear what is read
         if constexpr (H) {
             // row g's block maximum over its TPF threads (whole waves when TPF >= 64)
             C o[16];
             float m = 0.0f;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                o[q] = cmul(buf[g * P + lds_pad(lt + q * TPF)], wt[q]);
+                C &b = buf[g * P + lds_pad(lt + q * TPF)];
+                o[q] = cmul(b, wt[q]);
+                if (more) b = cmake<C>(0, 0);
                 m = fmaxf(m, cmaxabs(o[q]));
             }
             m = wave_max_group(m, TPF);
@@ -962,12 +1026,15 @@ k_passB_adj(const cx_t<R> *__restrict__ csort, int64_t L2, const R *__restrict__
                 for (int q = 0; q < 16; ++q) Zr[lt + q * TPF] = hx_pack(o[q], ex);
                 if (lt == 0) E[(int64_t)r * L2 + n2] = (int8_t)ex;
             }
-        } else if (r < fac.K) {
+        } else {
             C *Zr = Z + (int64_t)r * L + n2 * L1;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int k1 = lt + q * TPF;
-                Zr[k1] = cmul(buf[g * P + lds_pad(k1)], wt[q]);
+                C &b = buf[g * P + lds_pad(k1)];
+                const C v = b;
+                if (more) b = cmake<C>(0, 0);
+                if (r < fac.K) Zr[k1] = cmul(v, wt[q]);
             }
         }
         __syncthreads();   // the next chunk overwrites buf
