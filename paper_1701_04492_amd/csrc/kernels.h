@@ -57,6 +57,19 @@ __device__ __forceinline__ R rank_eval(const RankPoly<R> &p, R z)
     return p.odd ? acc * z : acc;
 }
 
+// rank_eval with the rank's parity given by the caller (a compile-time
+// constant where the caller's rank index is, as for the ranks of an unrolled
+// chunk that starts at an even rank)
+template <typename R>
+__device__ __forceinline__ R rank_eval_par(const RankPoly<R> &p, R z, bool odd)
+{
+    const R w = z * z;
+    R acc = p.c[rank_terms<R> - 1];
+#pragma unroll
+    for (int m = rank_terms<R> - 2; m >= 0; --m) acc = acc * w + p.c[m];
+    return odd ? acc * z : acc;
+}
+
 // Same polynomial from a coefficient table staged in LDS: for kernels where the
 // rank differs between the lanes of a wave (a per-lane index into the
 // kernel-argument table would turn every coefficient into a vector load).

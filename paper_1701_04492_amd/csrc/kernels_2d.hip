@@ -381,13 +381,17 @@ k_2d_passB_adj(const cx_t<R> *__restrict__ gin, int64_t N1, int64_t GY, const in
                 C w;   // exp(DIR i pi (Xx + Xy)) g_j P^y_r2(zy_j)
                 R zx;
             };
+            // the factor i^(r1 + r2) (type I) or i^-(r1 + r2) (adjoint), r1 = r0 + gg:
+            // the part of r0 + r2 is applied once per sample, that of gg (a
+            // compile-time index in the unrolled chunk) per rank
             auto load = [&](int i) -> Sample {
                 const Staged t = sst[i];
-                return Sample{(int)spos[i], cscale(cmake<C>(t.re, t.im), rank_eval(uy, t.zy)), t.zx};
+                return Sample{(int)spos[i], crot(cscale(cmake<C>(t.re, t.im), rank_eval(uy, t.zy)), -DIR * (r0 + r2)),
+                              t.zx};
             };
             auto contrib = [&](const Sample &sm, int gg) -> C {
-                // i^(r1 + r2) for the type I, i^-(r1 + r2) for the adjoint
-                return crot(cscale(sm.w, rank_eval(ux[gg], sm.zx)), -DIR * (r0 + gg + r2));
+                const bool odd = RC % 2 == 0 ? (gg & 1) != 0 : ((r0 + gg) & 1) != 0;
+                return crot(cscale(sm.w, rank_eval_par(ux[gg], sm.zx, odd)), -DIR * gg);
             };
             seg_spread<C, RC, NT>(cnt, nr, pos, load, contrib, buf, P, hv, tv, hix, tix, nxa, nxb);
             __syncthreads();

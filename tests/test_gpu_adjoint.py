@@ -284,3 +284,28 @@ def test_backward_graph_replay(dtype):
         torch.cuda.synchronize()
         assert torch.equal(gc, gc_ref), rep
         assert torch.equal(gx, gx_ref), rep
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_uneven_tiles(dtype, sign):
+    """Tiles the per-tile walk of pass B' splits unevenly: one grid point holding 3000
+    samples (more than a tile stages in LDS, so the rest of its run is read from
+    global memory), 400 points holding 5 copies each, a tile with one sample, long
+    stretches of empty tiles and a dense band.  Sampled k against the oracle, and a
+    second call gives the same bits."""
+    rng = W.rng_for(37)
+    x = np.concatenate([
+        rng.random(20000) * 0.3,
+        np.full(3000, 0.1234567),
+        np.repeat(0.3 + rng.random(400) * 0.1, 5),
+        [0.7],
+        0.75 + rng.random(15000) * 0.05,
+    ])
+    x = x[rng.permutation(x.shape[0])]
+    N = 1 << 15
+    g = W.complex_normal(rng, x.shape[0])
+    kq = np.unique(np.concatenate([rng.choice(N, 48, replace=False), [0, 1, N // 2, N - 1]]))
+    plan, out, _ = check_type1(x, g, N, dtype, sign, kq=kq, label="uneven tiles")
+    again = P.nufft1_exec(plan, _t(g, dtype), sign=sign).cpu().numpy()
+    assert np.array_equal(out, again)
