@@ -164,6 +164,20 @@ __device__ __forceinline__ int xcd_task(int T)
 
 static inline unsigned xcd_grid(int T) { return (unsigned)(8 * ((T + 7) / 8)); }
 
+// The same mapping for a grid of fewer blocks than tasks (a multiple of 8,
+// W = gridDim.x / 8 per XCD): block b takes the tasks first, first + step, ...
+// below end of its XCD's share, first = (b & 7) * ceil(T / 8) + (b >> 3),
+// step = W.  With the grid xcd_grid(T) every block takes the task xcd_task gives.
+__device__ __forceinline__ void xcd_tasks(int T, int *first, int *end, int *step)
+{
+    const int per = (T + 7) >> 3;
+    const int b = blockIdx.x;
+    const int base = (b & 7) * per;
+    *first = base + (b >> 3);
+    *end = min(T, base + per);
+    *step = (int)(gridDim.x >> 3);
+}
+
 
 // ---- destination-bucketed permutation writes ---------------------------------
 // Scattering values to random positions costs one DRAM transaction per value;

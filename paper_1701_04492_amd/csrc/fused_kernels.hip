@@ -633,26 +633,24 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     __shared__ C buf[RC * P];
     __shared__ C tw_s[TWG ? 1 : L1];
     const C *tw = TWG ? tw_g : tw_s;
-    const int task = xcd_task((int)L2 * splits);
-    if (task < 0) return;
+    const int T = (int)L2 * splits;
+    int task, tend, tstep;
+    xcd_tasks(T, &task, &tend, &tstep);
+    if (task >= tend) return;
     if (!TWG) load_tw_s<C, L1, -1, NT>(tw_s, tw_g);
     const int tid = threadIdx.x;
     const int g = tid / TPF, lt = tid % TPF;
-    const int64_t n2 = task / splits;
-    const int part = task % splits;
     const int64_t L = (int64_t)L1 * L2;
-    // this task's share of the tile's samples (the whole tile unless splits > 1)
-    const int64_t t_lo = off[n2 * L1], t_cnt = off[(n2 + 1) * L1] - t_lo;
-    const int64_t tile_lo = t_lo + t_cnt * part / splits, tile_hi = t_lo + t_cnt * (part + 1) / splits;
-    const C *Yrow = Y + n2 * L1 + lt;
-    const __half2 *Yhrow = reinterpret_cast<const __half2 *>(Y) + n2 * L1 + lt;
-    // Rank row rr of the tile, the lanes' 16 elements (zero for rr >= K), in
+    int64_t tile_lo = 0, tile_hi = 0;   // the current task's samples [tile_lo, tile_hi)
+    // Rank row rr of tile n2f, the lanes' 16 elements (zero for rr >= K), in
     // two steps so that a prefetch stays in flight: fetch issues the loads
     // into raw registers (fp16 pairs and exponents for H), take decodes them.
     using Raw = typename std::conditional<H, __half2, C>::type;
     // (a rank beyond K loads nothing: its lanes are zero and its transform is discarded)
-    auto fetch = [&](int rr, Raw (&w)[16], int8_t (&ev)[16]) __attribute__((always_inline)) {
+    auto fetch = [&](int64_t n2f, int rr, Raw (&w)[16], int8_t (&ev)[16]) __attribute__((always_inline)) {
         const bool in = rr < fac.K;
+        const C *Yrow = Y + n2f * L1 + lt;
+        const __half2 *Yhrow = reinterpret_cast<const __half2 *>(Y) + n2f * L1 + lt;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             if constexpr (H) {
@@ -693,6 +691,20 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
     // stay in LDS for all later rounds of the tile (many samples per tile: M >> N)
     const bool once = fac.K <= RC;
 
+    // the workgroup's tasks in turn; the first rank chunk of the next task is
+    // fetched while the last one of the current task is transformed
+    Raw vn[16];
+    int8_t en[16];
+    bool have = false;   // vn holds the first chunk of this task
+    for (; task < tend; task += tstep) {
+    const int64_t n2 = task / splits;
+    const int part = task % splits;
+    // this task's share of the tile's samples (the whole tile unless splits > 1)
+    const int64_t t_lo = off[n2 * L1], t_cnt = off[(n2 + 1) * L1] - t_lo;
+    tile_lo = t_lo + t_cnt * part / splits;
+    tile_hi = t_lo + t_cnt * (part + 1) / splits;
+    const int nxt = task + tstep;
+    if (tile_lo >= tile_hi) have = false;   // no sample: nothing is transformed
     for (int64_t c0 = tile_lo; c0 < tile_hi; c0 += CAP) {
         // the round's sample data: every load issued before any is used
         // (indices clamped into the tile), then one wait
@@ -708,14 +720,22 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[s] = cmake<C>(0, 0);
         const bool transform = !once || c0 == tile_lo;
-        Raw vn[16];
-        int8_t en[16];
-        if (transform) fetch(g, vn, en);
+        // last round: fetch the next task's rows (not where the registers run short:
+        // the 4096-point rows spill, the 128-point kernel would lose a wave per SIMD)
+        constexpr bool XPF = L1 >= 256 && L1 <= 2048;
+        const bool ahead = XPF && !once && c0 + CAP >= tile_hi && nxt < tend;
+        if (transform && !have) fetch(n2, g, vn, en);
+        have = false;
         for (int r0 = 0; r0 < fac.K; r0 += RC) {
             if (transform) {
                 C v[16];
                 take(vn, en, v);
-                if (r0 + RC < fac.K) fetch(r0 + RC + g, vn, en);
+                if (r0 + RC < fac.K) {
+                    fetch(n2, r0 + RC + g, vn, en);
+                } else if (ahead) {
+                    fetch(nxt / splits, g, vn, en);
+                    have = true;
+                }
                 __syncthreads();
                 // a rank slot beyond K (the last chunk of ranks) skips its transform
                 block_fft_regs<C, L1, -1, fft_wave_sync<L1>, FR>(buf + g * P, tw, lt, v, r0 + g < fac.K);
@@ -774,6 +794,7 @@ k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__
             }
         }
         if (!once) __syncthreads();   // the next round's transforms overwrite buf
+    }
     }
 }
 
@@ -1557,6 +1578,26 @@ static void launch_pass_a(const FusedArgs<R> &a, const cx_t<R> *c, int mode, hip
                        (int64_t)a.L1, a.fac.K, rca, mode, FR == 8 ? a.tw2r8 : a.tw2, a.hi, a.lo, a.Y, a.E);
 }
 
+// Grid for a kernel whose workgroups take their tasks in turn (xcd_tasks): the
+// workgroups the device holds at once (per-CU occupancy x CUs, rounded down to a
+// multiple of 8), at most xcd_grid(T).  Queried once per kernel and device.
+template <typename F>
+static unsigned resident_grid(F kernel, int threads, int T)
+{
+    constexpr int MAXDEV = 64;
+    static int cap[MAXDEV];   // 0: not queried yet; -1: no answer (one block per task)
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return xcd_grid(T);
+    if (cap[dev] == 0) {
+        int per_cu = 0, ncu = 0;
+        const bool ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) == hipSuccess &&
+                        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
+        cap[dev] = ok && per_cu * ncu >= 8 ? (per_cu * ncu) / 8 * 8 : -1;
+    }
+    const unsigned full = xcd_grid(T);
+    return cap[dev] > 0 && (unsigned)cap[dev] < full ? (unsigned)cap[dev] : full;
+}
+
 // Pass B writes its outputs through the destination-bucketed layout (a.bbuf,
 // then bucket_to_samples) when the plan has one and the shapes allow it; returns whether it did.
 template <typename R, int LL, int RR, int SS, bool HX, int FR>
@@ -1567,7 +1608,8 @@ static bool launch_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_
     // the bucket counts are scanned by the workgroup's threads, two each
     const bool buck = a.bdst && a.fac.K > RR && nbk <= 2 * RR * (LL / 16) &&
                       pass_b_buckets(LL, RR, SS, (int)sizeof(cx_t<R>));
-    hipLaunchKernelGGL((k_passB<R, LL, RR, SS, false, HX, FR>), dim3(xcd_grid(a.L2 * sp)), dim3(RR * LL / 16), 0, s,
+    const auto kern = k_passB<R, LL, RR, SS, false, HX, FR>;
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, RR * LL / 16, (int)a.L2 * sp)), dim3(RR * LL / 16), 0, s,
                        (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,
                        FR == 8 ? a.tw1r8 : a.tw1, f, mode, g, gx, a.E, sp, buck ? a.bdst : nullptr, a.bshift, nbk,
                        a.bbuf);
