@@ -21,6 +21,7 @@
 // transformed along n1, and pass A' transforms along n2, scales by v_r and
 // sums over r in registers.
 #include <algorithm>
+#include <atomic>
 
 #include "fused_common.h"
 
@@ -1580,22 +1581,25 @@ static void launch_pass_a(const FusedArgs<R> &a, const cx_t<R> *c, int mode, hip
 
 // Grid for a kernel whose workgroups take their tasks in turn (xcd_tasks): the
 // workgroups the device holds at once (per-CU occupancy x CUs, rounded down to a
-// multiple of 8), at most xcd_grid(T).  Queried once per kernel and device.
+// multiple of 8), at most xcd_grid(T).  cap caches the answer per device and
+// belongs to one kernel (kernels of one signature share the pointer type F, so
+// the caller keeps it: 0 not queried yet, -1 no answer, one block per task).
+constexpr int RESIDENT_MAXDEV = 64;
 template <typename F>
-static unsigned resident_grid(F kernel, int threads, int T)
+static unsigned resident_grid(F kernel, int threads, int T, std::atomic<int> (&cap)[RESIDENT_MAXDEV])
 {
-    constexpr int MAXDEV = 64;
-    static int cap[MAXDEV];   // 0: not queried yet; -1: no answer (one block per task)
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return xcd_grid(T);
-    if (cap[dev] == 0) {
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= RESIDENT_MAXDEV) return xcd_grid(T);
+    int c = cap[dev].load(std::memory_order_relaxed);
+    if (c == 0) {   // concurrent first calls may both query; they store the same answer
         int per_cu = 0, ncu = 0;
         const bool ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) == hipSuccess &&
                         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
-        cap[dev] = ok && per_cu * ncu >= 8 ? (per_cu * ncu) / 8 * 8 : -1;
+        c = ok && per_cu * ncu >= 8 ? (per_cu * ncu) / 8 * 8 : -1;
+        cap[dev].store(c, std::memory_order_relaxed);
     }
     const unsigned full = xcd_grid(T);
-    return cap[dev] > 0 && (unsigned)cap[dev] < full ? (unsigned)cap[dev] : full;
+    return c > 0 && (unsigned)c < full ? (unsigned)c : full;
 }
 
 // Pass B writes its outputs through the destination-bucketed layout (a.bbuf,
@@ -1609,7 +1613,8 @@ static bool launch_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_
     const bool buck = a.bdst && a.fac.K > RR && nbk <= 2 * RR * (LL / 16) &&
                       pass_b_buckets(LL, RR, SS, (int)sizeof(cx_t<R>));
     const auto kern = k_passB<R, LL, RR, SS, false, HX, FR>;
-    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, RR * LL / 16, (int)a.L2 * sp)), dim3(RR * LL / 16), 0, s,
+    static std::atomic<int> cap[RESIDENT_MAXDEV];   // this instantiation's resident workgroups per device
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, RR * LL / 16, (int)a.L2 * sp, cap)), dim3(RR * LL / 16), 0, s,
                        (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,
                        FR == 8 ? a.tw1r8 : a.tw1, f, mode, g, gx, a.E, sp, buck ? a.bdst : nullptr, a.bshift, nbk,
                        a.bbuf);
