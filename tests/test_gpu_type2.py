@@ -203,6 +203,41 @@ def test_many_samples_per_tile(dtype):
     check_type2(x, c, N, dtype, rows=rows, label="M = 256 N")
 
 
+@pytest.mark.parametrize("eps", [0.1, 1e-6])
+def test_tiles_taken_in_turn(eps):
+    """Pass B's workgroups take several output tiles each (2^20 modes: 1024 tiles, more
+    than the device holds workgroups at once) and fetch the next tile's first rank rows
+    ahead.  Half the tiles hold no sample, a band holds about eight per grid point, and
+    eps = 0.1 gives K = 4, where every rank is transformed once per tile and nothing is
+    fetched ahead.  At eps = 0.1 the error bound is too loose to show a misrouted tile,
+    so that case is compared with the oracle's low-rank transform at the same K (the same
+    approximation in FP64: FP32 rounding apart); eps = 1e-6 with the direct sum.  A
+    second call gives the same bits."""
+    N = 1 << 20
+    rng = W.rng_for(29)
+    x = np.concatenate([0.5 + rng.random(300000) * 0.5, 0.6 + rng.random(400000) * 0.05])
+    x = x[rng.permutation(x.shape[0])]
+    c = W.complex_normal(rng, N)
+    rows = _rows_subset(x, N, N, 256, 12)
+    if eps == 0.1:
+        xt, ct = _t(x, torch.float64), _t(c, C64)
+        plan = P.nufft2_plan(xt, N, eps, C64, P.NUFFT_FLAG_NO_AUTOTUNE)
+        assert plan.K == 4 and plan.grid == N, (plan.K, plan.grid)
+        f = P.nufft2_exec(plan, ct).cpu().numpy()
+        cc = ct.cpu().numpy().astype(np.complex128)
+        op = Lr.Plan(x, N, eps, gamma=plan.gamma)
+        assert op.K == plan.K
+        ref = op.type2(cc)
+        err = np.abs(f - ref).max() / np.abs(cc).sum()
+        _say("   K=4 against the FP64 low-rank transform: err/||c||_1 = %.3e" % err)
+        assert err <= 4e-6
+    else:
+        plan, f, _ = check_type2(x, c, N, C64, eps=eps, flags=P.NUFFT_FLAG_NO_AUTOTUNE, rows=rows,
+                                 label="tiles in turn")
+    again = P.nufft2_exec(plan, _t(c, C64)).cpu().numpy()
+    assert np.array_equal(f, again)
+
+
 def test_beyond_max_size_rejected():
     x = torch.zeros(4, dtype=torch.float64, device=DEV)
     with pytest.raises(P.NufftError):
