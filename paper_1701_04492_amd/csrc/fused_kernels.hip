@@ -558,6 +558,9 @@ k_passA_wide(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RC
 #pragma unroll
     for (int j = 0; j < 4; ++j) Bv[j] = tw_big<C, -1>(hi, lo, k1 * (n2_0 + 8 * ST * j));
     const ZMap zm = zmap(N);
+    // L1 is a power of two: row offsets are shifts (a runtime multiply is a quarter-rate
+    // integer instruction, and these are formed anew for every rank)
+    const int l1s = __builtin_ctzll((unsigned long long)L1);
     for (int r = r_lo; r < r_hi; ++r) {
         __syncthreads();   // earlier readers of buf are done
         // the sample coordinates are recomputed per rank: an empty asm makes the row
@@ -568,8 +571,9 @@ k_passA_wide(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RC
         for (int h = 0; h < 2; ++h) {
             C v[16];
             R wq[16], zk[16];
+            const int kc = (int)k1_0 + g + h * GH;   // mode indices are below 2^23
 #pragma unroll
-            for (int q = 0; q < 16; ++q) zk[q] = zcoord<R>((k1_0 + g + h * GH) + L1 * (int64_t)(lr + q * TPF), zm);
+            for (int q = 0; q < 16; ++q) zk[q] = zcoord<R>((int64_t)(kc + ((lr + q * TPF) << l1s)), zm);
             cheb_v_many<R, 16>(r, zk, wq);
 #pragma unroll
             for (int q = 0; q < 16; ++q) v[q] = cscale(cv[h][q], wq[q]);
@@ -587,7 +591,7 @@ k_passA_wide(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RC
             for (int ja = 0; ja < 8; ++ja) o[ja] = buf[go * P + lds_pad(n2o + ST * (8 * jb + ja))];
 #pragma unroll
             for (int ja = 0; ja < 8; ++ja)
-                Yr[(int64_t)(n2o + ST * (8 * jb + ja)) * L1] = cmul(cmul(o[ja], Bv[jb]), Av[ja]);
+                Yr[(int64_t)(n2o + ST * (8 * jb + ja)) << l1s] = cmul(cmul(o[ja], Bv[jb]), Av[ja]);
         }
     }
 }
@@ -1208,8 +1212,9 @@ k_sum_split_rows(const cx_t<R> *__restrict__ Zp, int splits, int K, int L1, int6
 // pass A measured faster, 35 against 40 us at 2^20); pass A' also needs
 // L1/G >= 256 column groups, since it cannot split its ranks over workgroups
 // (at 2^20, 64 wide workgroups took 101 us against 47 us for the narrow kernel).
-#define WIDE_A(L1, L2) ((L2) == 2048)
-#define WIDE_A_ADJ(L1, L2) ((L2) == 2048 && (L1) / 8 >= 256)
+// (L1 is a power of two on every plan; the wide kernels form row offsets by shifts)
+#define WIDE_A(L1, L2) ((L2) == 2048 && ((L1) & ((L1) - 1)) == 0)
+#define WIDE_A_ADJ(L1, L2) ((L2) == 2048 && (L1) / 8 >= 256 && ((L1) & ((L1) - 1)) == 0)
 // Pass A' with wide column blocks (FP32, full-precision exchange; launched at
 // L2 = 2048 with at least 256 column groups, see WIDE_A_ADJ): G columns per workgroup, each thread transforming two of them, so
 // that the intermediate is read in G*8-byte runs (64 bytes at G = 8; a
@@ -1240,6 +1245,7 @@ k_passA_adj_wide(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, co
     const int64_t L = L1 * L2;
     const ZMap zm = zmap(N);
     const int gg = tid % G, n2_0 = tid / G;
+    const int l1s = __builtin_ctzll((unsigned long long)L1);   // L1 is a power of two: offsets are shifts
     C acc[32];
 #pragma unroll
     for (int e = 0; e < 32; ++e) acc[e] = cmake<C>(0, 0);
@@ -1249,12 +1255,12 @@ k_passA_adj_wide(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, co
         // formed per rank instead of being kept in registers across ranks)
         int ti = tid;
         asm volatile("" : "+v"(ti));
-        const C *Zr = Z + (int64_t)r * L + k1_0 + ti % G + (int64_t)(ti / G) * L1;
+        const C *Zr = Z + (int64_t)r * L + k1_0 + ti % G + ((int64_t)(ti / G) << l1s);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             C cl[16];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) cl[e] = Zr[(int64_t)((h * 16 + e) * ST) * L1];
+            for (int e = 0; e < 16; ++e) cl[e] = Zr[(int64_t)((h * 16 + e) * ST) << l1s];
 #pragma unroll
             for (int e = 0; e < 16; ++e) buf[(ti % G) * P + lds_pad(ti / G + (h * 16 + e) * ST)] = cl[e];
         }
@@ -1267,7 +1273,7 @@ k_passA_adj_wide(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, co
         for (int h = 0; h < 32; h += 8) {
             R zq[8], wq[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) zq[e] = zcoord<R>(k1_0 + go + L1 * (int64_t)(n2o + ST * (h + e)), zm);
+            for (int e = 0; e < 8; ++e) zq[e] = zcoord<R>((int64_t)((int)k1_0 + go + ((n2o + ST * (h + e)) << l1s)), zm);
             cheb_v_many<R, 8>(r, zq, wq);
 #pragma unroll
             for (int e = 0; e < 8; ++e)
