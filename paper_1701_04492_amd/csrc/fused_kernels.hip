@@ -495,19 +495,22 @@ k_passA(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, in
     }
 }
 
-// Pass A with wide column blocks (FP32, full-precision exchange; launched at
-// L2 = 2048, see WIDE_A): G columns per workgroup with each thread transforming two of them
-// (columns g and g + G/2), so that the exchange is written in G*8-byte runs
-// (64 bytes at G = 8) at the register budget of G/2 columns.  Narrow runs
-// waste most of each DRAM burst: measured on this store pattern alone, 32-byte
-// runs reach 3.3 TB/s and 64-byte runs 5.7 TB/s.  The inter-pass twiddle of
-// output (k1, n2) is Bv[jb] * Av[ja] with n2 = n2_0 + (NT/G)(8 jb + ja): twelve
-// table values per thread instead of 32.
-template <typename R, int L2, int G, int FR = 16>
+// Pass A with wide column blocks (FP32; launched at L2 = 2048, see WIDE_A): G
+// columns per workgroup with each thread transforming two of them (columns g
+// and g + G/2), so that the exchange is written in G*8-byte runs (64 bytes at
+// G = 8; G*4 = 32 bytes for the half-precision exchange) at the register budget
+// of G/2 columns.  Narrow runs waste most of each DRAM burst: measured on this
+// store pattern alone, 32-byte runs reach 3.3 TB/s and 64-byte runs 5.7 TB/s.
+// The inter-pass twiddle of output (k1, n2) is Bv[jb] * Av[ja] with
+// n2 = n2_0 + (NT/G)(8 jb + ja): twelve table values per thread instead of 32.
+// H: Y in fp16 pairs scaled per (rank, column) by 2^E[r * L1 + k1]; a thread's
+// 32 outputs all lie in its column, so it forms them twice (for the column's
+// block maximum, then to pack them) instead of holding 64 more registers.
+template <typename R, int L2, int G, bool H = false, int FR = 16>
 __global__ void __launch_bounds__(G / 2 * L2 / 16)
 k_passA_wide(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RCA, int mode,
              const cx_t<R> *__restrict__ tw_g, const cx_t<R> *__restrict__ hi, const cx_t<R> *__restrict__ lo,
-             cx_t<R> *__restrict__ Y)
+             cx_t<R> *__restrict__ Y, int8_t *__restrict__ E = nullptr)
 {
     using C = cx_t<R>;
     constexpr int TPF = L2 / 16;
@@ -516,8 +519,10 @@ k_passA_wide(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RC
     constexpr int P = fft_pitch_g(L2, G);
     constexpr int ST = NT / G;           // rows between a thread's consecutive outputs
     static_assert(fft_radix_p(L2) == 1 && NT % G == 0 && G * L2 == 32 * NT, "two halves of 16 elements");
+    static_assert(!H || sizeof(R) == 4, "the half-precision exchange is an FP32 path");
     __shared__ C buf[G * P];
     __shared__ C tw_s[L2];
+    __shared__ unsigned smax[H ? 2 * G : 1];   // per-column block maxima (float bits), two parities
     const int nrc = (K + RCA - 1) / RCA;
     const int task = xcd_task((int)(L1 / G) * nrc);
     if (task < 0) return;
@@ -525,6 +530,7 @@ k_passA_wide(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RC
     const int r_lo = rc * RCA, r_hi = min(K, r_lo + RCA);
     load_tw_s<C, L2, -1, NT>(tw_s, tw_g);
     const int tid = threadIdx.x;
+    if (H && tid < 2 * G) smax[tid] = 0;
     const int g = tid / TPF, lt = tid % TPF;
     const int64_t k1_0 = (int64_t)cg * G;
     const int64_t L = L1 * L2;
@@ -583,15 +589,47 @@ k_passA_wide(const cx_t<R> *__restrict__ c, int64_t N, int64_t L1, int K, int RC
         // (opaque copies again: the 32 output addresses are formed here, not kept across ranks)
         int n2o = n2_0, go = gg;
         asm volatile("" : "+v"(n2o), "+v"(go));
-        C *Yr = Y + (int64_t)r * L + k1_0 + go;
+        if constexpr (H) {
+            float m = 0.0f;
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            C o[8];
+            for (int jb = 0; jb < 4; ++jb) {
+                C o[8];
 #pragma unroll
-            for (int ja = 0; ja < 8; ++ja) o[ja] = buf[go * P + lds_pad(n2o + ST * (8 * jb + ja))];
+                for (int ja = 0; ja < 8; ++ja) o[ja] = buf[go * P + lds_pad(n2o + ST * (8 * jb + ja))];
 #pragma unroll
-            for (int ja = 0; ja < 8; ++ja)
-                Yr[(int64_t)(n2o + ST * (8 * jb + ja)) << l1s] = cmul(cmul(o[ja], Bv[jb]), Av[ja]);
+                for (int ja = 0; ja < 8; ++ja) m = fmaxf(m, cmaxabs(cmul(cmul(o[ja], Bv[jb]), Av[ja])));
+            }
+            // lanes agreeing mod G share the column; lane l < G then holds column l's wave maximum
+            m = wave_max_mod(m, G);
+            unsigned *sm = smax + (r & 1) * G;
+            if ((tid & 63) < G) atomicMax(&sm[tid & 63], __float_as_uint(m));
+            __syncthreads();
+            const int ex = hx_exponent(__uint_as_float(sm[go]));
+            if (tid < G) {
+                E[(int64_t)r * L1 + k1_0 + tid] = (int8_t)ex;
+                smax[((r + 1) & 1) * G + tid] = 0;   // its last readers finished before this rank's first barrier
+            }
+            __half2 *Yh = reinterpret_cast<__half2 *>(Y) + (int64_t)r * L + k1_0 + go;
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                C o[8];
+#pragma unroll
+                for (int ja = 0; ja < 8; ++ja) o[ja] = buf[go * P + lds_pad(n2o + ST * (8 * jb + ja))];
+#pragma unroll
+                for (int ja = 0; ja < 8; ++ja)
+                    Yh[(int64_t)(n2o + ST * (8 * jb + ja)) << l1s] = hx_pack(cmul(cmul(o[ja], Bv[jb]), Av[ja]), ex);
+            }
+        } else {
+            C *Yr = Y + (int64_t)r * L + k1_0 + go;
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                C o[8];
+#pragma unroll
+                for (int ja = 0; ja < 8; ++ja) o[ja] = buf[go * P + lds_pad(n2o + ST * (8 * jb + ja))];
+#pragma unroll
+                for (int ja = 0; ja < 8; ++ja)
+                    Yr[(int64_t)(n2o + ST * (8 * jb + ja)) << l1s] = cmul(cmul(o[ja], Bv[jb]), Av[ja]);
+            }
         }
     }
 }
@@ -1215,17 +1253,20 @@ k_sum_split_rows(const cx_t<R> *__restrict__ Zp, int splits, int K, int L1, int6
 // (L1 is a power of two on every plan; the wide kernels form row offsets by shifts)
 #define WIDE_A(L1, L2) ((L2) == 2048 && ((L1) & ((L1) - 1)) == 0)
 #define WIDE_A_ADJ(L1, L2) ((L2) == 2048 && (L1) / 8 >= 256 && ((L1) & ((L1) - 1)) == 0)
-// Pass A' with wide column blocks (FP32, full-precision exchange; launched at
-// L2 = 2048 with at least 256 column groups, see WIDE_A_ADJ): G columns per workgroup, each thread transforming two of them, so
-// that the intermediate is read in G*8-byte runs (64 bytes at G = 8; a
+// Pass A' with wide column blocks (FP32; launched at L2 = 2048 with at least
+// 256 column groups, see WIDE_A_ADJ): G columns per workgroup, each thread
+// transforming two of them, so that the intermediate is read in G*8-byte runs
+// (64 bytes at G = 8, G*4 = 32 bytes for the half-precision exchange; a
 // 16-byte-run read of the same block measured 2.3 TB/s against 4.1 TB/s at
 // 64 bytes).  The rank's block goes to LDS in two rounds of sixteen loads per
 // thread (no register prefetch: the accumulators of 32 outputs hold the
 // registers); outputs (k1, n2) with k1 = tid mod G accumulate in registers.
-template <typename R, int L2, int G, int DIR, int FR = 16>
+// H: Z in fp16 pairs scaled per (rank, row) by 2^E[r * L2 + n2]; the rank's L2
+// row exponents are staged in LDS first (one 4-byte word per thread).
+template <typename R, int L2, int G, int DIR, bool H = false, int FR = 16>
 __global__ void __launch_bounds__(G / 2 * L2 / 16)
 k_passA_adj_wide(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, const cx_t<R> *__restrict__ tw_g,
-                 cx_t<R> *__restrict__ out)
+                 cx_t<R> *__restrict__ out, const int8_t *__restrict__ E = nullptr)
 {
     using C = cx_t<R>;
     constexpr int TPF = L2 / 16;
@@ -1234,8 +1275,10 @@ k_passA_adj_wide(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, co
     constexpr int P = fft_pitch_g(L2, G);
     constexpr int ST = NT / G;
     static_assert(fft_radix_p(L2) == 1 && NT % G == 0 && G * L2 == 32 * NT, "two halves of 16 elements");
+    static_assert(!H || (sizeof(R) == 4 && L2 == 4 * NT), "the half exchange: FP32, one exponent word per thread");
     __shared__ C buf[G * P];
     __shared__ C tw_s[L2];
+    __shared__ uint32_t sexp[H ? L2 / 4 : 1];   // the rank's row exponents (int8), four per word
     const int task = xcd_task((int)(L1 / G));
     if (task < 0) return;
     load_tw_s<C, L2, -1, NT>(tw_s, tw_g);   // tw_g already has the sign DIR
@@ -1255,14 +1298,27 @@ k_passA_adj_wide(const cx_t<R> *__restrict__ Z, int64_t N, int64_t L1, int K, co
         // formed per rank instead of being kept in registers across ranks)
         int ti = tid;
         asm volatile("" : "+v"(ti));
-        const C *Zr = Z + (int64_t)r * L + k1_0 + ti % G + ((int64_t)(ti / G) << l1s);
+        const int64_t zo = (int64_t)r * L + k1_0 + ti % G + ((int64_t)(ti / G) << l1s);
+        if constexpr (H) sexp[tid] = reinterpret_cast<const uint32_t *>(E + (int64_t)r * L2)[tid];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            C cl[16];
+            using Raw = typename std::conditional<H, __half2, C>::type;
+            Raw cl[16];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) cl[e] = Zr[(int64_t)((h * 16 + e) * ST) << l1s];
+            for (int e = 0; e < 16; ++e) {
+                const int64_t at = zo + ((int64_t)((h * 16 + e) * ST) << l1s);
+                if constexpr (H) cl[e] = reinterpret_cast<const __half2 *>(Z)[at];
+                else cl[e] = Z[at];
+            }
+            if (H && h == 0) __syncthreads();   // the exponents are visible (the first round's loads in flight)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) buf[(ti % G) * P + lds_pad(ti / G + (h * 16 + e) * ST)] = cl[e];
+            for (int e = 0; e < 16; ++e) {
+                const int n = ti / G + (h * 16 + e) * ST;
+                C v;
+                if constexpr (H) v = hx_unpack(cl[e], reinterpret_cast<const int8_t *>(sexp)[n]);
+                else v = cl[e];
+                buf[(ti % G) * P + lds_pad(n)] = v;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -1707,11 +1763,11 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
         else if (a.sched == 2) ok = tuned_pass_a<R, 2, 16>(a, c, mode, s);    // half the columns per workgroup
     }
     if constexpr (sizeof(R) == 4) {
-        if (!ok && !a.half && WIDE_A(a.L1, a.L2)) {   // L2 = 2048: eight columns per workgroup
+        if (!ok && WIDE_A(a.L1, a.L2)) {   // L2 = 2048: eight columns per workgroup
             const int ncg = a.L1 / 8, rca = pass_a_ranks(a.fac.K, ncg);
             const int T = ncg * ((a.fac.K + rca - 1) / rca);
-            hipLaunchKernelGGL((k_passA_wide<R, 2048, 8>), dim3(xcd_grid(T)), dim3(4 * 128), 0, s, c, a.N,
-                               (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y);
+            HX_DISPATCH(hipLaunchKernelGGL((k_passA_wide<R, 2048, 8, HX>), dim3(xcd_grid(T)), dim3(4 * 128), 0, s, c,
+                                           a.N, (int64_t)a.L1, a.fac.K, rca, mode, a.tw2, a.hi, a.lo, a.Y, a.E));
             ok = true;
         }
     }
@@ -1839,10 +1895,11 @@ static hipError_t fused_type1_dir(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<
         else if (a.sched == 2) ok = tuned_pass_a_adj<R, DIR, 2, 16>(a, f, s);
     }
     if constexpr (sizeof(R) == 4) {
-        if (!ok && !a.half && WIDE_A_ADJ(a.L1, a.L2)) {   // L2 = 2048: eight columns per workgroup
+        if (!ok && WIDE_A_ADJ(a.L1, a.L2)) {   // L2 = 2048: eight columns per workgroup
             const cx_t<R> *tw = DIR < 0 ? a.tw2 : a.tw2i;
-            hipLaunchKernelGGL((k_passA_adj_wide<R, 2048, 8, DIR>), dim3(xcd_grid(a.L1 / 8)), dim3(4 * 128), 0, s,
-                               (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K, tw, f);
+            HX_DISPATCH(hipLaunchKernelGGL((k_passA_adj_wide<R, 2048, 8, DIR, HX>), dim3(xcd_grid(a.L1 / 8)),
+                                           dim3(4 * 128), 0, s, (const cx_t<R> *)a.Y, a.N, (int64_t)a.L1, a.fac.K,
+                                           tw, f, a.E));
             ok = true;
         }
     }
