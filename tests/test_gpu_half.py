@@ -125,9 +125,11 @@ def test_half_block_scaling_range(scale):
     _check("adjoint scale %g" % scale, g[ks], D.nudft1(x, cc, N, k=ks, sign=+1), np.abs(cc).sum(), plan)
 
 
-def test_half_full_size_sampled():
-    """N = M = 2^22 (the forward+backward workload's shape) at eps = 2^-10, sampled rows."""
-    N = 1 << 22
+@pytest.mark.parametrize("N", [1 << 21, 1 << 22])
+def test_half_full_size_sampled(N):
+    """N = M = 2^22 (the forward+backward workload's shape) and 2^21 at eps = 2^-10, sampled
+    rows: the wide column blocks at 2048-point columns (at 2^21 pass A' stays narrow: 128
+    column groups), type II, adjoint and type I."""
     x, c = W.type2_case(3, N)
     plan = P.nufft2_plan(_t(x, torch.float64), N, EPS, C64, HALF | P.NUFFT_FLAG_NO_AUTOTUNE)
     assert plan.K == 7
@@ -135,10 +137,12 @@ def test_half_full_size_sampled():
     cc = ct.cpu().numpy().astype(np.complex128)
     rows = _rows(N, 48, 78)
     f = P.nufft2_exec(plan, ct).cpu().numpy()
-    _check("2^22 type II", f[rows], D.nudft2(x[rows], cc), np.abs(cc).sum(), plan)
+    _check("N=%d type II" % N, f[rows], D.nudft2(x[rows], cc), np.abs(cc).sum(), plan)
     ks = _rows(N, 24, 79)
     h = P.nufft1_exec(plan, ct, sign=+1).cpu().numpy()
-    _check("2^22 adjoint", h[ks], D.nudft1(x, cc, N, k=ks, sign=+1), np.abs(cc).sum(), plan)
+    _check("N=%d adjoint" % N, h[ks], D.nudft1(x, cc, N, k=ks, sign=+1), np.abs(cc).sum(), plan)
+    t1 = P.nufft1_exec(plan, ct, sign=-1).cpu().numpy()
+    _check("N=%d type I" % N, t1[ks], D.nudft1(x, cc, N, k=ks, sign=-1), np.abs(cc).sum(), plan)
 
 
 def test_half_flag_validation():
