@@ -659,7 +659,7 @@ __host__ __device__ constexpr bool pass_b_buckets(int L1, int RC, int S, int cby
 // transforming its rows and taking an equal slice of the tile's samples.
 // H: Y holds fp16 pairs scaled per (rank, column) by 2^E[r * L1 + k1].
 template <typename R, int L1, int RC, int S, bool TWG, bool H, int FR = 16>
-__global__ void __launch_bounds__(RC * L1 / 16)
+__global__ void __launch_bounds__(RC * L1 / 16, (L1 == 2048 && RC == 2 && S == 9) ? 2 : 1)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
         const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
         Factors<R> fac, const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ f, int mode,
@@ -1805,6 +1805,16 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
     if constexpr (sizeof(R) == 4) {
         if (a.sched == 1) ok = tuned_pass_b<R, 1, 8>(a, f, mode, g, gx, s, &buck);
         else if (a.sched == 2) ok = tuned_pass_b<R, 2, 16>(a, f, mode, g, gx, s, &buck);
+    }
+    if constexpr (sizeof(R) == 4) {
+        // the forward's 2048-point rows: two ranks side by side and nine sample slots, the
+        // registers held to two 4-wave workgroups per CU (some spill).  Measured at 2^22:
+        // 156 against 164 us; the derivative pass, with g and its double outputs on top,
+        // ran slower that way (187 against 171 us) and keeps the default shape.
+        if (!ok && mode == 0 && !a.half && a.L1 == 2048) {
+            buck = launch_pass_b<R, 2048, 2, 9, false, 16>(a, f, mode, g, gx, s);
+            ok = true;
+        }
     }
     if (!ok) {
         switch (a.L1) {
