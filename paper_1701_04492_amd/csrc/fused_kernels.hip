@@ -658,15 +658,18 @@ __host__ __device__ constexpr bool pass_b_buckets(int L1, int RC, int S, int cby
 // With many more samples than grid points, `splits` tasks share a tile, each
 // transforming its rows and taking an equal slice of the tile's samples.
 // H: Y holds fp16 pairs scaled per (rank, column) by 2^E[r * L1 + k1].
-template <typename R, int L1, int RC, int S, bool TWG, bool H, int FR = 16>
+// MODE: the output mode fixed at compile time (0 type II, 1 derivative), or -1 to
+// take the argument.
+template <typename R, int L1, int RC, int S, bool TWG, bool H, int FR = 16, int MODE = -1>
 __global__ void __launch_bounds__(RC * L1 / 16, (L1 == 2048 && RC == 2 && S == 9) ? 2 : 1)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
         const int32_t *__restrict__ perm, const R *__restrict__ Xs, const int32_t *__restrict__ off,
-        Factors<R> fac, const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ f, int mode,
+        Factors<R> fac, const cx_t<R> *__restrict__ tw_g, cx_t<R> *__restrict__ f, int mode_arg,
         const cx_t<R> *__restrict__ gup, double *__restrict__ gx, const int8_t *__restrict__ E, int splits,
         const int32_t *__restrict__ bdst, int bshift, int nbk, void *__restrict__ bout)
 {
     using C = cx_t<R>;
+    const int mode = MODE >= 0 ? MODE : mode_arg;
     constexpr int TPF = L1 / 16;
     constexpr int NT = RC * TPF;
     constexpr int P = fft_pitch(L1);
@@ -1666,7 +1669,7 @@ static unsigned resident_grid(F kernel, int threads, int T, std::atomic<int> (&c
 
 // Pass B writes its outputs through the destination-bucketed layout (a.bbuf,
 // then bucket_to_samples) when the plan has one and the shapes allow it; returns whether it did.
-template <typename R, int LL, int RR, int SS, bool HX, int FR>
+template <typename R, int LL, int RR, int SS, bool HX, int FR, int MODE = -1>
 static bool launch_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_t<R> *g, double *gx, hipStream_t s)
 {
     const int sp = pass_b_splits(a.M, a.L2, LL, RR * (LL / 16) * SS);
@@ -1674,7 +1677,7 @@ static bool launch_pass_b(const FusedArgs<R> &a, cx_t<R> *f, int mode, const cx_
     // the bucket counts are scanned by the workgroup's threads, two each
     const bool buck = a.bdst && a.fac.K > RR && nbk <= 2 * RR * (LL / 16) &&
                       pass_b_buckets(LL, RR, SS, (int)sizeof(cx_t<R>));
-    const auto kern = k_passB<R, LL, RR, SS, false, HX, FR>;
+    const auto kern = k_passB<R, LL, RR, SS, false, HX, FR, MODE>;
     static std::atomic<int> cap[RESIDENT_MAXDEV];   // this instantiation's resident workgroups per device
     hipLaunchKernelGGL(kern, dim3(resident_grid(kern, RR * LL / 16, (int)a.L2 * sp, cap)), dim3(RR * LL / 16), 0, s,
                        (const cx_t<R> *)a.Y, (int64_t)a.L2, a.M, a.keys, a.perm, a.Xs, a.off, a.fac,
@@ -1807,12 +1810,13 @@ hipError_t fused_type2(const FusedArgs<R> &a, const cx_t<R> *c, cx_t<R> *f, int 
         else if (a.sched == 2) ok = tuned_pass_b<R, 2, 16>(a, f, mode, g, gx, s, &buck);
     }
     if constexpr (sizeof(R) == 4) {
-        // the forward's 2048-point rows: two ranks side by side and nine sample slots, the
-        // registers held to two 4-wave workgroups per CU (some spill).  Measured at 2^22:
-        // 156 against 164 us; the derivative pass, with g and its double outputs on top,
-        // ran slower that way (187 against 171 us) and keeps the default shape.
-        if (!ok && mode == 0 && !a.half && a.L1 == 2048) {
-            buck = launch_pass_b<R, 2048, 2, 9, false, 16>(a, f, mode, g, gx, s);
+        // 2048-point rows: two ranks side by side and nine sample slots, the registers held
+        // to two 4-wave workgroups per CU (some spill), one kernel per mode so that each has
+        // its own register allocation (31 spills each, against 66 for one kernel serving
+        // both).  Measured at 2^22: forward 155 against 164 us, derivative 156 against 171.
+        if (!ok && !a.half && a.L1 == 2048) {
+            buck = mode == 0 ? launch_pass_b<R, 2048, 2, 9, false, 16, 0>(a, f, mode, g, gx, s)
+                             : launch_pass_b<R, 2048, 2, 9, false, 16, 1>(a, f, mode, g, gx, s);
             ok = true;
         }
     }
