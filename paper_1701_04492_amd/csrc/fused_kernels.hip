@@ -647,9 +647,12 @@ __host__ __device__ constexpr bool pass_b_buckets(int L1, int RC, int S, int cby
     return bucket_scratch_bytes(RC * L1 / 16, S, cbytes > 8 ? cbytes : 8) <= cbytes * RC * fft_pitch(L1);
 }
 
-// Pass B of type II.  Task = one output tile n2.  RC ranks are transformed
-// side by side (L1/16 threads each); the next chunk's rows are loaded into
-// registers while the current chunk is transformed and gathered.  Every
+// Pass B of type II.  Task = one output tile n2 (or a share of it, below); a
+// workgroup takes its XCD's tasks in turn (xcd_tasks), as many workgroups as the
+// device holds at once.  RC ranks are transformed side by side (L1/16 threads
+// each); the next chunk's rows, or at a task's last chunk the next task's first
+// rows, are loaded into registers while the current chunk is transformed and
+// gathered.  Every
 // sample of the tile (up to NT*S per round) gathers its RC spectrum values
 // from LDS and accumulates u_r(j) X_r[t_j] in registers.  When K <= RC the
 // transforms are done once per task and serve every round of its samples;
@@ -659,7 +662,8 @@ __host__ __device__ constexpr bool pass_b_buckets(int L1, int RC, int S, int cby
 // transforming its rows and taking an equal slice of the tile's samples.
 // H: Y holds fp16 pairs scaled per (rank, column) by 2^E[r * L1 + k1].
 // MODE: the output mode fixed at compile time (0 type II, 1 derivative), or -1 to
-// take the argument.
+// take the argument.  The two-rank, nine-slot shape at 2048 points asks for two
+// workgroups per CU in its launch bounds (the registers of two waves per SIMD).
 template <typename R, int L1, int RC, int S, bool TWG, bool H, int FR = 16, int MODE = -1>
 __global__ void __launch_bounds__(RC * L1 / 16, (L1 == 2048 && RC == 2 && S == 9) ? 2 : 1)
 k_passB(const cx_t<R> *__restrict__ Y, int64_t L2, int64_t M, const uint32_t *__restrict__ keys,
