@@ -114,12 +114,14 @@ def test_n2p23_max_size_sampled():
 
 # ---- gradients --------------------------------------------------------------
 
-def test_n2p22_backward_sampled():
+@pytest.mark.parametrize("dist", ["iid", "jitter"])
+def test_n2p22_backward_sampled(dist):
     """The backward of the bench step exactly as timed (N = M = 2^22, complex64,
     eps 1e-6, nufft2_backward): dL/dc on sampled modes, dL/dx on sampled samples
-    (seeded random ones, every wrap sample, the largest |delta|)."""
+    (seeded random ones, every wrap sample, the largest |delta|), and the forward on
+    the same samples, for iid and jittered samples."""
     N = 1 << 22
-    x, c = W.type2_case(3, N)
+    x, c = W.type2_case(3, N, N, dist)
     g = W.complex_normal(W.rng_for(28), N)
     plan = P.nufft2_plan(_t(x, torch.float64), N, EPS[C64], C64)
     ct, gt = _t(c, C64), _t(g, C64)
@@ -139,11 +141,14 @@ def test_n2p22_backward_sampled():
     rows = np.array(sorted(rows), dtype=np.int64)
     ref_x = D.grad_x(x[rows], cc, gg[rows])
     bound = 4 * EPS[C64] * np.abs(gg[rows]) * 2 * np.pi * (np.arange(N) * np.abs(cc)).sum()
-    _say("2^22 backward: K=%d dL/dc err/||g||_1 %.3e, dL/dx max err/bound %.3e"
-         % (plan.K, err_c, (np.abs(gx[rows] - ref_x) / bound).max()))
+    f = P.nufft2_exec(plan, ct).cpu().numpy()
+    err_f = np.abs(f[rows] - D.nudft2(x[rows], cc)).max() / np.abs(cc).sum()
+    _say("2^22 %s backward: K=%d dL/dc err/||g||_1 %.3e, dL/dx max err/bound %.3e, forward err/||c||_1 %.3e"
+         % (dist, plan.K, err_c, (np.abs(gx[rows] - ref_x) / bound).max(), err_f))
     assert np.all(np.isfinite(gc)) and np.all(np.isfinite(gx))
     assert err_c <= 4 * EPS[C64]
     assert np.all(np.abs(gx[rows] - ref_x) <= bound)
+    assert err_f <= 4 * EPS[C64]
 
 
 @pytest.mark.parametrize("dtype", [C64, C128])
